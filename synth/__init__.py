@@ -1,0 +1,302 @@
+"""Seeded synthetic inputs for batched IK: robot trees, joint draws, seeds.
+
+This module only *draws* numbers.  It holds none of the method's arithmetic
+(no forward kinematics, no residuals, no solver); both the FP64 oracle and
+the GPU path consume what it returns, and each computes targets = FK(q*)
+with its own code.
+
+Every floating-point value returned here is representable in FP32 (it is
+rounded to FP32 and promoted back), so both sides start from bit-identical
+inputs.  Draw order is fixed and documented per function so that a smaller
+request with the same seed is a prefix of a larger one.
+
+Robot families (the paper's workloads use real URDFs that are not available;
+these seeded families stand in for them):
+
+* ``arm7``  — 7-DoF serial revolute arm, axes z,y,z,y,z,y,z, link offsets
+  (U[0.05,0.30], 0, U[0.05,0.30]) in the parent frame, limits ±U[pi/2, pi].
+* ``tree34`` — humanoid-like tree: a 6-joint torso chain (z,y,z,y,z,y) and 4
+  branches of 7 joints (z,y,z,y,z,y,z) hanging off the torso's last joint,
+  branch c mounted with a rotation Rz(c*pi/2); one pose end effector per
+  branch.  34 DoF, 4 EEs.
+* ``hand16`` — 4 fingers of 4 joints (z,y,z,y) from the base, offsets
+  U[0.02,0.05], finger c's root shifted by (0, (c-1.5)*0.02, 0); one
+  position-only fingertip EE per finger.  16 DoF, 4 EEs.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import math
+
+import numpy as np
+
+__all__ = [
+    "Tree", "EE_POSE", "EE_POSITION", "arm7", "tree34", "hand16", "chain",
+    "planar2", "one_joint", "uniform_configs", "workload", "mlp_init",
+    "epoch_permutation", "f32",
+]
+
+EE_POSE = 0
+EE_POSITION = 1
+
+_AX = {"x": (1.0, 0.0, 0.0), "y": (0.0, 1.0, 0.0), "z": (0.0, 0.0, 1.0)}
+
+
+def f32(a):
+    """Round to FP32 and promote back to float64 (exact)."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+@dataclass
+class Tree:
+    """A revolute joint tree in topological order (parent[j] < j, -1 = base).
+
+    Joint j's frame is its parent's frame, translated by ``offset[j]``
+    (expressed in the parent frame), rotated by the mount rotation
+    ``mount_quat[j]`` (wxyz) and then by the joint rotation about ``axis[j]``
+    (expressed after the mount).  EE k is rigidly attached to joint
+    ``ee_joint[k]`` with ``ee_offset[k]`` / ``ee_quat[k]``.
+    """
+    name: str
+    parent: np.ndarray          # int32 [n]
+    mount_quat: np.ndarray      # [n,4] wxyz
+    offset: np.ndarray          # [n,3]
+    axis: np.ndarray            # [n,3]
+    lower: np.ndarray           # [n]
+    upper: np.ndarray           # [n]
+    ee_joint: np.ndarray        # int32 [m]
+    ee_offset: np.ndarray       # [m,3]
+    ee_quat: np.ndarray         # [m,4]
+    ee_kind: np.ndarray         # int32 [m]
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.parent.shape[0])
+
+    @property
+    def m(self) -> int:
+        return int(self.ee_joint.shape[0])
+
+    def target_width(self) -> list[int]:
+        """Per EE: 7 target values (p, quat) for pose EEs, 3 for position EEs."""
+        return [7 if k == EE_POSE else 3 for k in self.ee_kind]
+
+
+def _finish(name, parent, mount, offset, axis, lim, ee_joint, ee_offset, ee_quat,
+            ee_kind, meta=None) -> Tree:
+    lim = f32(lim)
+    return Tree(
+        name=name,
+        parent=np.asarray(parent, dtype=np.int32),
+        mount_quat=f32(mount).reshape(-1, 4),
+        offset=f32(offset).reshape(-1, 3),
+        axis=f32(axis).reshape(-1, 3),
+        lower=-lim.copy(),
+        upper=lim.copy(),
+        ee_joint=np.asarray(ee_joint, dtype=np.int32),
+        ee_offset=f32(ee_offset).reshape(-1, 3),
+        ee_quat=f32(ee_quat).reshape(-1, 4),
+        ee_kind=np.asarray(ee_kind, dtype=np.int32),
+        meta=dict(meta or {}),
+    )
+
+
+def _xz_offsets(rng, count, lo, hi):
+    """count offsets (x, 0, z); per offset x is drawn, then z."""
+    d = rng.uniform(lo, hi, size=(count, 2))
+    out = np.zeros((count, 3))
+    out[:, 0] = d[:, 0]
+    out[:, 2] = d[:, 1]
+    return out
+
+
+def chain(axes: str, seed: int, off_lo=0.05, off_hi=0.30, name=None) -> Tree:
+    """Serial revolute chain from the base with one pose EE at its tip.
+
+    Draw order (one PCG64 stream): n joint offsets, the EE offset, n limit
+    half-widths U[pi/2, pi].
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = len(axes)
+    offs = _xz_offsets(rng, n + 1, off_lo, off_hi)
+    lim = rng.uniform(math.pi / 2, math.pi, size=n)
+    ident = np.tile([1.0, 0.0, 0.0, 0.0], (n, 1))
+    return _finish(name or f"chain{n}", np.arange(n) - 1, ident, offs[:n],
+                   [_AX[a] for a in axes], lim, [n - 1], offs[n:n + 1],
+                   [[1.0, 0.0, 0.0, 0.0]], [EE_POSE], {"seed": seed, "axes": axes})
+
+
+def arm7(seed: int = 0) -> Tree:
+    return chain("zyzyzyz", seed, name="arm7")
+
+
+def tree34(seed: int = 5) -> Tree:
+    """Torso (6) + 4 branches (7 each) off the torso tip; 4 pose EEs.
+
+    Draw order: 34 joint offsets in joint order (torso, then branch 0..3),
+    4 EE offsets, 34 limit half-widths.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    torso, nb, lb = 6, 4, 7
+    n = torso + nb * lb
+    offs = _xz_offsets(rng, n, 0.05, 0.30)
+    eeo = _xz_offsets(rng, nb, 0.05, 0.30)
+    lim = rng.uniform(math.pi / 2, math.pi, size=n)
+    parent, axes, mount, ee_joint = [], [], [], []
+    for j in range(torso):
+        parent.append(j - 1)
+        axes.append(_AX["zy"[j % 2]])
+        mount.append([1.0, 0.0, 0.0, 0.0])
+    for c in range(nb):
+        for i in range(lb):
+            j = torso + c * lb + i
+            parent.append(torso - 1 if i == 0 else j - 1)
+            axes.append(_AX["zy"[i % 2]])
+            if i == 0:
+                h = c * math.pi / 4.0   # half-angle of Rz(c*pi/2)
+                mount.append([math.cos(h), 0.0, 0.0, math.sin(h)])
+            else:
+                mount.append([1.0, 0.0, 0.0, 0.0])
+        ee_joint.append(torso + c * lb + lb - 1)
+    return _finish("tree34", parent, mount, offs, axes, lim, ee_joint, eeo,
+                   np.tile([1.0, 0.0, 0.0, 0.0], (nb, 1)), [EE_POSE] * nb,
+                   {"seed": seed, "torso": torso, "branches": nb, "branch_len": lb})
+
+
+def hand16(seed: int = 8) -> Tree:
+    """4 fingers x 4 joints from the base; 4 position-only fingertip EEs.
+
+    Draw order: 16 joint offsets (finger-major), 4 fingertip offsets, 16 limit
+    half-widths.  Finger c's root offset gets (0, (c-1.5)*0.02, 0) added.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nf, lf = 4, 4
+    n = nf * lf
+    offs = _xz_offsets(rng, n, 0.02, 0.05)
+    eeo = _xz_offsets(rng, nf, 0.02, 0.05)
+    lim = rng.uniform(math.pi / 2, math.pi, size=n)
+    parent, axes, ee_joint = [], [], []
+    for c in range(nf):
+        for i in range(lf):
+            j = c * lf + i
+            parent.append(-1 if i == 0 else j - 1)
+            axes.append(_AX["zy"[i % 2]])
+            if i == 0:
+                offs[j, 1] += (c - 1.5) * 0.02
+        ee_joint.append(c * lf + lf - 1)
+    return _finish("hand16", parent, np.tile([1.0, 0, 0, 0], (n, 1)), offs, axes, lim,
+                   ee_joint, eeo, np.tile([1.0, 0, 0, 0], (nf, 1)), [EE_POSITION] * nf,
+                   {"seed": seed, "fingers": nf, "finger_len": lf})
+
+
+def planar2(l1: float = 0.6, l2: float = 0.4, kind: int = EE_POSE, lim=math.pi) -> Tree:
+    """Planar 2-link arm: two z joints, link lengths along x; EE at the tip."""
+    return _finish("planar2", [-1, 0], np.tile([1.0, 0, 0, 0], (2, 1)),
+                   [[0, 0, 0], [l1, 0, 0]], [_AX["z"], _AX["z"]], [lim, lim], [1],
+                   [[l2, 0, 0]], [[1.0, 0, 0, 0]], [kind])
+
+
+def one_joint(offset=(0.1, 0.2, 0.3), ee_offset=(0.5, 0.0, 0.0), axis="z",
+              lim=math.pi, kind: int = EE_POSE) -> Tree:
+    return _finish("one_joint", [-1], [[1.0, 0, 0, 0]], [offset], [_AX[axis]], [lim],
+                   [0], [ee_offset], [[1.0, 0, 0, 0]], [kind])
+
+
+def uniform_configs(tree: Tree, count: int, seed: int) -> np.ndarray:
+    """count x n joint vectors, q_j ~ U[lower_j, upper_j] (row-major draws)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.random(size=(count, tree.n))
+    return f32(tree.lower + u * (tree.upper - tree.lower))
+
+
+def _weights(w_pos=1.0, w_rot=0.5, w_limit=10.0, w_rest=0.0):
+    return {"w_pos": w_pos, "w_rot": w_rot, "w_limit": w_limit, "w_rest": w_rest}
+
+
+def _options(max_iters, early_exit=False):
+    return {"max_iters": max_iters, "lambda0": 1e-3, "nu_up": 10.0, "nu_down": 10.0,
+            "lambda_min": 1e-10, "lambda_max": 1e10, "early_exit": bool(early_exit),
+            "tol_pos": 1e-3, "tol_rot": 1e-2, "damping_floor": 1e-6, "pivot_rel": 1e-6}
+
+
+def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
+    """Seeded workload description.
+
+    ``name`` is one of:
+      * ``arm16``   — 16 targets on arm7, 1 seed each, pose+limit, 50 iterations;
+      * ``arm131k`` — 16384 targets x 8 seeds on arm7, pose+limit+rest(0.01),
+                      30 iterations, best-of-8;
+      * ``tree4k``  — 4096 problems on tree34 (4 pose EEs), pose+limit, 40 its;
+      * ``mixed84k``— 60000 arm7 + 20000 hand16 + 4096 tree34 problems, early
+                      exit, rest 0.01, up to 50 iterations;
+      * ``seeder``  — 2M training configurations + 131072 evaluation targets.
+    ``targets`` overrides the target count (a prefix of the same draws).
+    Returns q* (configurations whose FK are the targets) and seeds; the caller
+    computes the target poses with its own FK.
+    """
+    if name == "arm16":
+        r = arm7(0)
+        T = targets or 16
+        return {"groups": [{"tree": r, "q_star": uniform_configs(r, T, 1), "K": 1,
+                            "seeds": uniform_configs(r, T, 2)}],
+                "weights": _weights(), "options": _options(50)}
+    if name == "arm131k":
+        r = arm7(0)
+        T = targets or int(16384 * scale)
+        K = 8
+        return {"groups": [{"tree": r, "q_star": uniform_configs(r, T, 3), "K": K,
+                            "seeds": uniform_configs(r, T * K, 4)}],
+                "weights": _weights(w_rest=0.01), "options": _options(30)}
+    if name == "tree4k":
+        r = tree34(5)
+        T = targets or int(4096 * scale)
+        return {"groups": [{"tree": r, "q_star": uniform_configs(r, T, 6), "K": 1,
+                            "seeds": uniform_configs(r, T, 7)}],
+                "weights": _weights(), "options": _options(40)}
+    if name == "mixed84k":
+        counts = [60000, 20000, 4096]
+        if targets is not None:
+            counts = [targets] * 3
+        else:
+            counts = [max(1, int(c * scale)) for c in counts]
+        robots = [arm7(0), hand16(8), tree34(5)]
+        gs = []
+        for r, c, sq, ss in zip(robots, counts, (9, 10, 11), (12, 13, 14)):
+            gs.append({"tree": r, "q_star": uniform_configs(r, c, sq), "K": 1,
+                       "seeds": uniform_configs(r, c, ss)})
+        return {"groups": gs, "weights": _weights(w_rest=0.01),
+                "options": _options(50, early_exit=True)}
+    if name == "seeder":
+        r = arm7(0)
+        S = int(2_000_000 * scale)
+        T = targets or int(131072 * scale)
+        K = 8
+        return {"tree": r, "train_q": uniform_configs(r, S, 15),
+                "eval_q_star": uniform_configs(r, T, 16), "K": K,
+                "plain_seeds": uniform_configs(r, T * K, 17),
+                "weights": _weights(w_rest=0.01), "options": _options(30),
+                "mlp": {"hidden": 512, "depth": 3, "batch": 8192, "lr": 1e-3,
+                        "epochs": 20, "init_seed": 18, "shuffle_seed": 19}}
+    raise KeyError(name)
+
+
+def mlp_init(sizes: list[int], seed: int) -> list[tuple[np.ndarray, np.ndarray]]:
+    """Layer i: W [sizes[i+1], sizes[i]] then b [sizes[i+1]], both U(+-1/sqrt(fan_in)).
+
+    Draw order: W0, b0, W1, b1, ... from one PCG64 stream; FP32-rounded.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        a = 1.0 / math.sqrt(fi)
+        W = f32(rng.uniform(-a, a, size=(fo, fi)))
+        b = f32(rng.uniform(-a, a, size=fo))
+        out.append((W, b))
+    return out
+
+
+def epoch_permutation(count: int, seed: int, epoch: int) -> np.ndarray:
+    """Sample order for one training epoch (int32)."""
+    rng = np.random.Generator(np.random.PCG64([seed, epoch]))
+    return rng.permutation(count).astype(np.int32)

@@ -1,0 +1,190 @@
+"""Pins for the oracle's forward kinematics, residuals and Jacobian.
+
+FK (Sec. III-B, T_base<-i = FK(q)_i) is checked against closed forms
+(zero configuration, one joint, planar 2-link) and against an independent
+product of 4x4 homogeneous matrices built with scipy's Rotation.  The
+residuals (Sec. III-C) are checked against their definitions evaluated with
+scipy's matrix logarithm, and the analytic Jacobian against central finite
+differences of the residual.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import logm
+from scipy.spatial.transform import Rotation
+
+import synth
+
+rng = np.random.default_rng(99)
+TREES = [synth.arm7(0), synth.tree34(5), synth.hand16(8)]
+
+
+def homog(R, t):
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = t
+    return T
+
+
+def fk_homogeneous(tree, q):
+    """Independent FK: T_j = T_parent * Trans(t_j) * Rot(mount_j) * Rot(axis_j, q_j)."""
+    Ts = []
+    for j in range(tree.n):
+        par = tree.parent[j]
+        Tp = np.eye(4) if par < 0 else Ts[par]
+        mq = tree.mount_quat[j]
+        Rm = Rotation.from_quat([mq[1], mq[2], mq[3], mq[0]]).as_matrix()
+        Rq = Rotation.from_rotvec(tree.axis[j] / np.linalg.norm(tree.axis[j]) * q[j]).as_matrix()
+        Ts.append(Tp @ homog(np.eye(3), tree.offset[j]) @ homog(Rm, np.zeros(3)) @ homog(Rq, np.zeros(3)))
+    ees = []
+    for k in range(tree.m):
+        eq = tree.ee_quat[k]
+        Re = Rotation.from_quat([eq[1], eq[2], eq[3], eq[0]]).as_matrix()
+        ees.append(Ts[tree.ee_joint[k]] @ homog(Re, tree.ee_offset[k]))
+    return Ts, ees
+
+
+@pytest.mark.parametrize("tree", TREES, ids=lambda t: t.name)
+def test_fk_matches_homogeneous_product(ora, tree):
+    for q in synth.uniform_configs(tree, 20, 5):
+        R, p, Re, pe = ora.fk(tree, q)
+        Ts, ees = fk_homogeneous(tree, q)
+        for j in range(tree.n):
+            np.testing.assert_allclose(R[j], Ts[j][:3, :3], atol=1e-13)
+            np.testing.assert_allclose(p[j], Ts[j][:3, 3], atol=1e-13)
+        for k in range(tree.m):
+            np.testing.assert_allclose(Re[k], ees[k][:3, :3], atol=1e-13)
+            np.testing.assert_allclose(pe[k], ees[k][:3, 3], atol=1e-13)
+
+
+def test_fk_arm_zero_configuration(ora):
+    tree = synth.arm7(0)
+    _, _, Re, pe = ora.fk(tree, np.zeros(7))
+    np.testing.assert_allclose(Re[0], np.eye(3), atol=0)
+    np.testing.assert_allclose(pe[0], tree.offset.sum(0) + tree.ee_offset[0], atol=1e-15)
+
+
+def test_fk_tree_zero_configuration(ora):
+    tree = synth.tree34(5)
+    _, _, Re, pe = ora.fk(tree, np.zeros(34))
+    torso = tree.offset[:6].sum(0)
+    for c in range(4):
+        b = 6 + 7 * c
+        h = c * math.pi / 2
+        Rz = np.array([[math.cos(h), -math.sin(h), 0], [math.sin(h), math.cos(h), 0], [0, 0, 1]])
+        want = torso + tree.offset[b] + Rz @ (tree.offset[b + 1:b + 7].sum(0) + tree.ee_offset[c])
+        np.testing.assert_allclose(pe[c], want, atol=1e-7)   # mount quat is FP32-rounded
+        np.testing.assert_allclose(Re[c], Rz, atol=1e-7)
+
+
+def test_fk_one_joint_closed_form(ora):
+    t, e = np.array([0.1, 0.2, 0.3]), np.array([0.5, 0.0, 0.0])
+    tree = synth.one_joint(t, e)
+    for q in [-2.0, 0.0, 0.7, 3.0]:
+        _, _, Re, pe = ora.fk(tree, np.array([q]))
+        Rz = np.array([[math.cos(q), -math.sin(q), 0], [math.sin(q), math.cos(q), 0], [0, 0, 1]])
+        np.testing.assert_allclose(pe[0], t + Rz @ e, atol=1e-15)
+        np.testing.assert_allclose(Re[0], Rz, atol=1e-15)
+
+
+def test_fk_planar_two_link_closed_form(ora):
+    l1, l2 = 0.6, 0.4
+    tree = synth.planar2(l1, l2)
+    for q1, q2 in rng.uniform(-3, 3, size=(10, 2)):
+        _, _, Re, pe = ora.fk(tree, np.array([q1, q2]))
+        np.testing.assert_allclose(
+            pe[0], [l1 * math.cos(q1) + l2 * math.cos(q1 + q2),
+                    l1 * math.sin(q1) + l2 * math.sin(q1 + q2), 0.0], atol=1e-15)
+        np.testing.assert_allclose(ora.so3_log(Re[0]), [0, 0, (q1 + q2 + math.pi) % (2 * math.pi) - math.pi],
+                                   atol=1e-12)
+
+
+@pytest.mark.parametrize("tree", TREES, ids=lambda t: t.name)
+def test_fk_pose7_quaternion_consistent(ora, tree):
+    for q in synth.uniform_configs(tree, 10, 6):
+        pose = ora.fk_pose7(tree, q)
+        _, _, Re, pe = ora.fk(tree, q)
+        for k in range(tree.m):
+            assert pose[k, 3] >= 0
+            np.testing.assert_allclose(np.linalg.norm(pose[k, 3:]), 1.0, atol=1e-14)
+            np.testing.assert_allclose(ora.quat_to_R(pose[k, 3:]), Re[k], atol=1e-14)
+            np.testing.assert_allclose(pose[k, :3], pe[k], atol=0)
+
+
+WEIGHTS = {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 10.0, "w_rest": 0.01, "q_rest": None}
+
+
+@pytest.mark.parametrize("tree", TREES, ids=lambda t: t.name)
+def test_pose_residual_is_se3_log_of_relative_transform(ora, tree):
+    qs = synth.uniform_configs(tree, 6, 7)
+    tg = ora.targets_from(tree, synth.uniform_configs(tree, 6, 8))
+    for q, t in zip(qs, tg):
+        r, pe, re = ora.residual(tree, t, WEIGHTS, q)
+        _, ees = fk_homogeneous(tree, q)
+        row = 0
+        for k in range(tree.m):
+            Tt = homog(ora.quat_to_R(t[k, 3:]), t[k, :3])
+            if tree.ee_kind[k] == synth.EE_POSE:
+                L = np.real(logm(np.linalg.inv(Tt) @ ees[k]))
+                xi = np.array([L[0, 3], L[1, 3], L[2, 3], L[2, 1], L[0, 2], L[1, 0]])
+                np.testing.assert_allclose(r[row:row + 3], WEIGHTS["w_pos"] * xi[:3], atol=1e-9)
+                np.testing.assert_allclose(r[row + 3:row + 6], WEIGHTS["w_rot"] * xi[3:], atol=1e-9)
+                np.testing.assert_allclose(re[k], np.linalg.norm(xi[3:]), atol=1e-9)
+                row += 6
+            else:
+                np.testing.assert_allclose(r[row:row + 3], ees[k][:3, 3] - t[k, :3], atol=1e-14)
+                row += 3
+            np.testing.assert_allclose(pe[k], np.linalg.norm(ees[k][:3, 3] - t[k, :3]), atol=1e-14)
+        lim = r[row:row + tree.n]
+        want = WEIGHTS["w_limit"] * (np.maximum(0, q - tree.upper) + np.maximum(0, tree.lower - q))
+        np.testing.assert_allclose(lim, want, atol=0)
+        rest = r[row + tree.n:]
+        np.testing.assert_allclose(rest, WEIGHTS["w_rest"] * (q - 0.5 * (tree.lower + tree.upper)),
+                                   atol=1e-18)
+
+
+def test_limit_residual_values(ora):
+    tree = synth.one_joint(lim=1.0)
+    tg = ora.targets_from(tree, np.zeros((1, 1)))[0]
+    w = dict(WEIGHTS, w_rest=0.0)
+    for q, want in [(1.5, 0.5), (-1.25, 0.25), (0.3, 0.0), (1.0, 0.0)]:
+        r, _, _ = ora.residual(tree, tg, w, np.array([q]))
+        assert r[6] == pytest.approx(10.0 * want, abs=1e-15)
+
+
+def _fd_jac(ora, tree, t, w, q, h=1e-6):
+    J = np.zeros((ora.n_rows(tree), tree.n))
+    for j in range(tree.n):
+        e = np.zeros(tree.n)
+        e[j] = h
+        J[:, j] = (ora.residual(tree, t, w, q + e)[0] - ora.residual(tree, t, w, q - e)[0]) / (2 * h)
+    return J
+
+
+@pytest.mark.parametrize("tree", TREES + [synth.planar2(), synth.one_joint(kind=synth.EE_POSITION)],
+                         ids=lambda t: t.name + str(t.ee_kind[0]))
+def test_analytic_jacobian_matches_finite_differences(ora, tree):
+    qs = synth.uniform_configs(tree, 8, 11)
+    # Push a few joints outside their limits (away from the kink).
+    qs[::2, 0] = tree.upper[0] + 0.3
+    tg = ora.targets_from(tree, synth.uniform_configs(tree, 8, 12))
+    for q, t in zip(qs, tg):
+        J = ora.jacobian(tree, t, WEIGHTS, q)
+        Jf = _fd_jac(ora, tree, t, WEIGHTS, q)
+        rel = np.linalg.norm(J - Jf) / max(np.linalg.norm(Jf), 1e-6)
+        assert rel < 1e-7, rel
+
+
+def test_jacobian_zero_for_non_ancestors(ora):
+    tree = synth.hand16(8)
+    q = synth.uniform_configs(tree, 1, 3)[0]
+    tg = ora.targets_from(tree, synth.uniform_configs(tree, 1, 4))[0]
+    J = ora.jacobian(tree, tg, WEIGHTS, q)
+    for k in range(4):
+        blk = J[3 * k:3 * k + 3]
+        for j in range(16):
+            if j // 4 != k:
+                assert np.all(blk[:, j] == 0)
+            else:
+                assert np.any(blk[:, j] != 0)
