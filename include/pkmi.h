@@ -1,0 +1,195 @@
+/*
+ * pkmi.h -- C ABI of the MI355X (gfx950) batched Levenberg-Marquardt
+ * inverse-kinematics library (PyRoki, arXiv 2505.03728).
+ *
+ * The problem solved per (target, seed) pair is the paper's IK formulation
+ * (Sec. IV-A: a robot, a joint pose cost, joint limit and joint
+ * regularisation costs) minimised with Levenberg-Marquardt (Sec. III-A) over
+ * the weighted residuals of Sec. III-C.
+ *
+ * Conventions for every entry point:
+ *  - Return value: PK_OK (0) or a negative PK_E* code; pk_last_error() gives
+ *    a message.  No C++ exception crosses this boundary.
+ *  - "device" pointers are HIP device memory owned by the caller (e.g. the
+ *    data of a torch tensor) and must stay valid until the work enqueued on
+ *    `stream` has finished.  "host" pointers are read before the call
+ *    returns.
+ *  - Batched arrays are structure-of-arrays: a [planes][N] array stores
+ *    plane i of problem p at index i*N + p.  Every float is FP32.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the default
+ *    stream) unless stated otherwise.  A context is not thread-safe.
+ *  - The library allocates device memory only in pk_create, pk_robot_upload,
+ *    pk_seeder_create and when a solve needs a larger workspace than any
+ *    earlier call (the workspace grows, never shrinks).
+ */
+#ifndef PKMI_H
+#define PKMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pk_ctx pk_ctx;
+
+/* Return codes. */
+#define PK_OK 0
+#define PK_EINVAL (-1)        /* null pointer, bad size, malformed tree      */
+#define PK_EUNSUPPORTED (-2)  /* size above a library limit, variant absent  */
+#define PK_ENOMEM (-3)        /* device allocation failed                    */
+#define PK_EHIP (-4)          /* a HIP runtime call or launch failed          */
+#define PK_ENOTFOUND (-5)     /* unknown robot or seeder id                  */
+
+/* Per-problem status (low byte) and flag bits. */
+#define PK_CONVERGED 0        /* every EE within tol_pos / tol_rot           */
+#define PK_MAX_ITERS 1        /* iteration budget spent, not within tolerance */
+#define PK_STALLED 2          /* a step was rejected with lambda at lambda_max */
+#define PK_NONFINITE 3        /* NaN/Inf in the seed or target: left untouched */
+#define PK_FLAG_FP64 0x100    /* some Cholesky pivot fell below pivot_rel times
+                                 the largest diagonal and the step was re-solved
+                                 in FP64                                      */
+
+#define PK_EE_POSE 0          /* full SE(3) target: 7 values p, quat (wxyz)  */
+#define PK_EE_POSITION 1      /* position-only target: 3 values              */
+
+#define PK_MAX_JOINTS 64
+#define PK_MAX_EES 8
+
+/* Kernel variants for pk_lm_options.variant. */
+#define PK_VARIANT_AUTO 0     /* pick by robot shape and the autotune table  */
+#define PK_VARIANT_LANE 1     /* one problem per lane; star-of-chains robots  */
+#define PK_VARIANT_WAVE 2     /* one problem per 64-lane wavefront; any tree  */
+
+/* Robot description (host memory, FP64; rounded to FP32 on upload).
+ * Revolute joints in topological order (parent[j] < j, -1 = the base).
+ * Forward kinematics (Sec. III-B, T_base<-i = FK(q)_i):
+ *   p_j = p_parent + R_parent * offset_j,
+ *   R_j = R_parent * Rot(mount_quat_j) * Rot(axis_j, q_j),
+ * EE k is fixed to joint ee_joint[k] by (ee_offset[k], ee_quat[k]). */
+typedef struct {
+    int32_t n_joints;            /* 1..PK_MAX_JOINTS                          */
+    const int32_t *parent;       /* [n]                                       */
+    const double *mount_quat;    /* [n][4] wxyz, normalised on upload          */
+    const double *offset;        /* [n][3] metres, in the parent frame         */
+    const double *axis;          /* [n][3] unit joint axis after the mount     */
+    const double *lower;         /* [n] radians                                */
+    const double *upper;         /* [n] radians, >= lower                      */
+    int32_t n_ee;                /* 1..PK_MAX_EES                              */
+    const int32_t *ee_joint;     /* [m]                                       */
+    const double *ee_offset;     /* [m][3]                                    */
+    const double *ee_quat;       /* [m][4] wxyz                               */
+    const int32_t *ee_kind;      /* [m] PK_EE_POSE or PK_EE_POSITION           */
+} pk_tree;
+
+/* Residual weights (Sec. III-C: the costs are weighted residuals and LM
+ * minimises the sum of their squares):
+ *   pose EE:     [w_pos * rho ; w_rot * phi],  [rho; phi] = log(T_target^-1 T_ee)
+ *   position EE: w_pos * (p_ee - p_target)
+ *   limit:       w_limit * (max(0, q - upper) + max(0, lower - q))
+ *   rest:        w_rest * (q - q_rest)
+ * q_rest: device [n] or NULL for (lower + upper) / 2. */
+typedef struct {
+    float w_pos, w_rot, w_limit, w_rest;
+    const float *q_rest;
+} pk_cost_weights;
+
+/* Levenberg-Marquardt controls.  A trial step solves
+ * (J^T J + lambda * diag(max(J^T J_jj, damping_floor))) delta = -J^T r;
+ * it is accepted iff the cost strictly decreases, then
+ * lambda = max(lambda / nu_down, lambda_min), else
+ * lambda = min(lambda * nu_up, lambda_max) (a rejection with lambda already
+ * at lambda_max ends the problem as PK_STALLED).  Every trial counts as one
+ * iteration.  With early_exit, a problem stops as soon as every EE is within
+ * tol_pos (metres) and, for pose EEs, tol_rot (radians); the test is
+ * inclusive and runs at the seed and after every accepted step. */
+typedef struct {
+    int32_t max_iters;
+    float lambda0, nu_up, nu_down, lambda_min, lambda_max;
+    int32_t early_exit;
+    float tol_pos, tol_rot;
+    float damping_floor;         /* e.g. 1e-6                                 */
+    float pivot_rel;             /* FP64 re-solve below this pivot ratio (1e-6) */
+    int32_t variant;             /* PK_VARIANT_*                              */
+} pk_lm_options;
+
+/* A batch: T targets, K seeds each, N = T*K problems; problem p uses target
+ * p / K.
+ * targets (device): per EE k in order, 7 planes (px,py,pz,qw,qx,qy,qz) for a
+ *   pose EE or 3 planes (px,py,pz) for a position EE, each plane T floats:
+ *   total (sum of widths) * T floats.  Quaternions are normalised on use.
+ * seeds (device): [n][N] joint values. */
+typedef struct {
+    int64_t n_targets;
+    int32_t K;
+    const float *targets;
+    const float *seeds;
+} pk_ik_problem;
+
+/* Outputs (device).  Only `joints` is required; any other pointer may be
+ * NULL.  Errors are measured at the returned joints: pos_err = |p_ee - p_t|,
+ * rot_err = rotation angle of R_t^T R_ee (0 for position EEs).
+ * best_*: per target, the seed chosen among its K problems: if any meets the
+ * tolerance, the lowest total cost among those, else the lowest pose-only
+ * residual sum of squares; ties go to the lower seed index.
+ * trace_*: state after each of the first trace_iters iterations (debug). */
+typedef struct {
+    float *joints;               /* [n][N]                                    */
+    float *pos_err;              /* [m][N]                                    */
+    float *rot_err;              /* [m][N]                                    */
+    float *cost;                 /* [N] final sum of squared residuals        */
+    int32_t *iters;              /* [N] trials performed                      */
+    int32_t *accepts;            /* [N] accepted trials                       */
+    int32_t *status;             /* [N] PK_CONVERGED.. | PK_FLAG_FP64          */
+    int32_t *iters_to_tol;       /* [N] first iteration within tolerance, -1   */
+    int32_t *best_index;         /* [T] seed index k of the chosen problem     */
+    float *best_joints;          /* [n][T]                                    */
+    int32_t *target_success;     /* [T] 1 if some seed met the tolerance        */
+    int32_t trace_iters;         /* 0..64                                      */
+    float *trace_q;              /* [trace_iters][n][N]                        */
+    int32_t *trace_accept;       /* [trace_iters][N]                           */
+} pk_ik_outputs;
+
+/* Context on one device (ordinal as seen by HIP).  Allocates the context's
+ * device-side tables. */
+int pk_create(pk_ctx **out, int device_ordinal);
+int pk_destroy(pk_ctx *ctx);
+/* Message of the last failed call on ctx (never NULL; ctx may be NULL). */
+const char *pk_last_error(pk_ctx *ctx);
+
+/* Copies the tree to the device (FP32) and returns its id.  Validates shape,
+ * parent order, unit axes (within 1e-3; renormalised), limits and EE
+ * references.  Synchronous. */
+int pk_robot_upload(pk_ctx *ctx, const pk_tree *tree, int32_t *robot_id);
+/* n joints, m EEs, target floats per target (sum of EE widths), residual rows
+ * (6 per pose EE, 3 per position EE, then n limit and n rest rows), and the
+ * star shape used by the per-lane kernel (chains = 0 if not a star). */
+int pk_robot_info(pk_ctx *ctx, int32_t robot_id, int32_t *n, int32_t *m,
+                  int32_t *target_floats, int32_t *rows, int32_t *chains,
+                  int32_t *chain_len);
+
+/* Forward kinematics (Sec. III-B) for N configurations q [n][N] (device).
+ * ee_pose [m][7][N]: position and unit quaternion (wxyz, w >= 0).
+ * joint_frames (optional) [n][12][N]: R_j row-major (9) then p_j (3). */
+int pk_fk(pk_ctx *ctx, int32_t robot_id, int64_t N, const float *q, float *ee_pose,
+          float *joint_frames, void *stream);
+
+/* Residual vector and analytic Jacobian at q (debug / parity entry point).
+ * r [rows][N], J [rows][n][N] (row order as in pk_robot_info), problem p
+ * uses target p / K from the targets layout of pk_ik_problem. */
+int pk_residual_jacobian(pk_ctx *ctx, int32_t robot_id, int64_t N, int32_t K,
+                         const float *targets, const float *q,
+                         const pk_cost_weights *w, float *r, float *J, void *stream);
+
+/* Batched LM IK (the hot path): FK, residuals, analytic Jacobian, damped
+ * normal equations, per-problem Cholesky (FP64 re-solve on a small pivot),
+ * accept/reject and the lambda update, then best-of-K when requested. */
+int pk_ik_solve(pk_ctx *ctx, int32_t robot_id, const pk_ik_problem *problem,
+                const pk_cost_weights *w, const pk_lm_options *opt,
+                const pk_ik_outputs *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PKMI_H */

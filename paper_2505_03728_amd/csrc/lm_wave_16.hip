@@ -1,0 +1,11 @@
+// Instantiation of the wave-per-problem LM kernel for n <= 16, m <= 4.
+#include "lm_wave.hpp"
+
+namespace pk {
+
+hipError_t launch_lm_wave_16(const RobotC *rb, const SolveParams &P, hipStream_t s)
+{
+    return wave::launch_wave<16, 4>(rb, P, s);
+}
+
+}  // namespace pk

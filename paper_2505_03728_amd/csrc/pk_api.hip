@@ -1,0 +1,425 @@
+// C ABI of the batched-LM IK library: contexts, robot upload, validation,
+// workspace and kernel dispatch.  See include/pkmi.h for the contract.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "pk_internal.hpp"
+
+using namespace pk;
+
+struct RobotEntry {
+    RobotC host;
+    RobotC *dev = nullptr;
+};
+
+struct pk_ctx {
+    int device = 0;
+    std::string err;
+    std::vector<RobotEntry> robots;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+static std::string g_err_noctx;
+
+static int fail(pk_ctx *ctx, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_err_noctx = buf;
+    return code;
+}
+
+#define PK_HIP(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ctx, PK_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
+    } while (0)
+
+// ------------------------------------------------------------ host geometry (FP64)
+
+namespace {
+
+struct M3 {
+    double a[9];
+};
+
+M3 eye()
+{
+    M3 m{};
+    m.a[0] = m.a[4] = m.a[8] = 1.0;
+    return m;
+}
+
+M3 mul(const M3 &A, const M3 &B)
+{
+    M3 C{};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) C.a[3 * i + j] += A.a[3 * i + k] * B.a[3 * k + j];
+    return C;
+}
+
+M3 tr(const M3 &A)
+{
+    M3 T{};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T.a[3 * i + j] = A.a[3 * j + i];
+    return T;
+}
+
+M3 quat(const double *q)
+{
+    double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+    M3 R{};
+    R.a[0] = 1 - 2 * (y * y + z * z); R.a[1] = 2 * (x * y - w * z); R.a[2] = 2 * (x * z + w * y);
+    R.a[3] = 2 * (x * y + w * z); R.a[4] = 1 - 2 * (x * x + z * z); R.a[5] = 2 * (y * z - w * x);
+    R.a[6] = 2 * (x * z - w * y); R.a[7] = 2 * (y * z + w * x); R.a[8] = 1 - 2 * (x * x + y * y);
+    return R;
+}
+
+// A rotation taking e_z to the unit vector a (Rodrigues about e_z x a).
+M3 z_to(const double *a)
+{
+    if (a[2] > 1.0 - 1e-15) return eye();
+    if (a[2] < -1.0 + 1e-15) {
+        M3 R{};
+        R.a[0] = 1; R.a[4] = -1; R.a[8] = -1;
+        return R;
+    }
+    double k[3] = {-a[1], a[0], 0.0};          // e_z x a
+    double s = sqrt(k[0] * k[0] + k[1] * k[1]);
+    double c = a[2];
+    k[0] /= s; k[1] /= s;
+    double K[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+    M3 K2{}, R = eye();
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            for (int l = 0; l < 3; ++l) K2.a[3 * i + j] += K[3 * i + l] * K[3 * l + j];
+    for (int i = 0; i < 9; ++i) R.a[i] += s * K[i] + (1 - c) * K2.a[i];
+    return R;
+}
+
+void mv(const M3 &A, const double *x, double *y)
+{
+    for (int i = 0; i < 3; ++i) y[i] = A.a[3 * i] * x[0] + A.a[3 * i + 1] * x[1] + A.a[3 * i + 2] * x[2];
+}
+
+float snap(double v) { return fabs(v) < 1e-12 ? 0.f : (float)v; }
+
+bool finite_all(const double *v, int n)
+{
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- API
+
+extern "C" {
+
+int pk_create(pk_ctx **out, int device_ordinal)
+{
+    if (!out) return fail(nullptr, PK_EINVAL, "pk_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0)
+        return fail(nullptr, PK_EHIP, "pk_create: no HIP device");
+    if (device_ordinal < 0 || device_ordinal >= count)
+        return fail(nullptr, PK_EINVAL, "pk_create: device %d out of range [0,%d)", device_ordinal, count);
+    if (hipSetDevice(device_ordinal) != hipSuccess)
+        return fail(nullptr, PK_EHIP, "pk_create: hipSetDevice(%d) failed", device_ordinal);
+    pk_ctx *c = new pk_ctx;
+    c->device = device_ordinal;
+    *out = c;
+    return PK_OK;
+}
+
+int pk_destroy(pk_ctx *ctx)
+{
+    if (!ctx) return PK_OK;
+    (void)hipSetDevice(ctx->device);
+    for (auto &r : ctx->robots)
+        if (r.dev) (void)hipFree(r.dev);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    delete ctx;
+    return PK_OK;
+}
+
+const char *pk_last_error(pk_ctx *ctx)
+{
+    return ctx ? ctx->err.c_str() : g_err_noctx.c_str();
+}
+
+int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_robot_upload: ctx is NULL");
+    if (!t || !robot_id) return fail(ctx, PK_EINVAL, "pk_robot_upload: NULL argument");
+    const int n = t->n_joints, m = t->n_ee;
+    if (n < 1 || m < 1) return fail(ctx, PK_EINVAL, "pk_robot_upload: need >= 1 joint and EE");
+    if (n > PK_MAX_JOINTS || m > PK_MAX_EES)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_robot_upload: %d joints / %d EEs above %d / %d", n, m,
+                    PK_MAX_JOINTS, PK_MAX_EES);
+    if (!t->parent || !t->mount_quat || !t->offset || !t->axis || !t->lower || !t->upper ||
+        !t->ee_joint || !t->ee_offset || !t->ee_quat || !t->ee_kind)
+        return fail(ctx, PK_EINVAL, "pk_robot_upload: NULL array in tree");
+    if (!finite_all(t->mount_quat, 4 * n) || !finite_all(t->offset, 3 * n) ||
+        !finite_all(t->axis, 3 * n) || !finite_all(t->lower, n) || !finite_all(t->upper, n) ||
+        !finite_all(t->ee_offset, 3 * m) || !finite_all(t->ee_quat, 4 * m))
+        return fail(ctx, PK_EINVAL, "pk_robot_upload: non-finite tree value");
+
+    RobotC R;
+    memset(&R, 0, sizeof R);
+    R.n = n;
+    R.m = m;
+    std::vector<M3> U(n);
+    for (int j = 0; j < n; ++j) {
+        const int par = t->parent[j];
+        if (par < -1 || par >= j)
+            return fail(ctx, PK_EINVAL, "pk_robot_upload: parent[%d] = %d not in [-1, %d)", j, par, j);
+        const double *a = t->axis + 3 * j;
+        double an = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        if (fabs(an - 1.0) > 1e-3) return fail(ctx, PK_EINVAL, "pk_robot_upload: axis %d not unit (|a|=%g)", j, an);
+        double qn = sqrt(t->mount_quat[4 * j] * t->mount_quat[4 * j] + t->mount_quat[4 * j + 1] * t->mount_quat[4 * j + 1] +
+                         t->mount_quat[4 * j + 2] * t->mount_quat[4 * j + 2] + t->mount_quat[4 * j + 3] * t->mount_quat[4 * j + 3]);
+        if (qn < 1e-6) return fail(ctx, PK_EINVAL, "pk_robot_upload: mount quaternion %d is zero", j);
+        if (!(t->lower[j] <= t->upper[j]))
+            return fail(ctx, PK_EINVAL, "pk_robot_upload: lower[%d] > upper[%d]", j, j);
+        double au[3] = {a[0] / an, a[1] / an, a[2] / an};
+        U[j] = z_to(au);
+        M3 Upt = par < 0 ? eye() : tr(U[par]);
+        M3 G = mul(mul(Upt, quat(t->mount_quat + 4 * j)), U[j]);
+        double tt[3];
+        mv(Upt, t->offset + 3 * j, tt);
+        JointC &J = R.j[j];
+        M3 Ut = tr(U[j]);
+        for (int i = 0; i < 9; ++i) {
+            J.G[i] = snap(G.a[i]);
+            J.Ut[i] = snap(Ut.a[i]);
+        }
+        for (int i = 0; i < 3; ++i) J.t[i] = snap(tt[i]);
+        J.lo = (float)t->lower[j];
+        J.hi = (float)t->upper[j];
+        J.mid = (float)(0.5 * (t->lower[j] + t->upper[j]));
+        R.mid[j] = J.mid;
+        J.parent = par;
+        J.depth = par < 0 ? 0 : R.j[par].depth + 1;
+        if (J.depth > R.max_depth) R.max_depth = J.depth;
+    }
+    int tgt = 0, rows = 0;
+    for (int k = 0; k < m; ++k) {
+        const int e = t->ee_joint[k], kind = t->ee_kind[k];
+        if (e < 0 || e >= n) return fail(ctx, PK_EINVAL, "pk_robot_upload: ee_joint[%d] = %d out of range", k, e);
+        if (kind != PK_EE_POSE && kind != PK_EE_POSITION)
+            return fail(ctx, PK_EINVAL, "pk_robot_upload: ee_kind[%d] = %d", k, kind);
+        EEC &E = R.e[k];
+        M3 Uet = tr(U[e]);
+        M3 G = mul(Uet, quat(t->ee_quat + 4 * k));
+        double tt[3];
+        mv(Uet, t->ee_offset + 3 * k, tt);
+        for (int i = 0; i < 9; ++i) E.G[i] = snap(G.a[i]);
+        for (int i = 0; i < 3; ++i) E.t[i] = snap(tt[i]);
+        E.joint = e;
+        E.kind = kind;
+        E.tgt_off = tgt;
+        E.row_off = rows;
+        tgt += kind == PK_EE_POSE ? 7 : 3;
+        rows += kind == PK_EE_POSE ? 6 : 3;
+        uint64_t mask = 0;
+        for (int a = e; a >= 0; a = t->parent[a]) mask |= 1ull << a;
+        R.anc[k] = mask;
+    }
+    R.tgt_floats = tgt;
+    R.pose_rows = rows;
+
+    // Star-of-chains shape: C chains of L joints from the base, contiguous
+    // indices, EE c at the tip of chain c, one EE kind.
+    {
+        int roots = 0;
+        for (int j = 0; j < n; ++j) roots += t->parent[j] < 0;
+        bool star = roots >= 1 && n % roots == 0 && m == roots;
+        const int L = star ? n / roots : 0;
+        for (int j = 0; star && j < n; ++j)
+            star = (j % L == 0) ? t->parent[j] == -1 : t->parent[j] == j - 1;
+        for (int k = 0; star && k < m; ++k)
+            star = t->ee_joint[k] == k * L + L - 1 && t->ee_kind[k] == t->ee_kind[0];
+        R.chains = star ? roots : 0;
+        R.chain_len = star ? L : 0;
+    }
+
+    RobotEntry ent;
+    ent.host = R;
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    if (hipMalloc(&ent.dev, sizeof(RobotC)) != hipSuccess)
+        return fail(ctx, PK_ENOMEM, "pk_robot_upload: hipMalloc failed");
+    PK_HIP(ctx, hipMemcpy(ent.dev, &R, sizeof(RobotC), hipMemcpyHostToDevice));
+    ctx->robots.push_back(ent);
+    *robot_id = (int32_t)ctx->robots.size() - 1;
+    return PK_OK;
+}
+
+int pk_robot_info(pk_ctx *ctx, int32_t id, int32_t *n, int32_t *m, int32_t *tf, int32_t *rows,
+                  int32_t *chains, int32_t *chain_len)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_robot_info: ctx is NULL");
+    if (id < 0 || id >= (int)ctx->robots.size()) return fail(ctx, PK_ENOTFOUND, "unknown robot %d", id);
+    const RobotC &R = ctx->robots[id].host;
+    if (n) *n = R.n;
+    if (m) *m = R.m;
+    if (tf) *tf = R.tgt_floats;
+    if (rows) *rows = R.pose_rows + 2 * R.n;
+    if (chains) *chains = R.chains;
+    if (chain_len) *chain_len = R.chain_len;
+    return PK_OK;
+}
+
+static RobotEntry *robot_of(pk_ctx *ctx, int32_t id)
+{
+    if (id < 0 || id >= (int)ctx->robots.size()) return nullptr;
+    return &ctx->robots[id];
+}
+
+int pk_fk(pk_ctx *ctx, int32_t id, int64_t N, const float *q, float *ee_pose, float *frames,
+          void *stream)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_fk: ctx is NULL");
+    RobotEntry *r = robot_of(ctx, id);
+    if (!r) return fail(ctx, PK_ENOTFOUND, "pk_fk: unknown robot %d", id);
+    if (N < 0) return fail(ctx, PK_EINVAL, "pk_fk: N < 0");
+    if (N == 0) return PK_OK;
+    if (!q || !ee_pose) return fail(ctx, PK_EINVAL, "pk_fk: NULL q or ee_pose");
+    if (N > (int64_t)INT32_MAX * 32) return fail(ctx, PK_EUNSUPPORTED, "pk_fk: N too large");
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    PK_HIP(ctx, launch_fk(r->dev, N, q, ee_pose, frames, (hipStream_t)stream));
+    return PK_OK;
+}
+
+static void weights_into(const pk_cost_weights *w, SolveParams &P)
+{
+    P.w_pos = w->w_pos;
+    P.w_rot = w->w_rot;
+    P.w_limit = w->w_limit;
+    P.w_rest = w->w_rest;
+    P.q_rest = w->q_rest;
+}
+
+static bool finite_w(const pk_cost_weights *w)
+{
+    return isfinite(w->w_pos) && isfinite(w->w_rot) && isfinite(w->w_limit) && isfinite(w->w_rest);
+}
+
+int pk_residual_jacobian(pk_ctx *ctx, int32_t id, int64_t N, int32_t K, const float *targets,
+                         const float *q, const pk_cost_weights *w, float *r, float *J, void *stream)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_residual_jacobian: ctx is NULL");
+    RobotEntry *rb = robot_of(ctx, id);
+    if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_residual_jacobian: unknown robot %d", id);
+    if (N < 0 || K < 1 || N % K) return fail(ctx, PK_EINVAL, "pk_residual_jacobian: bad N=%lld K=%d", (long long)N, K);
+    if (N == 0) return PK_OK;
+    if (!targets || !q || !w || !r) return fail(ctx, PK_EINVAL, "pk_residual_jacobian: NULL argument");
+    if (!finite_w(w)) return fail(ctx, PK_EINVAL, "pk_residual_jacobian: non-finite weight");
+    SolveParams P;
+    memset(&P, 0, sizeof P);
+    weights_into(w, P);
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    PK_HIP(ctx, launch_residual_jacobian(rb->dev, N, K, targets, q, P, r, J, (hipStream_t)stream));
+    return PK_OK;
+}
+
+static int ensure_ws(pk_ctx *ctx, size_t bytes)
+{
+    if (bytes <= ctx->ws_bytes) return PK_OK;
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    if (hipMalloc(&ctx->ws, bytes) != hipSuccess) return fail(ctx, PK_ENOMEM, "workspace hipMalloc(%zu) failed", bytes);
+    ctx->ws_bytes = bytes;
+    return PK_OK;
+}
+
+int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_weights *w,
+                const pk_lm_options *o, const pk_ik_outputs *out, void *stream)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_ik_solve: ctx is NULL");
+    RobotEntry *rb = robot_of(ctx, id);
+    if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_ik_solve: unknown robot %d", id);
+    if (!pr || !w || !o || !out) return fail(ctx, PK_EINVAL, "pk_ik_solve: NULL argument");
+    if (pr->n_targets < 0 || pr->K < 1) return fail(ctx, PK_EINVAL, "pk_ik_solve: bad T=%lld K=%d", (long long)pr->n_targets, pr->K);
+    const int64_t N = pr->n_targets * pr->K;
+    if (N == 0) return PK_OK;
+    if (N >= (int64_t)1 << 31) return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve: %lld problems, limit 2^31 - 1", (long long)N);
+    if (!pr->targets || !pr->seeds || !out->joints) return fail(ctx, PK_EINVAL, "pk_ik_solve: NULL targets/seeds/joints");
+    if (o->max_iters < 0) return fail(ctx, PK_EINVAL, "pk_ik_solve: max_iters < 0");
+    if (!(o->lambda0 > 0) || !(o->nu_up > 1) || !(o->nu_down > 1) || !(o->lambda_min > 0) ||
+        !(o->lambda_max >= o->lambda_min) || !(o->damping_floor > 0) || !(o->pivot_rel >= 0) ||
+        !(o->tol_pos >= 0) || !(o->tol_rot >= 0))
+        return fail(ctx, PK_EINVAL, "pk_ik_solve: invalid LM option");
+    if (!finite_w(w)) return fail(ctx, PK_EINVAL, "pk_ik_solve: non-finite weight");
+    if (out->trace_iters < 0 || out->trace_iters > 64 ||
+        (out->trace_iters > 0 && (!out->trace_q || !out->trace_accept)))
+        return fail(ctx, PK_EINVAL, "pk_ik_solve: bad trace request");
+
+    const RobotC &H = rb->host;
+    int variant = o->variant;
+    const bool lane_ok = H.chains > 0 && lane_variant_available(H.chains, H.chain_len, H.e[0].kind);
+    const bool wave_ok = wave_variant_available(H.n);
+    if (variant == PK_VARIANT_AUTO) variant = lane_ok ? PK_VARIANT_LANE : PK_VARIANT_WAVE;
+    if (variant == PK_VARIANT_LANE && !lane_ok)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve: no per-lane kernel for this robot shape");
+    if (variant == PK_VARIANT_WAVE && !wave_ok)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve: no wave kernel for n=%d", H.n);
+    if (variant != PK_VARIANT_LANE && variant != PK_VARIANT_WAVE)
+        return fail(ctx, PK_EINVAL, "pk_ik_solve: unknown variant %d", variant);
+
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    const bool want_best = out->best_index || out->best_joints || out->target_success;
+    // Workspace: pose-only cost always; total cost and status when best-of-K
+    // needs them and the caller did not ask for them.
+    size_t need = (size_t)N * 4 * 3;
+    int rc = ensure_ws(ctx, need);
+    if (rc) return rc;
+    float *ws_f = (float *)ctx->ws;
+
+    SolveParams P;
+    memset(&P, 0, sizeof P);
+    weights_into(w, P);
+    P.lambda0 = o->lambda0; P.nu_up = o->nu_up; P.nu_down = o->nu_down;
+    P.lambda_min = o->lambda_min; P.lambda_max = o->lambda_max;
+    P.tol_pos = o->tol_pos; P.tol_rot = o->tol_rot;
+    P.damping_floor = o->damping_floor; P.pivot_rel = o->pivot_rel;
+    P.max_iters = o->max_iters; P.early_exit = o->early_exit ? 1 : 0;
+    P.K = pr->K; P.N = N; P.T = pr->n_targets;
+    P.targets = pr->targets; P.seeds = pr->seeds;
+    P.joints = out->joints; P.pos_err = out->pos_err; P.rot_err = out->rot_err;
+    P.pose_cost = ws_f;
+    P.cost = out->cost ? out->cost : (want_best ? ws_f + N : nullptr);
+    P.status = out->status ? out->status : (want_best ? (int32_t *)(ws_f + 2 * N) : nullptr);
+    P.iters = out->iters; P.accepts = out->accepts; P.iters_to_tol = out->iters_to_tol;
+    P.trace_iters = out->trace_iters; P.trace_q = out->trace_q; P.trace_acc = out->trace_accept;
+
+    hipStream_t s = (hipStream_t)stream;
+    if (variant == PK_VARIANT_LANE)
+        PK_HIP(ctx, launch_lm_lane(rb->dev, H, P, s));
+    else
+        PK_HIP(ctx, launch_lm_wave(rb->dev, H, P, s));
+    if (want_best)
+        PK_HIP(ctx, launch_best_of_k(P, H.n, out->best_index, out->best_joints, out->target_success, s));
+    return PK_OK;
+}
+
+}  // extern "C"

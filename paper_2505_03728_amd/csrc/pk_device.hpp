@@ -1,0 +1,232 @@
+// Device-side FP32 arithmetic shared by the LM kernels: the joint step of
+// forward kinematics, the SE(3) pose residual log(T_target^-1 T_ee) and the
+// right-Jacobian-inverse blocks used by the analytic Jacobian.
+//
+// Lie-group formulas: Barfoot, "State Estimation for Robotics" (2017),
+// Sec. 7.1 (SO(3)/SE(3) left Jacobians and the Q block), with
+// J_r^-1(xi) = J_l^-1(-xi).  Tangent order is xi = [rho; phi].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pk_internal.hpp"
+
+#define PK_DEV __device__ __forceinline__
+
+namespace pk {
+
+// 3x3 matrices are row-major float[9].
+
+// Hardware sin/cos (v_sin_f32 / v_cos_f32 on q / 2pi): joint angles stay
+// within a few turns, where the absolute error is ~1e-7.
+PK_DEV void joint_sincos(float q, float &s, float &c)
+{
+    s = __sinf(q);
+    c = __cosf(q);
+}
+
+// 1/sqrt(d): v_rsq_f32 (about 1 ulp) in FP32, exact in FP64.
+PK_DEV float rsqrt_t(float d) { return __builtin_amdgcn_rsqf(d); }
+PK_DEV double rsqrt_t(double d) { return 1.0 / sqrt(d); }
+
+// p = pp + Op t;  O = Op G Rz(q) with (s, c) = (sin q, cos q).
+PK_DEV void joint_step(const float *Op, const float *pp, const float *G, const float *t,
+                       float s, float c, float *O, float *p)
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        p[r] = pp[r] + Op[3 * r] * t[0] + Op[3 * r + 1] * t[1] + Op[3 * r + 2] * t[2];
+        float m0 = Op[3 * r] * G[0] + Op[3 * r + 1] * G[3] + Op[3 * r + 2] * G[6];
+        float m1 = Op[3 * r] * G[1] + Op[3 * r + 1] * G[4] + Op[3 * r + 2] * G[7];
+        float m2 = Op[3 * r] * G[2] + Op[3 * r + 1] * G[5] + Op[3 * r + 2] * G[8];
+        O[3 * r] = m0 * c + m1 * s;
+        O[3 * r + 1] = m1 * c - m0 * s;
+        O[3 * r + 2] = m2;
+    }
+}
+
+// EE frame: R = O G, p = pe + O t.
+PK_DEV void ee_frame(const float *O, const float *p, const float *G, const float *t,
+                     float *R, float *pe)
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        pe[r] = p[r] + O[3 * r] * t[0] + O[3 * r + 1] * t[1] + O[3 * r + 2] * t[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            R[3 * r + c] = O[3 * r] * G[c] + O[3 * r + 1] * G[3 + c] + O[3 * r + 2] * G[6 + c];
+    }
+}
+
+PK_DEV void mm3(const float *A, const float *B, float *C)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// C = A B^T
+PK_DEV void mmT3(const float *A, const float *B, float *C)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A[3 * i] * B[3 * j] + A[3 * i + 1] * B[3 * j + 1] + A[3 * i + 2] * B[3 * j + 2];
+}
+
+// C = A^T B
+PK_DEV void mTm3(const float *A, const float *B, float *C)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A[i] * B[j] + A[3 + i] * B[3 + j] + A[6 + i] * B[6 + j];
+}
+
+PK_DEV void hat(const float *w, float *W)
+{
+    W[0] = 0.f;   W[1] = -w[2]; W[2] = w[1];
+    W[3] = w[2];  W[4] = 0.f;   W[5] = -w[0];
+    W[6] = -w[1]; W[7] = w[0];  W[8] = 0.f;
+}
+
+PK_DEV void cross(const float *a, const float *b, float *c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Unit quaternion (w >= 0) of a rotation matrix, Shepperd's method.
+PK_DEV void rot_to_quat(const float *R, float &w, float &x, float &y, float &z)
+{
+    float tr = R[0] + R[4] + R[8];
+    if (tr >= R[0] && tr >= R[4] && tr >= R[8]) {
+        float s = 2.f * sqrtf(1.f + tr), is = 1.f / s;
+        w = 0.25f * s; x = (R[7] - R[5]) * is; y = (R[2] - R[6]) * is; z = (R[3] - R[1]) * is;
+    } else if (R[0] >= R[4] && R[0] >= R[8]) {
+        float s = 2.f * sqrtf(1.f + R[0] - R[4] - R[8]), is = 1.f / s;
+        w = (R[7] - R[5]) * is; x = 0.25f * s; y = (R[1] + R[3]) * is; z = (R[2] + R[6]) * is;
+    } else if (R[4] >= R[8]) {
+        float s = 2.f * sqrtf(1.f + R[4] - R[0] - R[8]), is = 1.f / s;
+        w = (R[2] - R[6]) * is; x = (R[1] + R[3]) * is; y = 0.25f * s; z = (R[5] + R[7]) * is;
+    } else {
+        float s = 2.f * sqrtf(1.f + R[8] - R[0] - R[4]), is = 1.f / s;
+        w = (R[3] - R[1]) * is; x = (R[2] + R[6]) * is; y = (R[5] + R[7]) * is; z = 0.25f * s;
+    }
+    if (w < 0.f) { w = -w; x = -x; y = -y; z = -z; }
+    float in = rsqrtf(w * w + x * x + y * y + z * z);
+    w *= in; x *= in; y *= in; z *= in;
+}
+
+// Rotation matrix of a (not necessarily unit) quaternion wxyz.
+PK_DEV void quat_to_rot(float w, float x, float y, float z, float *R)
+{
+    float in = rsqrtf(w * w + x * x + y * y + z * z);
+    w *= in; x *= in; y *= in; z *= in;
+    R[0] = 1.f - 2.f * (y * y + z * z); R[1] = 2.f * (x * y - w * z); R[2] = 2.f * (x * z + w * y);
+    R[3] = 2.f * (x * y + w * z); R[4] = 1.f - 2.f * (x * x + z * z); R[5] = 2.f * (y * z - w * x);
+    R[6] = 2.f * (x * z - w * y); R[7] = 2.f * (y * z + w * x); R[8] = 1.f - 2.f * (x * x + y * y);
+}
+
+// SE(3) logarithm of E = (R_E, t_E) = T_target^-1 T_ee.
+struct PoseLog {
+    float rho[3], phi[3];
+    float theta;
+    float sh, ch;      // sin(theta/2), cos(theta/2)
+};
+
+// Rt: target rotation; Re: EE rotation; d = p_ee - p_target (world frame).
+PK_DEV PoseLog pose_log(const float *Rt, const float *Re, const float *d)
+{
+    PoseLog L;
+    float RE[9], tE[3];
+    mTm3(Rt, Re, RE);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tE[i] = Rt[i] * d[0] + Rt[3 + i] * d[1] + Rt[6 + i] * d[2];
+    float w, x, y, z;
+    rot_to_quat(RE, w, x, y, z);
+    float s = sqrtf(x * x + y * y + z * z);
+    float theta = 2.f * atan2f(s, w);
+    // phi = theta * v / |v|;  theta / s -> 2 / w (1 - s^2 / (3 w^2)) as s -> 0.
+    float f = s < 1e-4f ? (2.f / w) * (1.f - s * s / (3.f * w * w)) : theta / s;
+    L.phi[0] = f * x; L.phi[1] = f * y; L.phi[2] = f * z;
+    L.theta = theta;
+    L.sh = s;
+    L.ch = w;
+    // rho = J_l^-1(phi) t_E = t_E - phi x t_E / 2 + k phi x (phi x t_E),
+    // k = (1 - (theta/2) cot(theta/2)) / theta^2, cot(theta/2) = w / s.
+    float t2 = theta * theta, k;
+    if (theta < 0.1f)
+        k = 1.f / 12.f + t2 * (1.f / 720.f + t2 * (1.f / 30240.f));
+    else
+        k = (1.f - 0.5f * theta * w / s) / t2;
+    float a[3], b[3];
+    cross(L.phi, tE, a);
+    cross(L.phi, a, b);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) L.rho[i] = tE[i] - 0.5f * a[i] + k * b[i];
+    return L;
+}
+
+// Blocks of the right-Jacobian inverse folded with the EE rotation:
+//   J_r^-1(xi) = [[P, B], [0, P]],  P = J_l^-1(-phi),  B = -P Q(-rho,-phi) P,
+// M = P Re^T, N = B Re^T, so that for a joint with world axis w and point
+// velocity v (world), d xi / d q = [M v + N w ; M w].
+PK_DEV void jr_inv_blocks(const PoseLog &L, const float *Re, float *M, float *N)
+{
+    const float th = L.theta, t2 = th * th;
+    float k, a1, a2, a3;
+    if (th < 0.1f)
+        k = 1.f / 12.f + t2 * (1.f / 720.f + t2 * (1.f / 30240.f));
+    else
+        k = (1.f - 0.5f * th * L.ch / L.sh) / t2;
+    if (th < 0.5f) {
+        a1 = 1.f / 6.f + t2 * (-1.f / 120.f + t2 * (1.f / 5040.f - t2 * (1.f / 362880.f)));
+        a2 = 1.f / 24.f + t2 * (-1.f / 720.f + t2 * (1.f / 40320.f - t2 * (1.f / 3628800.f)));
+        a3 = 1.f / 120.f + t2 * (-1.f / 2520.f + t2 * (1.f / 120960.f - t2 * (1.f / 9979200.f)));
+    } else {
+        const float st = 2.f * L.sh * L.ch, ct = L.ch * L.ch - L.sh * L.sh;
+        const float t3 = t2 * th, t4 = t2 * t2;
+        a1 = (th - st) / t3;
+        a2 = (t2 - 4.f * L.sh * L.sh) / (2.f * t4);       // 2 cos - 2 = -4 sin^2(th/2)
+        a3 = (2.f * th - 3.f * st + th * ct) / (2.f * t4 * th);
+    }
+    float Ph[9], Rh[9], PP[9];
+    hat(L.phi, Ph);
+    hat(L.rho, Rh);
+    mm3(Ph, Ph, PP);
+    float P[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P[i] = 0.5f * Ph[i] + k * PP[i];
+    P[0] += 1.f; P[4] += 1.f; P[8] += 1.f;
+    // Q(-rho,-phi) = -Rh/2 + a1 (Ph Rh + Rh Ph - Ph Rh Ph)
+    //               + a2 (-Ph Ph Rh - Rh Ph Ph + 3 Ph Rh Ph) + a3 (Ph Rh Ph Ph + Ph Ph Rh Ph)
+    float X[9], Y[9], Z[9], PPR[9], RPP[9], ZP[9], PZ[9];
+    mm3(Ph, Rh, X);
+    mm3(Rh, Ph, Y);
+    mm3(X, Ph, Z);
+    mm3(Ph, X, PPR);
+    mm3(Y, Ph, RPP);
+    mm3(Z, Ph, ZP);
+    mm3(Ph, Z, PZ);
+    float Q[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        Q[i] = -0.5f * Rh[i] + a1 * (X[i] + Y[i] - Z[i]) + a2 * (3.f * Z[i] - PPR[i] - RPP[i]) +
+               a3 * (ZP[i] + PZ[i]);
+    float T1[9], B[9];
+    mm3(P, Q, T1);
+    mm3(T1, P, B);
+    mmT3(P, Re, M);
+    float NB[9];
+    mmT3(B, Re, NB);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) N[i] = -NB[i];
+}
+
+}  // namespace pk

@@ -1,0 +1,76 @@
+// Internal host/device definitions of the MI355X batched-LM IK library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pkmi.h"
+
+namespace pk {
+
+// Joints are stored in "z-axis joint frames": frame j is the paper's joint
+// frame R_j rotated by a fixed U_j that maps e_z onto the joint axis, so the
+// joint rotation is always Rz(q_j).  Then one joint is
+//   O_j = O_parent * G_j * Rz(q_j),   p_j = p_parent + O_parent * t_j,
+// with G_j = U_parent^T R_mount,j U_j and t_j = U_parent^T offset_j, and the
+// world joint axis is the third column of O_j.  The host computes G and t in
+// FP64 from the FP64 tree and rounds them to FP32.
+struct JointC {
+    float G[9];        // row-major
+    float t[3];
+    float lo, hi, mid;
+    int32_t parent;
+    float Ut[9];       // U_j^T, to report the paper's R_j = O_j U_j^T
+    int32_t depth;
+    int32_t pad[2];
+};
+
+struct EEC {
+    float G[9];        // U_e^T R_eeoff
+    float t[3];        // U_e^T ee_offset
+    int32_t joint;
+    int32_t kind;      // PK_EE_POSE / PK_EE_POSITION
+    int32_t tgt_off;   // first target plane of this EE
+    int32_t row_off;   // first residual row of this EE
+};
+
+struct RobotC {
+    int32_t n, m, tgt_floats, pose_rows;   // pose_rows = sum of EE row counts
+    int32_t chains, chain_len, max_depth, pad;
+    uint64_t anc[PK_MAX_EES];              // bit j set iff joint j is an ancestor of EE k
+    JointC j[PK_MAX_JOINTS];
+    EEC e[PK_MAX_EES];
+    float mid[PK_MAX_JOINTS];              // (lower + upper) / 2, the default rest pose
+};
+
+// Uniform per-call data for the LM kernels (passed by value).
+struct SolveParams {
+    float w_pos, w_rot, w_limit, w_rest;
+    float lambda0, nu_up, nu_down, lambda_min, lambda_max;
+    float tol_pos, tol_rot, damping_floor, pivot_rel;
+    int32_t max_iters, early_exit, K, trace_iters;
+    int64_t N, T;
+    const float *targets, *seeds, *q_rest;
+    float *joints, *pos_err, *rot_err, *cost, *pose_cost;
+    int32_t *iters, *accepts, *status, *iters_to_tol;
+    float *trace_q;
+    int32_t *trace_acc;
+};
+
+// Launchers (defined next to their kernels).  Return hipSuccess or the
+// launch error.
+bool lane_variant_available(int chains, int chain_len, int kind);
+hipError_t launch_lm_lane(const RobotC *dev_robot, const RobotC &host_robot,
+                          const SolveParams &P, hipStream_t s);
+bool wave_variant_available(int n);
+hipError_t launch_lm_wave(const RobotC *dev_robot, const RobotC &host_robot,
+                          const SolveParams &P, hipStream_t s);
+hipError_t launch_best_of_k(const SolveParams &P, int n, int32_t *best_index,
+                            float *best_joints, int32_t *success, hipStream_t s);
+hipError_t launch_fk(const RobotC *dev_robot, int64_t N, const float *q, float *ee_pose,
+                     float *joint_frames, hipStream_t s);
+hipError_t launch_residual_jacobian(const RobotC *dev_robot, int64_t N, int32_t K,
+                                    const float *targets, const float *q,
+                                    const SolveParams &w, float *r, float *J, hipStream_t s);
+
+}  // namespace pk

@@ -1,0 +1,127 @@
+"""GPU parity of the wave-per-problem kernel (any tree) against the FP64
+oracle, and agreement between kernel variants on the same problems."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import borderline, solve_gpu
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2505_03728_amd as pk
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def _excusable(o):
+    return bool(o["trace_tie"].any()) or borderline(
+        {"pos_err": [o["pos_err"]], "rot_err": [o["rot_err"]]}, 0)
+
+
+def test_tree34_first_iterates_and_success(ctx):
+    import paper_2505_03728_amd as pk
+    wl = synth.workload("tree4k", targets=48)
+    g = wl["groups"][0]
+    tree = g["tree"]
+    rid = ctx.upload(tree)
+    tg = oracle.targets_from(tree, g["q_star"])
+    o = wl["options"]
+    res = solve_gpu(ctx, rid, tree, tg, g["seeds"], 1, wl["weights"], o, trace_iters=5,
+                    variant=pk.VARIANT_WAVE)
+    excluded = bad = excused = 0
+    for p in range(tg.shape[0]):
+        ora = oracle.lm_solve(tree, tg[p], wl["weights"], o, g["seeds"][p], n_trace=o["max_iters"])
+        if ora["trace_tie"][:5].any():
+            excluded += 1
+        else:
+            np.testing.assert_array_equal(res["trace_accept"][p], ora["trace_acc"][:5])
+            dq = np.abs(res["trace_q"][p] - ora["trace_q"][:5]).max()
+            assert dq <= 1e-4, (p, dq)
+        cg, co = (res["status"][p] & 0xff) == 0, (ora["status"] & 0xff) == 0
+        if cg != co:
+            if _excusable(ora):
+                excused += 1
+            else:
+                bad += 1
+    conv = ((res["status"] & 0xff) == 0).mean()
+    fb = ((res["status"] & 0x100) != 0).mean()
+    print(f"tree34: {excluded} excluded (near-ties), success {conv:.3f}, fp64 flag {fb:.3f}, "
+          f"excused {excused}, unexplained {bad}")
+    assert bad == 0
+
+
+@pytest.mark.parametrize("name", ["arm7", "hand16"])
+def test_wave_matches_lane_variant(ctx, name):
+    import paper_2505_03728_amd as pk
+    if name == "arm7":
+        wl = synth.workload("arm131k", targets=128)
+    else:
+        wl = synth.workload("mixed84k", targets=256)
+    g = [g for g in wl["groups"] if g["tree"].name == name][0]
+    tree, K = g["tree"], g["K"]
+    rid = ctx.upload(tree)
+    tg = oracle.targets_from(tree, g["q_star"])
+    o = dict(wl["options"], early_exit=False)
+    a = solve_gpu(ctx, rid, tree, tg, g["seeds"], K, wl["weights"], o, trace_iters=5,
+                  variant=pk.VARIANT_LANE)
+    b = solve_gpu(ctx, rid, tree, tg, g["seeds"], K, wl["weights"], o, trace_iters=5,
+                  variant=pk.VARIANT_WAVE)
+    # Same arithmetic up to reduction order: first iterates agree closely.
+    same_acc = np.all(a["trace_accept"] == b["trace_accept"], axis=1)
+    assert same_acc.mean() > 0.97
+    dq = np.abs(a["trace_q"] - b["trace_q"]).max(axis=(1, 2))[same_acc]
+    assert np.quantile(dq, 0.95) <= 1e-4
+    ca, cb = (a["status"] & 0xff) == 0, (b["status"] & 0xff) == 0
+    print(f"{name}: lane/wave success {ca.mean():.4f}/{cb.mean():.4f}, "
+          f"flag agreement {(ca == cb).mean():.4f}")
+    assert (ca == cb).mean() > 0.97
+
+
+def test_wave_status_paths(ctx):
+    import paper_2505_03728_amd as pk
+    pl = synth.planar2(0.6, 0.4, kind=synth.EE_POSITION)
+    rid = ctx.upload(pl)
+    far = np.array([[[2.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0]]])
+    w = {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 0.0, "w_rest": 0.0, "q_rest": None}
+    o = synth.workload("arm16")["options"]
+    res = solve_gpu(ctx, rid, pl, far, np.zeros((1, 2)), 1, w, o, lambda0=1e8)
+    ora = oracle.lm_solve(pl, far[0], w, o | {"lambda0": 1e8}, np.zeros(2))
+    assert res["status"][0] & 0xff == pk.STALLED == ora["status"] & 0xff
+    assert res["iters"][0] == ora["iters"] == 3 and res["accepts"][0] == 0
+    # non-finite seed on the tree robot
+    tree = synth.tree34(5)
+    rt = ctx.upload(tree)
+    g = synth.workload("tree4k", targets=4)["groups"][0]
+    tg = oracle.targets_from(tree, g["q_star"])
+    seeds = g["seeds"].copy()
+    seeds[2, 30] = np.nan
+    r = solve_gpu(ctx, rt, tree, tg, seeds, 1, w, o, max_iters=3)
+    assert r["status"][2] == pk.NONFINITE
+    assert np.all(r["status"][[0, 1, 3]] != pk.NONFINITE)
+
+
+def test_hand_early_exit_wave_vs_oracle(ctx):
+    import paper_2505_03728_amd as pk
+    wl = synth.workload("mixed84k", targets=64)
+    g = wl["groups"][1]
+    tree = g["tree"]
+    rid = ctx.upload(tree)
+    tg = oracle.targets_from(tree, g["q_star"])
+    o = wl["options"]
+    res = solve_gpu(ctx, rid, tree, tg, g["seeds"], 1, wl["weights"], o, variant=pk.VARIANT_WAVE)
+    bad = 0
+    for p in range(tg.shape[0]):
+        ora = oracle.lm_solve(tree, tg[p], wl["weights"], o, g["seeds"][p], n_trace=o["max_iters"])
+        cg, co = (res["status"][p] & 0xff) == 0, (ora["status"] & 0xff) == 0
+        if cg != co and not _excusable(ora):
+            bad += 1
+        if cg and co and not ora["trace_tie"].any():
+            assert res["iters"][p] == ora["iters"] == ora["iters_to_tol"]
+    assert bad == 0
