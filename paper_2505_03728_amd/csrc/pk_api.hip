@@ -8,26 +8,13 @@
 #include <string>
 #include <vector>
 
-#include "pk_internal.hpp"
+#include "pk_ctx.hpp"
 
 using namespace pk;
 
-struct RobotEntry {
-    RobotC host;
-    RobotC *dev = nullptr;
-};
-
-struct pk_ctx {
-    int device = 0;
-    std::string err;
-    std::vector<RobotEntry> robots;
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-};
-
 static std::string g_err_noctx;
 
-static int fail(pk_ctx *ctx, int code, const char *fmt, ...)
+int pk::fail(pk_ctx *ctx, int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -40,13 +27,6 @@ static int fail(pk_ctx *ctx, int code, const char *fmt, ...)
         g_err_noctx = buf;
     return code;
 }
-
-#define PK_HIP(ctx, call)                                                                  \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(ctx, PK_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));     \
-    } while (0)
 
 // ------------------------------------------------------------ host geometry (FP64)
 
@@ -157,6 +137,7 @@ int pk_destroy(pk_ctx *ctx)
     for (auto &r : ctx->robots)
         if (r.dev) (void)hipFree(r.dev);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    for (auto *sd : ctx->seeders) seeder_free(sd);
     delete ctx;
     return PK_OK;
 }
@@ -288,7 +269,7 @@ int pk_robot_info(pk_ctx *ctx, int32_t id, int32_t *n, int32_t *m, int32_t *tf, 
     return PK_OK;
 }
 
-static RobotEntry *robot_of(pk_ctx *ctx, int32_t id)
+RobotEntry *pk::robot_of(pk_ctx *ctx, int32_t id)
 {
     if (id < 0 || id >= (int)ctx->robots.size()) return nullptr;
     return &ctx->robots[id];

@@ -164,8 +164,9 @@ def test_lm_success_agreement(ctx, rids, name, wl_name, T):
     assert np.all(res["iters"] <= o["max_iters"])
     if not o["early_exit"]:
         # a fixed budget is spent unless the problem stalls at lambda_max
-        st_o = np.array([(x["status"] & 0xff) == oracle.STALLED for x in ora])
-        st_g = (res["status"] & 0xff) == 2
+        # (a stall after convergence reports CONVERGED)
+        st_o = np.array([(x["status"] & 0xff) in (oracle.STALLED, oracle.CONVERGED) for x in ora])
+        st_g = np.isin(res["status"] & 0xff, [0, 2])
         assert np.all((res["iters"] == o["max_iters"]) | st_g)
         assert np.all((its == o["max_iters"]) | st_o)
 
