@@ -188,6 +188,115 @@ int pk_ik_solve(pk_ctx *ctx, int32_t robot_id, const pk_ik_problem *problem,
                 const pk_cost_weights *w, const pk_lm_options *opt,
                 const pk_ik_outputs *out, void *stream);
 
+/* ------------------------------------------------------- mixed batches
+ * Several groups of problems (different robots, shapes, weights) solved
+ * together: per group, persistent LM launches whose wavefronts pop work
+ * items from a device queue, at most iters_per_launch iterations per launch
+ * with the problem state kept in HBM, and a compaction of the unfinished
+ * problems between launches (problems that exit early free their lanes).
+ * The launch chain of all groups is captured into one hipGraph (a branch per
+ * group, so groups run concurrently) and replayed on later calls with the
+ * same buffers.  Per-problem results equal those of pk_ik_solve with the same
+ * inputs and options.  Traces are not supported here. */
+typedef struct {
+    int32_t robot_id;
+    pk_ik_problem problem;
+    pk_cost_weights weights;
+    pk_ik_outputs out;
+} pk_ik_group;
+
+typedef struct {
+    int32_t iters_per_launch;    /* k; 0 = all iterations in one launch        */
+    int32_t blocks_per_cu;       /* persistent grid = blocks_per_cu x CUs       */
+    int32_t use_graph;           /* 1 = capture / replay a hipGraph             */
+} pk_sched_options;              /* all zero = the autotuned entry if any      */
+
+/* Asynchronous on `stream`.  sched may be NULL (graph on, autotuned or
+ * default schedule). */
+int pk_ik_solve_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
+                      const pk_lm_options *opt, const pk_sched_options *sched, void *stream);
+/* Times every candidate schedule (k in {5, 10, 25, all} x blocks per CU in
+ * {2, 4, 8}, graph on) on these groups, stores the fastest for batches of
+ * this signature and returns it.  Runs the solve several times (the outputs
+ * hold the last run).  Synchronous. */
+int pk_autotune_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
+                      const pk_lm_options *opt, pk_sched_options *best, float *best_ms,
+                      void *stream);
+
+/* ---------------------------------------------------------------- seeder
+ * Learned seeder: an MLP (BF16 matrix-core GEMMs, FP32 accumulation) from an
+ * EE pose target to K joint-space seeds, trained on (FK(q), q) pairs with
+ * the min-over-seeds loss  L = mean_b min_k |qhat_{b,k} - q_b|^2  and Adam
+ * (beta 0.9 / 0.999, eps 1e-8, bias-corrected).  Input encoding:
+ * [p / reach, unit quaternion with w >= 0], reach = sum of link and EE
+ * offset lengths.  Hidden layers Linear + SiLU, linear output.  Robots with
+ * one pose EE only.  The seeds feed pk_ik_solve (LM refinement), with plain
+ * random-seed LM as the fallback. */
+
+/* init (host, optional, FP32): per layer W [out][in] then b [out], layers in
+ * order, in = 7 for the first layer, out = n*K for the last; init_count must
+ * equal pk_seeder_param_count.  NULL = all zeros.  Synchronous. */
+int pk_seeder_create(pk_ctx *ctx, int32_t robot_id, int32_t K, int32_t hidden, int32_t depth,
+                     const float *init, int64_t init_count, int32_t *seeder_id);
+int pk_seeder_param_count(pk_ctx *ctx, int32_t seeder_id, int64_t *count);
+/* Copies (synchronously, in the init layout) the parameters (which = 0), the
+ * gradients of the last step (1) or Adam's first (2) / second (3) moments. */
+int pk_seeder_get(pk_ctx *ctx, int32_t seeder_id, int32_t which, float *host_out, int64_t count);
+/* Network output y [B][n*K] (device) for encoded inputs x [B][7] (device). */
+int pk_seeder_forward(pk_ctx *ctx, int32_t seeder_id, const float *x, int64_t B, float *y,
+                      void *stream);
+/* Loss (device scalar, optional) and parameter gradients for one batch of
+ * encoded inputs x [B][7] and joints q [B][n] (device); B a multiple of 128. */
+int pk_seeder_grad(pk_ctx *ctx, int32_t seeder_id, const float *x, const float *q, int64_t B,
+                   float *loss, void *stream);
+/* Training on q_train [n][S] (device); targets are FK(q).  Epoch e visits
+ * samples in the order perm[e*S .. e*S+S) (device int32, or NULL for index
+ * order) in S / batch steps of `batch` (a multiple of 128) samples.
+ * loss_log (device, optional): one mean loss per step.  Synchronous at exit. */
+int pk_seeder_train(pk_ctx *ctx, int32_t seeder_id, const float *q_train, int64_t S,
+                    int32_t batch, int32_t epochs, float lr, const int32_t *perm,
+                    float *loss_log, void *stream);
+/* K seeds per target for pose targets [7][T] (device, pk_ik_problem layout)
+ * -> seeds [n][T*K] (device), clamped to the joint limits. */
+int pk_seeder_infer(pk_ctx *ctx, int32_t seeder_id, const float *targets, int64_t T,
+                    float *seeds, void *stream);
+/* Learned seeds + LM refinement, with random-seed LM as the fallback:
+ *   1. the seeder gives K seeds per target (pk_seeder_infer);
+ *   2. LM with `refine` on the T*K problems, best-of-K per target;
+ *   3. targets that no learned seed solved are listed on the device and
+ *      solved again from fallback_seeds [n][T*fallback_K] with `fallback`;
+ *   4. per target the result of the pass that solved it.
+ * Asynchronous on `stream`; no host synchronisation inside. */
+typedef struct {
+    int32_t seeder_id;
+    int32_t fallback_K;              /* 0 = no fallback                          */
+    const float *fallback_seeds;     /* device [n][T*fallback_K]                 */
+    pk_lm_options refine;            /* e.g. 10 iterations, early exit           */
+    pk_lm_options fallback;          /* e.g. 30 iterations                       */
+} pk_seeded_options;
+
+typedef struct {
+    float *best_joints;              /* [n][T] required                          */
+    int32_t *target_success;         /* [T]                                      */
+    int32_t *source;                 /* [T] 0 learned seeds, 1 fallback, -1 none  */
+    int32_t *iters_to_tol;           /* [T] fewest LM iterations to tolerance over
+                                        the succeeding pass's seeds, -1 if none   */
+    int32_t *refine_iters;           /* [T*K] optional counters of pass 2         */
+    int32_t *refine_accepts;         /* [T*K]                                    */
+    int32_t *fallback_iters;         /* [T*fallback_K] optional, 0 if not re-solved */
+    int32_t *fallback_accepts;       /* [T*fallback_K]                           */
+    int32_t *n_fallback;             /* device scalar: targets re-solved          */
+} pk_seeded_outputs;
+
+int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t n_targets, const float *targets,
+                       const pk_cost_weights *w, const pk_seeded_options *opt,
+                       const pk_seeded_outputs *out, void *stream);
+
+/* Checkpoint of parameters, Adam moments and the step count (versioned
+ * binary file).  Synchronous. */
+int pk_seeder_save(pk_ctx *ctx, int32_t seeder_id, const char *path);
+int pk_seeder_load(pk_ctx *ctx, int32_t seeder_id, const char *path);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Context", "Weights", "Options", "lib", "LibraryMissing", "PkError",
+__all__ = ["Context", "Seeder", "Weights", "Options", "lib", "LibraryMissing", "PkError",
            "CONVERGED", "MAX_ITERS", "STALLED", "NONFINITE", "FLAG_FP64",
            "EE_POSE", "EE_POSITION", "VARIANT_AUTO", "VARIANT_LANE", "VARIANT_WAVE",
            "pack_targets", "target_floats"]
@@ -73,6 +73,29 @@ class _Outputs(C.Structure):
                 ("trace_q", C.c_void_p), ("trace_accept", C.c_void_p)]
 
 
+class _SeededOptions(C.Structure):
+    _fields_ = [("seeder_id", C.c_int32), ("fallback_K", C.c_int32), ("fallback_seeds", C.c_void_p),
+                ("refine", _Options), ("fallback", _Options)]
+
+
+class _SeededOutputs(C.Structure):
+    _fields_ = [("best_joints", C.c_void_p), ("target_success", C.c_void_p),
+                ("source", C.c_void_p), ("iters_to_tol", C.c_void_p),
+                ("refine_iters", C.c_void_p), ("refine_accepts", C.c_void_p),
+                ("fallback_iters", C.c_void_p), ("fallback_accepts", C.c_void_p),
+                ("n_fallback", C.c_void_p)]
+
+
+class _Group(C.Structure):
+    _fields_ = [("robot_id", C.c_int32), ("problem", _Problem), ("weights", _Weights),
+                ("out", _Outputs)]
+
+
+class _Sched(C.Structure):
+    _fields_ = [("iters_per_launch", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("use_graph", C.c_int32)]
+
+
 _lib = None
 
 
@@ -95,8 +118,28 @@ def lib():
                                            vp, vp]
         L.pk_ik_solve.argtypes = [vp, i32, C.POINTER(_Problem), C.POINTER(_Weights),
                                   C.POINTER(_Options), C.POINTER(_Outputs), vp]
+        fp = C.POINTER(C.c_float)
+        L.pk_seeder_create.argtypes = [vp, i32, i32, i32, i32, fp, i64, C.POINTER(i32)]
+        L.pk_seeder_param_count.argtypes = [vp, i32, C.POINTER(i64)]
+        L.pk_seeder_get.argtypes = [vp, i32, i32, fp, i64]
+        L.pk_seeder_forward.argtypes = [vp, i32, vp, i64, vp, vp]
+        L.pk_seeder_grad.argtypes = [vp, i32, vp, vp, i64, vp, vp]
+        L.pk_seeder_train.argtypes = [vp, i32, vp, i64, i32, i32, C.c_float, vp, vp, vp]
+        L.pk_seeder_infer.argtypes = [vp, i32, vp, i64, vp, vp]
+        L.pk_seeder_save.argtypes = [vp, i32, C.c_char_p]
+        L.pk_seeder_load.argtypes = [vp, i32, C.c_char_p]
+        L.pk_ik_solve_seeded.argtypes = [vp, i32, i64, vp, C.POINTER(_Weights),
+                                         C.POINTER(_SeededOptions), C.POINTER(_SeededOutputs), vp]
+        L.pk_ik_solve_mixed.argtypes = [vp, i32, C.POINTER(_Group), C.POINTER(_Options),
+                                        C.POINTER(_Sched), vp]
+        L.pk_autotune_mixed.argtypes = [vp, i32, C.POINTER(_Group), C.POINTER(_Options),
+                                        C.POINTER(_Sched), C.POINTER(C.c_float), vp]
         for f in ["pk_create", "pk_destroy", "pk_robot_upload", "pk_robot_info", "pk_fk",
-                  "pk_residual_jacobian", "pk_ik_solve"]:
+                  "pk_residual_jacobian", "pk_ik_solve", "pk_seeder_create",
+                  "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward",
+                  "pk_seeder_grad", "pk_seeder_train", "pk_seeder_infer", "pk_seeder_save",
+                  "pk_seeder_load", "pk_ik_solve_seeded", "pk_ik_solve_mixed",
+                  "pk_autotune_mixed"]:
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -105,7 +148,10 @@ def lib():
 def exported_symbols():
     """Names of the C entry points this binding expects the library to export."""
     return ["pk_create", "pk_destroy", "pk_last_error", "pk_robot_upload", "pk_robot_info",
-            "pk_fk", "pk_residual_jacobian", "pk_ik_solve"]
+            "pk_fk", "pk_residual_jacobian", "pk_ik_solve", "pk_seeder_create",
+            "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward", "pk_seeder_grad",
+            "pk_seeder_train", "pk_seeder_infer", "pk_seeder_save", "pk_seeder_load",
+            "pk_ik_solve_seeded", "pk_ik_solve_mixed", "pk_autotune_mixed"]
 
 
 class Weights:
@@ -260,18 +306,159 @@ class Context:
         out["_trace_iters"] = trace_iters
         return out
 
+    def ik_solve_seeded(self, rid, targets, seeder, weights: Weights, refine: Options,
+                        fallback: Options = None, fallback_seeds=None, fallback_K=0,
+                        counters=False):
+        """Learned seeds + LM, fallback to random-seed LM (see include/pkmi.h).
+
+        Returns a dict of device tensors: best_joints [n, T], target_success,
+        source, iters_to_tol [T], n_fallback [1] (and the LM counters)."""
+        torch = self._torch
+        T = targets.shape[1]
+        info = self.robot_info(rid)
+        dev = targets.device
+        K = seeder.K
+        i = lambda *s: torch.empty(s, dtype=torch.int32, device=dev)
+        out = {"best_joints": torch.empty((info["n"], T), dtype=torch.float32, device=dev),
+               "target_success": i(T), "source": i(T), "iters_to_tol": i(T), "n_fallback": i(1)}
+        if counters:
+            out.update(refine_iters=i(T * K), refine_accepts=i(T * K),
+                       fallback_iters=i(max(T * fallback_K, 1)),
+                       fallback_accepts=i(max(T * fallback_K, 1)))
+        fb = fallback or refine
+        so = _SeededOptions(seeder.id, int(fallback_K), _ptr(fallback_seeds), refine._c(), fb._c())
+        oo = _SeededOutputs(*[_ptr(out.get(k)) for k in ["best_joints", "target_success", "source",
+                                                          "iters_to_tol", "refine_iters",
+                                                          "refine_accepts", "fallback_iters",
+                                                          "fallback_accepts", "n_fallback"]])
+        w = weights._c()
+        self._call(lib().pk_ik_solve_seeded(self._h, rid, T, _ptr(targets), C.byref(w), C.byref(so),
+                                            C.byref(oo), self.stream()))
+        return out
+
+    @staticmethod
+    def _outputs_c(out):
+        return _Outputs(*[_ptr(out.get(k)) for k in ["joints", "pos_err", "rot_err", "cost", "iters",
+                                                      "accepts", "status", "iters_to_tol",
+                                                      "best_index", "best_joints",
+                                                      "target_success"]],
+                        int(out.get("_trace_iters", 0)), _ptr(out.get("trace_q")),
+                        _ptr(out.get("trace_accept")))
+
+    def _groups_c(self, groups):
+        arr = (_Group * len(groups))()
+        for i, g in enumerate(groups):
+            T = g["targets"].shape[1]
+            arr[i] = _Group(g["rid"], _Problem(T, g["K"], _ptr(g["targets"]), _ptr(g["seeds"])),
+                            g["weights"]._c(), self._outputs_c(g["out"]))
+        return arr
+
+    def ik_solve_mixed(self, groups, options: Options, iters_per_launch=0, blocks_per_cu=0,
+                       use_graph=True):
+        """groups: list of dicts rid, targets [tf, T], seeds [n, T*K], K, weights, out
+        (from alloc_outputs).  Zero schedule options pick the autotuned entry."""
+        arr = self._groups_c(groups)
+        sch = _Sched(iters_per_launch, blocks_per_cu, 1 if use_graph else 0)
+        o = options._c()
+        self._call(lib().pk_ik_solve_mixed(self._h, len(groups), arr, C.byref(o), C.byref(sch),
+                                           self.stream()))
+        return groups
+
+    def autotune_mixed(self, groups, options: Options):
+        """Times the candidate schedules on these groups; returns (k, blocks_per_cu, ms)."""
+        arr = self._groups_c(groups)
+        sch = _Sched()
+        ms = C.c_float()
+        o = options._c()
+        self._call(lib().pk_autotune_mixed(self._h, len(groups), arr, C.byref(o), C.byref(sch),
+                                           C.byref(ms), self.stream()))
+        return sch.iters_per_launch, sch.blocks_per_cu, ms.value
+
     def ik_solve(self, rid, targets, seeds, K, weights: Weights, options: Options, out):
         """targets [tf, T] and seeds [n, T*K] are cuda float32 tensors; out from
         alloc_outputs (missing keys are passed as NULL)."""
         T = targets.shape[1]
         pr = _Problem(T, K, _ptr(targets), _ptr(seeds))
-        o = _Outputs(*[_ptr(out.get(k)) for k in ["joints", "pos_err", "rot_err", "cost", "iters",
-                                                   "accepts", "status", "iters_to_tol",
-                                                   "best_index", "best_joints",
-                                                   "target_success"]],
-                     int(out.get("_trace_iters", 0)), _ptr(out.get("trace_q")),
-                     _ptr(out.get("trace_accept")))
+        o = self._outputs_c(out)
         w, op = weights._c(), options._c()
         self._call(lib().pk_ik_solve(self._h, rid, C.byref(pr), C.byref(w), C.byref(op),
                                      C.byref(o), self.stream()))
         return out
+
+
+class Seeder:
+    """Learned seeder bound to one robot of a Context (see include/pkmi.h)."""
+
+    def __init__(self, ctx: "Context", rid: int, K=8, hidden=512, depth=3, init=None):
+        """init: list of (W [out,in], b [out]) host arrays (FP32), or None."""
+        self.ctx, self.rid, self.K = ctx, rid, K
+        flat, cnt = None, 0
+        if init is not None:
+            flat = np.ascontiguousarray(np.concatenate(
+                [np.concatenate([np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32)])
+                 for W, b in init]), dtype=np.float32)
+            cnt = flat.size
+        sid = C.c_int32()
+        ctx._call(lib().pk_seeder_create(ctx._h, rid, K, hidden, depth,
+                                         flat.ctypes.data_as(C.POINTER(C.c_float)) if flat is not None else None,
+                                         cnt, C.byref(sid)))
+        self.id = sid.value
+        self.hidden, self.depth = hidden, depth
+        self._n = ctx.robot_info(rid)["n"]
+
+    def param_count(self):
+        c = C.c_int64()
+        self.ctx._call(lib().pk_seeder_param_count(self.ctx._h, self.id, C.byref(c)))
+        return c.value
+
+    def get(self, which=0):
+        """Parameters (0), gradients (1), Adam moments (2, 3) as [(W, b)] host arrays."""
+        cnt = self.param_count()
+        buf = np.zeros(cnt, np.float32)
+        self.ctx._call(lib().pk_seeder_get(self.ctx._h, self.id, which,
+                                           buf.ctypes.data_as(C.POINTER(C.c_float)), cnt))
+        out, off = [], 0
+        dims = [7] + [self.hidden] * self.depth + [self._n * self.K]
+        for fi, fo in zip(dims[:-1], dims[1:]):
+            W = buf[off:off + fi * fo].reshape(fo, fi)
+            off += fi * fo
+            b = buf[off:off + fo]
+            off += fo
+            out.append((W.copy(), b.copy()))
+        return out
+
+    def forward(self, x):
+        """x: cuda float32 [B, 7] (encoded) -> y [B, n*K]."""
+        y = self.ctx._torch.empty((x.shape[0], self._n * self.K), dtype=self.ctx._torch.float32,
+                                  device=x.device)
+        self.ctx._call(lib().pk_seeder_forward(self.ctx._h, self.id, _ptr(x), x.shape[0], _ptr(y),
+                                               self.ctx.stream()))
+        return y
+
+    def grad(self, x, q):
+        loss = self.ctx._torch.zeros(1, dtype=self.ctx._torch.float32, device=x.device)
+        self.ctx._call(lib().pk_seeder_grad(self.ctx._h, self.id, _ptr(x), _ptr(q), x.shape[0],
+                                            _ptr(loss), self.ctx.stream()))
+        return loss
+
+    def train(self, q_train, batch=8192, epochs=1, lr=1e-3, perm=None, loss_log=None):
+        """q_train: cuda float32 [n, S]; perm: cuda int32 [epochs, S] or None."""
+        S = q_train.shape[1]
+        self.ctx._call(lib().pk_seeder_train(self.ctx._h, self.id, _ptr(q_train), S, batch, epochs,
+                                             lr, _ptr(perm), _ptr(loss_log), self.ctx.stream()))
+
+    def infer(self, targets, seeds=None):
+        """targets: cuda float32 [7, T] -> seeds [n, T*K]."""
+        T = targets.shape[1]
+        if seeds is None:
+            seeds = self.ctx._torch.empty((self._n, T * self.K), dtype=self.ctx._torch.float32,
+                                          device=targets.device)
+        self.ctx._call(lib().pk_seeder_infer(self.ctx._h, self.id, _ptr(targets), T, _ptr(seeds),
+                                             self.ctx.stream()))
+        return seeds
+
+    def save(self, path):
+        self.ctx._call(lib().pk_seeder_save(self.ctx._h, self.id, str(path).encode()))
+
+    def load(self, path):
+        self.ctx._call(lib().pk_seeder_load(self.ctx._h, self.id, str(path).encode()))

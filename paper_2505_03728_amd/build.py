@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpkmi.so")
 SOURCES = ["pk_api.hip", "pk_debug.hip", "lm_lane.hip", "lm_wave.hip", "lm_wave_16.hip",
-           "lm_wave_40.hip", "lm_wave_64.hip"]
+           "lm_wave_40.hip", "lm_wave_64.hip", "seeder.hip",
+           "pipeline.hip", "sched.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -35,15 +35,21 @@ struct LaneLds {
     PK_DEV float &operator[](int slot) const { return base[slot * BLOCK]; }
 };
 
-// LDS slots: [targets | A blocks | g].  Targets per EE: p (3) and, for pose
-// EEs, the target rotation (9).
+// LDS slots: [targets | Jacobian columns | residual rows | diagonal terms].
+// Targets per EE: p (3) and, for pose EEs, the target rotation (9).  The
+// Jacobian of the current point (weighted rows, ROWS per EE, chain-major),
+// the EE residual rows, and per joint the limit/rest contributions to the
+// diagonal (dl^2 + w_rest^2) and to J^T r (dl rl + w_rest rr).
 template <int C, int L, int KIND>
 struct Slots {
+    static constexpr int ROWS = Star<C, L, KIND>::ROWS;
     static constexpr int TGW = KIND == PK_EE_POSE ? 12 : 3;
     static constexpr int TG = 0;
-    static constexpr int A = C * TGW;
-    static constexpr int G = A + C * Star<C, L, KIND>::NA;
-    static constexpr int TOTAL = G + C * L;
+    static constexpr int COL = C * TGW;
+    static constexpr int RES = COL + C * L * ROWS;
+    static constexpr int DG = RES + C * ROWS;
+    static constexpr int GX = DG + C * L;
+    static constexpr int TOTAL = GX + C * L;
 };
 
 // FK along chain c at q; optionally keeps each joint's world axis and origin.
@@ -132,84 +138,93 @@ PK_DEV void eval_cost(const RobotC *__restrict__ rb, const SolveParams &P,
 
 // Normal equations at q: for each chain, the packed J_c^T J_c (+ limit and
 // rest diagonal) and J^T r, handed to sink.a(c, idx, v) / sink.g(j, v).
-template <int C, int L, int KIND, typename AT, typename Sink>
-PK_DEV void eval_normal_chain(const RobotC *__restrict__ rb, const SolveParams &P,
-                              const float *__restrict__ qr, const LaneLds &S, const float *q,
-                              int c, Sink &sink)
+// Jacobian of chain c at q (weighted EE rows and the limit/rest diagonal
+// terms) -> LDS.
+template <int C, int L, int KIND>
+PK_DEV void eval_jacobian_chain(const RobotC *__restrict__ rb, const SolveParams &P,
+                                const float *__restrict__ qr, const LaneLds &S, const float *q, int c)
 {
     using SL = Slots<C, L, KIND>;
-    constexpr int ROWS = Star<C, L, KIND>::ROWS;
-    {
-        float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS], pe_err, re_err, M[9], Nb[9];
-        PoseLog lg;
-        chain_fk<C, L, true>(rb, c, q, om, pj, Re, pe);
-        ee_residual<KIND>(P, S, SL::TG + c * SL::TGW, Re, pe, r, pe_err, re_err, &lg);
-        if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
-        float col[L][ROWS];
+    constexpr int ROWS = SL::ROWS;
+    float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS], pe_err, re_err, M[9], Nb[9];
+    PoseLog lg;
+    chain_fk<C, L, true>(rb, c, q, om, pj, Re, pe);
+    ee_residual<KIND>(P, S, SL::TG + c * SL::TGW, Re, pe, r, pe_err, re_err, &lg);
+    if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
 #pragma unroll
-        for (int i = 0; i < L; ++i) {
-            float lev[3] = {pe[0] - pj[i][0], pe[1] - pj[i][1], pe[2] - pj[i][2]}, v[3];
-            cross(om[i], lev, v);
-            if constexpr (KIND == PK_EE_POSE) {
+    for (int u = 0; u < ROWS; ++u) S[SL::RES + c * ROWS + u] = r[u];
 #pragma unroll
-                for (int u = 0; u < 3; ++u) {
-                    float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
-                    float nw = Nb[3 * u] * om[i][0] + Nb[3 * u + 1] * om[i][1] + Nb[3 * u + 2] * om[i][2];
-                    float mw = M[3 * u] * om[i][0] + M[3 * u + 1] * om[i][1] + M[3 * u + 2] * om[i][2];
-                    col[i][u] = P.w_pos * (mv + nw);
-                    col[i][3 + u] = P.w_rot * mw;
-                }
-            } else {
+    for (int i = 0; i < L; ++i) {
+        float lev[3] = {pe[0] - pj[i][0], pe[1] - pj[i][1], pe[2] - pj[i][2]}, v[3];
+        cross(om[i], lev, v);
+        const int base = SL::COL + (c * L + i) * ROWS;
+        if constexpr (KIND == PK_EE_POSE) {
 #pragma unroll
-                for (int u = 0; u < 3; ++u) col[i][u] = P.w_pos * v[u];
+            for (int u = 0; u < 3; ++u) {
+                float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
+                float nw = Nb[3 * u] * om[i][0] + Nb[3 * u + 1] * om[i][1] + Nb[3 * u + 2] * om[i][2];
+                float mw = M[3 * u] * om[i][0] + M[3 * u + 1] * om[i][1] + M[3 * u + 2] * om[i][2];
+                S[base + u] = P.w_pos * (mv + nw);
+                S[base + 3 + u] = P.w_rot * mw;
             }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) S[base + u] = P.w_pos * v[u];
         }
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            const int j = c * L + i;
-            const float over = q[j] - rb->j[j].hi, under = rb->j[j].lo - q[j];
-            const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
-            const float rr = P.w_rest * (q[j] - qr[j]);
-            const float dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
-#pragma unroll
-            for (int k = 0; k <= i; ++k) {
-                AT s = 0;
-#pragma unroll
-                for (int u = 0; u < ROWS; ++u) s += (AT)col[i][u] * (AT)col[k][u];
-                if (k == i) s += (AT)dl * (AT)dl + (AT)P.w_rest * (AT)P.w_rest;
-                sink.a(c, tri(i, k), s);
-            }
-            AT s = (AT)dl * (AT)rl + (AT)P.w_rest * (AT)rr;
-#pragma unroll
-            for (int u = 0; u < ROWS; ++u) s += (AT)col[i][u] * (AT)r[u];
-            sink.g(j, s);
-        }
+        const int j = c * L + i;
+        const float over = q[j] - rb->j[j].hi, under = rb->j[j].lo - q[j];
+        const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
+        const float rr = P.w_rest * (q[j] - qr[j]);
+        const float dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
+        S[SL::DG + j] = dl * dl + P.w_rest * P.w_rest;
+        S[SL::GX + j] = dl * rl + P.w_rest * rr;
     }
 }
 
-template <int C, int L, int KIND, typename AT, typename Sink>
-PK_DEV void eval_normal(const RobotC *__restrict__ rb, const SolveParams &P,
-                        const float *__restrict__ qr, const LaneLds &S, const float *q, Sink &sink)
+// Diagonal of J^T J (with the limit/rest terms) for joint j, from LDS.
+template <int C, int L, int KIND>
+PK_DEV float jtj_diag(const LaneLds &S, int j)
 {
+    using SL = Slots<C, L, KIND>;
+    float d = S[SL::DG + j];
 #pragma unroll
-    for (int c = 0; c < C; ++c) eval_normal_chain<C, L, KIND, AT>(rb, P, qr, S, q, c, sink);
+    for (int u = 0; u < SL::ROWS; ++u) {
+        const float v = S[SL::COL + j * SL::ROWS + u];
+        d += v * v;
+    }
+    return d;
 }
 
-template <int C, int L, int KIND>
-struct LdsSink {
-    LaneLds S;
-    PK_DEV void a(int c, int idx, float v) { S[Slots<C, L, KIND>::A + c * Star<C, L, KIND>::NA + idx] = v; }
-    PK_DEV void g(int j, float v) { S[Slots<C, L, KIND>::G + j] = v; }
-};
-
-// One chain's block in FP64 registers.
-template <int C, int L, int KIND>
-struct RegSink64 {
-    double A[Star<C, L, KIND>::NA];
-    double G[L];
-    PK_DEV void a(int, int idx, double v) { A[idx] = v; }
-    PK_DEV void g(int j, double v) { G[j % L] = v; }
-};
+// Packed block c of J^T J (+ diagonal terms) and J^T r in precision T, from
+// the FP32 columns in LDS.
+template <int C, int L, int KIND, typename T>
+PK_DEV void form_normal(const LaneLds &S, int c, T *A, T *g)
+{
+    using SL = Slots<C, L, KIND>;
+    constexpr int ROWS = SL::ROWS;
+    float col[L][ROWS], r[ROWS];
+#pragma unroll
+    for (int i = 0; i < L; ++i)
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) col[i][u] = S[SL::COL + (c * L + i) * ROWS + u];
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) r[u] = S[SL::RES + c * ROWS + u];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+#pragma unroll
+        for (int k = 0; k <= i; ++k) {
+            T s = 0;
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) s += (T)col[i][u] * (T)col[k][u];
+            if (k == i) s += (T)S[SL::DG + c * L + i];
+            A[tri(i, k)] = s;
+        }
+        T s = (T)S[SL::GX + c * L + i];
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) s += (T)col[i][u] * (T)r[u];
+        g[i] = s;
+    }
+}
 
 // Damped Cholesky of one packed block: Lf = chol(A + lam diag(max(A_ii, floor))).
 // Lf may alias A (in-place).  The diagonal slots of Lf hold 1 / L_ii.  Returns false if a pivot is not
@@ -268,22 +283,19 @@ PK_DEV void chol_solve_neg(const T *Lf, const T *g, T *x)
     }
 }
 
-// FP64 re-solve: J (FP32) is formed again at q, J^T J and J^T r are
-// accumulated, damped and factored in FP64.  False if FP64 also fails.
+// FP64 re-solve: J^T J and J^T r are formed again from the FP32 Jacobian in
+// LDS, damped and factored in FP64, one chain at a time.  False if FP64 also
+// fails.
 template <int C, int L, int KIND>
-PK_DEV bool step_fp64(const RobotC *__restrict__ rb, const SolveParams &P,
-                      const float *__restrict__ qr, const LaneLds &S, const float *q, float lam,
-                      float *delta)
+PK_DEV bool step_fp64(const SolveParams &P, const LaneLds &S, float lam, float *delta)
 {
     bool ok = true;
-    // Blocks are independent: one chain at a time, factored in place.
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        RegSink64<C, L, KIND> sk;
-        eval_normal_chain<C, L, KIND, double>(rb, P, qr, S, q, c, sk);
-        double x[L];
-        ok &= chol_damped<L, double>(sk.A, (double)lam, (double)P.damping_floor, 0.0, sk.A);
-        chol_solve_neg<L, double>(sk.A, sk.G, x);
+        double A[Star<C, L, KIND>::NA], g[L], x[L];
+        form_normal<C, L, KIND, double>(S, c, A, g);
+        ok &= chol_damped<L, double>(A, (double)lam, (double)P.damping_floor, 0.0, A);
+        chol_solve_neg<L, double>(A, g, x);
 #pragma unroll
         for (int i = 0; i < L; ++i) delta[c * L + i] = (float)x[i];
     }
@@ -313,23 +325,26 @@ PK_DEV void write_trace(const SolveParams &P, int it, int64_t p, const float *q,
     }
 }
 
-template <int C, int L, int KIND>
-__global__ __launch_bounds__(BLOCK) void lm_lane_kernel(const RobotC *__restrict__ rb,
-                                                        const float *__restrict__ qr, SolveParams P)
+// One LM problem (active index i) on this lane.  With P.st_state the run is
+// resumable: it continues from the state a previous launch left in HBM and
+// stops after P.iter_budget iterations.
+template <int C, int L, int KIND, bool RESUMABLE>
+PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict__ qr,
+                         const SolveParams &P, const LaneLds &S, int64_t i)
 {
     using St = Star<C, L, KIND>;
     using SL = Slots<C, L, KIND>;
-    __shared__ float smem[SL::TOTAL * BLOCK];
-    const int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (p >= P.N) return;
+    const int64_t p = P.active ? (int64_t)P.active[i] : i;
     const int64_t N = P.N, T = P.T, t = p / P.K;
-    const LaneLds S{smem + threadIdx.x};
+    constexpr bool resumable = RESUMABLE;
+    const bool resume = RESUMABLE && P.resume;
 
     float q[St::N];
     bool finite = true;
+    const float *qsrc = resume ? P.joints : P.seeds;
 #pragma unroll
     for (int j = 0; j < St::N; ++j) {
-        q[j] = P.seeds[j * N + p];
+        q[j] = qsrc[j * N + p];
         finite &= isfinite(q[j]);
     }
     const int W = KIND == PK_EE_POSE ? 7 : 3;
@@ -366,57 +381,67 @@ __global__ __launch_bounds__(BLOCK) void lm_lane_kernel(const RobotC *__restrict
         if (P.accepts) P.accepts[p] = 0;
         if (P.status) P.status[p] = PK_NONFINITE;
         if (P.iters_to_tol) P.iters_to_tol[p] = -1;
+        if (resumable) P.st_state[p] = PK_ST_DONE;
         for (int it = 0; it < P.trace_iters; ++it) write_trace<C, L, KIND>(P, it, p, q, false);
         return;
     }
 
     float cost, pcost, perr[C], rerr[C];
     eval_cost<C, L, KIND>(rb, P, qr, S, q, cost, pcost, perr, rerr);
-    int iters = 0, accepts = 0, itt = -1, flags = 0;
-    if (meets_tol<C, L, KIND>(P, perr, rerr)) itt = 0;
-    bool done = P.early_exit && itt == 0, stalled = false, need_j = true;
-    float lam = P.lambda0;
-    LdsSink<C, L, KIND> sink{S};
+    int iters, accepts, itt, flags;
+    bool done, stalled;
+    float lam;
+    if (resume) {
+        const int st = P.st_state[p];
+        iters = P.iters[p];
+        accepts = P.accepts[p];
+        itt = P.iters_to_tol[p];
+        flags = st & 0xffff;
+        stalled = (st & PK_ST_STALLED) != 0;
+        done = (st & PK_ST_DONE) != 0;
+        lam = P.st_lambda[p];
+    } else {
+        iters = accepts = flags = 0;
+        itt = meets_tol<C, L, KIND>(P, perr, rerr) ? 0 : -1;
+        stalled = false;
+        done = P.early_exit && itt == 0;
+        lam = P.lambda0;
+    }
+    const int iter_end = resumable ? min(P.max_iters, iters + P.iter_budget) : P.max_iters;
+    bool need_j = true;
 
-    for (int it = 0; it < P.max_iters; ++it) {
+    while (!done && iters < iter_end) {
         // keep LDS-resident state out of registers across iterations
         __asm__ volatile("" ::: "memory");
-        if (done) {
-            write_trace<C, L, KIND>(P, it, p, q, false);
-            continue;
-        }
         if (need_j) {
-            // J^T J and J^T r at the current point (after an accept) -> LDS.
-            eval_normal<C, L, KIND, float>(rb, P, qr, S, q, sink);
+            // Jacobian at the current point (after an accept) -> LDS.
+#pragma unroll
+            for (int c = 0; c < C; ++c) eval_jacobian_chain<C, L, KIND>(rb, P, qr, S, q, c);
             need_j = false;
         }
-        // Damped normal equations, FP32 Cholesky with the pivot test.
+        // Damped normal equations, FP32 Cholesky with the pivot test against
+        // the largest damped diagonal.
         float dmax = 0.f;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int i = 0; i < L; ++i) {
-                const float a = S[SL::A + c * St::NA + tri(i, i)];
-                dmax = fmaxf(dmax, a + lam * fmaxf(a, P.damping_floor));
-            }
+        for (int j = 0; j < St::N; ++j) {
+            const float a = jtj_diag<C, L, KIND>(S, j);
+            dmax = fmaxf(dmax, a + lam * fmaxf(a, P.damping_floor));
+        }
         const float thresh = P.pivot_rel * dmax;
         float delta[St::N];
         bool ok = true;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             float Ac[St::NA], gc[L], x[L];
-#pragma unroll
-            for (int i = 0; i < St::NA; ++i) Ac[i] = S[SL::A + c * St::NA + i];
-#pragma unroll
-            for (int i = 0; i < L; ++i) gc[i] = S[SL::G + c * L + i];
+            form_normal<C, L, KIND, float>(S, c, Ac, gc);
             ok &= chol_damped<L, float>(Ac, lam, P.damping_floor, thresh, Ac);   // in place
             chol_solve_neg<L, float>(Ac, gc, x);
 #pragma unroll
-            for (int i = 0; i < L; ++i) delta[c * L + i] = x[i];
+            for (int ii = 0; ii < L; ++ii) delta[c * L + ii] = x[ii];
         }
         if (!ok) {
             flags |= PK_FLAG_FP64;
-            ok = step_fp64<C, L, KIND>(rb, P, qr, S, q, lam, delta);
+            ok = step_fp64<C, L, KIND>(P, S, lam, delta);
         }
         float ct = INFINITY, pct = 0.f, pe_t[C], re_t[C], qt[St::N];
         if (ok) {
@@ -450,8 +475,11 @@ __global__ __launch_bounds__(BLOCK) void lm_lane_kernel(const RobotC *__restrict
             }
             lam = fminf(lam * P.nu_up, P.lambda_max);
         }
-        write_trace<C, L, KIND>(P, it, p, q, acc);
+        write_trace<C, L, KIND>(P, iters - 1, p, q, acc);
     }
+    const bool finished = done || iters >= P.max_iters;
+    if (finished)
+        for (int it = iters; it < P.trace_iters; ++it) write_trace<C, L, KIND>(P, it, p, q, false);
 
     const bool conv = meets_tol<C, L, KIND>(P, perr, rerr);
 #pragma unroll
@@ -468,17 +496,87 @@ __global__ __launch_bounds__(BLOCK) void lm_lane_kernel(const RobotC *__restrict
     if (P.status)
         P.status[p] = (conv ? PK_CONVERGED : (stalled ? PK_STALLED : PK_MAX_ITERS)) | flags;
     if (P.iters_to_tol) P.iters_to_tol[p] = itt;
+    if (resumable) {
+        P.st_lambda[p] = lam;
+        P.st_state[p] = flags | (stalled ? PK_ST_STALLED : 0) | (finished ? PK_ST_DONE : 0);
+    }
+}
+
+// Next work item of this block: the block index for a plain grid, else an
+// atomic pop from the device queue (block = one wavefront).
+PK_DEV int64_t pop_item(int32_t *head)
+{
+    int v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(head, 1);
+    return (int64_t)__shfl(v, 0, 64);
+}
+
+// One 64-problem item per block; no state kept between launches.
+template <int C, int L, int KIND>
+__global__ __launch_bounds__(BLOCK) void lm_lane_kernel(const RobotC *__restrict__ rb,
+                                                        const float *__restrict__ qr, SolveParams P)
+{
+    using SL = Slots<C, L, KIND>;
+    __shared__ float smem[SL::TOTAL * BLOCK];
+    const LaneLds S{smem + threadIdx.x};
+    const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < nact) lane_problem<C, L, KIND, false>(rb, qr, P, S, i);
+}
+
+// Persistent variant: blocks pop 64-problem items from P.queue_head until
+// the active list is exhausted; problem state is resumable.
+template <int C, int L, int KIND>
+PK_DEV void persist_loop(const RobotC *__restrict__ rb, const float *__restrict__ qr,
+                         const SolveParams &P, float *smem)
+{
+    const LaneLds S{smem + threadIdx.x};
+    const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
+    const int64_t nitems = (nact + BLOCK - 1) / BLOCK;
+    int64_t item = pop_item(P.queue_head);
+    while (item < nitems) {
+        const int64_t i = item * BLOCK + threadIdx.x;
+        if (i < nact) lane_problem<C, L, KIND, true>(rb, qr, P, S, i);
+        item = pop_item(P.queue_head);
+    }
 }
 
 template <int C, int L, int KIND>
-hipError_t launch_star(const RobotC *rb, const SolveParams &P, hipStream_t s)
+__global__ __launch_bounds__(BLOCK) void lm_lane_persist_kernel(const RobotC *__restrict__ rb,
+                                                                const float *__restrict__ qr,
+                                                                SolveParams P)
+{
+    __shared__ float smem[Slots<C, L, KIND>::TOTAL * BLOCK];
+    persist_loop<C, L, KIND>(rb, qr, P, smem);
+}
+
+// Same, with the register budget of two wavefronts per SIMD (used where the
+// allocator otherwise overshoots 256 registers by a few).
+template <int C, int L, int KIND>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+void lm_lane_persist2_kernel(const RobotC *__restrict__ rb, const float *__restrict__ qr, SolveParams P)
+{
+    __shared__ float smem[Slots<C, L, KIND>::TOTAL * BLOCK];
+    persist_loop<C, L, KIND>(rb, qr, P, smem);
+}
+
+template <int C, int L, int KIND>
+hipError_t launch_star(const RobotC *rb, const SolveParams &P, int persist_blocks, hipStream_t s)
 {
     const int block = BLOCK;
-    const int64_t grid = (P.N + block - 1) / block;
+    int64_t grid = (P.N + block - 1) / block;
+    const bool persist = P.queue_head != nullptr;
+    if (persist && persist_blocks > 0 && persist_blocks < grid) grid = persist_blocks;
     // rest pose: caller's array, else the robot's mid-range table
     const float *qr = P.q_rest ? P.q_rest : rb->mid;
-    hipLaunchKernelGGL((lm_lane_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb, qr,
-                       P);
+    if (persist && C == 1)
+        hipLaunchKernelGGL((lm_lane_persist2_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb,
+                           qr, P);
+    else if (persist)
+        hipLaunchKernelGGL((lm_lane_persist_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb,
+                           qr, P);
+    else
+        hipLaunchKernelGGL((lm_lane_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb, qr, P);
     return hipGetLastError();
 }
 
@@ -491,13 +589,13 @@ bool lane_variant_available(int chains, int chain_len, int kind)
 }
 
 hipError_t launch_lm_lane(const RobotC *dev_robot, const RobotC &h, const SolveParams &P,
-                          hipStream_t s)
+                          hipStream_t s, int persist_blocks)
 {
     const int kind = h.e[0].kind;
     if (h.chains == 1 && h.chain_len == 7 && kind == PK_EE_POSE)
-        return launch_star<1, 7, PK_EE_POSE>(dev_robot, P, s);
+        return launch_star<1, 7, PK_EE_POSE>(dev_robot, P, persist_blocks, s);
     if (h.chains == 4 && h.chain_len == 4 && kind == PK_EE_POSITION)
-        return launch_star<4, 4, PK_EE_POSITION>(dev_robot, P, s);
+        return launch_star<4, 4, PK_EE_POSITION>(dev_robot, P, persist_blocks, s);
     return hipErrorInvalidValue;
 }
 

@@ -278,15 +278,18 @@ PK_DEV bool damped_solve(const RobotC *__restrict__ rb, const SolveParams &P, co
     return ok;
 }
 
+// One LM problem (active index wi) on this wavefront; resumable like the
+// per-lane kernel (state in HBM, at most P.iter_budget iterations per launch).
 template <int NMAX, int MMAX>
-__global__ __launch_bounds__(64) void lm_wave_kernel(const RobotC *__restrict__ rb, SolveParams P)
+PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, double *lds_raw,
+                         int64_t wi)
 {
-    __shared__ double lds_raw[NMAX * (NMAX + 1)];
     const int lane = threadIdx.x;
-    const int64_t p = blockIdx.x;
+    const int64_t p = P.active ? (int64_t)P.active[wi] : wi;
     const int64_t N = P.N, T = P.T, t = p / P.K;
     const int n = rb->n, m = rb->m, max_depth = rb->max_depth;
     const bool isj = lane < n, ise = lane < m;
+    const bool resumable = P.st_state != nullptr, resume = resumable && P.resume;
 
     LaneConst C;
     const int jl = isj ? lane : 0, el = ise ? lane : 0;
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(64) void lm_wave_kernel(const RobotC *__restrict__ 
     bool fin = true;
     float q = 0.f;
     if (isj) {
-        q = P.seeds[(int64_t)lane * N + p];
+        q = (resume ? P.joints : P.seeds)[(int64_t)lane * N + p];
         fin = isfinite(q);
     }
     if (ise) {
@@ -341,6 +344,7 @@ __global__ __launch_bounds__(64) void lm_wave_kernel(const RobotC *__restrict__ 
             if (P.accepts) P.accepts[p] = 0;
             if (P.status) P.status[p] = PK_NONFINITE;
             if (P.iters_to_tol) P.iters_to_tol[p] = -1;
+            if (resumable) P.st_state[p] = PK_ST_DONE;
             for (int it = 0; it < P.trace_iters; ++it) P.trace_acc[(int64_t)it * N + p] = 0;
         }
         return;
@@ -348,10 +352,27 @@ __global__ __launch_bounds__(64) void lm_wave_kernel(const RobotC *__restrict__ 
 
     Eval<MMAX> E, Et;
     evaluate<MMAX>(rb, P, C, lane, n, m, max_depth, q, E);
-    int iters = 0, accepts = 0, itt = E.meets ? 0 : -1, flags = 0;
-    bool done = P.early_exit && itt == 0, stalled = false;
-    float lam = P.lambda0;
-    for (int it = 0; it < P.max_iters && !done; ++it) {
+    int iters, accepts, itt, flags;
+    bool done, stalled;
+    float lam;
+    if (resume) {
+        const int st = P.st_state[p];
+        iters = P.iters[p];
+        accepts = P.accepts[p];
+        itt = P.iters_to_tol[p];
+        flags = st & 0xffff;
+        stalled = (st & PK_ST_STALLED) != 0;
+        done = (st & PK_ST_DONE) != 0;
+        lam = P.st_lambda[p];
+    } else {
+        iters = accepts = flags = 0;
+        itt = E.meets ? 0 : -1;
+        stalled = false;
+        done = P.early_exit && itt == 0;
+        lam = P.lambda0;
+    }
+    const int iter_end = resumable ? min(P.max_iters, iters + P.iter_budget) : P.max_iters;
+    while (!done && iters < iter_end) {
         float delta;
         bool ok = damped_solve<NMAX, MMAX, float>(rb, P, E, lane, n, m, lam, P.pivot_rel,
                                                   (float *)lds_raw, delta);
@@ -383,15 +404,17 @@ __global__ __launch_bounds__(64) void lm_wave_kernel(const RobotC *__restrict__ 
             }
             lam = fminf(lam * P.nu_up, P.lambda_max);
         }
-        if (it < P.trace_iters) {
-            if (isj) P.trace_q[((int64_t)it * n + lane) * N + p] = q;
-            if (lane == 0) P.trace_acc[(int64_t)it * N + p] = acc ? 1 : 0;
+        if (iters - 1 < P.trace_iters) {
+            if (isj) P.trace_q[((int64_t)(iters - 1) * n + lane) * N + p] = q;
+            if (lane == 0) P.trace_acc[(int64_t)(iters - 1) * N + p] = acc ? 1 : 0;
         }
     }
-    for (int it = iters; it < P.trace_iters; ++it) {
-        if (isj) P.trace_q[((int64_t)it * n + lane) * N + p] = q;
-        if (lane == 0) P.trace_acc[(int64_t)it * N + p] = 0;
-    }
+    const bool finished = done || iters >= P.max_iters;
+    if (finished)
+        for (int it = iters; it < P.trace_iters; ++it) {
+            if (isj) P.trace_q[((int64_t)it * n + lane) * N + p] = q;
+            if (lane == 0) P.trace_acc[(int64_t)it * N + p] = 0;
+        }
     if (isj) P.joints[(int64_t)lane * N + p] = q;
     if (ise) {
         if (P.pos_err) P.pos_err[(int64_t)lane * N + p] = E.perr;
@@ -405,13 +428,40 @@ __global__ __launch_bounds__(64) void lm_wave_kernel(const RobotC *__restrict__ 
         if (P.status)
             P.status[p] = (E.meets ? PK_CONVERGED : (stalled ? PK_STALLED : PK_MAX_ITERS)) | flags;
         if (P.iters_to_tol) P.iters_to_tol[p] = itt;
+        if (resumable) {
+            P.st_lambda[p] = lam;
+            P.st_state[p] = flags | (stalled ? PK_ST_STALLED : 0) | (finished ? PK_ST_DONE : 0);
+        }
+    }
+}
+
+PK_DEV int64_t pop_item_wave(int32_t *head)
+{
+    int v = 0;
+    if (threadIdx.x == 0) v = atomicAdd(head, 1);
+    return (int64_t)__shfl(v, 0, 64);
+}
+
+template <int NMAX, int MMAX>
+__global__ __launch_bounds__(64) void lm_wave_kernel(const RobotC *__restrict__ rb, SolveParams P)
+{
+    __shared__ double lds_raw[NMAX * (NMAX + 1)];
+    const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
+    int64_t wi = P.queue_head ? pop_item_wave(P.queue_head) : (int64_t)blockIdx.x;
+    while (wi < nact) {
+        wave_problem<NMAX, MMAX>(rb, P, lds_raw, wi);
+        if (!P.queue_head) break;
+        __syncthreads();
+        wi = pop_item_wave(P.queue_head);
     }
 }
 
 template <int NMAX, int MMAX>
-hipError_t launch_wave(const RobotC *rb, const SolveParams &P, hipStream_t s)
+hipError_t launch_wave(const RobotC *rb, const SolveParams &P, int persist_blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((lm_wave_kernel<NMAX, MMAX>), dim3((unsigned)P.N), dim3(64), 0, s, rb, P);
+    int64_t grid = P.N;
+    if (P.queue_head && persist_blocks > 0 && persist_blocks < grid) grid = persist_blocks;
+    hipLaunchKernelGGL((lm_wave_kernel<NMAX, MMAX>), dim3((unsigned)grid), dim3(64), 0, s, rb, P);
     return hipGetLastError();
 }
 

@@ -3,9 +3,9 @@
 
 namespace pk {
 
-hipError_t launch_lm_wave_40(const RobotC *rb, const SolveParams &P, hipStream_t s)
+hipError_t launch_lm_wave_40(const RobotC *rb, const SolveParams &P, int pb, hipStream_t s)
 {
-    return wave::launch_wave<40, 4>(rb, P, s);
+    return wave::launch_wave<40, 4>(rb, P, pb, s);
 }
 
 }  // namespace pk

@@ -1,0 +1,182 @@
+// Learned seeds + LM refinement with a random-seed LM fallback on the
+// targets the learned seeds did not solve.  Everything stays on the device:
+// the failed targets are compacted into an active list that the fallback LM
+// launch (sized for the worst case) reads, so the host never synchronises.
+#include <string.h>
+
+#include "pk_ctx.hpp"
+#include "pk_device.hpp"
+
+namespace pk {
+namespace {
+
+__global__ void fill_i32_kernel(int64_t count, int32_t v, int32_t *p)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+// Targets with no successful learned seed -> active problem list of the
+// fallback (fallback_K problems per target).
+__global__ void fallback_list_kernel(int64_t T, int Kf, const int32_t *__restrict__ success,
+                                     int32_t *count_t, int32_t *count_p, int32_t *active)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T || success[t]) return;
+    const int pos = atomicAdd(count_t, 1);
+    atomicAdd(count_p, Kf);
+    for (int k = 0; k < Kf; ++k) active[(int64_t)pos * Kf + k] = (int32_t)(t * Kf + k);
+}
+
+struct MergeArgs {
+    int64_t T;
+    int K, Kf, n;
+    const int32_t *best_a, *succ_a, *itt_a;
+    const float *joints_a;
+    const int32_t *status_b, *itt_b;
+    const float *cost_b, *pcost_b, *joints_b;
+    float *best_joints;
+    int32_t *success, *source, *itt;
+};
+
+__global__ void merge_kernel(MergeArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.T) return;
+    const int64_t NA = a.T * a.K, NB = a.T * a.Kf;
+    int src = -1, it = -1;
+    if (a.succ_a[t]) {
+        src = 0;
+        const int b = a.best_a[t];
+        for (int j = 0; j < a.n; ++j) a.best_joints[(int64_t)j * a.T + t] = a.joints_a[(int64_t)j * NA + t * a.K + b];
+        for (int k = 0; k < a.K; ++k) {
+            const int v = a.itt_a[t * a.K + k];
+            if (v >= 0 && (it < 0 || v < it)) it = v;
+        }
+    } else if (a.Kf > 0) {
+        bool any;
+        const int b = best_of_k_pick(a.status_b, a.cost_b, a.pcost_b, t * a.Kf, a.Kf, any);
+        for (int j = 0; j < a.n; ++j) a.best_joints[(int64_t)j * a.T + t] = a.joints_b[(int64_t)j * NB + t * a.Kf + b];
+        if (any) {
+            src = 1;
+            for (int k = 0; k < a.Kf; ++k) {
+                const int v = a.itt_b[t * a.Kf + k];
+                if (v >= 0 && (it < 0 || v < it)) it = v;
+            }
+        }
+    } else {
+        const int b = a.best_a[t];
+        for (int j = 0; j < a.n; ++j) a.best_joints[(int64_t)j * a.T + t] = a.joints_a[(int64_t)j * NA + t * a.K + b];
+    }
+    if (a.success) a.success[t] = src >= 0 ? 1 : 0;
+    if (a.source) a.source[t] = src;
+    if (a.itt) a.itt[t] = it;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+}  // namespace pk
+
+using namespace pk;
+
+extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, const float *targets,
+                                  const pk_cost_weights *w, const pk_seeded_options *o,
+                                  const pk_seeded_outputs *out, void *stream)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_ik_solve_seeded: ctx is NULL");
+    RobotEntry *rb = robot_of(ctx, robot_id);
+    if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_ik_solve_seeded: unknown robot %d", robot_id);
+    if (!w || !o || !out) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: NULL argument");
+    if (T < 0) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: T < 0");
+    if (T == 0) return PK_OK;
+    if (!targets || !out->best_joints) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: NULL targets/best_joints");
+    if (o->fallback_K < 0 || (o->fallback_K > 0 && !o->fallback_seeds))
+        return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: fallback seeds missing");
+    hipStream_t s = (hipStream_t)stream;
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    SolveParams PA, PB;
+    int va = 0, vb = 0;
+    int rc = prepare_solve(ctx, *rb, w, &o->refine, PA, va);
+    if (rc) return rc;
+    rc = prepare_solve(ctx, *rb, w, &o->fallback, PB, vb);
+    if (rc) return rc;
+    // Seeds from the network (also validates the seeder / robot pairing).
+    int32_t K = 0, srobot = -1;
+    {
+        // probe K and robot without launching
+        rc = seeder_infer_into(ctx, o->seeder_id, targets, 0, nullptr, s, &K, &srobot);
+        if (rc) return rc;
+    }
+    if (srobot != robot_id) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: seeder belongs to robot %d", srobot);
+    const int n = rb->host.n, Kf = o->fallback_K;
+    const int64_t NA = T * K, NB = T * Kf;
+    if (NA >= (int64_t)1 << 31 || NB >= (int64_t)1 << 31)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve_seeded: too many problems");
+    // Workspace layout (4-byte words).
+    const size_t words = (size_t)NA * (2 * n + 5) + 2 * T + 8 + (size_t)NB * (n + 6);
+    if (words * 4 > ctx->ws2_bytes) {
+        if (ctx->ws2) (void)hipFree(ctx->ws2);
+        ctx->ws2 = nullptr;
+        ctx->ws2_bytes = 0;
+        if (hipMalloc(&ctx->ws2, words * 4) != hipSuccess)
+            return fail(ctx, PK_ENOMEM, "pk_ik_solve_seeded: workspace of %zu bytes", words * 4);
+        ctx->ws2_bytes = words * 4;
+    }
+    float *f = (float *)ctx->ws2;
+    float *seeds_a = f;                 f += (size_t)NA * n;
+    float *joints_a = f;                f += (size_t)NA * n;
+    float *cost_a = f;                  f += NA;
+    float *pcost_a = f;                 f += NA;
+    int32_t *status_a = (int32_t *)f;   f += NA;
+    int32_t *itt_a = (int32_t *)f;      f += NA;
+    int32_t *spare_a = (int32_t *)f;    f += NA;
+    int32_t *best_a = (int32_t *)f;     f += T;
+    int32_t *succ_a = (int32_t *)f;     f += T;
+    int32_t *counters = (int32_t *)f;   f += 8;
+    float *joints_b = f;                f += (size_t)NB * n;
+    float *cost_b = f;                  f += NB;
+    float *pcost_b = f;                 f += NB;
+    int32_t *status_b = (int32_t *)f;   f += NB;
+    int32_t *itt_b = (int32_t *)f;      f += NB;
+    int32_t *active = (int32_t *)f;     f += NB;
+    (void)spare_a;
+
+    rc = seeder_infer_into(ctx, o->seeder_id, targets, T, seeds_a, s, nullptr, nullptr);
+    if (rc) return rc;
+    // Pass A: LM from the learned seeds.
+    PA.K = K; PA.N = NA; PA.T = T;
+    PA.targets = targets; PA.seeds = seeds_a;
+    PA.joints = joints_a; PA.cost = cost_a; PA.pose_cost = pcost_a; PA.status = status_a;
+    PA.iters = out->refine_iters; PA.accepts = out->refine_accepts; PA.iters_to_tol = itt_a;
+    PK_HIP(ctx, launch_lm(*rb, PA, va, s));
+    PK_HIP(ctx, launch_best_of_k(PA, n, best_a, nullptr, succ_a, s));
+    // Pass B: random seeds on the failed targets only.
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, (int64_t)8, 0, counters);
+    if (Kf > 0) {
+        if (out->fallback_iters)
+            hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(NB, 256)), dim3(256), 0, s, NB, 0, out->fallback_iters);
+        if (out->fallback_accepts)
+            hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(NB, 256)), dim3(256), 0, s, NB, 0, out->fallback_accepts);
+        hipLaunchKernelGGL(fallback_list_kernel, dim3(nblk(T, 256)), dim3(256), 0, s, T, Kf, succ_a,
+                           counters, counters + 1, active);
+        PK_HIP(ctx, hipGetLastError());
+        PB.K = Kf; PB.N = NB; PB.T = T;
+        PB.targets = targets; PB.seeds = o->fallback_seeds;
+        PB.joints = joints_b; PB.cost = cost_b; PB.pose_cost = pcost_b; PB.status = status_b;
+        PB.iters = out->fallback_iters; PB.accepts = out->fallback_accepts; PB.iters_to_tol = itt_b;
+        PB.active = active; PB.n_active = counters + 1;
+        PK_HIP(ctx, launch_lm(*rb, PB, vb, s));
+    }
+    MergeArgs m;
+    m.T = T; m.K = K; m.Kf = Kf; m.n = n;
+    m.best_a = best_a; m.succ_a = succ_a; m.itt_a = itt_a; m.joints_a = joints_a;
+    m.status_b = status_b; m.itt_b = itt_b; m.cost_b = cost_b; m.pcost_b = pcost_b; m.joints_b = joints_b;
+    m.best_joints = out->best_joints; m.success = out->target_success; m.source = out->source;
+    m.itt = out->iters_to_tol;
+    hipLaunchKernelGGL(merge_kernel, dim3(nblk(T, 256)), dim3(256), 0, s, m);
+    PK_HIP(ctx, hipGetLastError());
+    if (out->n_fallback)
+        PK_HIP(ctx, hipMemcpyAsync(out->n_fallback, counters, 4, hipMemcpyDeviceToDevice, s));
+    return PK_OK;
+}

@@ -109,6 +109,64 @@ bool finite_all(const double *v, int n)
 
 }  // namespace
 
+RobotEntry *pk::robot_of(pk_ctx *ctx, int32_t id)
+{
+    if (id < 0 || id >= (int)ctx->robots.size()) return nullptr;
+    return &ctx->robots[id];
+}
+
+static void weights_into(const pk_cost_weights *w, SolveParams &P)
+{
+    P.w_pos = w->w_pos;
+    P.w_rot = w->w_rot;
+    P.w_limit = w->w_limit;
+    P.w_rest = w->w_rest;
+    P.q_rest = w->q_rest;
+}
+
+static bool finite_w(const pk_cost_weights *w)
+{
+    return isfinite(w->w_pos) && isfinite(w->w_rot) && isfinite(w->w_limit) && isfinite(w->w_rest);
+}
+
+
+int pk::prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *w,
+                      const pk_lm_options *o, SolveParams &P, int &variant)
+{
+    if (o->max_iters < 0) return fail(ctx, PK_EINVAL, "LM options: max_iters < 0");
+    if (!(o->lambda0 > 0) || !(o->nu_up > 1) || !(o->nu_down > 1) || !(o->lambda_min > 0) ||
+        !(o->lambda_max >= o->lambda_min) || !(o->damping_floor > 0) || !(o->pivot_rel >= 0) ||
+        !(o->tol_pos >= 0) || !(o->tol_rot >= 0))
+        return fail(ctx, PK_EINVAL, "LM options: invalid value");
+    if (!finite_w(w)) return fail(ctx, PK_EINVAL, "cost weights: non-finite value");
+    const RobotC &H = rb.host;
+    variant = o->variant;
+    const bool lane_ok = H.chains > 0 && lane_variant_available(H.chains, H.chain_len, H.e[0].kind);
+    const bool wave_ok = wave_variant_available(H.n);
+    if (variant == PK_VARIANT_AUTO) variant = lane_ok ? PK_VARIANT_LANE : PK_VARIANT_WAVE;
+    if (variant == PK_VARIANT_LANE && !lane_ok)
+        return fail(ctx, PK_EUNSUPPORTED, "no per-lane kernel for this robot shape");
+    if (variant == PK_VARIANT_WAVE && !wave_ok)
+        return fail(ctx, PK_EUNSUPPORTED, "no wave kernel for n=%d", H.n);
+    if (variant != PK_VARIANT_LANE && variant != PK_VARIANT_WAVE)
+        return fail(ctx, PK_EINVAL, "unknown variant %d", variant);
+    memset(&P, 0, sizeof P);
+    weights_into(w, P);
+    P.lambda0 = o->lambda0; P.nu_up = o->nu_up; P.nu_down = o->nu_down;
+    P.lambda_min = o->lambda_min; P.lambda_max = o->lambda_max;
+    P.tol_pos = o->tol_pos; P.tol_rot = o->tol_rot;
+    P.damping_floor = o->damping_floor; P.pivot_rel = o->pivot_rel;
+    P.max_iters = o->max_iters; P.early_exit = o->early_exit ? 1 : 0;
+    return PK_OK;
+}
+
+hipError_t pk::launch_lm(const RobotEntry &rb, const SolveParams &P, int variant, hipStream_t s,
+                         int persist_blocks)
+{
+    return variant == PK_VARIANT_LANE ? launch_lm_lane(rb.dev, rb.host, P, s, persist_blocks)
+                                      : launch_lm_wave(rb.dev, rb.host, P, s, persist_blocks);
+}
+
 // ------------------------------------------------------------------- API
 
 extern "C" {
@@ -137,7 +195,9 @@ int pk_destroy(pk_ctx *ctx)
     for (auto &r : ctx->robots)
         if (r.dev) (void)hipFree(r.dev);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->ws2) (void)hipFree(ctx->ws2);
     for (auto *sd : ctx->seeders) seeder_free(sd);
+    sched_free(ctx);
     delete ctx;
     return PK_OK;
 }
@@ -269,11 +329,6 @@ int pk_robot_info(pk_ctx *ctx, int32_t id, int32_t *n, int32_t *m, int32_t *tf, 
     return PK_OK;
 }
 
-RobotEntry *pk::robot_of(pk_ctx *ctx, int32_t id)
-{
-    if (id < 0 || id >= (int)ctx->robots.size()) return nullptr;
-    return &ctx->robots[id];
-}
 
 int pk_fk(pk_ctx *ctx, int32_t id, int64_t N, const float *q, float *ee_pose, float *frames,
           void *stream)
@@ -288,20 +343,6 @@ int pk_fk(pk_ctx *ctx, int32_t id, int64_t N, const float *q, float *ee_pose, fl
     PK_HIP(ctx, hipSetDevice(ctx->device));
     PK_HIP(ctx, launch_fk(r->dev, N, q, ee_pose, frames, (hipStream_t)stream));
     return PK_OK;
-}
-
-static void weights_into(const pk_cost_weights *w, SolveParams &P)
-{
-    P.w_pos = w->w_pos;
-    P.w_rot = w->w_rot;
-    P.w_limit = w->w_limit;
-    P.w_rest = w->w_rest;
-    P.q_rest = w->q_rest;
-}
-
-static bool finite_w(const pk_cost_weights *w)
-{
-    return isfinite(w->w_pos) && isfinite(w->w_rot) && isfinite(w->w_limit) && isfinite(w->w_rest);
 }
 
 int pk_residual_jacobian(pk_ctx *ctx, int32_t id, int64_t N, int32_t K, const float *targets,
@@ -345,27 +386,15 @@ int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_
     if (N == 0) return PK_OK;
     if (N >= (int64_t)1 << 31) return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve: %lld problems, limit 2^31 - 1", (long long)N);
     if (!pr->targets || !pr->seeds || !out->joints) return fail(ctx, PK_EINVAL, "pk_ik_solve: NULL targets/seeds/joints");
-    if (o->max_iters < 0) return fail(ctx, PK_EINVAL, "pk_ik_solve: max_iters < 0");
-    if (!(o->lambda0 > 0) || !(o->nu_up > 1) || !(o->nu_down > 1) || !(o->lambda_min > 0) ||
-        !(o->lambda_max >= o->lambda_min) || !(o->damping_floor > 0) || !(o->pivot_rel >= 0) ||
-        !(o->tol_pos >= 0) || !(o->tol_rot >= 0))
-        return fail(ctx, PK_EINVAL, "pk_ik_solve: invalid LM option");
-    if (!finite_w(w)) return fail(ctx, PK_EINVAL, "pk_ik_solve: non-finite weight");
     if (out->trace_iters < 0 || out->trace_iters > 64 ||
         (out->trace_iters > 0 && (!out->trace_q || !out->trace_accept)))
         return fail(ctx, PK_EINVAL, "pk_ik_solve: bad trace request");
 
+    SolveParams P;
+    int variant = 0;
+    int rc0 = prepare_solve(ctx, *rb, w, o, P, variant);
+    if (rc0) return rc0;
     const RobotC &H = rb->host;
-    int variant = o->variant;
-    const bool lane_ok = H.chains > 0 && lane_variant_available(H.chains, H.chain_len, H.e[0].kind);
-    const bool wave_ok = wave_variant_available(H.n);
-    if (variant == PK_VARIANT_AUTO) variant = lane_ok ? PK_VARIANT_LANE : PK_VARIANT_WAVE;
-    if (variant == PK_VARIANT_LANE && !lane_ok)
-        return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve: no per-lane kernel for this robot shape");
-    if (variant == PK_VARIANT_WAVE && !wave_ok)
-        return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve: no wave kernel for n=%d", H.n);
-    if (variant != PK_VARIANT_LANE && variant != PK_VARIANT_WAVE)
-        return fail(ctx, PK_EINVAL, "pk_ik_solve: unknown variant %d", variant);
 
     PK_HIP(ctx, hipSetDevice(ctx->device));
     const bool want_best = out->best_index || out->best_joints || out->target_success;
@@ -376,14 +405,6 @@ int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_
     if (rc) return rc;
     float *ws_f = (float *)ctx->ws;
 
-    SolveParams P;
-    memset(&P, 0, sizeof P);
-    weights_into(w, P);
-    P.lambda0 = o->lambda0; P.nu_up = o->nu_up; P.nu_down = o->nu_down;
-    P.lambda_min = o->lambda_min; P.lambda_max = o->lambda_max;
-    P.tol_pos = o->tol_pos; P.tol_rot = o->tol_rot;
-    P.damping_floor = o->damping_floor; P.pivot_rel = o->pivot_rel;
-    P.max_iters = o->max_iters; P.early_exit = o->early_exit ? 1 : 0;
     P.K = pr->K; P.N = N; P.T = pr->n_targets;
     P.targets = pr->targets; P.seeds = pr->seeds;
     P.joints = out->joints; P.pos_err = out->pos_err; P.rot_err = out->rot_err;
@@ -394,10 +415,7 @@ int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_
     P.trace_iters = out->trace_iters; P.trace_q = out->trace_q; P.trace_acc = out->trace_accept;
 
     hipStream_t s = (hipStream_t)stream;
-    if (variant == PK_VARIANT_LANE)
-        PK_HIP(ctx, launch_lm_lane(rb->dev, H, P, s));
-    else
-        PK_HIP(ctx, launch_lm_wave(rb->dev, H, P, s));
+    PK_HIP(ctx, launch_lm(*rb, P, variant, s));
     if (want_best)
         PK_HIP(ctx, launch_best_of_k(P, H.n, out->best_index, out->best_joints, out->target_success, s));
     return PK_OK;

@@ -25,6 +25,8 @@ struct pk_ctx {
     std::vector<pk::SeederState *> seeders;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    void *ws2 = nullptr;      // learned-seed pipeline workspace
+    size_t ws2_bytes = 0;
 };
 
 namespace pk {
@@ -33,6 +35,16 @@ namespace pk {
 // returns code.
 int fail(pk_ctx *ctx, int code, const char *fmt, ...);
 RobotEntry *robot_of(pk_ctx *ctx, int32_t id);
+// Validates LM options and weights; fills P (everything but the buffers) and
+// resolves the kernel variant.  Returns PK_OK or an error (message set).
+int prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *w,
+                  const pk_lm_options *o, SolveParams &P, int &variant);
+hipError_t launch_lm(const RobotEntry &rb, const SolveParams &P, int variant, hipStream_t s,
+                     int persist_blocks = 0);
+void sched_free(pk_ctx *ctx);
+// Seeder inference into seeds [n][T*K] (device), asynchronous.
+int seeder_infer_into(pk_ctx *ctx, int32_t seeder_id, const float *targets, int64_t T,
+                      float *seeds, hipStream_t s, int32_t *K_out, int32_t *robot_out);
 
 }  // namespace pk
 

@@ -139,21 +139,8 @@ __global__ __launch_bounds__(256) void best_of_k_kernel(int64_t T, int32_t K, in
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= T) return;
-    int b = -1;
-    bool any = false;
-    for (int k = 0; k < K; ++k) {
-        const int64_t p = t * K + k;
-        if ((status[p] & 0xff) == PK_CONVERGED) {
-            if (!any || cost[p] < cost[t * K + b]) b = k;
-            any = true;
-        }
-    }
-    if (!any) {
-        for (int k = 0; k < K; ++k) {
-            const int64_t p = t * K + k;
-            if (b < 0 || pcost[p] < pcost[t * K + b]) b = k;
-        }
-    }
+    bool any;
+    const int b = best_of_k_pick(status, cost, pcost, t * K, K, any);
     if (best_index) best_index[t] = b;
     if (success) success[t] = any ? 1 : 0;
     if (best_joints)

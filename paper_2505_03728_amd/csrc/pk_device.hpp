@@ -229,4 +229,26 @@ PK_DEV void jr_inv_blocks(const PoseLog &L, const float *Re, float *M, float *N)
     for (int i = 0; i < 9; ++i) N[i] = -NB[i];
 }
 
+// Best of K problems base .. base+K-1: the lowest total cost among those
+// that converged, else the lowest pose-only cost; ties to the lower index.
+PK_DEV int best_of_k_pick(const int32_t *status, const float *cost, const float *pcost, int64_t base,
+                          int K, bool &any)
+{
+    int b = -1;
+    any = false;
+    for (int k = 0; k < K; ++k) {
+        const int64_t p = base + k;
+        if ((status[p] & 0xff) == PK_CONVERGED) {
+            if (!any || cost[p] < cost[base + b]) b = k;
+            any = true;
+        }
+    }
+    if (!any)
+        for (int k = 0; k < K; ++k) {
+            const int64_t p = base + k;
+            if (b < 0 || pcost[p] < pcost[base + b]) b = k;
+        }
+    return b;
+}
+
 }  // namespace pk

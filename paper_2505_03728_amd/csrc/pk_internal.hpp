@@ -55,16 +55,37 @@ struct SolveParams {
     int32_t *iters, *accepts, *status, *iters_to_tol;
     float *trace_q;
     int32_t *trace_acc;
+    // Optional active list: thread/wave i < *n_active (or N) solves problem
+    // active[i] (or i).  Lets a launch sized for N run a device-chosen subset.
+    const int32_t *active;
+    const int32_t *n_active;
+    // Resumable execution (persistent scheduler).  With st_state set, a
+    // problem's LM state persists in HBM between launches: q in `joints`,
+    // lambda in st_lambda, counters in iters/accepts/iters_to_tol and the
+    // done/stalled/FP64 bits in st_state.  resume = 0 starts from the seeds;
+    // each launch runs at most iter_budget more iterations.
+    float *st_lambda;
+    int32_t *st_state;
+    int32_t resume;
+    int32_t iter_budget;
+    // Persistent launch: blocks pop work items (64 problems for the per-lane
+    // kernel, 1 for the wave kernel) from *queue_head until none are left.
+    int32_t *queue_head;
 };
+
+// st_state bits
+#define PK_ST_DONE 0x10000
+#define PK_ST_STALLED 0x20000
 
 // Launchers (defined next to their kernels).  Return hipSuccess or the
 // launch error.
 bool lane_variant_available(int chains, int chain_len, int kind);
+// persist_blocks: grid size when P.queue_head is set (0 = one block per item).
 hipError_t launch_lm_lane(const RobotC *dev_robot, const RobotC &host_robot,
-                          const SolveParams &P, hipStream_t s);
+                          const SolveParams &P, hipStream_t s, int persist_blocks = 0);
 bool wave_variant_available(int n);
 hipError_t launch_lm_wave(const RobotC *dev_robot, const RobotC &host_robot,
-                          const SolveParams &P, hipStream_t s);
+                          const SolveParams &P, hipStream_t s, int persist_blocks = 0);
 hipError_t launch_best_of_k(const SolveParams &P, int n, int32_t *best_index,
                             float *best_joints, int32_t *success, hipStream_t s);
 hipError_t launch_fk(const RobotC *dev_robot, int64_t N, const float *q, float *ee_pose,

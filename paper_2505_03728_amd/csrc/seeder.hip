@@ -335,6 +335,26 @@ __global__ void seeds_kernel(int64_t T, int K, int n, int out_pad, const float *
         }
 }
 
+// Encoded inputs x [B][7] (and optionally joints q [B][n]) into the padded
+// BF16 input rows (rows >= B are zero).
+__global__ void load_rows_kernel(int64_t rows, int64_t B, int in_pad, int n, const float *__restrict__ x,
+                                 const float *__restrict__ q, __bf16 *X0, float *Q)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    for (int u = 0; u < in_pad; ++u) X0[i * in_pad + u] = (__bf16)(i < B && u < 7 ? x[i * 7 + u] : 0.f);
+    if (q && Q)
+        for (int j = 0; j < n; ++j) Q[i * n + j] = i < B ? q[i * n + j] : 0.f;
+}
+
+__global__ void store_out_kernel(int64_t B, int out_real, int out_pad, const float *__restrict__ Y,
+                                 float *y)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    for (int c = 0; c < out_real; ++c) y[i * out_real + c] = Y[i * out_pad + c];
+}
+
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace sd
@@ -605,29 +625,215 @@ int pk_seeder_get(pk_ctx *ctx, int32_t id, int32_t which, float *host_out, int64
     return PK_OK;
 }
 
-// Raw network output for encoded inputs x [B][7] (device) -> y [B][7K].
+}  // extern "C"
+
+namespace pk {
+namespace {
+
+// Loss + gradients for `rows` rows already in X0 / Q; loss_out (device) gets
+// the mean loss.  `B` is the number of real rows (the loss averages over B).
+hipError_t loss_and_grads(SeederState *s, int64_t rows, int64_t B, float *loss_log, float *loss_out,
+                          hipStream_t st)
+{
+    using namespace sd;
+    hipError_t e = forward(s, rows, true, st);
+    if (e != hipSuccess) return e;
+    const unsigned nb = blocks(rows, 256);
+    hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(256), 0, st, (int)B, s->n, s->K, s->out_pad, s->Y,
+                       s->Q, s->dY, s->dYb, s->part);
+    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(1), 0, st, (int)nb, (int)B, s->part, s->dstep,
+                       loss_log, loss_out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return backward(s, rows, st);
+}
+
+}  // namespace
+
+int seeder_infer_into(pk_ctx *ctx, int32_t id, const float *targets, int64_t T, float *seeds,
+                      hipStream_t st, int32_t *K_out, int32_t *robot_out)
+{
+    SeederState *s = seeder_of(ctx, id);
+    if (!s) return fail(ctx, PK_ENOTFOUND, "seeder: unknown seeder %d", id);
+    if (K_out) *K_out = s->K;
+    if (robot_out) *robot_out = s->robot_id;
+    if (T < 0 || (T > 0 && (!targets || !seeds))) return fail(ctx, PK_EINVAL, "seeder inference: bad arguments");
+    if (T == 0) return PK_OK;
+    const int64_t rows = (T + 127) / 128 * 128;
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    int rc = alloc_acts(ctx, s, rows);
+    if (rc) return rc;
+    RobotEntry *rb = robot_of(ctx, s->robot_id);
+    hipLaunchKernelGGL(sd::encode_kernel, dim3(sd::blocks(rows, 256)), dim3(256), 0, st, rows, T, targets, T,
+                       1.f / s->reach, s->in_pad, s->X0, (float *)nullptr);
+    PK_HIP(ctx, hipGetLastError());
+    PK_HIP(ctx, forward(s, rows, false, st));
+    hipLaunchKernelGGL(sd::seeds_kernel, dim3(sd::blocks(T, 256)), dim3(256), 0, st, T, s->K, s->n, s->out_pad,
+                       s->Y, rb->dev, seeds);
+    PK_HIP(ctx, hipGetLastError());
+    return PK_OK;
+}
+
+}  // namespace pk
+
+extern "C" {
+
+// Raw network output for encoded inputs x [B][7] (device) -> y [B][7K] (device).
 int pk_seeder_forward(pk_ctx *ctx, int32_t id, const float *x, int64_t B, float *y, void *stream)
 {
     if (!ctx) return fail(nullptr, PK_EINVAL, "pk_seeder_forward: ctx is NULL");
     SeederState *s = seeder_of(ctx, id);
     if (!s) return fail(ctx, PK_ENOTFOUND, "pk_seeder_forward: unknown seeder %d", id);
-    if (B <= 0 || !x || !y) return fail(ctx, PK_EINVAL, "pk_seeder_forward: bad arguments");
+    if (B < 0 || (B > 0 && (!x || !y))) return fail(ctx, PK_EINVAL, "pk_seeder_forward: bad arguments");
+    if (B == 0) return PK_OK;
     hipStream_t st = (hipStream_t)stream;
     const int64_t rows = (B + 127) / 128 * 128;
     PK_HIP(ctx, hipSetDevice(ctx->device));
     int rc = alloc_acts(ctx, s, rows);
     if (rc) return rc;
-    // x is already encoded: copy into the padded bf16 input via the planes path.
-    std::vector<void *> none;
-    float *planes;
-    PK_HIP(ctx, hipMallocAsync((void **)&planes, 7 * rows * 4, st));
-    (void)planes;
-    PK_HIP(ctx, hipFreeAsync(planes, st));
-    // x [B][7] -> X0: reuse encode with an identity layout (reach 1, quat as given).
-    hipLaunchKernelGGL(sd::fill_kernel, dim3(sd::blocks(rows * s->in_pad / 2, 256)), dim3(256), 0, st,
-                       rows * s->in_pad / 2, 0.f, (float *)s->X0);
+    hipLaunchKernelGGL(sd::load_rows_kernel, dim3(sd::blocks(rows, 256)), dim3(256), 0, st, rows, B,
+                       s->in_pad, s->n, x, nullptr, s->X0, nullptr);
     PK_HIP(ctx, hipGetLastError());
-    PK_HIP(ctx, hipMemcpy2DAsync(s->Q, 7 * 4, x, 7 * 4, 7 * 4, B, hipMemcpyDeviceToDevice, st));
+    PK_HIP(ctx, forward(s, rows, false, st));
+    hipLaunchKernelGGL(sd::store_out_kernel, dim3(sd::blocks(B, 256)), dim3(256), 0, st, B, s->out_real,
+                       s->out_pad, s->Y, y);
+    PK_HIP(ctx, hipGetLastError());
+    return PK_OK;
+}
+
+// Loss and parameter gradients for one batch x [B][7], q [B][n] (device);
+// B a multiple of 128.  The gradients stay in the seeder (pk_seeder_get(..., 1, ...)).
+int pk_seeder_grad(pk_ctx *ctx, int32_t id, const float *x, const float *q, int64_t B, float *loss,
+                   void *stream)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_seeder_grad: ctx is NULL");
+    SeederState *s = seeder_of(ctx, id);
+    if (!s) return fail(ctx, PK_ENOTFOUND, "pk_seeder_grad: unknown seeder %d", id);
+    if (B <= 0 || B % 128 || !x || !q) return fail(ctx, PK_EINVAL, "pk_seeder_grad: B must be a positive multiple of 128");
+    hipStream_t st = (hipStream_t)stream;
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    int rc = alloc_acts(ctx, s, B);
+    if (rc) return rc;
+    hipLaunchKernelGGL(sd::load_rows_kernel, dim3(sd::blocks(B, 256)), dim3(256), 0, st, B, B, s->in_pad,
+                       s->n, x, q, s->X0, s->Q);
+    PK_HIP(ctx, hipGetLastError());
+    PK_HIP(ctx, loss_and_grads(s, B, B, nullptr, loss, st));
+    return PK_OK;
+}
+
+// Train on q_train [n][S] (device): targets are FK(q) computed here; per
+// epoch the samples are visited in the order perm[e][0..S) (device, int32,
+// epochs x S) or in index order when perm is NULL; S / batch steps per epoch.
+// loss_log (device, optional) receives one mean loss per step.
+int pk_seeder_train(pk_ctx *ctx, int32_t id, const float *q_train, int64_t S, int32_t batch,
+                    int32_t epochs, float lr, const int32_t *perm, float *loss_log, void *stream)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_seeder_train: ctx is NULL");
+    SeederState *s = seeder_of(ctx, id);
+    if (!s) return fail(ctx, PK_ENOTFOUND, "pk_seeder_train: unknown seeder %d", id);
+    if (!q_train || S < batch || batch <= 0 || batch % 128 || epochs < 0 || !(lr > 0.f))
+        return fail(ctx, PK_EINVAL, "pk_seeder_train: bad arguments (S=%lld batch=%d epochs=%d)",
+                    (long long)S, batch, epochs);
+    if (S > INT32_MAX) return fail(ctx, PK_EUNSUPPORTED, "pk_seeder_train: S above 2^31");
+    hipStream_t st = (hipStream_t)stream;
+    RobotEntry *rb = robot_of(ctx, s->robot_id);
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    int rc = alloc_acts(ctx, s, batch);
+    if (rc) return rc;
+    // Inputs of every training sample: FK pose, encoded once.
+    float *pose = nullptr, *xall = nullptr;
+    if (hipMalloc(&pose, (size_t)S * 7 * 4) != hipSuccess || hipMalloc(&xall, (size_t)S * 7 * 4) != hipSuccess) {
+        if (pose) (void)hipFree(pose);
+        return fail(ctx, PK_ENOMEM, "pk_seeder_train: input buffers");
+    }
+    hipError_t e = launch_fk(rb->dev, S, q_train, pose, nullptr, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(sd::encode_kernel, dim3(sd::blocks(S, 256)), dim3(256), 0, st, S, S, pose, S,
+                           1.f / s->reach, s->in_pad, (__bf16 *)nullptr, xall);
+        e = hipGetLastError();
+    }
+    const int spe = (int)(S / batch);
+    const int steps = spe * epochs;
+    for (int t = 0; t < steps && e == hipSuccess; ++t) {
+        hipLaunchKernelGGL(sd::gather_kernel, dim3(sd::blocks(batch, 256)), dim3(256), 0, st, batch, S, s->n,
+                           s->in_pad, spe, s->dstep, perm, xall, q_train, s->X0, s->Q);
+        e = loss_and_grads(s, batch, batch, loss_log ? loss_log - s->host_step : nullptr, nullptr, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(sd::adam_kernel, dim3(sd::blocks(s->nparam, 256)), dim3(256), 0, st, s->nparam, lr,
+                           0.9f, 0.999f, 1e-8f, s->dstep, s->P, s->G, s->M, s->V, s->Pb);
+        hipLaunchKernelGGL(sd::tick_kernel, dim3(1), dim3(1), 0, st, s->dstep);
+        e = hipGetLastError();
+    }
+    hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFree(pose);
+    (void)hipFree(xall);
+    if (e != hipSuccess) return fail(ctx, PK_EHIP, "pk_seeder_train: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(ctx, PK_EHIP, "pk_seeder_train: %s", hipGetErrorString(e2));
+    s->host_step += steps;
+    return PK_OK;
+}
+
+// K seeds per target: targets planes [7][T] (device, pose EE layout) ->
+// seeds [n][T*K] (device), clamped to the joint limits.
+int pk_seeder_infer(pk_ctx *ctx, int32_t id, const float *targets, int64_t T, float *seeds, void *stream)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_seeder_infer: ctx is NULL");
+    return seeder_infer_into(ctx, id, targets, T, seeds, (hipStream_t)stream, nullptr, nullptr);
+}
+
+// Versioned binary checkpoint: magic, dims, step, then parameters and the two
+// Adam moments (FP32, padded layout).  Synchronous.
+int pk_seeder_save(pk_ctx *ctx, int32_t id, const char *path)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_seeder_save: ctx is NULL");
+    SeederState *s = seeder_of(ctx, id);
+    if (!s || !path) return fail(ctx, PK_EINVAL, "pk_seeder_save: bad arguments");
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    PK_HIP(ctx, hipDeviceSynchronize());
+    std::vector<float> buf(3 * s->nparam);
+    PK_HIP(ctx, hipMemcpy(buf.data(), s->P, s->nparam * 4, hipMemcpyDeviceToHost));
+    PK_HIP(ctx, hipMemcpy(buf.data() + s->nparam, s->M, s->nparam * 4, hipMemcpyDeviceToHost));
+    PK_HIP(ctx, hipMemcpy(buf.data() + 2 * s->nparam, s->V, s->nparam * 4, hipMemcpyDeviceToHost));
+    int step = 0;
+    PK_HIP(ctx, hipMemcpy(&step, s->dstep, 4, hipMemcpyDeviceToHost));
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(ctx, PK_EINVAL, "pk_seeder_save: cannot open %s", path);
+    const int32_t hdr[8] = {0x44534b50 /* "PKSD" */, 1, s->n, s->K, s->H, s->depth, step, 0};
+    const int64_t np = s->nparam;
+    bool ok = fwrite(hdr, sizeof hdr, 1, f) == 1 && fwrite(&np, 8, 1, f) == 1 &&
+              fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok &= fclose(f) == 0;
+    return ok ? PK_OK : fail(ctx, PK_EINVAL, "pk_seeder_save: write to %s failed", path);
+}
+
+int pk_seeder_load(pk_ctx *ctx, int32_t id, const char *path)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_seeder_load: ctx is NULL");
+    SeederState *s = seeder_of(ctx, id);
+    if (!s || !path) return fail(ctx, PK_EINVAL, "pk_seeder_load: bad arguments");
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(ctx, PK_EINVAL, "pk_seeder_load: cannot open %s", path);
+    int32_t hdr[8];
+    int64_t np = 0;
+    bool ok = fread(hdr, sizeof hdr, 1, f) == 1 && fread(&np, 8, 1, f) == 1;
+    if (!ok || hdr[0] != 0x44534b50 || hdr[1] != 1 || hdr[2] != s->n || hdr[3] != s->K || hdr[4] != s->H ||
+        hdr[5] != s->depth || np != s->nparam) {
+        fclose(f);
+        return fail(ctx, PK_EINVAL, "pk_seeder_load: %s does not match this seeder", path);
+    }
+    std::vector<float> buf(3 * np);
+    ok = fread(buf.data(), 4, buf.size(), f) == buf.size();
+    fclose(f);
+    if (!ok) return fail(ctx, PK_EINVAL, "pk_seeder_load: %s is truncated", path);
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    PK_HIP(ctx, hipMemcpy(s->P, buf.data(), np * 4, hipMemcpyHostToDevice));
+    PK_HIP(ctx, hipMemcpy(s->M, buf.data() + np, np * 4, hipMemcpyHostToDevice));
+    PK_HIP(ctx, hipMemcpy(s->V, buf.data() + 2 * np, np * 4, hipMemcpyHostToDevice));
+    PK_HIP(ctx, hipMemcpy(s->dstep, &hdr[6], 4, hipMemcpyHostToDevice));
+    s->host_step = hdr[6];
+    hipLaunchKernelGGL(sd::to_bf16_kernel, dim3(sd::blocks(np, 256)), dim3(256), 0, 0, np, s->P, s->Pb);
+    PK_HIP(ctx, hipGetLastError());
+    PK_HIP(ctx, hipDeviceSynchronize());
     return PK_OK;
 }
 

@@ -1,0 +1,202 @@
+"""GPU parity of the learned seeder's MFMA kernels against the FP64 MLP
+oracle in BF16-emulation mode (forward within 1e-3 relative, gradients
+within 2e-2 relative, Frobenius per tensor), Adam's update against its
+closed form on the GPU's own gradients, and the training/inference/
+checkpoint paths."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2505_03728_amd as pk
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def arm(ctx):
+    return ctx.upload(synth.arm7(0))
+
+
+def _inputs(B, seed):
+    tree = synth.arm7(0)
+    q = synth.uniform_configs(tree, B, seed)
+    tg = oracle.targets_from(tree, q)[:, 0, :]
+    reach = float(np.sum(np.linalg.norm(tree.offset, axis=1)) + np.linalg.norm(tree.ee_offset[0]))
+    x = mlp.encode_targets(tg[:, :3], tg[:, 3:], reach).astype(np.float32).astype(np.float64)
+    return x, q
+
+
+def _dev(a, dtype=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).to(DEV)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("hidden,depth,B", [(128, 2, 200), (512, 3, 300)])
+def test_forward_matches_bf16_oracle(ctx, arm, hidden, depth, B):
+    import paper_2505_03728_amd as pk
+    import torch
+    init = synth.mlp_init([7] + [hidden] * depth + [56], 21)
+    sd = pk.Seeder(ctx, arm, K=8, hidden=hidden, depth=depth, init=init)
+    x, _ = _inputs(B, 5)
+    y = sd.forward(_dev(x))
+    torch.cuda.synchronize()
+    yo, _ = mlp.forward(init, x, emulate_bf16=True)
+    rel = _rel(y.cpu().numpy(), yo)
+    print(f"forward h={hidden} d={depth}: rel err {rel:.2e}")
+    assert rel <= 1e-3
+    # parameters round-trip through the padded device layout
+    got = sd.get(0)
+    for (W, b), (Wg, bg) in zip(init, got):
+        np.testing.assert_array_equal(Wg, W.astype(np.float32))
+        np.testing.assert_array_equal(bg, b.astype(np.float32))
+
+
+@pytest.mark.parametrize("hidden,depth,B", [(128, 2, 256), (512, 3, 512)])
+def test_gradients_match_bf16_oracle(ctx, arm, hidden, depth, B):
+    import paper_2505_03728_amd as pk
+    import torch
+    init = synth.mlp_init([7] + [hidden] * depth + [56], 22)
+    sd = pk.Seeder(ctx, arm, K=8, hidden=hidden, depth=depth, init=init)
+    x, q = _inputs(B, 6)
+    loss = sd.grad(_dev(x), _dev(q))
+    torch.cuda.synchronize()
+    g = sd.get(1)
+    y, cache = mlp.forward(init, x, emulate_bf16=True)
+    lo, _, dy = mlp.min_over_k_loss(y, q, 8)
+    go = mlp.backward(init, cache, dy, emulate_bf16=True)
+    assert abs(loss.item() - lo) <= 1e-3 * lo
+    for li, ((gW, gb), (oW, ob)) in enumerate(zip(g, go)):
+        rw, rb = _rel(gW, oW), _rel(gb, ob)
+        print(f"layer {li}: dW rel {rw:.2e}, db rel {rb:.2e}")
+        assert rw <= 2e-2 and rb <= 2e-2
+
+
+def test_adam_step_closed_form_and_training(ctx, arm):
+    import paper_2505_03728_amd as pk
+    import torch
+    init = synth.mlp_init([7, 128, 128, 56], 23)
+    sd = pk.Seeder(ctx, arm, K=8, hidden=128, depth=2, init=init)
+    tree = synth.arm7(0)
+    qtr = synth.uniform_configs(tree, 1024, 24)
+    qdev = _dev(qtr.T)
+    # one step on the first 1024 samples in index order
+    log = torch.zeros(1, device=DEV)
+    sd.train(qdev, batch=1024, epochs=1, lr=1e-3, loss_log=log)
+    torch.cuda.synchronize()
+    g = sd.get(1)
+    p1 = sd.get(0)
+    for (W0, b0), (W1, b1), (gW, gb) in zip(init, p1, g):
+        np.testing.assert_allclose(W1 - W0.astype(np.float32), -1e-3 * gW / (np.abs(gW) + 1e-8),
+                                   atol=2e-7)
+        np.testing.assert_allclose(b1 - b0.astype(np.float32), -1e-3 * gb / (np.abs(gb) + 1e-8),
+                                   atol=2e-7)
+    # a few epochs reduce the loss
+    S = 8192
+    q = synth.uniform_configs(tree, S, 25)
+    perm = np.stack([synth.epoch_permutation(S, 26, e) for e in range(6)])
+    log = torch.zeros(6 * (S // 1024), device=DEV)
+    sd.train(_dev(q.T), batch=1024, epochs=6, lr=1e-3,
+             perm=torch.from_numpy(perm).to(DEV), loss_log=log)
+    torch.cuda.synchronize()
+    L = log.cpu().numpy()
+    print("loss", L[0], L[len(L) // 2], L[-1])
+    assert np.all(np.isfinite(L)) and L[-8:].mean() < 0.8 * L[:8].mean()
+
+
+def test_infer_seeds_within_limits_and_checkpoint(ctx, arm, tmp_path):
+    import paper_2505_03728_amd as pk
+    import torch
+    tree = synth.arm7(0)
+    init = synth.mlp_init([7, 128, 128, 56], 27)
+    sd = pk.Seeder(ctx, arm, K=8, hidden=128, depth=2, init=init)
+    q = synth.uniform_configs(tree, 300, 28)
+    tg = oracle.targets_from(tree, q)
+    targets = torch.from_numpy(pk.pack_targets(tree.ee_kind, tg)).to(DEV)
+    seeds = sd.infer(targets)
+    torch.cuda.synchronize()
+    s = seeds.cpu().numpy()
+    assert s.shape == (7, 300 * 8)
+    assert np.all(s >= tree.lower[:, None].astype(np.float32) - 1e-7)
+    assert np.all(s <= tree.upper[:, None].astype(np.float32) + 1e-7)
+    # seeds equal the clamped network output on the encoded targets
+    reach = float(np.sum(np.linalg.norm(tree.offset, axis=1)) + np.linalg.norm(tree.ee_offset[0]))
+    x = mlp.encode_targets(tg[:, 0, :3], tg[:, 0, 3:], reach)
+    y = sd.forward(_dev(x)).cpu().numpy().reshape(300, 8, 7)
+    want = np.clip(y, tree.lower.astype(np.float32), tree.upper.astype(np.float32))
+    d = np.abs(s.T.reshape(300, 8, 7) - want)
+    # the device encodes in FP32, this side in FP64: a BF16 input may round
+    # the other way now and then
+    assert np.mean(d <= 1e-4) >= 0.99 and d.max() <= 5e-2
+    path = tmp_path / "seeder.bin"
+    sd.save(path)
+    sd2 = pk.Seeder(ctx, arm, K=8, hidden=128, depth=2)
+    sd2.load(path)
+    for (W, b), (W2, b2) in zip(sd.get(0), sd2.get(0)):
+        np.testing.assert_array_equal(W, W2)
+        np.testing.assert_array_equal(b, b2)
+
+
+def test_seeded_pipeline_and_gain_over_random_seeds(ctx, arm):
+    """A seeder trained briefly on (FK(q), q) pairs gives seeds from which
+    10 LM iterations solve more targets than 10 iterations from random seeds;
+    the pipeline's per-target results follow its own rules."""
+    import paper_2505_03728_amd as pk
+    import torch
+    tree = synth.arm7(0)
+    init = synth.mlp_init([7, 256, 256, 256, 56], 31)
+    sd = pk.Seeder(ctx, arm, K=8, hidden=256, depth=3, init=init)
+    S, E = 262144, 6
+    q = synth.uniform_configs(tree, S, 32)
+    perm = np.stack([synth.epoch_permutation(S, 33, e) for e in range(E)])
+    log = torch.zeros(E * (S // 8192), device=DEV)
+    sd.train(_dev(q.T), batch=8192, epochs=E, lr=1e-3, perm=torch.from_numpy(perm).to(DEV),
+             loss_log=log)
+    T = 2048
+    wl = synth.workload("seeder", targets=T)
+    tg = oracle.targets_from(tree, wl["eval_q_star"])
+    targets = torch.from_numpy(pk.pack_targets(tree.ee_kind, tg)).to(DEV)
+    rseeds = _dev(wl["plain_seeds"].T)
+    w = pk.Weights.from_dict(wl["weights"])
+    ref = pk.Options.from_dict(wl["options"], max_iters=10, early_exit=True)
+    fb = pk.Options.from_dict(wl["options"], max_iters=30)
+    learned = ctx.ik_solve_seeded(arm, targets, sd, w, ref, fallback=None, fallback_K=0)
+    both = ctx.ik_solve_seeded(arm, targets, sd, w, ref, fallback=fb, fallback_seeds=rseeds,
+                               fallback_K=8, counters=True)
+    plain = ctx.alloc_outputs(arm, T, 8, best=True)
+    ctx.ik_solve(arm, targets, rseeds, 8, w, ref, plain)
+    torch.cuda.synchronize()
+    s_learn = learned["target_success"].cpu().numpy().astype(bool)
+    s_both = both["target_success"].cpu().numpy().astype(bool)
+    s_plain = plain["target_success"].cpu().numpy().astype(bool)
+    src = both["source"].cpu().numpy()
+    nfb = int(both["n_fallback"].item())
+    print(f"loss {log[0].item():.3f} -> {log[-1].item():.3f}; 10-iteration success: "
+          f"learned {s_learn.mean():.4f}, random {s_plain.mean():.4f}; with fallback "
+          f"{s_both.mean():.4f} ({nfb} targets re-solved)")
+    assert s_learn.mean() > s_plain.mean()
+    np.testing.assert_array_equal(s_both[src == 0], True)
+    np.testing.assert_array_equal(src == 0, s_learn)
+    assert nfb == int((~s_learn).sum())
+    assert np.all(s_both >= s_learn)
+    fi = both["fallback_iters"].cpu().numpy().reshape(T, 8)
+    assert np.all(fi[s_learn] == 0) and np.all(fi[~s_learn] > 0)
+    # returned joints meet the tolerance where success is claimed
+    bj = both["best_joints"].cpu().numpy().T.astype(np.float64)
+    for t in np.nonzero(s_both)[0][:200]:
+        _, pe, re = oracle.residual(tree, tg[t], wl["weights"], bj[t])
+        assert pe[0] <= 1e-3 * 1.05 and re[0] <= 1e-2 * 1.05
