@@ -33,6 +33,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--targets", type=int, default=16384)
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--workload", default="arm131k",
+                    choices=["arm131k", "tree4k", "mixed84k", "seeder"])
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -72,6 +77,9 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                                    f"--gpus {args.gpus} is not supported"}))
         sys.exit(2)
+    if args.workload != "arm131k":
+        {"tree4k": run_tree, "mixed84k": run_mixed, "seeder": run_seeder}[args.workload](args)
+        return
     import numpy as np
     import torch
 
@@ -141,6 +149,13 @@ def main():
     solved = itt_t < 10 ** 6
     hbm = lm_bytes(info["n"], info["m"], info["target_floats"], N, T)
 
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# copy probe: 268435456 bytes read + written", file=sys.stderr, flush=True)
+
     res = {
         "metric": "IK solves/sec at 1mm/0.01rad success",
         "value": round(value, 1),
@@ -177,6 +192,271 @@ def main():
         res["cpu_baseline"] = cpu_baseline(tree, wl, T, K, args.cpu_seconds)
     print(json.dumps(res), flush=True)
     ctx.close()
+
+
+# ------------------------------------------------------------------ extra workloads
+
+def _line(metric, value, unit, args, ms, config, **kw):
+    d = {"metric": metric, "value": round(value, 1), "unit": unit, "n_gpus": 1,
+         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+         "data": "synthetic", "config": config}
+    d.update(kw)
+    return d
+
+
+def _time(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _dev_targets(ctx, rid, tree, q_star):
+    import numpy as np
+    import torch
+    q = torch.from_numpy(np.ascontiguousarray(q_star.T.astype(np.float32))).cuda()
+    ee = ctx.fk(rid, q)
+    return torch.cat([ee[k, :(7 if kd == 0 else 3)] for k, kd in enumerate(tree.ee_kind)], 0).contiguous()
+
+
+def _oracle_rate(groups, weights, options, budget_s):
+    """FP64 oracle over the groups' problems (round robin chunks) within the budget."""
+    import oracle
+    threads = max(1, min(16, os.cpu_count() or 1))
+    done = succ = 0
+    elapsed = 0.0
+    off = [0] * len(groups)
+    while elapsed < budget_s and any(o < g["q_star"].shape[0] for o, g in zip(off, groups)):
+        for gi, g in enumerate(groups):
+            a = off[gi]
+            if a >= g["q_star"].shape[0]:
+                continue
+            b = min(g["q_star"].shape[0], a + 256)
+            tg = oracle.targets_from(g["tree"], g["q_star"][a:b])
+            s0 = time.perf_counter()
+            r = oracle.lm_solve_batch(g["tree"], tg, g["seeds"][a * g["K"]:b * g["K"]], g["K"],
+                                      g.get("w", weights), options, threads=threads)
+            _, ok = oracle.best_of_k(r["status"], r["cost"], r["pose_cost"], g["K"])
+            elapsed += time.perf_counter() - s0
+            succ += int(ok.sum())
+            done += b - a
+            off[gi] = b
+    return succ / elapsed if elapsed else 0.0, threads, done, elapsed
+
+
+def run_tree(args):
+    """34-DoF tree, 4 pose EEs, 4096 problems, 40 iterations (wave-per-problem kernel)."""
+    import numpy as np
+    import torch
+
+    import paper_2505_03728_amd as pk
+    from paper_2505_03728_amd.flops import lm_flops
+    import synth
+    wl = synth.workload("tree4k")
+    g = wl["groups"][0]
+    tree, K = g["tree"], 1
+    T = g["q_star"].shape[0]
+    ctx = pk.Context(0)
+    rid = ctx.upload(tree)
+    targets = _dev_targets(ctx, rid, tree, g["q_star"])
+    seeds = torch.from_numpy(np.ascontiguousarray(g["seeds"].T.astype(np.float32))).cuda()
+    w, o = pk.Weights.from_dict(wl["weights"]), pk.Options.from_dict(wl["options"])
+    out = ctx.alloc_outputs(rid, T, K)
+    ms = _time(lambda: ctx.ik_solve(rid, targets, seeds, K, w, o, out), args.steps, args.warmup)
+    conv = int(((out["status"] & 0xFF) == 0).sum().item())
+    flops = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, [tree.n], int(out["iters"].sum()),
+                     int(out["accepts"].sum()), T)
+    ach = flops / (ms / 1e3) / 1e12
+    res = _line("IK solves/sec at 1mm/0.01rad success", conv / (ms / 1e3), "solves/s", args, ms,
+                {"workload": f"34-DoF tree (torso 6 + 4x7), 4 pose EEs, {T} problems x 1 seed, "
+                             f"{wl['options']['max_iters']} iterations, pose + limit", "problems": T},
+                success_rate=conv / T,
+                fp64_fallback_fraction=float(((out["status"] & 0x100) != 0).float().mean()),
+                roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
+                          "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
+                          "kernel": "lm_wave_kernel<40,4>", "kernel_ms": round(ms, 5),
+                          "algorithmic_flops": flops})
+    if not args.no_cpu:
+        rate, th, done, el = _oracle_rate([{"tree": tree, "q_star": g["q_star"], "seeds": g["seeds"],
+                                            "K": 1}], wl["weights"], wl["options"], args.cpu_seconds)
+        res["cpu_baseline"] = {"value": rate, "unit": "solves/s", "cores": th, "kind": "oracle",
+                               "sample": f"first {done} of {T} problems, {el:.1f} s"}
+    print(json.dumps(res), flush=True)
+
+
+def run_mixed(args):
+    """60000 arm + 20000 hand + 4096 tree problems in one scheduled graph launch."""
+    import numpy as np
+    import torch
+
+    import paper_2505_03728_amd as pk
+    from paper_2505_03728_amd.flops import lm_flops
+    import synth
+    wl = synth.workload("mixed84k")
+    ctx = pk.Context(0)
+    groups = []
+    for g in wl["groups"]:
+        tree = g["tree"]
+        rid = ctx.upload(tree)
+        T = g["q_star"].shape[0]
+        groups.append({"rid": rid, "tree": tree, "K": 1, "q_star": g["q_star"], "seeds_np": g["seeds"],
+                       "targets": _dev_targets(ctx, rid, tree, g["q_star"]),
+                       "seeds": torch.from_numpy(np.ascontiguousarray(g["seeds"].T.astype(np.float32))).cuda(),
+                       "weights": pk.Weights.from_dict(g["weights"]), "wd": g["weights"],
+                       "out": ctx.alloc_outputs(rid, T, 1)})
+    o = pk.Options.from_dict(wl["options"])
+    k, bpc, tune_ms = ctx.autotune_mixed(groups, o)
+    print(f"# autotuned k={k} blocks/CU={bpc} ({tune_ms:.3f} ms)", file=sys.stderr, flush=True)
+    ms = _time(lambda: ctx.ik_solve_mixed(groups, o), args.steps, args.warmup)
+    # the same groups launched one by one without the scheduler
+    ms_sep = _time(lambda: [ctx.ik_solve(g["rid"], g["targets"], g["seeds"], 1, g["weights"], o, g["out"])
+                            for g in groups], args.steps, args.warmup)
+    ctx.ik_solve_mixed(groups, o)
+    torch.cuda.synchronize()
+    conv, flops, per = 0, 0.0, {}
+    for g in groups:
+        out, tree = g["out"], g["tree"]
+        c = int(((out["status"] & 0xFF) == 0).sum().item())
+        conv += c
+        info = ctx.robot_info(g["rid"])
+        blocks = [info["chain_len"]] * info["chains"] if info["chains"] else [info["n"]]
+        flops += lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(out["iters"].sum()),
+                          int(out["accepts"].sum()), out["joints"].shape[1])
+        per[tree.name] = {"problems": out["joints"].shape[1], "success_rate": c / out["joints"].shape[1],
+                          "mean_iters": float(out["iters"].float().mean())}
+    N = sum(g["out"]["joints"].shape[1] for g in groups)
+    ach = flops / (ms / 1e3) / 1e12
+    res = _line("IK solves/sec at 1mm/0.01rad success", conv / (ms / 1e3), "solves/s", args, ms,
+                {"workload": "mixed batch in one graph launch: 60000 7-DoF arm + 20000 16-DoF hand "
+                             "(4 fingertip positions) + 4096 34-DoF tree problems, early exit, <= 50 "
+                             "iterations", "problems": N, "iters_per_launch": k, "blocks_per_cu": bpc},
+                success_rate=conv / N, groups=per, ms_separate_launches=round(ms_sep, 5),
+                roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
+                          "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
+                          "kernel": "persistent LM kernels (3 groups)", "algorithmic_flops": flops})
+    if not args.no_cpu:
+        rate, th, done, el = _oracle_rate(
+            [{"tree": g["tree"], "q_star": g["q_star"], "seeds": g["seeds_np"], "K": 1, "w": g["wd"]}
+             for g in groups], wl["weights"], wl["options"], args.cpu_seconds)
+        res["cpu_baseline"] = {"value": rate, "unit": "solves/s", "cores": th, "kind": "oracle",
+                               "sample": f"{done} of {N} problems (round robin over the groups), {el:.1f} s"}
+    print(json.dumps(res), flush=True)
+
+
+def run_seeder(args):
+    """Learned seeder (trained here) + <= 10 LM iterations with fallback, against
+    8 random seeds x 30 iterations, on 131072 fresh targets of the 7-DoF arm."""
+    import numpy as np
+    import torch
+
+    import paper_2505_03728_amd as pk
+    from paper_2505_03728_amd.flops import lm_flops
+    import synth
+    wl = synth.workload("seeder")
+    tree, K = wl["tree"], wl["K"]
+    mc = wl["mlp"]
+    ctx = pk.Context(0)
+    rid = ctx.upload(tree)
+    init = synth.mlp_init([7] + [mc["hidden"]] * mc["depth"] + [7 * K], mc["init_seed"])
+    sd = pk.Seeder(ctx, rid, K=K, hidden=mc["hidden"], depth=mc["depth"], init=init)
+    S = wl["train_q"].shape[0]
+    E = args.epochs
+    qtr = torch.from_numpy(np.ascontiguousarray(wl["train_q"].T.astype(np.float32))).cuda()
+    perm = torch.from_numpy(np.stack([synth.epoch_permutation(S, mc["shuffle_seed"], e)
+                                      for e in range(E)])).cuda()
+    steps_tr = E * (S // mc["batch"])
+    log = torch.zeros(steps_tr, device="cuda")
+    t0 = time.perf_counter()
+    sd.train(qtr, batch=mc["batch"], epochs=E, lr=mc["lr"], perm=perm, loss_log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del perm, qtr
+    print(f"# trained {steps_tr} steps in {train_s:.2f} s, loss {log[0].item():.4f} -> "
+          f"{log[-1].item():.4f}", file=sys.stderr, flush=True)
+    T = wl["eval_q_star"].shape[0]
+    targets = _dev_targets(ctx, rid, tree, wl["eval_q_star"])
+    rseeds = torch.from_numpy(np.ascontiguousarray(wl["plain_seeds"].T.astype(np.float32))).cuda()
+    w = pk.Weights.from_dict(wl["weights"])
+    plain_o = pk.Options.from_dict(wl["options"])                          # 30 iterations
+    ref_o = pk.Options.from_dict(wl["options"], max_iters=10, early_exit=True)
+    plain = ctx.alloc_outputs(rid, T, K, best=True)
+    ms_plain = _time(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, plain_o, plain), args.steps,
+                     args.warmup)
+    plain10 = ctx.alloc_outputs(rid, T, K, best=True)
+    ms_plain10 = _time(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, ref_o, plain10), args.steps,
+                       args.warmup)
+    res_l = {}
+
+    def learned():
+        res_l["o"] = ctx.ik_solve_seeded(rid, targets, sd, w, ref_o, fallback=plain_o,
+                                         fallback_seeds=rseeds, fallback_K=K, counters=True)
+    ms_learn = _time(learned, args.steps, args.warmup)
+    seeds_buf = torch.empty((7, T * K), device="cuda")
+    ms_infer = _time(lambda: sd.infer(targets, seeds_buf), args.steps, args.warmup)
+    torch.cuda.synchronize()
+    lo = res_l["o"]
+    s_plain = int(plain["target_success"].sum())
+    s_plain10 = int(plain10["target_success"].sum())
+    s_learn = int(lo["target_success"].sum())
+    src = lo["source"].cpu().numpy()
+    itt_l = lo["iters_to_tol"].cpu().numpy()
+    itt_p = plain["iters_to_tol"].cpu().numpy().reshape(T, K)
+    itt_p = np.where(itt_p >= 0, itt_p, 10 ** 6).min(1)
+    blocks = [7]
+    fl_plain = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(plain["iters"].sum()),
+                        int(plain["accepts"].sum()), T * K)
+    n_fb = int(lo["n_fallback"].item())
+    fl_lm = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["refine_iters"].sum()),
+                     int(lo["refine_accepts"].sum()), T * K)
+    fl_lm += lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["fallback_iters"].sum()),
+                      int(lo["fallback_accepts"].sum()), n_fb * K)
+    dims = [7] + [mc["hidden"]] * mc["depth"] + [7 * K]
+    fl_mlp = 2.0 * T * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+    v_learn = s_learn / (ms_learn / 1e3)
+    v_plain = s_plain / (ms_plain / 1e3)
+    res = _line("IK solves/sec at 1mm/0.01rad success", v_learn, "solves/s", args, ms_learn,
+                {"workload": f"7-DoF arm, {T} fresh targets: learned seeder (MLP 7-512-512-512-56, "
+                             f"K={K}, BF16 MFMA) + <=10 LM iterations (early exit) + fallback to "
+                             f"{K} random seeds x 30 iterations, vs plain {K} random seeds x 30 "
+                             f"iterations", "targets": T, "seeds_per_target": K,
+                 "train_samples": S, "epochs": E, "batch": mc["batch"]},
+                success_rate=s_learn / T,
+                learned={"solves_per_s": round(v_learn, 1), "success_rate": s_learn / T,
+                         "success_from_learned_seeds": float(np.mean(src == 0)),
+                         "fallback_targets": n_fb, "ms": round(ms_learn, 5),
+                         "iters_to_tol_mean": float(itt_l[itt_l >= 0].mean()),
+                         "lm_tflops": round(fl_lm / ((ms_learn - ms_infer) / 1e3) / 1e12, 4),
+                         "lm_frac_fp32": round(fl_lm / ((ms_learn - ms_infer) / 1e3) / 1e12 / FP32_VALU_PEAK, 6)},
+                plain_random={"solves_per_s": round(v_plain, 1), "success_rate": s_plain / T,
+                              "ms": round(ms_plain, 5),
+                              "iters_to_tol_mean": float(itt_p[itt_p < 10 ** 6].mean()),
+                              "tflops": round(fl_plain / (ms_plain / 1e3) / 1e12, 4),
+                              "frac_fp32": round(fl_plain / (ms_plain / 1e3) / 1e12 / FP32_VALU_PEAK, 6),
+                              "success_rate_10_iters": s_plain10 / T,
+                              "solves_per_s_10_iters": round(s_plain10 / (ms_plain10 / 1e3), 1)},
+                speedup_vs_plain=round(v_learn / v_plain, 3),
+                seeder_training={"steps": steps_tr, "seconds": round(train_s, 3),
+                                 "loss_first": float(log[0]), "loss_last": float(log[-1])},
+                roofline={"bound": "mfma", "achieved": round(fl_mlp / (ms_infer / 1e3) / 1e12, 3),
+                          "peak": 2500.0, "unit": "TFLOP/s",
+                          "frac": round(fl_mlp / (ms_infer / 1e3) / 1e12 / 2500.0, 5), "traffic": None,
+                          "kernel": "seeder inference (4 BF16 MFMA GEMMs + encode + seeds)",
+                          "kernel_ms": round(ms_infer, 5), "algorithmic_flops": fl_mlp})
+    if not args.no_cpu:
+        g = {"tree": tree, "q_star": wl["eval_q_star"], "seeds": wl["plain_seeds"], "K": K}
+        rate, th, done, el = _oracle_rate([g], wl["weights"], wl["options"], args.cpu_seconds)
+        res["cpu_baseline"] = {"value": rate, "unit": "solves/s", "cores": th, "kind": "oracle",
+                               "sample": f"plain form: first {done} of {T} targets x {K} seeds, {el:.1f} s"}
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -229,7 +229,8 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
                       30 iterations, best-of-8;
       * ``tree4k``  — 4096 problems on tree34 (4 pose EEs), pose+limit, 40 its;
       * ``mixed84k``— 60000 arm7 + 20000 hand16 + 4096 tree34 problems, early
-                      exit, rest 0.01, up to 50 iterations;
+                      exit, rest 0.01, up to 50 iterations (per-group weights in
+                      each group's ``weights``);
       * ``seeder``  — 2M training configurations + 131072 evaluation targets.
     ``targets`` overrides the target count (a prefix of the same draws).
     Returns q* (configurations whose FK are the targets) and seeds; the caller
@@ -261,10 +262,14 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
         else:
             counts = [max(1, int(c * scale)) for c in counts]
         robots = [arm7(0), hand16(8), tree34(5)]
+        # The hand's links are an order of magnitude shorter than the arm's:
+        # its position residuals (metres) get a 10x weight so that the rest
+        # term (radians) does not dominate its optimum.
+        wts = [_weights(w_rest=0.01), _weights(w_pos=10.0, w_rest=0.01), _weights(w_rest=0.01)]
         gs = []
-        for r, c, sq, ss in zip(robots, counts, (9, 10, 11), (12, 13, 14)):
+        for r, c, sq, ss, w in zip(robots, counts, (9, 10, 11), (12, 13, 14), wts):
             gs.append({"tree": r, "q_star": uniform_configs(r, c, sq), "K": 1,
-                       "seeds": uniform_configs(r, c, ss)})
+                       "seeds": uniform_configs(r, c, ss), "weights": w})
         return {"groups": gs, "weights": _weights(w_rest=0.01),
                 "options": _options(50, early_exit=True)}
     if name == "seeder":

@@ -153,8 +153,9 @@ def test_lm_success_agreement(ctx, rids, name, wl_name, T):
     tree, K = g["tree"], g["K"]
     tg = oracle.targets_from(tree, g["q_star"])
     o = dict(wl["options"])
-    res = solve_gpu(ctx, rids[name], tree, tg, g["seeds"], K, wl["weights"], o)
-    ora = _oracle_traces(tree, tg, g["seeds"], K, wl["weights"], o, o["max_iters"])
+    w = g.get("weights", wl["weights"])
+    res = solve_gpu(ctx, rids[name], tree, tg, g["seeds"], K, w, o)
+    ora = _oracle_traces(tree, tg, g["seeds"], K, w, o, o["max_iters"])
     bad, excused = _agreement(res, ora, K)
     agree = 1 - (len(bad) + excused) / len(ora)
     print(f"{name}/{wl_name}: agreement {agree:.4f}, excused {excused}, unexplained {bad}")

@@ -32,7 +32,7 @@ def batch(ctx):
         tg = oracle.targets_from(tree, g["q_star"])
         groups.append({"rid": rid, "tree": tree, "tg": tg, "seeds_np": g["seeds"],
                        "targets": targets_dev(tree, tg, DEV), "seeds": soa(g["seeds"], DEV),
-                       "K": g["K"], "weights": pk.Weights.from_dict(wl["weights"])})
+                       "K": g["K"], "weights": pk.Weights.from_dict(g["weights"]), "wd": g["weights"]})
     return wl, groups
 
 
@@ -90,7 +90,7 @@ def test_autotune_and_oracle_sample(ctx, batch):
     for g, out in zip(groups, got):
         N = g["seeds_np"].shape[0]
         for p in rng.choice(N, min(N, 40), replace=False):
-            o = oracle.lm_solve(g["tree"], g["tg"][p // g["K"]], wl["weights"], wl["options"],
+            o = oracle.lm_solve(g["tree"], g["tg"][p // g["K"]], g["wd"], wl["options"],
                                 g["seeds_np"][p], n_trace=wl["options"]["max_iters"])
             cg, co = (out["status"][p] & 0xff) == 0, (o["status"] & 0xff) == 0
             if cg != co:

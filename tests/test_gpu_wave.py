@@ -69,9 +69,10 @@ def test_wave_matches_lane_variant(ctx, name):
     rid = ctx.upload(tree)
     tg = oracle.targets_from(tree, g["q_star"])
     o = dict(wl["options"], early_exit=False)
-    a = solve_gpu(ctx, rid, tree, tg, g["seeds"], K, wl["weights"], o, trace_iters=5,
+    wts = g.get("weights", wl["weights"])
+    a = solve_gpu(ctx, rid, tree, tg, g["seeds"], K, wts, o, trace_iters=5,
                   variant=pk.VARIANT_LANE)
-    b = solve_gpu(ctx, rid, tree, tg, g["seeds"], K, wl["weights"], o, trace_iters=5,
+    b = solve_gpu(ctx, rid, tree, tg, g["seeds"], K, wts, o, trace_iters=5,
                   variant=pk.VARIANT_WAVE)
     # Same arithmetic up to reduction order: first iterates agree closely.
     same_acc = np.all(a["trace_accept"] == b["trace_accept"], axis=1)
@@ -115,10 +116,11 @@ def test_hand_early_exit_wave_vs_oracle(ctx):
     rid = ctx.upload(tree)
     tg = oracle.targets_from(tree, g["q_star"])
     o = wl["options"]
-    res = solve_gpu(ctx, rid, tree, tg, g["seeds"], 1, wl["weights"], o, variant=pk.VARIANT_WAVE)
+    wts = g["weights"]
+    res = solve_gpu(ctx, rid, tree, tg, g["seeds"], 1, wts, o, variant=pk.VARIANT_WAVE)
     bad = 0
     for p in range(tg.shape[0]):
-        ora = oracle.lm_solve(tree, tg[p], wl["weights"], o, g["seeds"][p], n_trace=o["max_iters"])
+        ora = oracle.lm_solve(tree, tg[p], wts, o, g["seeds"][p], n_trace=o["max_iters"])
         cg, co = (res["status"][p] & 0xff) == 0, (ora["status"] & 0xff) == 0
         if cg != co and not _excusable(ora):
             bad += 1
