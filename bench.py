@@ -139,7 +139,7 @@ def main():
     k_ms = e0.elapsed_time(e1) / ks
     iters = int(out2["iters"].sum().item())
     accepts = int(out2["accepts"].sum().item())
-    blocks = [info["chain_len"]] * info["chains"] if (info["chains"] and args.variant != 2) else [info["n"]]
+    blocks = [info["chain_len"]] * info["chains"] if (info["chains"] and args.variant != 2) else None
     flops = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, iters, accepts, N)
     achieved = flops / (k_ms / 1e3) / 1e12
     conv = ((out2["status"] & 0xFF) == pk.CONVERGED).float().mean().item()
@@ -273,7 +273,7 @@ def run_tree(args):
     out = ctx.alloc_outputs(rid, T, K)
     ms = _time(lambda: ctx.ik_solve(rid, targets, seeds, K, w, o, out), args.steps, args.warmup)
     conv = int(((out["status"] & 0xFF) == 0).sum().item())
-    flops = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, [tree.n], int(out["iters"].sum()),
+    flops = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, None, int(out["iters"].sum()),
                      int(out["accepts"].sum()), T)
     ach = flops / (ms / 1e3) / 1e12
     res = _line("IK solves/sec at 1mm/0.01rad success", conv / (ms / 1e3), "solves/s", args, ms,
@@ -283,7 +283,7 @@ def run_tree(args):
                 fp64_fallback_fraction=float(((out["status"] & 0x100) != 0).float().mean()),
                 roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
                           "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
-                          "kernel": "lm_wave_kernel<40,4>", "kernel_ms": round(ms, 5),
+                          "kernel": "lm_wave_kernel<16,4>", "kernel_ms": round(ms, 5),
                           "algorithmic_flops": flops})
     if not args.no_cpu:
         rate, th, done, el = _oracle_rate([{"tree": tree, "q_star": g["q_star"], "seeds": g["seeds"],
@@ -328,7 +328,7 @@ def run_mixed(args):
         c = int(((out["status"] & 0xFF) == 0).sum().item())
         conv += c
         info = ctx.robot_info(g["rid"])
-        blocks = [info["chain_len"]] * info["chains"] if info["chains"] else [info["n"]]
+        blocks = [info["chain_len"]] * info["chains"] if info["chains"] else None
         flops += lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(out["iters"].sum()),
                           int(out["accepts"].sum()), out["joints"].shape[1])
         per[tree.name] = {"problems": out["joints"].shape[1], "success_rate": c / out["joints"].shape[1],

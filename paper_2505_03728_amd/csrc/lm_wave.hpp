@@ -1,16 +1,21 @@
 // Wave-per-problem Levenberg-Marquardt IK kernel for any revolute tree
 // (up to 64 joints, 8 EEs): one problem per 64-lane wavefront, lane j owns
-// joint j.
+// joint j, lane k < m also owns EE k.
 //
 //  * FK runs level by level over tree depth; a lane reads its parent's frame
 //    with a lane shuffle.
-//  * Lane k < m evaluates EE k (pose log, errors, right-Jacobian-inverse
-//    blocks); those values are broadcast to all lanes with readlane.
-//  * Lane j forms its Jacobian column for every EE it is an ancestor of,
-//    then row j of J^T J from the other lanes' columns (readlane).
-//  * Right-looking Cholesky with the rows in registers; column k is
-//    broadcast with readlane.  The forward solve works on the rows; L is
-//    transposed through LDS once for the backward solve.
+//  * EE lanes evaluate the pose log and residual; the right-Jacobian-inverse
+//    blocks and the Jacobian columns are formed only for accepted points.
+//    Lane j writes its column (6 rows per EE) to LDS.
+//  * Tree structure of the normal equations.  (J^T J)_ij is non-zero only
+//    when one of i, j is an ancestor of the other (both sit on a path from the
+//    root to an EE), so lane j stores row j of the lower triangle indexed by
+//    ancestor depth: r[d] = A(j, ancestor of j at depth d), plus its diagonal.
+//    Eliminating joints leaves first (descending index, parents have smaller
+//    indices) creates no fill: the update of step k touches only the
+//    ancestors of k, which already form a dense block.  The factorization is
+//    A = L^T D L without square roots; one step costs O(depth) per lane and
+//    the back substitution runs level by level over depth.
 //  * Decisions (accept/reject, lambda, pivot test, early exit) are uniform
 //    across the wave, so the whole LM loop runs without divergence.
 //
@@ -38,6 +43,15 @@ PK_DEV double bcast(double v, int lane)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+PK_DEV int bcast_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+PK_DEV uint64_t bcast_u64(uint64_t v, int lane)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 PK_DEV float wave_sum(float v)
 {
 #pragma unroll
@@ -52,15 +66,29 @@ PK_DEV float wave_max(float v)
     return v;
 }
 
-template <int MMAX>
-struct Eval {
-    float col[MMAX][6];   // this lane's Jacobian column for each EE (0 if not an ancestor)
-    float g;              // (J^T r)_j
-    float dl;             // limit-row derivative of joint j
-    float cost, pcost;    // uniform
-    float perr, rerr;     // EE lane values
-    bool meets;           // uniform
+PK_DEV float recip(float x) { return rcp(x); }
+PK_DEV double recip(double x) { return 1.0 / x; }
+
+// Byte d of the packed ancestor table of this lane (ancestor at depth d).
+template <int DMAX>
+PK_DEV int anc_lane(const uint32_t (&ancp)[DMAX / 4], int d)
+{
+    return (int)((ancp[d >> 2] >> (8 * (d & 3))) & 0xffu);
+}
+
+// LDS layout of one wavefront's problem (float offsets).
+template <int DMAX, int MMAX>
+struct Lds {
+    static constexpr int JS = 6 * MMAX;            // floats per Jacobian column row
+    static constexpr int ES = 60;                  // floats per EE record
+    static constexpr int JC = 0;                   // [64][JS]  Jacobian columns (current point)
+    static constexpr int RS = JC + 64 * JS;        // [6 * MMAX] EE residual rows (current point)
+    static constexpr int FR = RS + 6 * MMAX;       // [64][12] joint frames O, p (last evaluated point)
+    static constexpr int EX = FR + 64 * 12;        // [MMAX][ES] EE records (last evaluated point)
+    static constexpr int FLOATS = EX + MMAX * ES;
 };
+// Slots of an EE record.
+enum { E_PE = 0, E_R = 4, E_RE = 12, E_LG = 24, E_M = 36, E_N = 48 };
 
 // Per-lane constants of the joint and EE owned by this lane.
 struct LaneConst {
@@ -71,219 +99,282 @@ struct LaneConst {
     float tp[3], tR[9];   // this lane's EE target
 };
 
-template <int MMAX>
-PK_DEV void evaluate(const RobotC *__restrict__ rb, const SolveParams &P, const LaneConst &C,
-                     int lane, int n, int m, int max_depth, float q, Eval<MMAX> &E)
+// Scalars of one evaluated point (the rest of it is in LDS).
+struct PointVal {
+    float rl, rr, dl;     // joint lane: limit and rest residuals, limit-row derivative
+    float perr, rerr;     // EE lane errors
+    float cost, pcost;    // uniform
+    bool meets;           // uniform
+};
+
+// FK, EE residuals, limit/rest residuals and the cost at q.  Joint frames
+// and EE records of the point go to LDS.
+template <int DMAX, int MMAX>
+PK_DEV void point(const SolveParams &P, const LaneConst &C, int lane, int n, int m, int max_depth,
+                  float q, float *lds, PointVal &X)
 {
+    using L = Lds<DMAX, MMAX>;
     const bool isj = lane < n, ise = lane < m;
     float s = 0.f, c = 1.f;
     if (isj) joint_sincos(q, s, c);
-    // FK, one tree level at a time.
-    float O[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, pos[3] = {0.f, 0.f, 0.f};
-    const int src = C.parent < 0 ? 0 : C.parent;
+    // FK, one tree level at a time, through LDS.
     for (int d = 0; d <= max_depth; ++d) {
-        float Op[9], pp[3];
-#pragma unroll
-        for (int u = 0; u < 9; ++u) Op[u] = __shfl(O[u], src, 64);
-#pragma unroll
-        for (int u = 0; u < 3; ++u) pp[u] = __shfl(pos[u], src, 64);
         if (C.depth == d) {
-            if (C.parent < 0) {
+            float Op[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, pp[3] = {0.f, 0.f, 0.f};
+            if (C.parent >= 0) {
+                const float *f = lds + L::FR + C.parent * 12;
 #pragma unroll
-                for (int u = 0; u < 9; ++u) Op[u] = (u % 4 == 0) ? 1.f : 0.f;
-                pp[0] = pp[1] = pp[2] = 0.f;
+                for (int u = 0; u < 9; ++u) Op[u] = f[u];
+#pragma unroll
+                for (int u = 0; u < 3; ++u) pp[u] = f[9 + u];
             }
+            float O[9], pos[3];
             joint_step(Op, pp, C.G, C.t, s, c, O, pos);
+            float *f = lds + L::FR + lane * 12;
+#pragma unroll
+            for (int u = 0; u < 9; ++u) f[u] = O[u];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) f[9 + u] = pos[u];
         }
+        __syncthreads();
     }
-    // EE lanes: frame of the EE joint, residual, errors, J_r^-1 blocks.
-    float Oe[9], pj[3];
-    const int esrc = ise ? C.ee_joint : 0;
-#pragma unroll
-    for (int u = 0; u < 9; ++u) Oe[u] = __shfl(O[u], esrc, 64);
-#pragma unroll
-    for (int u = 0; u < 3; ++u) pj[u] = __shfl(pos[u], esrc, 64);
-    float r[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, M[9], Nb[9], pe[3];
+    // EE lanes: frame of the EE joint, residual, errors.
     float ecost = 0.f;
-    E.perr = 0.f;
-    E.rerr = 0.f;
+    X.perr = X.rerr = 0.f;
     if (ise) {
-        float Re[9], d[3];
+        const float *f = lds + L::FR + C.ee_joint * 12;
+        float Oe[9], pj[3], Re[9], pe[3], d[3], r[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int u = 0; u < 9; ++u) Oe[u] = f[u];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) pj[u] = f[9 + u];
         ee_frame(Oe, pj, C.eG, C.et, Re, pe);
 #pragma unroll
         for (int u = 0; u < 3; ++u) d[u] = pe[u] - C.tp[u];
-        E.perr = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        X.perr = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        float *e = lds + L::EX + lane * L::ES;
         if (C.ee_kind == PK_EE_POSE) {
-            PoseLog lg = pose_log(C.tR, Re, d);
+            const PoseLog lg = pose_log(C.tR, Re, d);
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
                 r[u] = P.w_pos * lg.rho[u];
                 r[3 + u] = P.w_rot * lg.phi[u];
+                e[E_LG + u] = lg.rho[u];
+                e[E_LG + 3 + u] = lg.phi[u];
             }
-            E.rerr = lg.theta;
-            jr_inv_blocks(lg, Re, M, Nb);
+            e[E_LG + 6] = lg.theta;
+            e[E_LG + 7] = lg.sh;
+            e[E_LG + 8] = lg.ch;
+            X.rerr = lg.theta;
         } else {
 #pragma unroll
             for (int u = 0; u < 3; ++u) r[u] = P.w_pos * d[u];
-#pragma unroll
-            for (int u = 0; u < 9; ++u) M[u] = Nb[u] = 0.f;
         }
 #pragma unroll
-        for (int u = 0; u < 6; ++u) ecost += r[u] * r[u];
+        for (int u = 0; u < 3; ++u) e[E_PE + u] = pe[u];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+            e[E_R + u] = r[u];
+            ecost += r[u] * r[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 9; ++u) e[E_RE + u] = Re[u];
     }
     // Joint lanes: limit and rest rows.
-    float jcost = 0.f, rl = 0.f, rr = 0.f;
-    E.dl = 0.f;
+    float jcost = 0.f;
+    X.rl = X.rr = X.dl = 0.f;
     if (isj) {
         const float over = q - C.hi, under = C.lo - q;
-        rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
-        rr = P.w_rest * (q - C.qr);
-        E.dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
-        jcost = rl * rl + rr * rr;
+        X.rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
+        X.rr = P.w_rest * (q - C.qr);
+        X.dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
+        jcost = X.rl * X.rl + X.rr * X.rr;
     }
-    E.pcost = wave_sum(ecost);
-    E.cost = wave_sum(ecost + jcost);
+    X.pcost = wave_sum(ecost);
+    X.cost = wave_sum(ecost + jcost);
     bool ok = true;
-    if (ise) ok = E.perr <= P.tol_pos && (C.ee_kind != PK_EE_POSE || E.rerr <= P.tol_rot);
-    E.meets = __all(ok);
-    // Jacobian columns of this lane's joint, one per EE.
-    const float om[3] = {O[2], O[5], O[8]};
-    float g = E.dl * rl + P.w_rest * rr;
+    if (ise) ok = X.perr <= P.tol_pos && (C.ee_kind != PK_EE_POSE || X.rerr <= P.tol_rot);
+    X.meets = __all(ok);
+}
+
+// Jacobian of the last evaluated point: lane j's column (one 6-row block per
+// EE, zero where j is not an ancestor of the EE) and the EE residual rows
+// into LDS.
+template <int DMAX, int MMAX>
+PK_DEV void jacobian(const RobotC *__restrict__ rb, const SolveParams &P, int lane, int n, int m,
+                     float *lds)
+{
+    using L = Lds<DMAX, MMAX>;
+    const bool isj = lane < n, ise = lane < m;
+    if (ise) {
+        float *e = lds + L::EX + lane * L::ES;
+        if (rb->e[lane].kind == PK_EE_POSE) {
+            PoseLog lg;
+            float Re[9], M[9], Nb[9];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                lg.rho[u] = e[E_LG + u];
+                lg.phi[u] = e[E_LG + 3 + u];
+            }
+            lg.theta = e[E_LG + 6];
+            lg.sh = e[E_LG + 7];
+            lg.ch = e[E_LG + 8];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) Re[u] = e[E_RE + u];
+            jr_inv_blocks(lg, Re, M, Nb);
+#pragma unroll
+            for (int u = 0; u < 9; ++u) {
+                e[E_M + u] = M[u];
+                e[E_N + u] = Nb[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 6; ++u) lds[L::RS + 6 * lane + u] = e[E_R + u];
+    }
+    __syncthreads();
+    const float *f = lds + L::FR + (isj ? lane : 0) * 12;
+    const float om[3] = {f[2], f[5], f[8]}, pj[3] = {f[9], f[10], f[11]};
+    float *jc = lds + L::JC + lane * L::JS;
 #pragma unroll
     for (int k = 0; k < MMAX; ++k) {
-#pragma unroll
-        for (int u = 0; u < 6; ++u) E.col[k][u] = 0.f;
         if (k < m) {
+            const float *e = lds + L::EX + k * L::ES;
             const int kind = rb->e[k].kind;
             const bool anc = isj && ((rb->anc[k] >> lane) & 1ull);
-            float bpe[3], bM[9], bN[9], br[6];
-#pragma unroll
-            for (int u = 0; u < 3; ++u) bpe[u] = bcast(pe[u], k);
-#pragma unroll
-            for (int u = 0; u < 6; ++u) br[u] = bcast(r[u], k);
-            float lev[3] = {bpe[0] - pos[0], bpe[1] - pos[1], bpe[2] - pos[2]}, v[3];
+            float col[6];
+            float lev[3] = {e[E_PE] - pj[0], e[E_PE + 1] - pj[1], e[E_PE + 2] - pj[2]}, v[3];
             cross(om, lev, v);
             if (kind == PK_EE_POSE) {
 #pragma unroll
-                for (int u = 0; u < 9; ++u) {
-                    bM[u] = bcast(M[u], k);
-                    bN[u] = bcast(Nb[u], k);
-                }
-#pragma unroll
                 for (int u = 0; u < 3; ++u) {
-                    float mv = bM[3 * u] * v[0] + bM[3 * u + 1] * v[1] + bM[3 * u + 2] * v[2];
-                    float nw = bN[3 * u] * om[0] + bN[3 * u + 1] * om[1] + bN[3 * u + 2] * om[2];
-                    float mw = bM[3 * u] * om[0] + bM[3 * u + 1] * om[1] + bM[3 * u + 2] * om[2];
-                    E.col[k][u] = anc ? P.w_pos * (mv + nw) : 0.f;
-                    E.col[k][3 + u] = anc ? P.w_rot * mw : 0.f;
+                    const float *Mu = e + E_M + 3 * u, *Nu = e + E_N + 3 * u;
+                    float mv = Mu[0] * v[0] + Mu[1] * v[1] + Mu[2] * v[2];
+                    float nw = Nu[0] * om[0] + Nu[1] * om[1] + Nu[2] * om[2];
+                    float mw = Mu[0] * om[0] + Mu[1] * om[1] + Mu[2] * om[2];
+                    col[u] = anc ? P.w_pos * (mv + nw) : 0.f;
+                    col[3 + u] = anc ? P.w_rot * mw : 0.f;
                 }
             } else {
 #pragma unroll
-                for (int u = 0; u < 3; ++u) E.col[k][u] = anc ? P.w_pos * v[u] : 0.f;
+                for (int u = 0; u < 3; ++u) {
+                    col[u] = anc ? P.w_pos * v[u] : 0.f;
+                    col[3 + u] = 0.f;
+                }
             }
 #pragma unroll
-            for (int u = 0; u < 6; ++u) g += E.col[k][u] * br[u];
+            for (int u = 0; u < 6; ++u) jc[6 * k + u] = col[u];
         }
     }
-    E.g = isj ? g : 0.f;
 }
 
-// Form row `lane` of A + lambda diag(max(A_jj, floor)) in precision T from
-// the Jacobian columns, factor it (rows in registers), and solve for
-// delta = -(L L^T)^-1 g.  Returns false if a pivot is not above
-// pivot_rel * max diagonal (thresh_rel > 0) or not positive (thresh_rel = 0).
-template <int NMAX, int MMAX, typename T>
-PK_DEV bool damped_solve(const RobotC *__restrict__ rb, const SolveParams &P, const Eval<MMAX> &E,
-                         int lane, int n, int m, float lam, float thresh_rel, T *lds, float &delta)
+// Row j of J^T J by ancestor depth, r[d] = A(j, ancestor of j at depth d)
+// for d < depth j, in precision T from the FP32 columns in LDS (products of
+// FP32 entries summed in T), and g = J^T r over the EE rows; returns the
+// diagonal A_jj.
+template <int DMAX, int MMAX, typename T>
+PK_DEV T jtj_rows(const float *lds, const uint32_t (&ancp)[DMAX / 4], int lane, int dep, int m,
+                  int max_depth, T (&r)[DMAX], T &g)
 {
-    const bool isj = lane < n;
-    T a[NMAX];
-    // own diagonal of J^T J (+ limit/rest rows) and the damping term
+    using L = Lds<DMAX, MMAX>;
+    T acc[DMAX];
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) acc[d] = 0;
+    g = 0;
+    for (int e = 0; e < 6 * m; ++e) {
+        const T ce = (T)lds[L::JC + lane * L::JS + e];
+        g += ce * (T)lds[L::RS + e];
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d)
+            if (d <= max_depth) acc[d] += ce * (T)lds[L::JC + anc_lane<DMAX>(ancp, d) * L::JS + e];
+    }
     T diag = 0;
 #pragma unroll
-    for (int k = 0; k < MMAX; ++k)
-#pragma unroll
-        for (int u = 0; u < 6; ++u) diag += (T)E.col[k][u] * (T)E.col[k][u];
-    diag += (T)E.dl * (T)E.dl + (T)P.w_rest * (T)P.w_rest;
-    const T D = diag > (T)P.damping_floor ? diag : (T)P.damping_floor;
-    const T dampd = isj ? diag + (T)lam * D : (T)0;
-#pragma unroll
-    for (int c = 0; c < NMAX; ++c) {
-        T s = 0;
-        if (c < n) {
-#pragma unroll
-            for (int k = 0; k < MMAX; ++k) {
-                if (k < m && ((rb->anc[k] >> c) & 1ull)) {
-#pragma unroll
-                    for (int u = 0; u < 6; ++u) s += (T)E.col[k][u] * (T)bcast(E.col[k][u], c);
-                }
-            }
-        }
-        a[c] = (lane == c) ? dampd : s;
+    for (int d = 0; d < DMAX; ++d) {
+        r[d] = d < dep ? acc[d] : (T)0;
+        diag = d == dep ? acc[d] : diag;
     }
-    T thresh = 0;
-    if (thresh_rel > 0.f) thresh = (T)thresh_rel * (T)wave_max((float)dampd);
-    bool ok = true;
-    // Right-looking Cholesky; lane i holds row i.
-#pragma unroll
-    for (int k = 0; k < NMAX; ++k) {
-        if (k < n) {
-            T d = bcast(a[k], k);
-            if (!(d > thresh) || !(d < (T)INFINITY)) {
-                ok = false;
-                d = 1;
-            }
-            const T lkk = sqrt(d), inv = (T)1 / lkk;
-            if (lane > k) a[k] *= inv;
-            if (lane == k) a[k] = lkk;
-#pragma unroll
-            for (int j = k + 1; j < NMAX; ++j) {
-                if (j < n) {
-                    const T ljk = bcast(a[k], j);
-                    if (lane >= j) a[j] -= a[k] * ljk;
-                }
-            }
-        }
-    }
-    // Forward: L y = -g (lane i ends with y_i).
-    T b = isj ? -(T)E.g : (T)0;
-#pragma unroll
-    for (int k = 0; k < NMAX; ++k) {
-        if (k < n) {
-            const T yk = bcast(b, k) / bcast(a[k], k);
-            if (lane > k) b -= a[k] * yk;
-            if (lane == k) b = yk;
-        }
-    }
-    // Transpose L through LDS: lane k then holds column k (lt[i] = L_ik).
-    if (isj) {
-#pragma unroll
-        for (int c = 0; c < NMAX; ++c) lds[lane * (NMAX + 1) + c] = a[c];
-    }
-    __syncthreads();
-    T lt[NMAX];
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i) lt[i] = (i < n && isj) ? lds[i * (NMAX + 1) + lane] : (T)0;
-    __syncthreads();
-    // Backward: L^T x = y.
-#pragma unroll
-    for (int i = NMAX - 1; i >= 0; --i) {
-        if (i < n) {
-            const T xi = bcast(b, i) / bcast(lt[i], i);
-            if (lane < i) b -= lt[i] * xi;
-            if (lane == i) b = xi;
-        }
-    }
-    delta = isj ? (float)b : 0.f;
-    return ok;
+    return diag;
 }
 
-// One LM problem (active index wi) on this wavefront; resumable like the
-// per-lane kernel (state in HBM, at most P.iter_budget iterations per launch).
-template <int NMAX, int MMAX>
-PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, double *lds_raw,
-                         int64_t wi)
+// Solve (A + lam diag(max(A_jj, floor))) delta = -g for the tree-structured A
+// given as depth-indexed rows r and undamped diagonal dgu (consumed).
+// Returns false if a pivot is not above thresh_rel * max damped diagonal
+// (thresh_rel > 0) or not positive and finite.
+template <int DMAX, typename T>
+PK_DEV bool tree_solve(T (&r)[DMAX], T dgu, T g, float lam, float dfloor, float thresh_rel,
+                       int lane, int n, int dep, uint64_t ancm, const uint32_t (&ancp)[DMAX / 4],
+                       int max_depth, float &delta)
 {
+    const bool isj = lane < n;
+    T dg = isj ? dgu + (T)lam * (dgu > (T)dfloor ? dgu : (T)dfloor) : (T)0;
+    T thresh = 0;
+    if (thresh_rel > 0.f) thresh = (T)thresh_rel * (T)wave_max((float)dg);
+    T b = isj ? -g : (T)0;
+    // Leaves first: step k removes joint k from its ancestors' rows.
+    for (int k = n - 1; k >= 0; --k) {
+        const int dk = bcast_i(dep, k);
+        const T piv = bcast(dg, k);
+        if (!(piv > thresh) || !(piv < (T)INFINITY)) return false;
+        const T ip = recip(piv);
+        const bool is_anc = (bcast_u64(ancm, k) >> lane) & 1ull;
+        const T bk = bcast(b, k);
+        T sel = 0;
+        if constexpr (DMAX <= 16) {
+            T wk[DMAX];
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                if ((d & 3) == 0 && d >= dk) break;
+                wk[d] = bcast(r[d], k);
+                sel = dep == d ? wk[d] : sel;
+            }
+            const T c = is_anc ? sel * ip : (T)0;
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                if ((d & 3) == 0 && d >= dk) break;
+                r[d] -= c * wk[d];
+            }
+            dg -= c * sel;
+            b -= c * bk;
+        } else {
+            // Row k is not changed by its own step (k is not its own
+            // ancestor), so it is read twice instead of held in SGPRs.
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                if ((d & 3) == 0 && d >= dk) break;
+                const T w = bcast(r[d], k);
+                sel = dep == d ? w : sel;
+            }
+            const T c = is_anc ? sel * ip : (T)0;
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) {
+                if ((d & 3) == 0 && d >= dk) break;
+                r[d] -= c * bcast(r[d], k);
+            }
+            dg -= c * sel;
+            b -= c * bk;
+        }
+    }
+    // Back substitution, root first: x_j = (b_j - sum_d r_j[d] x_anc(d)) / pivot_j.
+    const T ipj = isj ? recip(dg) : (T)0;
+    T s = 0, x = 0;
+#pragma unroll
+    for (int D = 0; D < DMAX; ++D) {
+        if (D <= max_depth) {
+            if (dep == D) x = (b - s) * ipj;
+            const T xa = __shfl(x, anc_lane<DMAX>(ancp, D), 64);
+            if (dep > D) s += r[D] * xa;
+        }
+    }
+    delta = isj ? (float)x : 0.f;
+    return true;
+}
+
+// One LM problem (active index wi) on this wavefront; resumable (state in
+// HBM, at most P.iter_budget iterations per launch when P.st_state is set).
+template <int DMAX, int MMAX>
+PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, float *lds, int64_t wi)
+{
+    using L = Lds<DMAX, MMAX>;
     const int lane = threadIdx.x;
     const int64_t p = P.active ? (int64_t)P.active[wi] : wi;
     const int64_t N = P.N, T = P.T, t = p / P.K;
@@ -308,6 +399,13 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, do
     for (int u = 0; u < 3; ++u) C.et[u] = rb->e[el].t[u];
     C.ee_joint = rb->e[el].joint;
     C.ee_kind = rb->e[el].kind;
+    uint32_t ancp[DMAX / 4];
+    const uint32_t *arow = (const uint32_t *)rb->anc_at[jl];
+#pragma unroll
+    for (int i = 0; i < DMAX / 4; ++i) ancp[i] = isj ? arow[i] : 0u;
+    const uint64_t ancm = isj ? rb->janc[jl] : 0ull;
+    const int dep = C.depth;
+
     bool fin = true;
     float q = 0.f;
     if (isj) {
@@ -318,9 +416,12 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, do
         const int off = rb->e[el].tgt_off;
         const int W = C.ee_kind == PK_EE_POSE ? 7 : 3;
         float v[7] = {0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f};
-        for (int u = 0; u < W; ++u) {
-            v[u] = P.targets[(int64_t)(off + u) * T + t];
-            fin = fin && isfinite(v[u]);
+#pragma unroll
+        for (int u = 0; u < 7; ++u) {
+            if (u < W) {
+                v[u] = P.targets[(int64_t)(off + u) * T + t];
+                fin = fin && isfinite(v[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < 3; ++u) C.tp[u] = v[u];
@@ -350,11 +451,9 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, do
         return;
     }
 
-    Eval<MMAX> E, Et;
-    evaluate<MMAX>(rb, P, C, lane, n, m, max_depth, q, E);
-    int iters, accepts, itt, flags;
-    bool done, stalled;
-    float lam;
+    int iters = 0, accepts = 0, itt = -1, flags = 0;
+    bool done = false, stalled = false;
+    float lam = P.lambda0;
     if (resume) {
         const int st = P.st_state[p];
         iters = P.iters[p];
@@ -364,50 +463,95 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, do
         stalled = (st & PK_ST_STALLED) != 0;
         done = (st & PK_ST_DONE) != 0;
         lam = P.st_lambda[p];
-    } else {
-        iters = accepts = flags = 0;
-        itt = E.meets ? 0 : -1;
-        stalled = false;
-        done = P.early_exit && itt == 0;
-        lam = P.lambda0;
     }
     const int iter_end = resumable ? min(P.max_iters, iters + P.iter_budget) : P.max_iters;
-    while (!done && iters < iter_end) {
-        float delta;
-        bool ok = damped_solve<NMAX, MMAX, float>(rb, P, E, lane, n, m, lam, P.pivot_rel,
-                                                  (float *)lds_raw, delta);
-        if (!ok) {
-            flags |= PK_FLAG_FP64;
-            ok = damped_solve<NMAX, MMAX, double>(rb, P, E, lane, n, m, lam, 0.f, lds_raw, delta);
+
+    // Current point: scalars and J^T J rows in registers, Jacobian columns
+    // and residual rows in LDS.  Each pass evaluates one point (first the
+    // start point, then each trial), so every stage has a single call site.
+    PointVal X;
+    float cost = INFINITY, pcost = 0.f, perr = 0.f, rerr = 0.f, rl = 0.f, rr = 0.f, dl = 0.f;
+    float g = 0.f, dgu = 0.f, rows[DMAX];
+#pragma unroll
+    for (int d = 0; d < DMAX; ++d) rows[d] = 0.f;
+    bool meets = false;
+    float qt = q;
+    bool first = true, evaluate = true;
+    for (;;) {
+        bool acc = false;
+        if (evaluate) {
+            point<DMAX, MMAX>(P, C, lane, n, m, max_depth, qt, lds, X);
+            acc = first || X.cost < cost;
         }
-        float ct = INFINITY;
-        const float qt = q + delta;
-        if (ok) {
-            evaluate<MMAX>(rb, P, C, lane, n, m, max_depth, qt, Et);
-            ct = Et.cost;
-        }
-        ++iters;
-        const bool acc = ct < E.cost;
+        if (!first) ++iters;
         if (acc) {
             q = qt;
-            E = Et;
-            lam = fmaxf(lam / P.nu_down, P.lambda_min);
-            ++accepts;
-            if (E.meets) {
-                if (itt < 0) itt = iters;
-                if (P.early_exit) done = true;
+            cost = X.cost;
+            pcost = X.pcost;
+            perr = X.perr;
+            rerr = X.rerr;
+            rl = X.rl;
+            rr = X.rr;
+            dl = X.dl;
+            meets = X.meets;
+            if (first) {
+                if (!resume) {
+                    itt = meets ? 0 : -1;
+                    done = P.early_exit && itt == 0;
+                }
+            } else {
+                lam = fmaxf(lam / P.nu_down, P.lambda_min);
+                ++accepts;
+                if (meets) {
+                    if (itt < 0) itt = iters;
+                    if (P.early_exit) done = true;
+                }
             }
-        } else {
+            if (!done && iters < iter_end) {
+                __syncthreads();
+                jacobian<DMAX, MMAX>(rb, P, lane, n, m, lds);
+                __syncthreads();
+                float ge;
+                dgu = jtj_rows<DMAX, MMAX, float>(lds, ancp, lane, dep, m, max_depth, rows, ge) +
+                      dl * dl + P.w_rest * P.w_rest;
+                g = isj ? ge + dl * rl + P.w_rest * rr : 0.f;
+            }
+        } else if (!first) {
             if (lam >= P.lambda_max) {
                 stalled = true;
                 done = true;
             }
             lam = fminf(lam * P.nu_up, P.lambda_max);
         }
-        if (iters - 1 < P.trace_iters) {
+        if (!first && iters - 1 < P.trace_iters) {
             if (isj) P.trace_q[((int64_t)(iters - 1) * n + lane) * N + p] = q;
             if (lane == 0) P.trace_acc[(int64_t)(iters - 1) * N + p] = acc ? 1 : 0;
         }
+        first = false;
+        if (done || iters >= iter_end) break;
+        // Damped step from the current point.
+        float delta = 0.f;
+        bool ok;
+        {
+            float r[DMAX];
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d) r[d] = rows[d];
+            ok = tree_solve<DMAX, float>(r, dgu, g, lam, P.damping_floor, P.pivot_rel, lane, n, dep,
+                                         ancm, ancp, max_depth, delta);
+        }
+        if (!ok) {
+            // Re-form the damped system and gradient in FP64 from the FP32
+            // Jacobian and residuals, and solve again.
+            flags |= PK_FLAG_FP64;
+            double r[DMAX], gd;
+            double dgd = jtj_rows<DMAX, MMAX, double>(lds, ancp, lane, dep, m, max_depth, r, gd) +
+                         (double)dl * dl + (double)P.w_rest * P.w_rest;
+            gd += (double)dl * rl + (double)P.w_rest * rr;
+            ok = tree_solve<DMAX, double>(r, dgd, isj ? gd : 0.0, lam, P.damping_floor, 0.f, lane,
+                                          n, dep, ancm, ancp, max_depth, delta);
+        }
+        qt = q + delta;
+        evaluate = ok;   // a failed solve counts as a rejected step
     }
     const bool finished = done || iters >= P.max_iters;
     if (finished)
@@ -417,16 +561,16 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, do
         }
     if (isj) P.joints[(int64_t)lane * N + p] = q;
     if (ise) {
-        if (P.pos_err) P.pos_err[(int64_t)lane * N + p] = E.perr;
-        if (P.rot_err) P.rot_err[(int64_t)lane * N + p] = E.rerr;
+        if (P.pos_err) P.pos_err[(int64_t)lane * N + p] = perr;
+        if (P.rot_err) P.rot_err[(int64_t)lane * N + p] = rerr;
     }
     if (lane == 0) {
-        if (P.cost) P.cost[p] = E.cost;
-        P.pose_cost[p] = E.pcost;
+        if (P.cost) P.cost[p] = cost;
+        P.pose_cost[p] = pcost;
         if (P.iters) P.iters[p] = iters;
         if (P.accepts) P.accepts[p] = accepts;
         if (P.status)
-            P.status[p] = (E.meets ? PK_CONVERGED : (stalled ? PK_STALLED : PK_MAX_ITERS)) | flags;
+            P.status[p] = (meets ? PK_CONVERGED : (stalled ? PK_STALLED : PK_MAX_ITERS)) | flags;
         if (P.iters_to_tol) P.iters_to_tol[p] = itt;
         if (resumable) {
             P.st_lambda[p] = lam;
@@ -442,26 +586,27 @@ PK_DEV int64_t pop_item_wave(int32_t *head)
     return (int64_t)__shfl(v, 0, 64);
 }
 
-template <int NMAX, int MMAX>
-__global__ __launch_bounds__(64) void lm_wave_kernel(const RobotC *__restrict__ rb, SolveParams P)
+template <int DMAX, int MMAX>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void lm_wave_kernel(const RobotC *__restrict__ rb, SolveParams P)
 {
-    __shared__ double lds_raw[NMAX * (NMAX + 1)];
+    using L = Lds<DMAX, MMAX>;
+    __shared__ float lds[L::FLOATS];
     const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
     int64_t wi = P.queue_head ? pop_item_wave(P.queue_head) : (int64_t)blockIdx.x;
     while (wi < nact) {
-        wave_problem<NMAX, MMAX>(rb, P, lds_raw, wi);
+        wave_problem<DMAX, MMAX>(rb, P, lds, wi);
         if (!P.queue_head) break;
         __syncthreads();
         wi = pop_item_wave(P.queue_head);
     }
 }
 
-template <int NMAX, int MMAX>
+template <int DMAX, int MMAX>
 hipError_t launch_wave(const RobotC *rb, const SolveParams &P, int persist_blocks, hipStream_t s)
 {
     int64_t grid = P.N;
     if (P.queue_head && persist_blocks > 0 && persist_blocks < grid) grid = persist_blocks;
-    hipLaunchKernelGGL((lm_wave_kernel<NMAX, MMAX>), dim3((unsigned)grid), dim3(64), 0, s, rb, P);
+    hipLaunchKernelGGL((lm_wave_kernel<DMAX, MMAX>), dim3((unsigned)grid), dim3(64), 0, s, rb, P);
     return hipGetLastError();
 }
 

@@ -261,6 +261,9 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
         J.parent = par;
         J.depth = par < 0 ? 0 : R.j[par].depth + 1;
         if (J.depth > R.max_depth) R.max_depth = J.depth;
+        R.janc[j] = par < 0 ? 0 : (R.janc[par] | (1ull << par));
+        for (int d = 0; d < J.depth; ++d) R.anc_at[j][d] = R.anc_at[par][d];
+        R.anc_at[j][J.depth] = (uint8_t)j;
     }
     int tgt = 0, rows = 0;
     for (int k = 0; k < m; ++k) {

@@ -25,6 +25,9 @@ PK_DEV void joint_sincos(float q, float &s, float &c)
     c = __cosf(q);
 }
 
+// 1/x: v_rcp_f32 (about 1 ulp).
+PK_DEV float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // 1/sqrt(d): v_rsq_f32 (about 1 ulp) in FP32, exact in FP64.
 PK_DEV float rsqrt_t(float d) { return __builtin_amdgcn_rsqf(d); }
 PK_DEV double rsqrt_t(double d) { return 1.0 / sqrt(d); }
@@ -106,16 +109,16 @@ PK_DEV void rot_to_quat(const float *R, float &w, float &x, float &y, float &z)
 {
     float tr = R[0] + R[4] + R[8];
     if (tr >= R[0] && tr >= R[4] && tr >= R[8]) {
-        float s = 2.f * sqrtf(1.f + tr), is = 1.f / s;
+        float s = 2.f * sqrtf(1.f + tr), is = rcp(s);
         w = 0.25f * s; x = (R[7] - R[5]) * is; y = (R[2] - R[6]) * is; z = (R[3] - R[1]) * is;
     } else if (R[0] >= R[4] && R[0] >= R[8]) {
-        float s = 2.f * sqrtf(1.f + R[0] - R[4] - R[8]), is = 1.f / s;
+        float s = 2.f * sqrtf(1.f + R[0] - R[4] - R[8]), is = rcp(s);
         w = (R[7] - R[5]) * is; x = 0.25f * s; y = (R[1] + R[3]) * is; z = (R[2] + R[6]) * is;
     } else if (R[4] >= R[8]) {
-        float s = 2.f * sqrtf(1.f + R[4] - R[0] - R[8]), is = 1.f / s;
+        float s = 2.f * sqrtf(1.f + R[4] - R[0] - R[8]), is = rcp(s);
         w = (R[2] - R[6]) * is; x = (R[1] + R[3]) * is; y = 0.25f * s; z = (R[5] + R[7]) * is;
     } else {
-        float s = 2.f * sqrtf(1.f + R[8] - R[0] - R[4]), is = 1.f / s;
+        float s = 2.f * sqrtf(1.f + R[8] - R[0] - R[4]), is = rcp(s);
         w = (R[3] - R[1]) * is; x = (R[2] + R[6]) * is; y = (R[5] + R[7]) * is; z = 0.25f * s;
     }
     if (w < 0.f) { w = -w; x = -x; y = -y; z = -z; }
@@ -153,7 +156,8 @@ PK_DEV PoseLog pose_log(const float *Rt, const float *Re, const float *d)
     float s = sqrtf(x * x + y * y + z * z);
     float theta = 2.f * atan2f(s, w);
     // phi = theta * v / |v|;  theta / s -> 2 / w (1 - s^2 / (3 w^2)) as s -> 0.
-    float f = s < 1e-4f ? (2.f / w) * (1.f - s * s / (3.f * w * w)) : theta / s;
+    const float iw = rcp(w);
+    float f = s < 1e-4f ? 2.f * iw * (1.f - (1.f / 3.f) * s * s * iw * iw) : theta * rcp(s);
     L.phi[0] = f * x; L.phi[1] = f * y; L.phi[2] = f * z;
     L.theta = theta;
     L.sh = s;
@@ -164,7 +168,7 @@ PK_DEV PoseLog pose_log(const float *Rt, const float *Re, const float *d)
     if (theta < 0.1f)
         k = 1.f / 12.f + t2 * (1.f / 720.f + t2 * (1.f / 30240.f));
     else
-        k = (1.f - 0.5f * theta * w / s) / t2;
+        k = (1.f - 0.5f * theta * w * rcp(s)) * rcp(t2);
     float a[3], b[3];
     cross(L.phi, tE, a);
     cross(L.phi, a, b);
@@ -184,17 +188,17 @@ PK_DEV void jr_inv_blocks(const PoseLog &L, const float *Re, float *M, float *N)
     if (th < 0.1f)
         k = 1.f / 12.f + t2 * (1.f / 720.f + t2 * (1.f / 30240.f));
     else
-        k = (1.f - 0.5f * th * L.ch / L.sh) / t2;
+        k = (1.f - 0.5f * th * L.ch * rcp(L.sh)) * rcp(t2);
     if (th < 0.5f) {
         a1 = 1.f / 6.f + t2 * (-1.f / 120.f + t2 * (1.f / 5040.f - t2 * (1.f / 362880.f)));
         a2 = 1.f / 24.f + t2 * (-1.f / 720.f + t2 * (1.f / 40320.f - t2 * (1.f / 3628800.f)));
         a3 = 1.f / 120.f + t2 * (-1.f / 2520.f + t2 * (1.f / 120960.f - t2 * (1.f / 9979200.f)));
     } else {
         const float st = 2.f * L.sh * L.ch, ct = L.ch * L.ch - L.sh * L.sh;
-        const float t3 = t2 * th, t4 = t2 * t2;
-        a1 = (th - st) / t3;
-        a2 = (t2 - 4.f * L.sh * L.sh) / (2.f * t4);       // 2 cos - 2 = -4 sin^2(th/2)
-        a3 = (2.f * th - 3.f * st + th * ct) / (2.f * t4 * th);
+        const float it = rcp(th), it2 = it * it, it3 = it2 * it;
+        a1 = (th - st) * it3;
+        a2 = (t2 - 4.f * L.sh * L.sh) * (0.5f * it2 * it2);   // 2 cos - 2 = -4 sin^2(th/2)
+        a3 = (2.f * th - 3.f * st + th * ct) * (0.5f * it3 * it2);
     }
     float Ph[9], Rh[9], PP[9];
     hat(L.phi, Ph);

@@ -41,6 +41,8 @@ struct RobotC {
     JointC j[PK_MAX_JOINTS];
     EEC e[PK_MAX_EES];
     float mid[PK_MAX_JOINTS];              // (lower + upper) / 2, the default rest pose
+    uint64_t janc[PK_MAX_JOINTS];          // bit i set iff joint i is a proper ancestor of joint j
+    uint8_t anc_at[PK_MAX_JOINTS][PK_MAX_JOINTS];   // [j][d]: ancestor of j at depth d (d <= depth j; j itself at its depth)
 };
 
 // Uniform per-call data for the LM kernels (passed by value).

@@ -36,17 +36,18 @@ PK_DEV float silu_grad(float z)
     return s * (1.f + z * (1.f - s));
 }
 
-struct EpiStore {           // C = acc (FP32)
+struct EpiStore {           // C[z] = acc (FP32); z = split-K slice, slices `zstride` apart
     float *C;
     int ld;
-    PK_DEV void operator()(int m, int n, float v) const { C[(size_t)m * ld + n] = v; }
+    size_t zstride;
+    PK_DEV void operator()(int m, int n, int z, float v) const { C[z * zstride + (size_t)m * ld + n] = v; }
 };
 struct EpiHidden {          // z = acc + b; Z = z; H = bf16(SiLU(z))
     const float *bias;
     float *Z;
     __bf16 *H;
     int ld;
-    PK_DEV void operator()(int m, int n, float v) const
+    PK_DEV void operator()(int m, int n, int, float v) const
     {
         const float z = v + bias[n];
         if (Z) Z[(size_t)m * ld + n] = z;
@@ -57,14 +58,14 @@ struct EpiOut {             // y = acc + b
     const float *bias;
     float *Y;
     int ld;
-    PK_DEV void operator()(int m, int n, float v) const { Y[(size_t)m * ld + n] = v + bias[n]; }
+    PK_DEV void operator()(int m, int n, int, float v) const { Y[(size_t)m * ld + n] = v + bias[n]; }
 };
 struct EpiBackHidden {      // dZ = acc * SiLU'(Z): FP32 and BF16 copies
     const float *Z;
     float *dZ;
     __bf16 *dZb;
     int ld;
-    PK_DEV void operator()(int m, int n, float v) const
+    PK_DEV void operator()(int m, int n, int, float v) const
     {
         const size_t i = (size_t)m * ld + n;
         const float g = v * silu_grad(Z[i]);
@@ -73,6 +74,8 @@ struct EpiBackHidden {      // dZ = acc * SiLU'(Z): FP32 and BF16 copies
     }
 };
 
+// blockIdx.z selects one of gridDim.z equal slices of K (split-K); the
+// epilogue receives the slice index so partial products can be kept apart.
 template <int AL, int BL, int WM, int WN, class Epi>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __bf16 *__restrict__ A,
                                                    int lda, const __bf16 *__restrict__ B, int ldb,
@@ -90,7 +93,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    const int kslice = K / (int)gridDim.z;
+    const int kbeg = (int)blockIdx.z * kslice, kend = kbeg + kslice;
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
         if (AL == A_MK) {
             for (int v = tid; v < BM * 4; v += 256) {
                 const int r = v >> 2, c = (v & 3) * 8;
@@ -140,35 +145,56 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __
             for (int e = 0; e < 4; ++e) {
                 const int m = m0 + wm * 16 * WM + 16 * i + 4 * (lane >> 4) + e;
                 const int n = n0 + wn * 16 * WN + 16 * j + (lane & 15);
-                epi(m, n, acc[i][j][e]);
+                epi(m, n, (int)blockIdx.z, acc[i][j][e]);
             }
 }
 
 template <int AL, int BL, int WM, int WN, class Epi>
 hipError_t gemm_tile(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb, Epi epi,
-                     hipStream_t s)
+                     hipStream_t s, int splits)
 {
-    dim3 grid(N / (32 * WN), M / (32 * WM));
+    dim3 grid(N / (32 * WN), M / (32 * WM), splits);
     hipLaunchKernelGGL((gemm_kernel<AL, BL, WM, WN, Epi>), grid, dim3(256), 0, s, M, N, K, A, lda, B,
                        ldb, epi);
     return hipGetLastError();
 }
 
-// Picks the tile for the shape (M % 64 == 0, N % 32 == 0, K % 32 == 0).
+// Picks the tile for the shape (M % 64 == 0, N % 32 == 0, K % (32 * splits) == 0).
 template <int AL, int BL, class Epi>
 hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb, Epi epi,
-                hipStream_t s)
+                hipStream_t s, int splits = 1)
 {
-    if (M % 64 || N % 32 || K % 32) return hipErrorInvalidValue;
+    if (M % 64 || N % 32 || splits < 1 || K % (32 * splits)) return hipErrorInvalidValue;
     const bool m128 = M % 128 == 0;
     if (N % 128 == 0)
-        return m128 ? gemm_tile<AL, BL, 4, 4>(M, N, K, A, lda, B, ldb, epi, s)
-                    : gemm_tile<AL, BL, 2, 4>(M, N, K, A, lda, B, ldb, epi, s);
+        return m128 ? gemm_tile<AL, BL, 4, 4>(M, N, K, A, lda, B, ldb, epi, s, splits)
+                    : gemm_tile<AL, BL, 2, 4>(M, N, K, A, lda, B, ldb, epi, s, splits);
     if (N % 64 == 0)
-        return m128 ? gemm_tile<AL, BL, 4, 2>(M, N, K, A, lda, B, ldb, epi, s)
-                    : gemm_tile<AL, BL, 2, 2>(M, N, K, A, lda, B, ldb, epi, s);
-    return m128 ? gemm_tile<AL, BL, 4, 1>(M, N, K, A, lda, B, ldb, epi, s)
-                : gemm_tile<AL, BL, 2, 1>(M, N, K, A, lda, B, ldb, epi, s);
+        return m128 ? gemm_tile<AL, BL, 4, 2>(M, N, K, A, lda, B, ldb, epi, s, splits)
+                    : gemm_tile<AL, BL, 2, 2>(M, N, K, A, lda, B, ldb, epi, s, splits);
+    return m128 ? gemm_tile<AL, BL, 4, 1>(M, N, K, A, lda, B, ldb, epi, s, splits)
+                : gemm_tile<AL, BL, 2, 1>(M, N, K, A, lda, B, ldb, epi, s, splits);
+}
+
+// Number of K slices so that an (M x N) output with a K-long reduction
+// fills the device: about 256 workgroups, each slice at least 256 long.
+inline int split_for(int M, int N, int K)
+{
+    const int tm = M % 128 == 0 ? 128 : 64, tn = N % 128 == 0 ? 128 : N % 64 == 0 ? 64 : 32;
+    const int tiles = (M / tm) * (N / tn);
+    int sp = 1;
+    while (tiles * sp < 256 && K % (64 * sp) == 0 && K / (2 * sp) >= 256) sp *= 2;
+    return sp;
+}
+
+// out[i] = sum over z of part[z * count + i] (fixed order).
+__global__ void split_reduce_kernel(int64_t count, int splits, const float *__restrict__ part, float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[z * count + i];
+    out[i] = s;
 }
 
 // ------------------------------------------------------------ small kernels
@@ -375,6 +401,8 @@ struct SeederState {
     int64_t cap = 0;
     __bf16 *X0 = nullptr, *Hb = nullptr, *dZb = nullptr, *dYb = nullptr;
     float *Z = nullptr, *Y = nullptr, *dZ = nullptr, *dY = nullptr, *Q = nullptr, *part = nullptr;
+    float *splitbuf = nullptr;          // split-K partial weight gradients
+    size_t splitbuf_floats = 0;
     std::vector<void *> extra;
 };
 
@@ -382,7 +410,7 @@ void seeder_free(SeederState *s)
 {
     if (!s) return;
     void *ptrs[] = {s->P, s->G, s->M, s->V, s->Pb, s->dstep, s->X0, s->Hb, s->dZb, s->dYb, s->Z,
-                    s->Y, s->dZ, s->dY, s->Q, s->part};
+                    s->Y, s->dZ, s->dY, s->Q, s->part, s->splitbuf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (void *p : s->extra)
@@ -412,6 +440,16 @@ int alloc_acts(pk_ctx *ctx, SeederState *s, int64_t rows)
     ok &= hipMalloc(&s->Q, rows * s->n * sizeof(float)) == hipSuccess;
     ok &= hipMalloc(&s->part, (rows / 256 + 1) * (size_t)std::max(s->H, s->out_pad) * sizeof(float) +
                                   4096) == hipSuccess;
+    size_t need = 0;
+    for (int l = 0; l <= L; ++l) {
+        const int M = s->lout[l], N = s->lin[l];
+        const int sp = sd::split_for(M, N, (int)rows);
+        if (sp > 1) need = std::max(need, (size_t)sp * M * N);
+    }
+    if (s->splitbuf) (void)hipFree(s->splitbuf);
+    s->splitbuf = nullptr;
+    s->splitbuf_floats = need;
+    if (need) ok &= hipMalloc(&s->splitbuf, need * sizeof(float)) == hipSuccess;
     if (!ok) {
         s->cap = 0;
         return fail(ctx, PK_ENOMEM, "seeder: activation allocation for %lld rows failed", (long long)rows);
@@ -448,6 +486,22 @@ hipError_t forward(SeederState *s, int64_t rows, bool train, hipStream_t st)
                             EpiOut{s->P + s->boff[L], s->Y, s->out_pad}, st);
 }
 
+// Weight gradient dW [M][N] = A^T B reduced over `rows` (split-K + fixed-order sum).
+hipError_t weight_grad(SeederState *s, int M, int N, int64_t rows, const __bf16 *A, int lda,
+                       const __bf16 *B, int ldb, float *out, hipStream_t st)
+{
+    using namespace sd;
+    const int sp = split_for(M, N, (int)rows);
+    if (sp == 1)
+        return gemm<A_KM, B_KN>(M, N, (int)rows, A, lda, B, ldb, EpiStore{out, N, 0}, st);
+    const size_t cnt = (size_t)M * N;
+    hipError_t e = gemm<A_KM, B_KN>(M, N, (int)rows, A, lda, B, ldb, EpiStore{s->splitbuf, N, cnt}, st, sp);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(split_reduce_kernel, dim3(blocks((int64_t)cnt, 256)), dim3(256), 0, st, (int64_t)cnt, sp,
+                       s->splitbuf, out);
+    return hipGetLastError();
+}
+
 // Loss gradient in dY/dYb -> parameter gradients in G.
 hipError_t backward(SeederState *s, int64_t rows, hipStream_t st)
 {
@@ -457,8 +511,7 @@ hipError_t backward(SeederState *s, int64_t rows, hipStream_t st)
     const int nchunk = (int)((rows + 255) / 256);
     // output layer
     const __bf16 *Hlast = s->Hb + (size_t)(L - 1) * rows * s->H;
-    e = gemm<A_KM, B_KN>(s->out_pad, s->H, (int)rows, s->dYb, s->out_pad, Hlast, s->H,
-                         EpiStore{s->G + s->woff[L], s->H}, st);
+    e = weight_grad(s, s->out_pad, s->H, rows, s->dYb, s->out_pad, Hlast, s->H, s->G + s->woff[L], st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(colsum_pass1, dim3(blocks(s->out_pad, 256), nchunk), dim3(256), 0, st, (int)rows,
                        s->out_pad, s->dY, s->part);
@@ -474,8 +527,7 @@ hipError_t backward(SeederState *s, int64_t rows, hipStream_t st)
         if (e != hipSuccess) return e;
         const __bf16 *inl = l == 0 ? s->X0 : s->Hb + (size_t)(l - 1) * rows * s->H;
         const int ldin = l == 0 ? s->in_pad : s->H;
-        e = gemm<A_KM, B_KN>(s->H, s->lin[l], (int)rows, s->dZb, s->H, inl, ldin,
-                             EpiStore{s->G + s->woff[l], s->lin[l]}, st);
+        e = weight_grad(s, s->H, s->lin[l], rows, s->dZb, s->H, inl, ldin, s->G + s->woff[l], st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(colsum_pass1, dim3(blocks(s->H, 256), nchunk), dim3(256), 0, st, (int)rows,
                            s->H, s->dZ, s->part);

@@ -16,6 +16,10 @@ Per term (n joints, m EEs, a_k ancestors of EE k):
   Cholesky           b^3 / 3 per factored block of size b
   triangular solves  2 b^2 per block
   damping + update   3 n
+or, for the leaves-first tree factorization (blocks=None; d_k = number of
+proper ancestors of joint k, the factor has no fill):
+  L^T D L factor     sum_k d_k (d_k + 1) + d_k
+  triangular solves  4 sum_k d_k
 """
 from __future__ import annotations
 
@@ -31,8 +35,22 @@ def ancestors(parent, ee_joint):
     return out
 
 
+def depths(parent):
+    d = []
+    for j, p in enumerate(parent):
+        d.append(0 if int(p) < 0 else d[int(p)] + 1)
+    return d
+
+
+def tree_solve_flops(parent):
+    """Leaves-first L^T D L factor of a tree-structured J^T J plus both solves."""
+    ds = depths(parent)
+    return float(sum(d * (d + 1) + d for d in ds) + 4 * sum(ds))
+
+
 def per_unit(parent, ee_joint, ee_kind, blocks):
-    """(FLOPs per trial, extra FLOPs per accepted trial)."""
+    """(FLOPs per trial, extra FLOPs per accepted trial).  blocks: sizes of
+    the dense diagonal blocks factored, or None for the tree factorization."""
     n, m = len(parent), len(ee_joint)
     anc = ancestors(parent, ee_joint)
     trial = 36 * n + 18 * m + 9 * n + 3 * n
@@ -44,8 +62,11 @@ def per_unit(parent, ee_joint, ee_kind, blocks):
         else:
             trial += 12
             acc += 12 * a + 6 * a * (a + 1) // 2 + 6 * a
-    for b in blocks:
-        trial += b ** 3 / 3.0 + 2 * b * b
+    if blocks is None:
+        trial += tree_solve_flops(parent)
+    else:
+        for b in blocks:
+            trial += b ** 3 / 3.0 + 2 * b * b
     return float(trial), float(acc)
 
 

@@ -47,6 +47,19 @@ def solve_gpu(ctx, rid, tree, tg, seeds, K, weights, options, trace_iters=0, bes
     return res
 
 
+def borderline_at(tree, tg, w, trace_q, it, tol_pos=1e-3, tol_rot=1e-2, frac=0.05):
+    """The oracle's iterate after iteration `it` (1-based) has an EE error
+    within 5% of a tolerance, so the iteration at which FP32 first meets the
+    tolerance may differ from FP64's by rounding."""
+    import oracle
+    if it < 1 or it > len(trace_q):
+        return False
+    _, pe, re = oracle.residual(tree, tg, w, trace_q[it - 1])
+    pose = np.asarray(tree.ee_kind) == 0
+    return bool(np.any(np.abs(pe - tol_pos) <= frac * tol_pos) or
+                np.any((np.abs(re - tol_rot) <= frac * tol_rot) & pose))
+
+
 def borderline(ora_res, p, tol_pos=1e-3, tol_rot=1e-2, frac=0.05):
     """Oracle's final error within 5% of a tolerance (success not decidable in FP32)."""
     pe, re = ora_res["pos_err"][p], ora_res["rot_err"][p]

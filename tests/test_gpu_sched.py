@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import borderline, soa, targets_dev
+from tests.gpu_util import borderline, borderline_at, soa, targets_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -98,8 +98,12 @@ def test_autotune_and_oracle_sample(ctx, batch):
                     excused += 1
                 else:
                     bad += 1
-            elif cg and not o["trace_tie"].any():
-                assert out["iters"][p] == o["iters"]
+            elif cg and not o["trace_tie"].any() and out["iters"][p] != o["iters"]:
+                # the tolerance crossing itself may be borderline in FP32
+                it = int(min(out["iters"][p], o["iters"]))
+                assert borderline_at(g["tree"], g["tg"][p // g["K"]], g["wd"], o["trace_q"], it), \
+                    (g["tree"].name, int(p), int(out["iters"][p]), int(o["iters"]))
+                excused += 1
         print(f"{g['tree'].name}: success {np.mean((out['status'] & 0xff) == 0):.3f}")
     print(f"oracle sample: {bad} unexplained, {excused} excused")
     assert bad == 0

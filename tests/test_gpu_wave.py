@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import borderline, solve_gpu
+from tests.gpu_util import borderline, borderline_at, solve_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -125,5 +125,8 @@ def test_hand_early_exit_wave_vs_oracle(ctx):
         if cg != co and not _excusable(ora):
             bad += 1
         if cg and co and not ora["trace_tie"].any():
-            assert res["iters"][p] == ora["iters"] == ora["iters_to_tol"]
+            assert ora["iters"] == ora["iters_to_tol"]
+            if res["iters"][p] != ora["iters"]:
+                it = int(min(res["iters"][p], ora["iters"]))
+                assert borderline_at(tree, tg[p], wts, ora["trace_q"], it), (p, res["iters"][p], ora["iters"])
     assert bad == 0
