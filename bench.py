@@ -21,6 +21,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VALU_PEAK = 157.3      # TFLOP/s, MI355X FP32 vector (datasheet; packed FP32)
+
+# HBM traffic per launch of the arm LM kernel: rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for
+# a 256 MiB device-to-device copy (--copy-probe).  Valid only while the kernel
+# sources hash to `sha256`; otherwise the bench reports traffic as null.
+LANE_KERNEL_SOURCES = ["paper_2505_03728_amd/csrc/lm_lane.hip", "paper_2505_03728_amd/csrc/pk_device.hpp",
+                       "paper_2505_03728_amd/csrc/pk_internal.hpp", "include/pkmi.h"]
+ARM_TRAFFIC = {"sha256": "1e34b4d2241b8097", "fetch_kib": 2920.0, "write_kib": 7680.0, "fetch_scale": 2.0,
+               "write_scale": 1.0}
+
+
+def sources_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in files:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def arm_traffic_bytes():
+    t = ARM_TRAFFIC
+    if t["sha256"] is None or t["sha256"] != sources_hash(LANE_KERNEL_SOURCES):
+        return None
+    return round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
 FP32_VALU_UNPACKED = 78.6   # TFLOP/s, 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 
 
@@ -180,7 +206,8 @@ def main():
         "iters_to_tol_mean_per_target": float(itt_t[solved].mean()) if solved.any() else None,
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP32_VALU_PEAK,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK, 5),
-                     "traffic": None, "kernel": "lm_lane_kernel<1,7,pose>" if args.variant != 2
+                     "traffic": arm_traffic_bytes() if args.variant != 2 else None,
+                     "kernel": "lm_lane_kernel<1,7,pose>" if args.variant != 2
                      else "lm_wave_kernel", "kernel_ms": round(k_ms, 5),
                      "algorithmic_flops": flops, "algorithmic_hbm_bytes": hbm,
                      "peak_unpacked_fp32": FP32_VALU_UNPACKED,

@@ -76,12 +76,17 @@ struct EpiBackHidden {      // dZ = acc * SiLU'(Z): FP32 and BF16 copies
 
 // blockIdx.z selects one of gridDim.z equal slices of K (split-K); the
 // epilogue receives the slice index so partial products can be kept apart.
-template <int AL, int BL, int WM, int WN, class Epi>
+// The next K stage is fetched from global memory into registers while the
+// current stage, staged in LDS with the reduction dimension contiguous, feeds
+// the MFMAs.
+template <int AL, int BL, int WM, int WN, int BK, class Epi>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __bf16 *__restrict__ A,
                                                    int lda, const __bf16 *__restrict__ B, int ldb,
                                                    Epi epi)
 {
-    constexpr int BM = 32 * WM, BN = 32 * WN, BK = 32, LDK = BK + 8;
+    constexpr int BM = 32 * WM, BN = 32 * WN, LDK = BK + 8;
+    constexpr int NVA = BM * BK / 8, NVB = BN * BK / 8;             // 8-element vectors per stage
+    constexpr int RA = (NVA + 255) / 256, RB = (NVB + 255) / 256;   // per thread
     __shared__ __attribute__((aligned(16))) __bf16 sA[BM * LDK];
     __shared__ __attribute__((aligned(16))) __bf16 sB[BN * LDK];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -93,48 +98,83 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    bf16x8 ra[RA], rb[RB];
+    // Vector v of a stage: MK/NK layout -> (row v / (BK/8), k 8 * (v % (BK/8)));
+    // KM/KN layout -> (k v / (BM/8), row 8 * (v % (BM/8))).
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < RA; ++i) {
+            const int v = tid + 256 * i;
+            if (v < NVA) {
+                if (AL == A_MK)
+                    ra[i] = *(const bf16x8 *)&A[(size_t)(m0 + v / (BK / 8)) * lda + k0 + 8 * (v % (BK / 8))];
+                else
+                    ra[i] = *(const bf16x8 *)&A[(size_t)(k0 + v / (BM / 8)) * lda + m0 + 8 * (v % (BM / 8))];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int v = tid + 256 * i;
+            if (v < NVB) {
+                if (BL == B_NK)
+                    rb[i] = *(const bf16x8 *)&B[(size_t)(n0 + v / (BK / 8)) * ldb + k0 + 8 * (v % (BK / 8))];
+                else
+                    rb[i] = *(const bf16x8 *)&B[(size_t)(k0 + v / (BN / 8)) * ldb + n0 + 8 * (v % (BN / 8))];
+            }
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < RA; ++i) {
+            const int v = tid + 256 * i;
+            if (v < NVA) {
+                if (AL == A_MK) {
+                    *(bf16x8 *)&sA[(v / (BK / 8)) * LDK + 8 * (v % (BK / 8))] = ra[i];
+                } else {
+                    const int kk = v / (BM / 8), mm = 8 * (v % (BM / 8));
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) sA[(mm + e) * LDK + kk] = ra[i][e];
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int v = tid + 256 * i;
+            if (v < NVB) {
+                if (BL == B_NK) {
+                    *(bf16x8 *)&sB[(v / (BK / 8)) * LDK + 8 * (v % (BK / 8))] = rb[i];
+                } else {
+                    const int kk = v / (BN / 8), nn = 8 * (v % (BN / 8));
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) sB[(nn + e) * LDK + kk] = rb[i][e];
+                }
+            }
+        }
+    };
+
     const int kslice = K / (int)gridDim.z;
     const int kbeg = (int)blockIdx.z * kslice, kend = kbeg + kslice;
+    gload(kbeg);
     for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        if (AL == A_MK) {
-            for (int v = tid; v < BM * 4; v += 256) {
-                const int r = v >> 2, c = (v & 3) * 8;
-                *(bf16x8 *)&sA[r * LDK + c] = *(const bf16x8 *)&A[(size_t)(m0 + r) * lda + k0 + c];
-            }
-        } else {
-            for (int v = tid; v < BK * (BM / 8); v += 256) {
-                const int kk = v / (BM / 8), mm = (v % (BM / 8)) * 8;
-                const bf16x8 x = *(const bf16x8 *)&A[(size_t)(k0 + kk) * lda + m0 + mm];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) sA[(mm + e) * LDK + kk] = x[e];
-            }
-        }
-        if (BL == B_NK) {
-            for (int v = tid; v < BN * 4; v += 256) {
-                const int r = v >> 2, c = (v & 3) * 8;
-                *(bf16x8 *)&sB[r * LDK + c] = *(const bf16x8 *)&B[(size_t)(n0 + r) * ldb + k0 + c];
-            }
-        } else {
-            for (int v = tid; v < BK * (BN / 8); v += 256) {
-                const int kk = v / (BN / 8), nn = (v % (BN / 8)) * 8;
-                const bf16x8 x = *(const bf16x8 *)&B[(size_t)(k0 + kk) * ldb + n0 + nn];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) sB[(nn + e) * LDK + kk] = x[e];
-            }
-        }
         __syncthreads();
-        bf16x8 af[WM], bfr[WN];
-        const int kq = 8 * (lane >> 4), r16 = lane & 15;
-#pragma unroll
-        for (int i = 0; i < WM; ++i) af[i] = *(const bf16x8 *)&sA[(wm * 16 * WM + 16 * i + r16) * LDK + kq];
-#pragma unroll
-        for (int j = 0; j < WN; ++j) bfr[j] = *(const bf16x8 *)&sB[(wn * 16 * WN + 16 * j + r16) * LDK + kq];
-#pragma unroll
-        for (int i = 0; i < WM; ++i)
-#pragma unroll
-            for (int j = 0; j < WN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        lstore();
         __syncthreads();
+        if (k0 + BK < kend) gload(k0 + BK);
+        const int r16 = lane & 15;
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 32) {
+            const int kq = ks + 8 * (lane >> 4);
+            bf16x8 af[WM], bfr[WN];
+#pragma unroll
+            for (int i = 0; i < WM; ++i) af[i] = *(const bf16x8 *)&sA[(wm * 16 * WM + 16 * i + r16) * LDK + kq];
+#pragma unroll
+            for (int j = 0; j < WN; ++j) bfr[j] = *(const bf16x8 *)&sB[(wn * 16 * WN + 16 * j + r16) * LDK + kq];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
     }
     // D layout: lane l holds rows 4*(l/16)+e, column l%16 of each 16x16 tile.
 #pragma unroll
@@ -154,8 +194,12 @@ hipError_t gemm_tile(int M, int N, int K, const __bf16 *A, int lda, const __bf16
                      hipStream_t s, int splits)
 {
     dim3 grid(N / (32 * WN), M / (32 * WM), splits);
-    hipLaunchKernelGGL((gemm_kernel<AL, BL, WM, WN, Epi>), grid, dim3(256), 0, s, M, N, K, A, lda, B,
-                       ldb, epi);
+    if ((K / splits) % 64 == 0)
+        hipLaunchKernelGGL((gemm_kernel<AL, BL, WM, WN, 64, Epi>), grid, dim3(256), 0, s, M, N, K, A, lda,
+                           B, ldb, epi);
+    else
+        hipLaunchKernelGGL((gemm_kernel<AL, BL, WM, WN, 32, Epi>), grid, dim3(256), 0, s, M, N, K, A, lda,
+                           B, ldb, epi);
     return hipGetLastError();
 }
 
@@ -184,6 +228,17 @@ inline int split_for(int M, int N, int K)
     const int tiles = (M / tm) * (N / tn);
     int sp = 1;
     while (tiles * sp < 256 && K % (64 * sp) == 0 && K / (2 * sp) >= 256) sp *= 2;
+    return sp;
+}
+
+// Largest split_for(M, N, K) over all K: the smallest power of two that
+// brings the tile count to 256.
+inline int split_max(int M, int N)
+{
+    const int tm = M % 128 == 0 ? 128 : 64, tn = N % 128 == 0 ? 128 : N % 64 == 0 ? 64 : 32;
+    const int tiles = (M / tm) * (N / tn);
+    int sp = 1;
+    while (tiles * sp < 256) sp *= 2;
     return sp;
 }
 
@@ -223,17 +278,21 @@ __global__ void encode_kernel(int64_t rows, int64_t valid, const float *__restri
 
 // One training batch: X0 rows from the pre-encoded inputs, Q from the joint
 // values, sample order from the caller's permutation.
-__global__ void gather_kernel(int B, int64_t S, int n, int in_pad, int steps_per_epoch,
-                              const int *__restrict__ dstep, const int *__restrict__ perm,
+// Training rows of local step (*dstep - step0) of a train call with nsteps
+// steps: epoch e uses perm row e (or index order), batch b its rows b*B...
+__global__ void gather_kernel(int B, int64_t S, int n, int in_pad, int steps_per_epoch, int nsteps,
+                              int step0, const int *__restrict__ dstep, const int *__restrict__ perm,
                               const float *__restrict__ xall, const float *__restrict__ qtrain,
                               __bf16 *X0, float *Q)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B) return;
-    const int step = *dstep;
-    const int64_t e = step / steps_per_epoch, b = step % steps_per_epoch;
+    const int local = *dstep - step0;
+    if (local < 0 || local >= nsteps) return;
+    const int64_t e = local / steps_per_epoch, b = local % steps_per_epoch;
     const int64_t pos = b * B + i;
     const int64_t idx = perm ? perm[e * S + pos] : pos;
+    if (idx < 0 || idx >= S) return;
     for (int u = 0; u < in_pad; ++u) X0[(int64_t)i * in_pad + u] = (__bf16)(u < 7 ? xall[idx * 7 + u] : 0.f);
     for (int j = 0; j < n; ++j) Q[(int64_t)i * n + j] = qtrain[(int64_t)j * S + idx];
 }
@@ -281,14 +340,17 @@ __global__ __launch_bounds__(256) void loss_kernel(int B, int n, int K, int out_
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// loss_log[*dstep - step0] (when within [0, nlog)) and/or *loss_out.
 __global__ void loss_finish_kernel(int nparts, int B, const float *__restrict__ partial,
-                                   const int *__restrict__ dstep, float *loss_log, float *loss_out)
+                                   const int *__restrict__ dstep, int step0, int nlog, float *loss_log,
+                                   float *loss_out)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     float s = 0.f;
     for (int i = 0; i < nparts; ++i) s += partial[i];
     s /= (float)B;
-    if (loss_log) loss_log[*dstep] = s;
+    const int li = *dstep - step0;
+    if (loss_log && li >= 0 && li < nlog) loss_log[li] = s;
     if (loss_out) *loss_out = s;
 }
 
@@ -440,16 +502,19 @@ int alloc_acts(pk_ctx *ctx, SeederState *s, int64_t rows)
     ok &= hipMalloc(&s->Q, rows * s->n * sizeof(float)) == hipSuccess;
     ok &= hipMalloc(&s->part, (rows / 256 + 1) * (size_t)std::max(s->H, s->out_pad) * sizeof(float) +
                                   4096) == hipSuccess;
+    // Split-K partials: sized for the largest split any row count can pick.
     size_t need = 0;
     for (int l = 0; l <= L; ++l) {
         const int M = s->lout[l], N = s->lin[l];
-        const int sp = sd::split_for(M, N, (int)rows);
-        if (sp > 1) need = std::max(need, (size_t)sp * M * N);
+        need = std::max(need, (size_t)sd::split_max(M, N) * M * N);
     }
     if (s->splitbuf) (void)hipFree(s->splitbuf);
     s->splitbuf = nullptr;
-    s->splitbuf_floats = need;
-    if (need) ok &= hipMalloc(&s->splitbuf, need * sizeof(float)) == hipSuccess;
+    s->splitbuf_floats = 0;
+    if (hipMalloc(&s->splitbuf, need * sizeof(float)) == hipSuccess)
+        s->splitbuf_floats = need;
+    else
+        ok = false;
     if (!ok) {
         s->cap = 0;
         return fail(ctx, PK_ENOMEM, "seeder: activation allocation for %lld rows failed", (long long)rows);
@@ -491,7 +556,8 @@ hipError_t weight_grad(SeederState *s, int M, int N, int64_t rows, const __bf16 
                        const __bf16 *B, int ldb, float *out, hipStream_t st)
 {
     using namespace sd;
-    const int sp = split_for(M, N, (int)rows);
+    int sp = split_for(M, N, (int)rows);
+    while (sp > 1 && (size_t)sp * M * N > s->splitbuf_floats) sp /= 2;
     if (sp == 1)
         return gemm<A_KM, B_KN>(M, N, (int)rows, A, lda, B, ldb, EpiStore{out, N, 0}, st);
     const size_t cnt = (size_t)M * N;
@@ -684,8 +750,10 @@ namespace {
 
 // Loss + gradients for `rows` rows already in X0 / Q; loss_out (device) gets
 // the mean loss.  `B` is the number of real rows (the loss averages over B).
-hipError_t loss_and_grads(SeederState *s, int64_t rows, int64_t B, float *loss_log, float *loss_out,
-                          hipStream_t st)
+// Loss (into loss_log[step - step0] for steps within [step0, step0 + nlog),
+// and/or *loss_out) and parameter gradients of rows rows (B of them valid).
+hipError_t loss_and_grads(SeederState *s, int64_t rows, int64_t B, float *loss_log, int step0, int nlog,
+                          float *loss_out, hipStream_t st)
 {
     using namespace sd;
     hipError_t e = forward(s, rows, true, st);
@@ -694,7 +762,7 @@ hipError_t loss_and_grads(SeederState *s, int64_t rows, int64_t B, float *loss_l
     hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(256), 0, st, (int)B, s->n, s->K, s->out_pad, s->Y,
                        s->Q, s->dY, s->dYb, s->part);
     hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(1), 0, st, (int)nb, (int)B, s->part, s->dstep,
-                       loss_log, loss_out);
+                       step0, nlog, loss_log, loss_out);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return backward(s, rows, st);
@@ -769,7 +837,7 @@ int pk_seeder_grad(pk_ctx *ctx, int32_t id, const float *x, const float *q, int6
     hipLaunchKernelGGL(sd::load_rows_kernel, dim3(sd::blocks(B, 256)), dim3(256), 0, st, B, B, s->in_pad,
                        s->n, x, q, s->X0, s->Q);
     PK_HIP(ctx, hipGetLastError());
-    PK_HIP(ctx, loss_and_grads(s, B, B, nullptr, loss, st));
+    PK_HIP(ctx, loss_and_grads(s, B, B, nullptr, 0, 0, loss, st));
     return PK_OK;
 }
 
@@ -808,8 +876,8 @@ int pk_seeder_train(pk_ctx *ctx, int32_t id, const float *q_train, int64_t S, in
     const int steps = spe * epochs;
     for (int t = 0; t < steps && e == hipSuccess; ++t) {
         hipLaunchKernelGGL(sd::gather_kernel, dim3(sd::blocks(batch, 256)), dim3(256), 0, st, batch, S, s->n,
-                           s->in_pad, spe, s->dstep, perm, xall, q_train, s->X0, s->Q);
-        e = loss_and_grads(s, batch, batch, loss_log ? loss_log - s->host_step : nullptr, nullptr, st);
+                           s->in_pad, spe, steps, s->host_step, s->dstep, perm, xall, q_train, s->X0, s->Q);
+        e = loss_and_grads(s, batch, batch, loss_log, s->host_step, steps, nullptr, st);
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(sd::adam_kernel, dim3(sd::blocks(s->nparam, 256)), dim3(256), 0, st, s->nparam, lr,
                            0.9f, 0.999f, 1e-8f, s->dstep, s->P, s->G, s->M, s->V, s->Pb);
@@ -821,7 +889,8 @@ int pk_seeder_train(pk_ctx *ctx, int32_t id, const float *q_train, int64_t S, in
     (void)hipFree(xall);
     if (e != hipSuccess) return fail(ctx, PK_EHIP, "pk_seeder_train: %s", hipGetErrorString(e));
     if (e2 != hipSuccess) return fail(ctx, PK_EHIP, "pk_seeder_train: %s", hipGetErrorString(e2));
-    s->host_step += steps;
+    // the next call's local steps count from the device counter
+    PK_HIP(ctx, hipMemcpy(&s->host_step, s->dstep, sizeof(int), hipMemcpyDeviceToHost));
     return PK_OK;
 }
 

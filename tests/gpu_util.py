@@ -60,6 +60,58 @@ def borderline_at(tree, tg, w, trace_q, it, tol_pos=1e-3, tol_rot=1e-2, frac=0.0
                 np.any((np.abs(re - tol_rot) <= frac * tol_rot) & pose))
 
 
+def fp32_fragile(tree, tg, w, o, seed, ora, t, rel_tie=1e-5, eps_step=1e-6):
+    """Whether the oracle's accept decision at iteration t (1-based) is one
+    FP32 cannot settle.  Replays the oracle to the state before iteration t
+    (its trace and lambda schedule), forms the damped system there in FP64 and
+    compares |c' - c| with rel_tie * c plus the first-order change of c' that
+    a relative step error of eps_step * cond(A_lambda) causes; eps_step is the
+    relative accuracy of an FP32-formed Jacobian (about 16 ulps)."""
+    import oracle
+    q = np.asarray(seed, dtype=np.float64) if t == 1 else ora["trace_q"][t - 2]
+    lam = o["lambda0"]
+    for i in range(t - 1):
+        lam = max(lam / o["nu_down"], o["lambda_min"]) if ora["trace_acc"][i] else \
+            min(lam * o["nu_up"], o["lambda_max"])
+    r, _, _ = oracle.residual(tree, tg, w, q)
+    J = oracle.jacobian(tree, tg, w, q)
+    A = J.T @ J
+    g = J.T @ r
+    Al = A + lam * np.diag(np.maximum(np.diag(A), o["damping_floor"]))
+    d = np.linalg.solve(Al, -g)
+    c, ct = oracle.cost(tree, tg, w, q), oracle.cost(tree, tg, w, q + d)
+    return bool(abs(ct - c) <= rel_tie * c + eps_step * np.linalg.cond(Al) * 2 * abs(g @ d))
+
+
+def first_divergence(acc_gpu, acc_ora):
+    """First iteration (1-based) at which two accept sequences differ, or 0."""
+    n = min(len(acc_gpu), len(acc_ora))
+    for i in range(n):
+        if int(acc_gpu[i]) != int(acc_ora[i]):
+            return i + 1
+    return 0
+
+
+def compare_outcome(ctx, rid, tree, tg, seed, w, o, status, iters, ora, variant=0):
+    """'same' when the GPU's success flag (and, if both converged, iteration
+    count) equals the oracle's; 'excused' when the difference traces back to
+    something FP32 cannot settle (a near-tie, a final or crossing error within
+    5% of a tolerance, or a first differing decision that is FP32-fragile);
+    else 'bad'.  ora: oracle.lm_solve result with a full trace."""
+    cg, co = (status & 0xff) == 0, (ora["status"] & 0xff) == 0
+    if cg == co and (not cg or iters == ora["iters"]):
+        return "same"
+    if ora["trace_tie"].any() or borderline({"pos_err": [ora["pos_err"]], "rot_err": [ora["rot_err"]]}, 0):
+        return "excused"
+    if cg and co and borderline_at(tree, tg, w, ora["trace_q"], int(min(iters, ora["iters"]))):
+        return "excused"
+    kw = {"variant": variant} if variant else {}
+    res = solve_gpu(ctx, rid, tree, tg[None], np.asarray(seed)[None], 1, w, o,
+                    trace_iters=o["max_iters"], **kw)
+    t = first_divergence(res["trace_accept"][0], ora["trace_acc"])
+    return "excused" if t > 0 and fp32_fragile(tree, tg, w, o, seed, ora, t) else "bad"
+
+
 def borderline(ora_res, p, tol_pos=1e-3, tol_rot=1e-2, frac=0.05):
     """Oracle's final error within 5% of a tolerance (success not decidable in FP32)."""
     pe, re = ora_res["pos_err"][p], ora_res["rot_err"][p]
