@@ -28,7 +28,7 @@ FP32_VALU_PEAK = 157.3      # TFLOP/s, MI355X FP32 vector (datasheet; packed FP3
 # sources hash to `sha256`; otherwise the bench reports traffic as null.
 LANE_KERNEL_SOURCES = ["paper_2505_03728_amd/csrc/lm_lane.hip", "paper_2505_03728_amd/csrc/pk_device.hpp",
                        "paper_2505_03728_amd/csrc/pk_internal.hpp", "include/pkmi.h"]
-ARM_TRAFFIC = {"sha256": "1e34b4d2241b8097", "fetch_kib": 2920.0, "write_kib": 7680.0, "fetch_scale": 2.0,
+ARM_TRAFFIC = {"sha256": "f3667a2f2f2bad6a", "fetch_kib": 2920.0, "write_kib": 7680.0, "fetch_scale": 2.0,
                "write_scale": 1.0}
 
 
@@ -341,8 +341,10 @@ def run_mixed(args):
                        "weights": pk.Weights.from_dict(g["weights"]), "wd": g["weights"],
                        "out": ctx.alloc_outputs(rid, T, 1)})
     o = pk.Options.from_dict(wl["options"])
-    k, bpc, tune_ms = ctx.autotune_mixed(groups, o)
-    print(f"# autotuned k={k} blocks/CU={bpc} ({tune_ms:.3f} ms)", file=sys.stderr, flush=True)
+    k, bpc, tune_ms, variants = ctx.autotune_mixed(groups, o)
+    vnames = ["lane" if v == pk.VARIANT_LANE else "wave" for v in variants]
+    print(f"# autotuned k={k} blocks/CU={bpc} variants={vnames} ({tune_ms:.3f} ms)", file=sys.stderr,
+          flush=True)
     ms = _time(lambda: ctx.ik_solve_mixed(groups, o), args.steps, args.warmup)
     # the same groups launched one by one without the scheduler
     ms_sep = _time(lambda: [ctx.ik_solve(g["rid"], g["targets"], g["seeds"], 1, g["weights"], o, g["out"])
@@ -365,7 +367,9 @@ def run_mixed(args):
     res = _line("IK solves/sec at 1mm/0.01rad success", conv / (ms / 1e3), "solves/s", args, ms,
                 {"workload": "mixed batch in one graph launch: 60000 7-DoF arm + 20000 16-DoF hand "
                              "(4 fingertip positions) + 4096 34-DoF tree problems, early exit, <= 50 "
-                             "iterations", "problems": N, "iters_per_launch": k, "blocks_per_cu": bpc},
+                             "iterations", "problems": N, "iters_per_launch": k, "blocks_per_cu": bpc,
+                 "lanes_per_problem": {g["tree"].name: (1 if v == pk.VARIANT_LANE else 64)
+                                       for g, v in zip(groups, variants)}},
                 success_rate=conv / N, groups=per, ms_separate_launches=round(ms_sep, 5),
                 roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
                           "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,

@@ -205,20 +205,26 @@ typedef struct {
     pk_ik_outputs out;
 } pk_ik_group;
 
+#define PK_MAX_GROUPS 16
+
 typedef struct {
     int32_t iters_per_launch;    /* k; 0 = all iterations in one launch        */
     int32_t blocks_per_cu;       /* persistent grid = blocks_per_cu x CUs       */
     int32_t use_graph;           /* 1 = capture / replay a hipGraph             */
-} pk_sched_options;              /* all zero = the autotuned entry if any      */
+    int32_t variant[PK_MAX_GROUPS];  /* per group: lanes per problem, PK_VARIANT_LANE (1)
+                                        or PK_VARIANT_WAVE (64); PK_VARIANT_AUTO = the
+                                        options' choice                          */
+} pk_sched_options;              /* k and blocks_per_cu zero = the autotuned entry if any */
 
 /* Asynchronous on `stream`.  sched may be NULL (graph on, autotuned or
  * default schedule). */
 int pk_ik_solve_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
                       const pk_lm_options *opt, const pk_sched_options *sched, void *stream);
 /* Times every candidate schedule (k in {5, 10, 25, all} x blocks per CU in
- * {2, 4, 8}, graph on) on these groups, stores the fastest for batches of
- * this signature and returns it.  Runs the solve several times (the outputs
- * hold the last run).  Synchronous. */
+ * {2, 4, 8} x, for each group whose robot the per-lane kernel supports, one or
+ * 64 lanes per problem; graph on) on these groups, stores the fastest for
+ * batches of this signature and returns it.  Runs the solve several times
+ * (the outputs hold the last run).  Synchronous. */
 int pk_autotune_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
                       const pk_lm_options *opt, pk_sched_options *best, float *best_ms,
                       void *stream);

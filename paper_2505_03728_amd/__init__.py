@@ -91,9 +91,12 @@ class _Group(C.Structure):
                 ("out", _Outputs)]
 
 
+MAX_GROUPS = 16
+
+
 class _Sched(C.Structure):
     _fields_ = [("iters_per_launch", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("variant", C.c_int32 * MAX_GROUPS)]
 
 
 _lib = None
@@ -354,25 +357,28 @@ class Context:
         return arr
 
     def ik_solve_mixed(self, groups, options: Options, iters_per_launch=0, blocks_per_cu=0,
-                       use_graph=True):
+                       use_graph=True, variants=None):
         """groups: list of dicts rid, targets [tf, T], seeds [n, T*K], K, weights, out
-        (from alloc_outputs).  Zero schedule options pick the autotuned entry."""
+        (from alloc_outputs).  variants: per group VARIANT_LANE / VARIANT_WAVE (None =
+        the options' choice).  Zero k and blocks_per_cu pick the autotuned entry."""
         arr = self._groups_c(groups)
-        sch = _Sched(iters_per_launch, blocks_per_cu, 1 if use_graph else 0)
+        v = (C.c_int32 * MAX_GROUPS)(*(list(variants or []) + [0] * MAX_GROUPS)[:MAX_GROUPS])
+        sch = _Sched(iters_per_launch, blocks_per_cu, 1 if use_graph else 0, v)
         o = options._c()
         self._call(lib().pk_ik_solve_mixed(self._h, len(groups), arr, C.byref(o), C.byref(sch),
                                            self.stream()))
         return groups
 
     def autotune_mixed(self, groups, options: Options):
-        """Times the candidate schedules on these groups; returns (k, blocks_per_cu, ms)."""
+        """Times the candidate schedules on these groups; returns (k, blocks_per_cu, ms,
+        per-group variants)."""
         arr = self._groups_c(groups)
         sch = _Sched()
         ms = C.c_float()
         o = options._c()
         self._call(lib().pk_autotune_mixed(self._h, len(groups), arr, C.byref(o), C.byref(sch),
                                            C.byref(ms), self.stream()))
-        return sch.iters_per_launch, sch.blocks_per_cu, ms.value
+        return sch.iters_per_launch, sch.blocks_per_cu, ms.value, list(sch.variant)[:len(groups)]
 
     def ik_solve(self, rid, targets, seeds, K, weights: Weights, options: Options, out):
         """targets [tf, T] and seeds [n, T*K] are cuda float32 tensors; out from

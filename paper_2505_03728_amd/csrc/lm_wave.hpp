@@ -276,22 +276,51 @@ PK_DEV T jtj_rows(const float *lds, const uint32_t (&ancp)[DMAX / 4], int lane, 
                   int max_depth, T (&r)[DMAX], T &g)
 {
     using L = Lds<DMAX, MMAX>;
-    T acc[DMAX];
+    float cj[6 * MMAX];
+    const float *own = lds + L::JC + lane * L::JS;
 #pragma unroll
-    for (int d = 0; d < DMAX; ++d) acc[d] = 0;
+    for (int k = 0; k < MMAX; ++k)
+#pragma unroll
+        for (int u = 0; u < 6; ++u) cj[6 * k + u] = k < m ? own[6 * k + u] : 0.f;
     g = 0;
-    for (int e = 0; e < 6 * m; ++e) {
-        const T ce = (T)lds[L::JC + lane * L::JS + e];
-        g += ce * (T)lds[L::RS + e];
 #pragma unroll
-        for (int d = 0; d < DMAX; ++d)
-            if (d <= max_depth) acc[d] += ce * (T)lds[L::JC + anc_lane<DMAX>(ancp, d) * L::JS + e];
-    }
+    for (int k = 0; k < MMAX; ++k)
+        if (k < m)
+#pragma unroll
+            for (int u = 0; u < 6; ++u) g += (T)cj[6 * k + u] * (T)lds[L::RS + 6 * k + u];
     T diag = 0;
+    if constexpr (sizeof(T) == 8) {
+        // FP64 (cold path): one Jacobian row at a time, all depths at once.
+        T acc[DMAX];
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) acc[d] = 0;
+        for (int e = 0; e < 6 * m; ++e) {
+            const T ce = (T)own[e];
+#pragma unroll
+            for (int d = 0; d < DMAX; ++d)
+                if (d <= max_depth) acc[d] += ce * (T)lds[L::JC + anc_lane<DMAX>(ancp, d) * L::JS + e];
+        }
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) {
+            r[d] = d < dep ? acc[d] : (T)0;
+            diag = d == dep ? acc[d] : diag;
+        }
+        return diag;
+    }
 #pragma unroll
     for (int d = 0; d < DMAX; ++d) {
-        r[d] = d < dep ? acc[d] : (T)0;
-        diag = d == dep ? acc[d] : diag;
+        T s = 0;
+        if (d <= max_depth) {
+            const float *ca = lds + L::JC + anc_lane<DMAX>(ancp, d) * L::JS;
+#pragma unroll
+            for (int k = 0; k < MMAX; ++k)
+                if (k < m)
+#pragma unroll
+                    for (int u = 0; u < 6; ++u) s += (T)cj[6 * k + u] * (T)ca[6 * k + u];
+        }
+        r[d] = d < dep ? s : (T)0;
+        diag = d == dep ? s : diag;
+        __asm__ volatile("" ::: "memory");   // one ancestor row in flight at a time
     }
     return diag;
 }
@@ -587,7 +616,7 @@ PK_DEV int64_t pop_item_wave(int32_t *head)
 }
 
 template <int DMAX, int MMAX>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void lm_wave_kernel(const RobotC *__restrict__ rb, SolveParams P)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((DMAX <= 16 && MMAX <= 4) ? 2 : 1))) void lm_wave_kernel(const RobotC *__restrict__ rb, SolveParams P)
 {
     using L = Lds<DMAX, MMAX>;
     __shared__ float lds[L::FLOATS];

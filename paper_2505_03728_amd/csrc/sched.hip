@@ -163,7 +163,7 @@ hipError_t enqueue(pk_ctx *ctx, SchedCache &C, std::vector<GroupPlan> &plans, in
 }
 
 int build_plans(pk_ctx *ctx, SchedCache &C, int n_groups, const pk_ik_group *groups,
-                const pk_lm_options *opt, std::vector<GroupPlan> &plans)
+                const pk_lm_options *opt, const pk_sched_options &sch, std::vector<GroupPlan> &plans)
 {
     // workspace sizing: per problem lambda, state, iters, accepts, itt,
     // pose_cost, cost, status and two lists (4-byte words) + counters.
@@ -199,7 +199,9 @@ int build_plans(pk_ctx *ctx, SchedCache &C, int n_groups, const pk_ik_group *gro
         GroupPlan pl;
         pl.rb = rb;
         pl.out = gr.out;
-        int rc = prepare_solve(ctx, *rb, &gr.weights, opt, pl.P, pl.variant);
+        pk_lm_options og = *opt;
+        if (sch.variant[g] != PK_VARIANT_AUTO) og.variant = sch.variant[g];
+        int rc = prepare_solve(ctx, *rb, &gr.weights, &og, pl.P, pl.variant);
         if (rc) return rc;
         SolveParams &P = pl.P;
         P.K = pr.K;
@@ -231,7 +233,7 @@ int run(pk_ctx *ctx, int n_groups, const pk_ik_group *groups, const pk_lm_option
 {
     SchedCache &C = g_sched[ctx];
     std::vector<GroupPlan> plans;
-    int rc = build_plans(ctx, C, n_groups, groups, opt, plans);
+    int rc = build_plans(ctx, C, n_groups, groups, opt, sch, plans);
     if (rc) return rc;
     const int k = sch.iters_per_launch, bpc = sch.blocks_per_cu > 0 ? sch.blocks_per_cu : 4;
     if (!sch.use_graph) {
@@ -253,7 +255,12 @@ int run(pk_ctx *ctx, int n_groups, const pk_ik_group *groups, const pk_lm_option
         key += kb;
     }
     snprintf(kb, sizeof kb, "k%d.b%d.", k, bpc);
-    key += kb + signature(n_groups, groups, opt);
+    key += kb;
+    for (int g = 0; g < n_groups; ++g) {
+        snprintf(kb, sizeof kb, "v%d.", plans[g].variant);
+        key += kb;
+    }
+    key += signature(n_groups, groups, opt);
     snprintf(kb, sizeof kb, "|%g,%g,%g,%g,%g,%g,%g,%g,%g", opt->lambda0, opt->nu_up, opt->nu_down,
              opt->lambda_min, opt->lambda_max, opt->tol_pos, opt->tol_rot, opt->damping_floor,
              opt->pivot_rel);
@@ -317,17 +324,19 @@ int pk_ik_solve_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
                       const pk_lm_options *opt, const pk_sched_options *sched, void *stream)
 {
     if (!ctx) return fail(nullptr, PK_EINVAL, "pk_ik_solve_mixed: ctx is NULL");
-    if (n_groups < 1 || n_groups > 16 || !groups || !opt)
+    if (n_groups < 1 || n_groups > PK_MAX_GROUPS || !groups || !opt)
         return fail(ctx, PK_EINVAL, "pk_ik_solve_mixed: need 1..16 groups and options");
     PK_HIP(ctx, hipSetDevice(ctx->device));
-    pk_sched_options s = {0, 0, 1};
+    pk_sched_options s = {};
+    s.use_graph = 1;
     if (sched) s = *sched;
     if (s.iters_per_launch == 0 && s.blocks_per_cu == 0) {
         auto &C = g_sched[ctx];
         auto it = C.tuned.find(signature(n_groups, groups, opt));
         if (it != C.tuned.end()) {
-            s.iters_per_launch = it->second.iters_per_launch;
-            s.blocks_per_cu = it->second.blocks_per_cu;
+            const int ug = s.use_graph;
+            s = it->second;
+            s.use_graph = ug;
         }
     }
     if (s.iters_per_launch < 0 || s.blocks_per_cu < 0)
@@ -339,36 +348,76 @@ int pk_autotune_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
                       const pk_lm_options *opt, pk_sched_options *best, float *best_ms, void *stream)
 {
     if (!ctx) return fail(nullptr, PK_EINVAL, "pk_autotune_mixed: ctx is NULL");
-    if (!best || n_groups < 1 || !groups || !opt) return fail(ctx, PK_EINVAL, "pk_autotune_mixed: bad arguments");
+    if (!best || n_groups < 1 || n_groups > PK_MAX_GROUPS || !groups || !opt)
+        return fail(ctx, PK_EINVAL, "pk_autotune_mixed: bad arguments");
     PK_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     const int ks[] = {5, 10, 25, 0};
     const int bs[] = {2, 4, 8};
+    // Lanes per problem: both mappings for groups the per-lane kernel
+    // supports (all combinations up to 4 such groups, else each one flipped
+    // on its own), the wave mapping for the others.
+    std::vector<int> flex;
+    for (int g = 0; g < n_groups; ++g) {
+        const RobotEntry *rb = robot_of(ctx, groups[g].robot_id);
+        if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_autotune_mixed: group %d: unknown robot", g);
+        const RobotC &H = rb->host;
+        if (H.chains > 0 && lane_variant_available(H.chains, H.chain_len, H.e[0].kind)) flex.push_back(g);
+    }
+    std::vector<std::vector<int>> vsets;
+    auto base = [&]() {
+        std::vector<int> v(PK_MAX_GROUPS, PK_VARIANT_AUTO);
+        for (int g = 0; g < n_groups; ++g) v[g] = PK_VARIANT_WAVE;
+        for (int g : flex) v[g] = PK_VARIANT_LANE;
+        return v;
+    };
+    if (flex.size() <= 4) {
+        for (unsigned mask = 0; mask < (1u << flex.size()); ++mask) {
+            std::vector<int> v = base();
+            for (size_t i = 0; i < flex.size(); ++i)
+                if (mask >> i & 1u) v[flex[i]] = PK_VARIANT_WAVE;
+            vsets.push_back(v);
+        }
+    } else {
+        vsets.push_back(base());
+        for (int g : flex) {
+            std::vector<int> v = base();
+            v[g] = PK_VARIANT_WAVE;
+            vsets.push_back(v);
+        }
+    }
     hipEvent_t a, b;
     PK_HIP(ctx, hipEventCreate(&a));
     PK_HIP(ctx, hipEventCreate(&b));
     float bestt = 1e30f;
-    pk_sched_options bo = {0, 4, 1};
-    for (int k : ks)
-        for (int bpc : bs) {
-            pk_sched_options s = {k, bpc, 1};
-            int rc = run(ctx, n_groups, groups, opt, s, st);   // capture + warm-up
-            if (rc) return rc;
-            PK_HIP(ctx, hipEventRecord(a, st));
-            for (int r = 0; r < 3; ++r) {
-                rc = run(ctx, n_groups, groups, opt, s, st);
+    pk_sched_options bo = {};
+    bo.blocks_per_cu = 4;
+    bo.use_graph = 1;
+    for (const auto &vs : vsets)
+        for (int k : ks)
+            for (int bpc : bs) {
+                pk_sched_options s = {};
+                s.iters_per_launch = k;
+                s.blocks_per_cu = bpc;
+                s.use_graph = 1;
+                for (int g = 0; g < PK_MAX_GROUPS; ++g) s.variant[g] = vs[g];
+                int rc = run(ctx, n_groups, groups, opt, s, st);   // capture + warm-up
                 if (rc) return rc;
+                PK_HIP(ctx, hipEventRecord(a, st));
+                for (int r = 0; r < 3; ++r) {
+                    rc = run(ctx, n_groups, groups, opt, s, st);
+                    if (rc) return rc;
+                }
+                PK_HIP(ctx, hipEventRecord(b, st));
+                PK_HIP(ctx, hipEventSynchronize(b));
+                float ms = 0.f;
+                PK_HIP(ctx, hipEventElapsedTime(&ms, a, b));
+                ms /= 3.f;
+                if (ms < bestt) {
+                    bestt = ms;
+                    bo = s;
+                }
             }
-            PK_HIP(ctx, hipEventRecord(b, st));
-            PK_HIP(ctx, hipEventSynchronize(b));
-            float ms = 0.f;
-            PK_HIP(ctx, hipEventElapsedTime(&ms, a, b));
-            ms /= 3.f;
-            if (ms < bestt) {
-                bestt = ms;
-                bo = s;
-            }
-        }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     g_sched[ctx].tuned[signature(n_groups, groups, opt)] = bo;

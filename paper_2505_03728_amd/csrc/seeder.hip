@@ -74,6 +74,27 @@ struct EpiBackHidden {      // dZ = acc * SiLU'(Z): FP32 and BF16 copies
     }
 };
 
+// Element e of R row vectors, packed along k: R consecutive bf16 in one store.
+// (The vectors are reinterpreted whole as 16-bit integers and then indexed.)
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+template <int R>
+PK_DEV void store_kpack(__bf16 *dst, const bf16x8 (&v)[R], int e)
+{
+    u16x8 w[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) w[i] = __builtin_bit_cast(u16x8, v[i]);
+    if constexpr (R == 4) {
+        *(uint2 *)dst = make_uint2((unsigned)w[0][e] | ((unsigned)w[1][e] << 16),
+                                   (unsigned)w[2][e] | ((unsigned)w[3][e] << 16));
+    } else if constexpr (R == 2) {
+        *(unsigned *)dst = (unsigned)w[0][e] | ((unsigned)w[1][e] << 16);
+    } else {
+        unsigned short *d = (unsigned short *)dst;
+#pragma unroll
+        for (int i = 0; i < R; ++i) d[i] = w[i][e];
+    }
+}
+
 // blockIdx.z selects one of gridDim.z equal slices of K (split-K); the
 // epilogue receives the slice index so partial products can be kept apart.
 // The next K stage is fetched from global memory into registers while the
@@ -99,56 +120,55 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __
         for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     bf16x8 ra[RA], rb[RB];
-    // Vector v of a stage: MK/NK layout -> (row v / (BK/8), k 8 * (v % (BK/8)));
-    // KM/KN layout -> (k v / (BM/8), row 8 * (v % (BM/8))).
+    // MK/NK layouts: vector v of a stage is (row v / (BK/8), k 8 * (v % (BK/8))).
+    // KM/KN layouts: thread t owns R consecutive k rows (R = RA or RB) of the
+    // 8-wide row group t % (rows/8), so its LDS writes pack R values per row.
+    constexpr int GA = BM / 8, GB = BN / 8;
+    const int amg = tid % GA, akq = tid / GA, bng = tid % GB, bkq = tid / GB;
     auto gload = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < RA; ++i) {
-            const int v = tid + 256 * i;
-            if (v < NVA) {
-                if (AL == A_MK)
+            if (AL == A_MK) {
+                const int v = tid + 256 * i;
+                if (v < NVA)
                     ra[i] = *(const bf16x8 *)&A[(size_t)(m0 + v / (BK / 8)) * lda + k0 + 8 * (v % (BK / 8))];
-                else
-                    ra[i] = *(const bf16x8 *)&A[(size_t)(k0 + v / (BM / 8)) * lda + m0 + 8 * (v % (BM / 8))];
+            } else {
+                const int kk = akq * RA + i;
+                if (kk < BK) ra[i] = *(const bf16x8 *)&A[(size_t)(k0 + kk) * lda + m0 + 8 * amg];
             }
         }
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
-            const int v = tid + 256 * i;
-            if (v < NVB) {
-                if (BL == B_NK)
+            if (BL == B_NK) {
+                const int v = tid + 256 * i;
+                if (v < NVB)
                     rb[i] = *(const bf16x8 *)&B[(size_t)(n0 + v / (BK / 8)) * ldb + k0 + 8 * (v % (BK / 8))];
-                else
-                    rb[i] = *(const bf16x8 *)&B[(size_t)(k0 + v / (BN / 8)) * ldb + n0 + 8 * (v % (BN / 8))];
+            } else {
+                const int kk = bkq * RB + i;
+                if (kk < BK) rb[i] = *(const bf16x8 *)&B[(size_t)(k0 + kk) * ldb + n0 + 8 * bng];
             }
         }
     };
     auto lstore = [&]() {
+        if (AL == A_MK) {
 #pragma unroll
-        for (int i = 0; i < RA; ++i) {
-            const int v = tid + 256 * i;
-            if (v < NVA) {
-                if (AL == A_MK) {
-                    *(bf16x8 *)&sA[(v / (BK / 8)) * LDK + 8 * (v % (BK / 8))] = ra[i];
-                } else {
-                    const int kk = v / (BM / 8), mm = 8 * (v % (BM / 8));
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) sA[(mm + e) * LDK + kk] = ra[i][e];
-                }
+            for (int i = 0; i < RA; ++i) {
+                const int v = tid + 256 * i;
+                if (v < NVA) *(bf16x8 *)&sA[(v / (BK / 8)) * LDK + 8 * (v % (BK / 8))] = ra[i];
             }
+        } else if (akq * RA < BK) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) store_kpack<RA>(&sA[(8 * amg + e) * LDK + akq * RA], ra, e);
         }
+        if (BL == B_NK) {
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int v = tid + 256 * i;
-            if (v < NVB) {
-                if (BL == B_NK) {
-                    *(bf16x8 *)&sB[(v / (BK / 8)) * LDK + 8 * (v % (BK / 8))] = rb[i];
-                } else {
-                    const int kk = v / (BN / 8), nn = 8 * (v % (BN / 8));
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) sB[(nn + e) * LDK + kk] = rb[i][e];
-                }
+            for (int i = 0; i < RB; ++i) {
+                const int v = tid + 256 * i;
+                if (v < NVB) *(bf16x8 *)&sB[(v / (BK / 8)) * LDK + 8 * (v % (BK / 8))] = rb[i];
             }
+        } else if (bkq * RB < BK) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) store_kpack<RB>(&sB[(8 * bng + e) * LDK + bkq * RB], rb, e);
         }
     };
 
@@ -298,78 +318,104 @@ __global__ void gather_kernel(int B, int64_t S, int n, int in_pad, int steps_per
 }
 
 // Min-over-seeds loss: per sample the closest seed (ties -> lowest k) gets
-// the gradient 2 (y - q) / B; per-block partial sums of the loss.
-__global__ __launch_bounds__(256) void loss_kernel(int B, int n, int K, int out_pad,
+// the gradient 2 (y - q) / B.  One wavefront per row, lane = output column
+// (K n <= 64), four rows per wavefront, sixteen per block; per-block partial
+// sums of the loss in a fixed order.  Rows in [B, rows) get zero gradients.
+__global__ __launch_bounds__(256) void loss_kernel(int rows, int B, int n, int K, int out_pad,
                                                    const float *__restrict__ Y,
                                                    const float *__restrict__ Q, float *dY,
                                                    __bf16 *dYb, float *partial)
 {
-    __shared__ float red[256];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    float li = 0.f;
-    if (i < B) {
-        int best = 0;
-        float bd = INFINITY;
-        for (int k = 0; k < K; ++k) {
-            float d = 0.f;
-            for (int j = 0; j < n; ++j) {
-                const float t = Y[(int64_t)i * out_pad + k * n + j] - Q[(int64_t)i * n + j];
-                d += t * t;
-            }
-            if (d < bd) {
-                bd = d;
-                best = k;
+    __shared__ float red[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kn = K * n;
+    const float sc = 2.f / (float)B;
+    float wl = 0.f;
+    for (int rr = 0; rr < 4; ++rr) {
+        const int64_t i = (int64_t)blockIdx.x * 16 + w * 4 + rr;
+        if (i >= rows) break;                          // uniform per wavefront
+        const bool valid = i < B;
+        float diff = 0.f;
+        if (valid && lane < kn) diff = Y[i * out_pad + lane] - Q[i * n + lane % n];
+        const float s2 = diff * diff;
+        // squared distance of seed k = lane (sum over j in order)
+        float dk = 0.f;
+        for (int j = 0; j < n; ++j) dk += __shfl(s2, (lane < K ? lane : 0) * n + j, 64);
+        float bd = lane < K ? dk : INFINITY;
+        int bi = lane;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            const float od = __shfl_xor(bd, o, 64);
+            const int oi = __shfl_xor(bi, o, 64);
+            if (od < bd || (od == bd && oi < bi)) {
+                bd = od;
+                bi = oi;
             }
         }
-        li = bd;
-        const float sc = 2.f / (float)B;
-        for (int c = 0; c < out_pad; ++c) {
-            float g = 0.f;
-            const int k = c / n, j = c % n;
-            if (c < K * n && k == best) g = sc * (Y[(int64_t)i * out_pad + c] - Q[(int64_t)i * n + j]);
-            dY[(int64_t)i * out_pad + c] = g;
-            dYb[(int64_t)i * out_pad + c] = (__bf16)g;
+        const float g = (valid && lane < kn && lane / n == bi) ? sc * diff : 0.f;
+        for (int c = lane; c < out_pad; c += 64) {
+            const float gc = c == lane ? g : 0.f;
+            dY[i * out_pad + c] = gc;
+            dYb[i * out_pad + c] = (__bf16)gc;
         }
+        if (valid) wl += bd;
     }
-    red[threadIdx.x] = li;
+    if (lane == 0) red[w] = wl;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// loss_log[*dstep - step0] (when within [0, nlog)) and/or *loss_out: the sum
+// of the partials / B, as a fixed-order 256-thread reduction.
+__global__ __launch_bounds__(256) void loss_finish_kernel(int nparts, int B, const float *__restrict__ partial,
+                                                          const int *__restrict__ dstep, int step0, int nlog,
+                                                          float *loss_log, float *loss_out)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < nparts; i += 256) s += partial[i];
+    red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-// loss_log[*dstep - step0] (when within [0, nlog)) and/or *loss_out.
-__global__ void loss_finish_kernel(int nparts, int B, const float *__restrict__ partial,
-                                   const int *__restrict__ dstep, int step0, int nlog, float *loss_log,
-                                   float *loss_out)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float s = 0.f;
-    for (int i = 0; i < nparts; ++i) s += partial[i];
-    s /= (float)B;
+    if (threadIdx.x != 0) return;
+    const float v = red[0] / (float)B;
     const int li = *dstep - step0;
-    if (loss_log && li >= 0 && li < nlog) loss_log[li] = s;
-    if (loss_out) *loss_out = s;
+    if (loss_log && li >= 0 && li < nlog) loss_log[li] = v;
+    if (loss_out) *loss_out = v;
 }
 
-// Column sums of dZ [R][C] (bias gradient), two deterministic passes.
-__global__ void colsum_pass1(int R, int C, const float *__restrict__ X, float *part)
+// Column sums of dZ [R][C] (bias gradient), two deterministic passes.  Pass
+// 1: per 128-row chunk, 64 columns x 4 row phases per block.
+constexpr int COLSUM_ROWS = 128;
+__global__ __launch_bounds__(256) void colsum_pass1(int R, int C, const float *__restrict__ X, float *part)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x, r0 = blockIdx.y * 256;
-    if (c >= C) return;
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl, r0 = blockIdx.y * COLSUM_ROWS;
+    const int r1 = min(r0 + COLSUM_ROWS, R);
     float s = 0.f;
-    for (int r = r0; r < r0 + 256 && r < R; ++r) s += X[(int64_t)r * C + c];
-    part[(int64_t)blockIdx.y * C + c] = s;
+    if (c < C)
+        for (int r = r0 + ph; r < r1; r += 4) s += X[(int64_t)r * C + c];
+    red[ph][cl] = s;
+    __syncthreads();
+    if (ph == 0 && c < C) part[(int64_t)blockIdx.y * C + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
-__global__ void colsum_pass2(int nchunk, int C, const float *__restrict__ part, float *out)
+// Pass 2: out[c] = sum of the chunk partials, 64 columns x 4 chunk phases
+// per block, fixed order.
+__global__ __launch_bounds__(256) void colsum_pass2(int nchunk, int C, const float *__restrict__ part, float *out)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+    __shared__ float red[4][64];
+    const int cl = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + cl;
     float s = 0.f;
-    for (int i = 0; i < nchunk; ++i) s += part[(int64_t)i * C + c];
-    out[c] = s;
+    if (c < C)
+        for (int i = ph; i < nchunk; i += 4) s += part[(int64_t)i * C + c];
+    red[ph][cl] = s;
+    __syncthreads();
+    if (ph == 0 && c < C) out[c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
 
 // Adam (Kingma & Ba 2015) with bias correction; t = step + 1 from the device
@@ -500,8 +546,9 @@ int alloc_acts(pk_ctx *ctx, SeederState *s, int64_t rows)
     ok &= hipMalloc(&s->dZ, hsz * sizeof(float)) == hipSuccess;
     ok &= hipMalloc(&s->dY, rows * s->out_pad * sizeof(float)) == hipSuccess;
     ok &= hipMalloc(&s->Q, rows * s->n * sizeof(float)) == hipSuccess;
-    ok &= hipMalloc(&s->part, (rows / 256 + 1) * (size_t)std::max(s->H, s->out_pad) * sizeof(float) +
-                                  4096) == hipSuccess;
+    // column-sum partials (one row per 128-row chunk) or loss partials (one per 16 rows)
+    ok &= hipMalloc(&s->part, ((rows / sd::COLSUM_ROWS + 1) * (size_t)std::max(s->H, s->out_pad) +
+                               rows / 16 + 1) * sizeof(float) + 4096) == hipSuccess;
     // Split-K partials: sized for the largest split any row count can pick.
     size_t need = 0;
     for (int l = 0; l <= L; ++l) {
@@ -574,14 +621,14 @@ hipError_t backward(SeederState *s, int64_t rows, hipStream_t st)
     using namespace sd;
     hipError_t e;
     const int L = s->depth;
-    const int nchunk = (int)((rows + 255) / 256);
+    const int nchunk = (int)((rows + sd::COLSUM_ROWS - 1) / sd::COLSUM_ROWS);
     // output layer
     const __bf16 *Hlast = s->Hb + (size_t)(L - 1) * rows * s->H;
     e = weight_grad(s, s->out_pad, s->H, rows, s->dYb, s->out_pad, Hlast, s->H, s->G + s->woff[L], st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(colsum_pass1, dim3(blocks(s->out_pad, 256), nchunk), dim3(256), 0, st, (int)rows,
+    hipLaunchKernelGGL(colsum_pass1, dim3(blocks(s->out_pad, 64), nchunk), dim3(256), 0, st, (int)rows,
                        s->out_pad, s->dY, s->part);
-    hipLaunchKernelGGL(colsum_pass2, dim3(blocks(s->out_pad, 256)), dim3(256), 0, st, nchunk, s->out_pad,
+    hipLaunchKernelGGL(colsum_pass2, dim3(blocks(s->out_pad, 64)), dim3(256), 0, st, nchunk, s->out_pad,
                        s->part, s->G + s->boff[L]);
     // dZ of the last hidden layer = (dY W_out) * SiLU'(Z)
     const __bf16 *gin = s->dYb;
@@ -595,9 +642,9 @@ hipError_t backward(SeederState *s, int64_t rows, hipStream_t st)
         const int ldin = l == 0 ? s->in_pad : s->H;
         e = weight_grad(s, s->H, s->lin[l], rows, s->dZb, s->H, inl, ldin, s->G + s->woff[l], st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(colsum_pass1, dim3(blocks(s->H, 256), nchunk), dim3(256), 0, st, (int)rows,
+        hipLaunchKernelGGL(colsum_pass1, dim3(blocks(s->H, 64), nchunk), dim3(256), 0, st, (int)rows,
                            s->H, s->dZ, s->part);
-        hipLaunchKernelGGL(colsum_pass2, dim3(blocks(s->H, 256)), dim3(256), 0, st, nchunk, s->H,
+        hipLaunchKernelGGL(colsum_pass2, dim3(blocks(s->H, 64)), dim3(256), 0, st, nchunk, s->H,
                            s->part, s->G + s->boff[l]);
         gin = s->dZb;
         gld = s->H;
@@ -637,8 +684,10 @@ int pk_seeder_create(pk_ctx *ctx, int32_t robot_id, int32_t K, int32_t hidden, i
     const RobotC &R = rb->host;
     if (R.m != 1 || R.e[0].kind != PK_EE_POSE)
         return fail(ctx, PK_EUNSUPPORTED, "pk_seeder_create: needs a robot with one pose EE");
-    if (K < 1 || depth < 1 || depth > 8 || hidden < 128 || hidden % 128 || R.n * K > 256)
+    if (K < 1 || depth < 1 || depth > 8 || hidden < 128 || hidden % 128)
         return fail(ctx, PK_EINVAL, "pk_seeder_create: bad K=%d hidden=%d depth=%d", K, hidden, depth);
+    if (R.n * K > 64)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_seeder_create: K * n = %d above 64 outputs", R.n * K);
     SeederState *s = new SeederState;
     s->robot_id = robot_id;
     s->n = R.n;
@@ -758,10 +807,10 @@ hipError_t loss_and_grads(SeederState *s, int64_t rows, int64_t B, float *loss_l
     using namespace sd;
     hipError_t e = forward(s, rows, true, st);
     if (e != hipSuccess) return e;
-    const unsigned nb = blocks(rows, 256);
-    hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(256), 0, st, (int)B, s->n, s->K, s->out_pad, s->Y,
-                       s->Q, s->dY, s->dYb, s->part);
-    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(1), 0, st, (int)nb, (int)B, s->part, s->dstep,
+    const unsigned nb = blocks(rows, 16);
+    hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(256), 0, st, (int)rows, (int)B, s->n, s->K, s->out_pad,
+                       s->Y, s->Q, s->dY, s->dYb, s->part);
+    hipLaunchKernelGGL(loss_finish_kernel, dim3(1), dim3(256), 0, st, (int)nb, (int)B, s->part, s->dstep,
                        step0, nlog, loss_log, loss_out);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

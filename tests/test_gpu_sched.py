@@ -72,15 +72,44 @@ def test_mixed_equals_separate_launches(ctx, batch):
         print(f"k={k} blocks/CU={bpc} graph={graph}: identical to separate launches")
 
 
+def test_mixed_per_group_variants_equal_separate_launches(ctx, batch):
+    """Every group on the wave mapping (64 lanes per problem) through the
+    scheduler equals pk_ik_solve with the wave variant, bit for bit."""
+    import paper_2505_03728_amd as pk
+    import torch
+    wl, groups = batch
+    sep = _fresh(ctx, [dict(g) for g in groups])
+    opt_w = pk.Options.from_dict(wl["options"], variant=pk.VARIANT_WAVE)
+    for g in sep:
+        ctx.ik_solve(g["rid"], g["targets"], g["seeds"], g["K"], g["weights"], opt_w, g["out"])
+    torch.cuda.synchronize()
+    ref = _host(sep)
+    opt = pk.Options.from_dict(wl["options"])
+    gs = _fresh(ctx, [dict(g) for g in groups])
+    ctx.ik_solve_mixed(gs, opt, iters_per_launch=10, blocks_per_cu=4, use_graph=True,
+                       variants=[pk.VARIANT_WAVE] * len(groups))
+    torch.cuda.synchronize()
+    got = _host(gs)
+    for gi, (a, b) in enumerate(zip(ref, got)):
+        for key in KEYS:
+            np.testing.assert_array_equal(a[key], b[key], err_msg=f"group {gi} {key}")
+    # a lane mapping requested for the tree robot is refused
+    with pytest.raises(pk.PkError):
+        ctx.ik_solve_mixed(_fresh(ctx, [dict(g) for g in groups]), opt, iters_per_launch=10,
+                           blocks_per_cu=4, variants=[0, 0, pk.VARIANT_LANE])
+
+
 def test_autotune_and_oracle_sample(ctx, batch):
     import paper_2505_03728_amd as pk
     import torch
     wl, groups = batch
     opt = pk.Options.from_dict(wl["options"])
     gs = _fresh(ctx, [dict(g) for g in groups], best=True)
-    k, bpc, ms = ctx.autotune_mixed(gs, opt)
-    print(f"autotuned: k={k}, blocks/CU={bpc}, {ms:.3f} ms")
+    k, bpc, ms, variants = ctx.autotune_mixed(gs, opt)
+    print(f"autotuned: k={k}, blocks/CU={bpc}, variants={variants}, {ms:.3f} ms")
     assert k in (5, 10, 25, 0) and bpc in (2, 4, 8) and ms > 0
+    # the tree robot has only the wave mapping; the others may take either
+    assert variants[2] == pk.VARIANT_WAVE and all(v in (pk.VARIANT_LANE, pk.VARIANT_WAVE) for v in variants)
     gs = _fresh(ctx, [dict(g) for g in groups], best=True)
     ctx.ik_solve_mixed(gs, opt)            # uses the tuned entry
     torch.cuda.synchronize()
