@@ -28,7 +28,7 @@ FP32_VALU_PEAK = 157.3      # TFLOP/s, MI355X FP32 vector (datasheet; packed FP3
 # sources hash to `sha256`; otherwise the bench reports traffic as null.
 LANE_KERNEL_SOURCES = ["paper_2505_03728_amd/csrc/lm_lane.hip", "paper_2505_03728_amd/csrc/pk_device.hpp",
                        "paper_2505_03728_amd/csrc/pk_internal.hpp", "include/pkmi.h"]
-ARM_TRAFFIC = {"sha256": "f3667a2f2f2bad6a", "fetch_kib": 2920.0, "write_kib": 7680.0, "fetch_scale": 2.0,
+ARM_TRAFFIC = {"sha256": "9eaac127ef72429c", "fetch_kib": 2873.5, "write_kib": 7680.0, "fetch_scale": 2.0,
                "write_scale": 1.0}
 
 
@@ -426,10 +426,19 @@ def run_seeder(args):
     ms_plain10 = _time(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, ref_o, plain10), args.steps,
                        args.warmup)
     res_l = {}
+    sched = {"k": 0}
 
     def learned():
         res_l["o"] = ctx.ik_solve_seeded(rid, targets, sd, w, ref_o, fallback=plain_o,
-                                         fallback_seeds=rseeds, fallback_K=K, counters=True)
+                                         fallback_seeds=rseeds, fallback_K=K, counters=True,
+                                         refine_iters_per_launch=sched["k"], refine_blocks_per_cu=4)
+    # refinement schedule: one launch, or k iterations per launch with compaction
+    tune = {}
+    for k in (0, 2, 3, 5):
+        sched["k"] = k
+        tune[k] = _time(learned, 3, 1)
+    sched["k"] = min(tune, key=tune.get)
+    print(f"# refinement schedule: {tune} -> k={sched['k']}", file=sys.stderr, flush=True)
     ms_learn = _time(learned, args.steps, args.warmup)
     seeds_buf = torch.empty((7, T * K), device="cuda")
     ms_infer = _time(lambda: sd.infer(targets, seeds_buf), args.steps, args.warmup)
@@ -459,7 +468,8 @@ def run_seeder(args):
                              f"K={K}, BF16 MFMA) + <=10 LM iterations (early exit) + fallback to "
                              f"{K} random seeds x 30 iterations, vs plain {K} random seeds x 30 "
                              f"iterations", "targets": T, "seeds_per_target": K,
-                 "train_samples": S, "epochs": E, "batch": mc["batch"]},
+                 "train_samples": S, "epochs": E, "batch": mc["batch"],
+                 "refine_iters_per_launch": sched["k"]},
                 success_rate=s_learn / T,
                 learned={"solves_per_s": round(v_learn, 1), "success_rate": s_learn / T,
                          "success_from_learned_seeds": float(np.mean(src == 0)),

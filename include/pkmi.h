@@ -279,6 +279,11 @@ typedef struct {
     const float *fallback_seeds;     /* device [n][T*fallback_K]                 */
     pk_lm_options refine;            /* e.g. 10 iterations, early exit           */
     pk_lm_options fallback;          /* e.g. 30 iterations                       */
+    int32_t refine_iters_per_launch; /* 0 = the refinement in one launch; k > 0 =
+                                        k iterations per launch with the unfinished
+                                        problems compacted in between (persistent
+                                        kernel, hipGraph), as pk_ik_solve_mixed   */
+    int32_t refine_blocks_per_cu;    /* persistent grid for k > 0 (0 = 4)        */
 } pk_seeded_options;
 
 typedef struct {

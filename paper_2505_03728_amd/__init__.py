@@ -75,7 +75,8 @@ class _Outputs(C.Structure):
 
 class _SeededOptions(C.Structure):
     _fields_ = [("seeder_id", C.c_int32), ("fallback_K", C.c_int32), ("fallback_seeds", C.c_void_p),
-                ("refine", _Options), ("fallback", _Options)]
+                ("refine", _Options), ("fallback", _Options), ("refine_iters_per_launch", C.c_int32),
+                ("refine_blocks_per_cu", C.c_int32)]
 
 
 class _SeededOutputs(C.Structure):
@@ -311,7 +312,7 @@ class Context:
 
     def ik_solve_seeded(self, rid, targets, seeder, weights: Weights, refine: Options,
                         fallback: Options = None, fallback_seeds=None, fallback_K=0,
-                        counters=False):
+                        counters=False, refine_iters_per_launch=0, refine_blocks_per_cu=0):
         """Learned seeds + LM, fallback to random-seed LM (see include/pkmi.h).
 
         Returns a dict of device tensors: best_joints [n, T], target_success,
@@ -329,7 +330,8 @@ class Context:
                        fallback_iters=i(max(T * fallback_K, 1)),
                        fallback_accepts=i(max(T * fallback_K, 1)))
         fb = fallback or refine
-        so = _SeededOptions(seeder.id, int(fallback_K), _ptr(fallback_seeds), refine._c(), fb._c())
+        so = _SeededOptions(seeder.id, int(fallback_K), _ptr(fallback_seeds), refine._c(), fb._c(),
+                            int(refine_iters_per_launch), int(refine_blocks_per_cu))
         oo = _SeededOutputs(*[_ptr(out.get(k)) for k in ["best_joints", "target_success", "source",
                                                           "iters_to_tol", "refine_iters",
                                                           "refine_accepts", "fallback_iters",

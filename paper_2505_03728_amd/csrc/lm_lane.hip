@@ -325,23 +325,15 @@ PK_DEV void write_trace(const SolveParams &P, int it, int64_t p, const float *q,
     }
 }
 
-// One LM problem (active index i) on this lane.  With P.st_state the run is
-// resumable: it continues from the state a previous launch left in HBM and
-// stops after P.iter_budget iterations.
-template <int C, int L, int KIND, bool RESUMABLE>
-PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict__ qr,
-                         const SolveParams &P, const LaneLds &S, int64_t i)
+// Loads problem p's starting point (from qsrc) into q and its targets into
+// the TG slots; false if any of them is not finite.
+template <int C, int L, int KIND>
+PK_DEV bool load_problem(const SolveParams &P, const LaneLds &S, const float *qsrc, int64_t p, float *q)
 {
     using St = Star<C, L, KIND>;
     using SL = Slots<C, L, KIND>;
-    const int64_t p = P.active ? (int64_t)P.active[i] : i;
     const int64_t N = P.N, T = P.T, t = p / P.K;
-    constexpr bool resumable = RESUMABLE;
-    const bool resume = RESUMABLE && P.resume;
-
-    float q[St::N];
     bool finite = true;
-    const float *qsrc = resume ? P.joints : P.seeds;
 #pragma unroll
     for (int j = 0; j < St::N; ++j) {
         q[j] = qsrc[j * N + p];
@@ -366,121 +358,73 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
             for (int u = 0; u < 9; ++u) S[base + 3 + u] = R[u];
         }
     }
+    return finite;
+}
 
-    if (!finite) {
+// Outputs of a problem with a non-finite seed or target.
+template <int C, int L, int KIND>
+PK_DEV void write_nonfinite(const SolveParams &P, int64_t p, const float *q, bool resumable)
+{
+    using St = Star<C, L, KIND>;
+    const int64_t N = P.N;
 #pragma unroll
-        for (int j = 0; j < St::N; ++j) P.joints[j * N + p] = q[j];
+    for (int j = 0; j < St::N; ++j) P.joints[j * N + p] = q[j];
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            if (P.pos_err) P.pos_err[c * N + p] = NAN;
-            if (P.rot_err) P.rot_err[c * N + p] = NAN;
-        }
-        if (P.cost) P.cost[p] = NAN;
-        P.pose_cost[p] = NAN;
-        if (P.iters) P.iters[p] = 0;
-        if (P.accepts) P.accepts[p] = 0;
-        if (P.status) P.status[p] = PK_NONFINITE;
-        if (P.iters_to_tol) P.iters_to_tol[p] = -1;
-        if (resumable) P.st_state[p] = PK_ST_DONE;
-        for (int it = 0; it < P.trace_iters; ++it) write_trace<C, L, KIND>(P, it, p, q, false);
-        return;
+    for (int c = 0; c < C; ++c) {
+        if (P.pos_err) P.pos_err[c * N + p] = NAN;
+        if (P.rot_err) P.rot_err[c * N + p] = NAN;
     }
+    if (P.cost) P.cost[p] = NAN;
+    P.pose_cost[p] = NAN;
+    if (P.iters) P.iters[p] = 0;
+    if (P.accepts) P.accepts[p] = 0;
+    if (P.status) P.status[p] = PK_NONFINITE;
+    if (P.iters_to_tol) P.iters_to_tol[p] = -1;
+    if (resumable) P.st_state[p] = PK_ST_DONE;
+    for (int it = 0; it < P.trace_iters; ++it) write_trace<C, L, KIND>(P, it, p, q, false);
+}
 
-    float cost, pcost, perr[C], rerr[C];
-    eval_cost<C, L, KIND>(rb, P, qr, S, q, cost, pcost, perr, rerr);
-    int iters, accepts, itt, flags;
-    bool done, stalled;
-    float lam;
-    if (resume) {
-        const int st = P.st_state[p];
-        iters = P.iters[p];
-        accepts = P.accepts[p];
-        itt = P.iters_to_tol[p];
-        flags = st & 0xffff;
-        stalled = (st & PK_ST_STALLED) != 0;
-        done = (st & PK_ST_DONE) != 0;
-        lam = P.st_lambda[p];
-    } else {
-        iters = accepts = flags = 0;
-        itt = meets_tol<C, L, KIND>(P, perr, rerr) ? 0 : -1;
-        stalled = false;
-        done = P.early_exit && itt == 0;
-        lam = P.lambda0;
+// Damped step from the Jacobian in LDS: FP32 Cholesky with the pivot test
+// against the largest damped diagonal, FP64 re-solve on a small pivot.
+// False if that fails too.
+template <int C, int L, int KIND>
+PK_DEV bool lane_step(const SolveParams &P, const LaneLds &S, float lam, int &flags, float *delta)
+{
+    using St = Star<C, L, KIND>;
+    float dmax = 0.f;
+#pragma unroll
+    for (int j = 0; j < St::N; ++j) {
+        const float a = jtj_diag<C, L, KIND>(S, j);
+        dmax = fmaxf(dmax, a + lam * fmaxf(a, P.damping_floor));
     }
-    const int iter_end = resumable ? min(P.max_iters, iters + P.iter_budget) : P.max_iters;
-    bool need_j = true;
+    const float thresh = P.pivot_rel * dmax;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        float Ac[St::NA], gc[L], x[L];
+        form_normal<C, L, KIND, float>(S, c, Ac, gc);
+        ok &= chol_damped<L, float>(Ac, lam, P.damping_floor, thresh, Ac);   // in place
+        chol_solve_neg<L, float>(Ac, gc, x);
+#pragma unroll
+        for (int ii = 0; ii < L; ++ii) delta[c * L + ii] = x[ii];
+    }
+    if (!ok) {
+        flags |= PK_FLAG_FP64;
+        ok = step_fp64<C, L, KIND>(P, S, lam, delta);
+    }
+    return ok;
+}
 
-    while (!done && iters < iter_end) {
-        // keep LDS-resident state out of registers across iterations
-        __asm__ volatile("" ::: "memory");
-        if (need_j) {
-            // Jacobian at the current point (after an accept) -> LDS.
-#pragma unroll
-            for (int c = 0; c < C; ++c) eval_jacobian_chain<C, L, KIND>(rb, P, qr, S, q, c);
-            need_j = false;
-        }
-        // Damped normal equations, FP32 Cholesky with the pivot test against
-        // the largest damped diagonal.
-        float dmax = 0.f;
-#pragma unroll
-        for (int j = 0; j < St::N; ++j) {
-            const float a = jtj_diag<C, L, KIND>(S, j);
-            dmax = fmaxf(dmax, a + lam * fmaxf(a, P.damping_floor));
-        }
-        const float thresh = P.pivot_rel * dmax;
-        float delta[St::N];
-        bool ok = true;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            float Ac[St::NA], gc[L], x[L];
-            form_normal<C, L, KIND, float>(S, c, Ac, gc);
-            ok &= chol_damped<L, float>(Ac, lam, P.damping_floor, thresh, Ac);   // in place
-            chol_solve_neg<L, float>(Ac, gc, x);
-#pragma unroll
-            for (int ii = 0; ii < L; ++ii) delta[c * L + ii] = x[ii];
-        }
-        if (!ok) {
-            flags |= PK_FLAG_FP64;
-            ok = step_fp64<C, L, KIND>(P, S, lam, delta);
-        }
-        float ct = INFINITY, pct = 0.f, pe_t[C], re_t[C], qt[St::N];
-        if (ok) {
-#pragma unroll
-            for (int j = 0; j < St::N; ++j) qt[j] = q[j] + delta[j];
-            eval_cost<C, L, KIND>(rb, P, qr, S, qt, ct, pct, pe_t, re_t);
-        }
-        ++iters;
-        const bool acc = ct < cost;
-        if (acc) {
-#pragma unroll
-            for (int j = 0; j < St::N; ++j) q[j] = qt[j];
-            cost = ct;
-            pcost = pct;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                perr[c] = pe_t[c];
-                rerr[c] = re_t[c];
-            }
-            lam = fmaxf(lam / P.nu_down, P.lambda_min);
-            ++accepts;
-            need_j = true;
-            if (meets_tol<C, L, KIND>(P, perr, rerr)) {
-                if (itt < 0) itt = iters;
-                if (P.early_exit) done = true;
-            }
-        } else {
-            if (lam >= P.lambda_max) {
-                stalled = true;
-                done = true;
-            }
-            lam = fminf(lam * P.nu_up, P.lambda_max);
-        }
-        write_trace<C, L, KIND>(P, iters - 1, p, q, acc);
-    }
-    const bool finished = done || iters >= P.max_iters;
+// Final outputs of problem p (and its trace after the last iteration).
+template <int C, int L, int KIND>
+PK_DEV void write_result(const SolveParams &P, int64_t p, const float *q, float cost, float pcost,
+                         const float *perr, const float *rerr, int iters, int accepts, int itt,
+                         int flags, bool stalled, bool finished)
+{
+    using St = Star<C, L, KIND>;
+    const int64_t N = P.N;
     if (finished)
         for (int it = iters; it < P.trace_iters; ++it) write_trace<C, L, KIND>(P, it, p, q, false);
-
     const bool conv = meets_tol<C, L, KIND>(P, perr, rerr);
 #pragma unroll
     for (int j = 0; j < St::N; ++j) P.joints[j * N + p] = q[j];
@@ -496,6 +440,114 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
     if (P.status)
         P.status[p] = (conv ? PK_CONVERGED : (stalled ? PK_STALLED : PK_MAX_ITERS)) | flags;
     if (P.iters_to_tol) P.iters_to_tol[p] = itt;
+}
+
+// One LM problem (active index i) on this lane.  With P.st_state the run is
+// resumable: it continues from the state a previous launch left in HBM and
+// stops after P.iter_budget iterations.  Each pass of the loop evaluates one
+// point (first the starting point, then each trial), so the cost evaluation
+// has a single call site.
+template <int C, int L, int KIND, bool RESUMABLE>
+PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict__ qr,
+                         const SolveParams &P, const LaneLds &S, int64_t i)
+{
+    using St = Star<C, L, KIND>;
+    const int64_t p = P.active ? (int64_t)P.active[i] : i;
+    constexpr bool resumable = RESUMABLE;
+    const bool resume = RESUMABLE && P.resume;
+
+    float q[St::N], qt[St::N];
+    if (!load_problem<C, L, KIND>(P, S, resume ? P.joints : P.seeds, p, q)) {
+        write_nonfinite<C, L, KIND>(P, p, q, resumable);
+        return;
+    }
+    int iters = 0, accepts = 0, itt = -1, flags = 0;
+    bool done = false, stalled = false;
+    float lam = P.lambda0;
+    if (resume) {
+        const int st = P.st_state[p];
+        iters = P.iters[p];
+        accepts = P.accepts[p];
+        itt = P.iters_to_tol[p];
+        flags = st & 0xffff;
+        stalled = (st & PK_ST_STALLED) != 0;
+        done = (st & PK_ST_DONE) != 0;
+        lam = P.st_lambda[p];
+    }
+    const int iter_end = resumable ? min(P.max_iters, iters + P.iter_budget) : P.max_iters;
+    float cost = 0.f, pcost = 0.f, perr[C], rerr[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) perr[c] = rerr[c] = 0.f;
+#pragma unroll
+    for (int j = 0; j < St::N; ++j) qt[j] = q[j];
+    bool first = true, need_j = true;
+
+    for (;;) {
+        // keep LDS-resident state out of registers across iterations
+        __asm__ volatile("" ::: "memory");
+        bool ok = true;
+        if (!first) {
+            if (need_j) {
+                // Jacobian at the current point (after an accept) -> LDS.
+#pragma unroll
+                for (int c = 0; c < C; ++c) eval_jacobian_chain<C, L, KIND>(rb, P, qr, S, q, c);
+                need_j = false;
+            }
+            float delta[St::N];
+            ok = lane_step<C, L, KIND>(P, S, lam, flags, delta);
+#pragma unroll
+            for (int j = 0; j < St::N; ++j) qt[j] = q[j] + delta[j];
+        }
+        float ct = INFINITY, pct = 0.f, pe_t[C], re_t[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) pe_t[c] = re_t[c] = 0.f;
+        if (ok) eval_cost<C, L, KIND>(rb, P, qr, S, qt, ct, pct, pe_t, re_t);
+        if (first) {
+            cost = ct;
+            pcost = pct;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                perr[c] = pe_t[c];
+                rerr[c] = re_t[c];
+            }
+            if (!resume) {
+                itt = meets_tol<C, L, KIND>(P, perr, rerr) ? 0 : -1;
+                done = P.early_exit && itt == 0;
+            }
+            first = false;
+        } else {
+            ++iters;
+            const bool acc = ct < cost;
+            if (acc) {
+#pragma unroll
+                for (int j = 0; j < St::N; ++j) q[j] = qt[j];
+                cost = ct;
+                pcost = pct;
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    perr[c] = pe_t[c];
+                    rerr[c] = re_t[c];
+                }
+                lam = fmaxf(lam / P.nu_down, P.lambda_min);
+                ++accepts;
+                need_j = true;
+                if (meets_tol<C, L, KIND>(P, perr, rerr)) {
+                    if (itt < 0) itt = iters;
+                    if (P.early_exit) done = true;
+                }
+            } else {
+                if (lam >= P.lambda_max) {
+                    stalled = true;
+                    done = true;
+                }
+                lam = fminf(lam * P.nu_up, P.lambda_max);
+            }
+            write_trace<C, L, KIND>(P, iters - 1, p, q, acc);
+        }
+        if (done || iters >= iter_end) break;
+    }
+    const bool finished = done || iters >= P.max_iters;
+    write_result<C, L, KIND>(P, p, q, cost, pcost, perr, rerr, iters, accepts, itt, flags, stalled, finished);
     if (resumable) {
         P.st_lambda[p] = lam;
         P.st_state[p] = flags | (stalled ? PK_ST_STALLED : 0) | (finished ? PK_ST_DONE : 0);
@@ -550,16 +602,6 @@ __global__ __launch_bounds__(BLOCK) void lm_lane_persist_kernel(const RobotC *__
     persist_loop<C, L, KIND>(rb, qr, P, smem);
 }
 
-// Same, with the register budget of two wavefronts per SIMD (used where the
-// allocator otherwise overshoots 256 registers by a few).
-template <int C, int L, int KIND>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
-void lm_lane_persist2_kernel(const RobotC *__restrict__ rb, const float *__restrict__ qr, SolveParams P)
-{
-    __shared__ float smem[Slots<C, L, KIND>::TOTAL * BLOCK];
-    persist_loop<C, L, KIND>(rb, qr, P, smem);
-}
-
 template <int C, int L, int KIND>
 hipError_t launch_star(const RobotC *rb, const SolveParams &P, int persist_blocks, hipStream_t s)
 {
@@ -569,10 +611,7 @@ hipError_t launch_star(const RobotC *rb, const SolveParams &P, int persist_block
     if (persist && persist_blocks > 0 && persist_blocks < grid) grid = persist_blocks;
     // rest pose: caller's array, else the robot's mid-range table
     const float *qr = P.q_rest ? P.q_rest : rb->mid;
-    if (persist && C == 1)
-        hipLaunchKernelGGL((lm_lane_persist2_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb,
-                           qr, P);
-    else if (persist)
+    if (persist)
         hipLaunchKernelGGL((lm_lane_persist_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb,
                            qr, P);
     else

@@ -149,8 +149,35 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
     PA.targets = targets; PA.seeds = seeds_a;
     PA.joints = joints_a; PA.cost = cost_a; PA.pose_cost = pcost_a; PA.status = status_a;
     PA.iters = out->refine_iters; PA.accepts = out->refine_accepts; PA.iters_to_tol = itt_a;
-    PK_HIP(ctx, launch_lm(*rb, PA, va, s));
-    PK_HIP(ctx, launch_best_of_k(PA, n, best_a, nullptr, succ_a, s));
+    if (o->refine_iters_per_launch > 0) {
+        // Persistent, compacted schedule (same per-problem results).
+        pk_ik_group g;
+        memset(&g, 0, sizeof g);
+        g.robot_id = robot_id;
+        g.problem.n_targets = T;
+        g.problem.K = K;
+        g.problem.targets = targets;
+        g.problem.seeds = seeds_a;
+        g.weights = *w;
+        g.out.joints = joints_a;
+        g.out.cost = cost_a;
+        g.out.iters = out->refine_iters;
+        g.out.accepts = out->refine_accepts;
+        g.out.status = status_a;
+        g.out.iters_to_tol = itt_a;
+        g.out.best_index = best_a;
+        g.out.target_success = succ_a;
+        pk_sched_options so;
+        memset(&so, 0, sizeof so);
+        so.iters_per_launch = o->refine_iters_per_launch;
+        so.blocks_per_cu = o->refine_blocks_per_cu > 0 ? o->refine_blocks_per_cu : 4;
+        so.use_graph = 1;
+        rc = sched_run(ctx, 1, &g, &o->refine, so, s);
+        if (rc) return rc;
+    } else {
+        PK_HIP(ctx, launch_lm(*rb, PA, va, s));
+        PK_HIP(ctx, launch_best_of_k(PA, n, best_a, nullptr, succ_a, s));
+    }
     // Pass B: random seeds on the failed targets only.
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, (int64_t)8, 0, counters);
     if (Kf > 0) {

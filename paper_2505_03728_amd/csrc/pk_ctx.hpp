@@ -42,6 +42,10 @@ int prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *w,
 hipError_t launch_lm(const RobotEntry &rb, const SolveParams &P, int variant, hipStream_t s,
                      int persist_blocks = 0);
 void sched_free(pk_ctx *ctx);
+// The mixed scheduler on these groups (no argument checks beyond the
+// per-group ones); used by the seeded pipeline's refinement.
+int sched_run(pk_ctx *ctx, int n_groups, const pk_ik_group *groups, const pk_lm_options *opt,
+              const pk_sched_options &sch, hipStream_t stream);
 // Seeder inference into seeds [n][T*K] (device), asynchronous.
 int seeder_infer_into(pk_ctx *ctx, int32_t seeder_id, const float *targets, int64_t T,
                       float *seeds, hipStream_t s, int32_t *K_out, int32_t *robot_out);

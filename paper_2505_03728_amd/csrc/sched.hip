@@ -244,11 +244,12 @@ int run(pk_ctx *ctx, int n_groups, const pk_ik_group *groups, const pk_lm_option
     char kb[256];
     std::string key;
     for (int g = 0; g < n_groups; ++g) {
-        snprintf(kb, sizeof kb, "%p.%p.%p.%p.%p.%p.%p.%p.%p.%p.%p|", groups[g].problem.targets,
-                 groups[g].problem.seeds, (void *)groups[g].out.joints, (void *)groups[g].out.status,
-                 (void *)groups[g].out.cost, (void *)groups[g].out.iters, (void *)groups[g].out.accepts,
-                 (void *)groups[g].out.pos_err, (void *)groups[g].out.best_joints,
-                 (void *)groups[g].out.target_success, (void *)groups[g].weights.q_rest);
+        const pk_ik_outputs &go = groups[g].out;
+        snprintf(kb, sizeof kb, "%p.%p.%p.%p.%p.%p.%p.%p.%p.%p.%p.%p.%p.%p|", groups[g].problem.targets,
+                 groups[g].problem.seeds, (void *)go.joints, (void *)go.status, (void *)go.cost,
+                 (void *)go.iters, (void *)go.accepts, (void *)go.pos_err, (void *)go.rot_err,
+                 (void *)go.iters_to_tol, (void *)go.best_index, (void *)go.best_joints,
+                 (void *)go.target_success, (void *)groups[g].weights.q_rest);
         key += kb;
         snprintf(kb, sizeof kb, "%g,%g,%g,%g;", groups[g].weights.w_pos, groups[g].weights.w_rot,
                  groups[g].weights.w_limit, groups[g].weights.w_rest);
@@ -299,6 +300,12 @@ int run(pk_ctx *ctx, int n_groups, const pk_ik_group *groups, const pk_lm_option
 }
 
 }  // namespace
+
+int sched_run(pk_ctx *ctx, int n_groups, const pk_ik_group *groups, const pk_lm_options *opt,
+              const pk_sched_options &sch, hipStream_t stream)
+{
+    return run(ctx, n_groups, groups, opt, sch, stream);
+}
 
 void sched_free(pk_ctx *ctx)
 {

@@ -200,3 +200,14 @@ def test_seeded_pipeline_and_gain_over_random_seeds(ctx, arm):
     for t in np.nonzero(s_both)[0][:200]:
         _, pe, re = oracle.residual(tree, tg[t], wl["weights"], bj[t])
         assert pe[0] <= 1e-3 * 1.05 and re[0] <= 1e-2 * 1.05
+    # the compacted refinement schedule (k iterations per launch) gives the
+    # same per-target results as the single launch
+    for k in (2, 3):
+        comp = ctx.ik_solve_seeded(arm, targets, sd, w, ref, fallback=fb, fallback_seeds=rseeds,
+                                   fallback_K=8, counters=True, refine_iters_per_launch=k,
+                                   refine_blocks_per_cu=4)
+        torch.cuda.synchronize()
+        for key in ["best_joints", "target_success", "source", "iters_to_tol", "refine_iters",
+                    "refine_accepts", "fallback_iters"]:
+            np.testing.assert_array_equal(comp[key].cpu().numpy(), both[key].cpu().numpy(),
+                                          err_msg=f"k={k} {key}")
