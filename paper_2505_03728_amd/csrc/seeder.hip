@@ -36,41 +36,56 @@ PK_DEV float silu_grad(float z)
     return s * (1.f + z * (1.f - s));
 }
 
+// Epilogues receive four consecutive output columns n..n+3 of row m.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
 struct EpiStore {           // C[z] = acc (FP32); z = split-K slice, slices `zstride` apart
     float *C;
     int ld;
     size_t zstride;
-    PK_DEV void operator()(int m, int n, int z, float v) const { C[z * zstride + (size_t)m * ld + n] = v; }
+    PK_DEV void operator()(int m, int n, int z, f32x4 v) const
+    {
+        *(f32x4 *)&C[z * zstride + (size_t)m * ld + n] = v;
+    }
 };
 struct EpiHidden {          // z = acc + b; Z = z; H = bf16(SiLU(z))
     const float *bias;
     float *Z;
     __bf16 *H;
     int ld;
-    PK_DEV void operator()(int m, int n, int, float v) const
+    PK_DEV void operator()(int m, int n, int, f32x4 v) const
     {
-        const float z = v + bias[n];
-        if (Z) Z[(size_t)m * ld + n] = z;
-        H[(size_t)m * ld + n] = (__bf16)silu(z);
+        const f32x4 b = *(const f32x4 *)&bias[n];
+        const f32x4 z = v + b;
+        const size_t i = (size_t)m * ld + n;
+        if (Z) *(f32x4 *)&Z[i] = z;
+        const bf16x4 h = {(__bf16)silu(z[0]), (__bf16)silu(z[1]), (__bf16)silu(z[2]), (__bf16)silu(z[3])};
+        *(bf16x4 *)&H[i] = h;
     }
 };
 struct EpiOut {             // y = acc + b
     const float *bias;
     float *Y;
     int ld;
-    PK_DEV void operator()(int m, int n, int, float v) const { Y[(size_t)m * ld + n] = v + bias[n]; }
+    PK_DEV void operator()(int m, int n, int, f32x4 v) const
+    {
+        *(f32x4 *)&Y[(size_t)m * ld + n] = v + *(const f32x4 *)&bias[n];
+    }
 };
 struct EpiBackHidden {      // dZ = acc * SiLU'(Z): FP32 and BF16 copies
     const float *Z;
     float *dZ;
     __bf16 *dZb;
     int ld;
-    PK_DEV void operator()(int m, int n, int, float v) const
+    PK_DEV void operator()(int m, int n, int, f32x4 v) const
     {
         const size_t i = (size_t)m * ld + n;
-        const float g = v * silu_grad(Z[i]);
-        dZ[i] = g;
-        dZb[i] = (__bf16)g;
+        const f32x4 z = *(const f32x4 *)&Z[i];
+        const f32x4 g = {v[0] * silu_grad(z[0]), v[1] * silu_grad(z[1]), v[2] * silu_grad(z[2]),
+                         v[3] * silu_grad(z[3])};
+        *(f32x4 *)&dZ[i] = g;
+        const bf16x4 gb = {(__bf16)g[0], (__bf16)g[1], (__bf16)g[2], (__bf16)g[3]};
+        *(bf16x4 *)&dZb[i] = gb;
     }
 };
 
@@ -112,7 +127,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __
     __shared__ __attribute__((aligned(16))) __bf16 sB[BN * LDK];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    // Workgroups are handed to the 8 XCDs in turn (linear id mod 8).  Give
+    // each XCD a contiguous run of tiles instead, so the N tiles that share
+    // an A row block run together behind one L2.
+    const int nx = (int)gridDim.x, ntile = nx * (int)gridDim.y;
+    int b = (int)blockIdx.x + nx * (int)blockIdx.y;
+    if (ntile % 8 == 0) b = (b % 8) * (ntile / 8) + b / 8;
+    const int m0 = (b / nx) * BM, n0 = (b % nx) * BN;
     f32x4 acc[WM][WN];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -193,20 +214,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __
             for (int i = 0; i < WM; ++i)
 #pragma unroll
                 for (int j = 0; j < WN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
         }
     }
-    // D layout: lane l holds rows 4*(l/16)+e, column l%16 of each 16x16 tile.
+    // The B fragment is the MFMA's first operand, so the 16x16 result is the
+    // transposed tile: lane l holds row l%16 and columns 4*(l/16)..+3.
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < WN; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int m = m0 + wm * 16 * WM + 16 * i + 4 * (lane >> 4) + e;
-                const int n = n0 + wn * 16 * WN + 16 * j + (lane & 15);
-                epi(m, n, (int)blockIdx.z, acc[i][j][e]);
-            }
+        for (int j = 0; j < WN; ++j) {
+            const int m = m0 + wm * 16 * WM + 16 * i + (lane & 15);
+            const int n = n0 + wn * 16 * WN + 16 * j + 4 * (lane >> 4);
+            epi(m, n, (int)blockIdx.z, acc[i][j]);
+        }
 }
 
 template <int AL, int BL, int WM, int WN, class Epi>
@@ -455,18 +475,19 @@ __global__ void fill_kernel(int64_t count, float v, float *p)
     if (i < count) p[i] = v;
 }
 
-// Seeds [n][T*K] from the network output, clamped to the joint limits.
+// Seeds [n][T*K] from the network output, clamped to the joint limits.  One
+// thread per (target, seed): its n outputs are contiguous in Y, and
+// neighbouring threads write neighbouring seeds of each joint plane.
 __global__ void seeds_kernel(int64_t T, int K, int n, int out_pad, const float *__restrict__ Y,
                              const RobotC *__restrict__ rb, float *seeds)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= T) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // = t * K + k
     const int64_t NK = T * K;
-    for (int k = 0; k < K; ++k)
-        for (int j = 0; j < n; ++j) {
-            const float v = Y[t * out_pad + k * n + j];
-            seeds[(int64_t)j * NK + t * K + k] = fminf(fmaxf(v, rb->j[j].lo), rb->j[j].hi);
-        }
+    if (i >= NK) return;
+    const int64_t t = i / K;
+    const int k = (int)(i - t * K);
+    const float *y = Y + t * out_pad + k * n;
+    for (int j = 0; j < n; ++j) seeds[(int64_t)j * NK + i] = fminf(fmaxf(y[j], rb->j[j].lo), rb->j[j].hi);
 }
 
 // Encoded inputs x [B][7] (and optionally joints q [B][n]) into the padded
@@ -837,7 +858,7 @@ int seeder_infer_into(pk_ctx *ctx, int32_t id, const float *targets, int64_t T, 
                        1.f / s->reach, s->in_pad, s->X0, (float *)nullptr);
     PK_HIP(ctx, hipGetLastError());
     PK_HIP(ctx, forward(s, rows, false, st));
-    hipLaunchKernelGGL(sd::seeds_kernel, dim3(sd::blocks(T, 256)), dim3(256), 0, st, T, s->K, s->n, s->out_pad,
+    hipLaunchKernelGGL(sd::seeds_kernel, dim3(sd::blocks(T * s->K, 256)), dim3(256), 0, st, T, s->K, s->n, s->out_pad,
                        s->Y, rb->dev, seeds);
     PK_HIP(ctx, hipGetLastError());
     return PK_OK;
