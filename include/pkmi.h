@@ -248,9 +248,15 @@ int pk_seeder_param_count(pk_ctx *ctx, int32_t seeder_id, int64_t *count);
 /* Copies (synchronously, in the init layout) the parameters (which = 0), the
  * gradients of the last step (1) or Adam's first (2) / second (3) moments. */
 int pk_seeder_get(pk_ctx *ctx, int32_t seeder_id, int32_t which, float *host_out, int64_t count);
-/* Network output y [B][n*K] (device) for encoded inputs x [B][7] (device). */
+/* Network output y [B][n*K] (device) for encoded inputs x [B][7] (device).
+ * Hidden widths 128, 256 and 512 with n*K <= 128 run as one fused kernel
+ * (activations kept on chip); other shapes layer by layer. */
 int pk_seeder_forward(pk_ctx *ctx, int32_t seeder_id, const float *x, int64_t B, float *y,
                       void *stream);
+/* The same output computed layer by layer with the training pass's GEMMs
+ * (activations through HBM); for checking the fused inference pass. */
+int pk_seeder_forward_layers(pk_ctx *ctx, int32_t seeder_id, const float *x, int64_t B, float *y,
+                             void *stream);
 /* Loss (device scalar, optional) and parameter gradients for one batch of
  * encoded inputs x [B][7] and joints q [B][n] (device); B a multiple of 128. */
 int pk_seeder_grad(pk_ctx *ctx, int32_t seeder_id, const float *x, const float *q, int64_t B,

@@ -127,6 +127,7 @@ def lib():
         L.pk_seeder_param_count.argtypes = [vp, i32, C.POINTER(i64)]
         L.pk_seeder_get.argtypes = [vp, i32, i32, fp, i64]
         L.pk_seeder_forward.argtypes = [vp, i32, vp, i64, vp, vp]
+        L.pk_seeder_forward_layers.argtypes = [vp, i32, vp, i64, vp, vp]
         L.pk_seeder_grad.argtypes = [vp, i32, vp, vp, i64, vp, vp]
         L.pk_seeder_train.argtypes = [vp, i32, vp, i64, i32, i32, C.c_float, vp, vp, vp]
         L.pk_seeder_infer.argtypes = [vp, i32, vp, i64, vp, vp]
@@ -141,7 +142,8 @@ def lib():
         for f in ["pk_create", "pk_destroy", "pk_robot_upload", "pk_robot_info", "pk_fk",
                   "pk_residual_jacobian", "pk_ik_solve", "pk_seeder_create",
                   "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward",
-                  "pk_seeder_grad", "pk_seeder_train", "pk_seeder_infer", "pk_seeder_save",
+                  "pk_seeder_forward_layers", "pk_seeder_grad", "pk_seeder_train",
+                  "pk_seeder_infer", "pk_seeder_save",
                   "pk_seeder_load", "pk_ik_solve_seeded", "pk_ik_solve_mixed",
                   "pk_autotune_mixed"]:
             getattr(L, f).restype = C.c_int
@@ -153,7 +155,8 @@ def exported_symbols():
     """Names of the C entry points this binding expects the library to export."""
     return ["pk_create", "pk_destroy", "pk_last_error", "pk_robot_upload", "pk_robot_info",
             "pk_fk", "pk_residual_jacobian", "pk_ik_solve", "pk_seeder_create",
-            "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward", "pk_seeder_grad",
+            "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward",
+            "pk_seeder_forward_layers", "pk_seeder_grad",
             "pk_seeder_train", "pk_seeder_infer", "pk_seeder_save", "pk_seeder_load",
             "pk_ik_solve_seeded", "pk_ik_solve_mixed", "pk_autotune_mixed"]
 
@@ -435,12 +438,13 @@ class Seeder:
             out.append((W.copy(), b.copy()))
         return out
 
-    def forward(self, x):
-        """x: cuda float32 [B, 7] (encoded) -> y [B, n*K]."""
+    def forward(self, x, layers=False):
+        """x: cuda float32 [B, 7] (encoded) -> y [B, n*K].  layers=True takes the
+        layer-by-layer GEMM path instead of the fused inference kernel."""
         y = self.ctx._torch.empty((x.shape[0], self._n * self.K), dtype=self.ctx._torch.float32,
                                   device=x.device)
-        self.ctx._call(lib().pk_seeder_forward(self.ctx._h, self.id, _ptr(x), x.shape[0], _ptr(y),
-                                               self.ctx.stream()))
+        fn = lib().pk_seeder_forward_layers if layers else lib().pk_seeder_forward
+        self.ctx._call(fn(self.ctx._h, self.id, _ptr(x), x.shape[0], _ptr(y), self.ctx.stream()))
         return y
 
     def grad(self, x, q):

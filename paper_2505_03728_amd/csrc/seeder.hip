@@ -4,13 +4,10 @@
 //
 //   x = [p / reach, quat (w >= 0)]  (7 inputs, zero-padded to 32)
 //   h_l = SiLU(W_l h_{l-1} + b_l)   (hidden width H, `depth` layers)
-//   y = W_out h + b_out             (7K outputs, padded to a multiple of 32)
+//   y = W_out h + b_out             (7K <= 64 outputs, padded to 64)
 //   L = mean_b min_k |y_{b,k} - q_b|^2
 //
-// GEMMs: C[M,N] = A[M,K] B[K,N] with v_mfma_f32_16x16x32_bf16; a 256-thread
-// block (2x2 waves) computes a (32 WM) x (32 WN) tile, K in steps of 32 staged
-// through LDS with the reduction dimension contiguous.  Epilogues fuse bias,
-// SiLU / SiLU', the BF16 down-conversion and the FP32 copies backward needs.
+// The GEMMs (BF16 MFMA, FP32 accumulation, fused epilogues) are in sd_gemm.hpp.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -20,267 +17,11 @@
 #include "pk_ctx.hpp"
 #include "pk_device.hpp"
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+#include "sd_gemm.hpp"
+#include "sd_mlp.hpp"
 
 namespace pk {
 namespace sd {
-
-enum { A_MK = 0, A_KM = 1 };   // A(m,k) = A[m*lda + k]  or  A[k*lda + m]
-enum { B_NK = 0, B_KN = 1 };   // B(k,n) = B[n*ldb + k]  or  B[k*ldb + n]
-
-PK_DEV float silu(float z) { return z / (1.f + __expf(-z)); }
-PK_DEV float silu_grad(float z)
-{
-    const float s = 1.f / (1.f + __expf(-z));
-    return s * (1.f + z * (1.f - s));
-}
-
-// Epilogues receive four consecutive output columns n..n+3 of row m.
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-
-struct EpiStore {           // C[z] = acc (FP32); z = split-K slice, slices `zstride` apart
-    float *C;
-    int ld;
-    size_t zstride;
-    PK_DEV void operator()(int m, int n, int z, f32x4 v) const
-    {
-        *(f32x4 *)&C[z * zstride + (size_t)m * ld + n] = v;
-    }
-};
-struct EpiHidden {          // z = acc + b; Z = z; H = bf16(SiLU(z))
-    const float *bias;
-    float *Z;
-    __bf16 *H;
-    int ld;
-    PK_DEV void operator()(int m, int n, int, f32x4 v) const
-    {
-        const f32x4 b = *(const f32x4 *)&bias[n];
-        const f32x4 z = v + b;
-        const size_t i = (size_t)m * ld + n;
-        if (Z) *(f32x4 *)&Z[i] = z;
-        const bf16x4 h = {(__bf16)silu(z[0]), (__bf16)silu(z[1]), (__bf16)silu(z[2]), (__bf16)silu(z[3])};
-        *(bf16x4 *)&H[i] = h;
-    }
-};
-struct EpiOut {             // y = acc + b
-    const float *bias;
-    float *Y;
-    int ld;
-    PK_DEV void operator()(int m, int n, int, f32x4 v) const
-    {
-        *(f32x4 *)&Y[(size_t)m * ld + n] = v + *(const f32x4 *)&bias[n];
-    }
-};
-struct EpiBackHidden {      // dZ = acc * SiLU'(Z): FP32 and BF16 copies
-    const float *Z;
-    float *dZ;
-    __bf16 *dZb;
-    int ld;
-    PK_DEV void operator()(int m, int n, int, f32x4 v) const
-    {
-        const size_t i = (size_t)m * ld + n;
-        const f32x4 z = *(const f32x4 *)&Z[i];
-        const f32x4 g = {v[0] * silu_grad(z[0]), v[1] * silu_grad(z[1]), v[2] * silu_grad(z[2]),
-                         v[3] * silu_grad(z[3])};
-        *(f32x4 *)&dZ[i] = g;
-        const bf16x4 gb = {(__bf16)g[0], (__bf16)g[1], (__bf16)g[2], (__bf16)g[3]};
-        *(bf16x4 *)&dZb[i] = gb;
-    }
-};
-
-// Element e of R row vectors, packed along k: R consecutive bf16 in one store.
-// (The vectors are reinterpreted whole as 16-bit integers and then indexed.)
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-template <int R>
-PK_DEV void store_kpack(__bf16 *dst, const bf16x8 (&v)[R], int e)
-{
-    u16x8 w[R];
-#pragma unroll
-    for (int i = 0; i < R; ++i) w[i] = __builtin_bit_cast(u16x8, v[i]);
-    if constexpr (R == 4) {
-        *(uint2 *)dst = make_uint2((unsigned)w[0][e] | ((unsigned)w[1][e] << 16),
-                                   (unsigned)w[2][e] | ((unsigned)w[3][e] << 16));
-    } else if constexpr (R == 2) {
-        *(unsigned *)dst = (unsigned)w[0][e] | ((unsigned)w[1][e] << 16);
-    } else {
-        unsigned short *d = (unsigned short *)dst;
-#pragma unroll
-        for (int i = 0; i < R; ++i) d[i] = w[i][e];
-    }
-}
-
-// blockIdx.z selects one of gridDim.z equal slices of K (split-K); the
-// epilogue receives the slice index so partial products can be kept apart.
-// The next K stage is fetched from global memory into registers while the
-// current stage, staged in LDS with the reduction dimension contiguous, feeds
-// the MFMAs.
-template <int AL, int BL, int WM, int WN, int BK, class Epi>
-__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __bf16 *__restrict__ A,
-                                                   int lda, const __bf16 *__restrict__ B, int ldb,
-                                                   Epi epi)
-{
-    constexpr int BM = 32 * WM, BN = 32 * WN, LDK = BK + 8;
-    constexpr int NVA = BM * BK / 8, NVB = BN * BK / 8;             // 8-element vectors per stage
-    constexpr int RA = (NVA + 255) / 256, RB = (NVB + 255) / 256;   // per thread
-    __shared__ __attribute__((aligned(16))) __bf16 sA[BM * LDK];
-    __shared__ __attribute__((aligned(16))) __bf16 sB[BN * LDK];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int wm = wave >> 1, wn = wave & 1;
-    // Workgroups are handed to the 8 XCDs in turn (linear id mod 8).  Give
-    // each XCD a contiguous run of tiles instead, so the N tiles that share
-    // an A row block run together behind one L2.
-    const int nx = (int)gridDim.x, ntile = nx * (int)gridDim.y;
-    int b = (int)blockIdx.x + nx * (int)blockIdx.y;
-    if (ntile % 8 == 0) b = (b % 8) * (ntile / 8) + b / 8;
-    const int m0 = (b / nx) * BM, n0 = (b % nx) * BN;
-    f32x4 acc[WM][WN];
-#pragma unroll
-    for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    bf16x8 ra[RA], rb[RB];
-    // MK/NK layouts: vector v of a stage is (row v / (BK/8), k 8 * (v % (BK/8))).
-    // KM/KN layouts: thread t owns R consecutive k rows (R = RA or RB) of the
-    // 8-wide row group t % (rows/8), so its LDS writes pack R values per row.
-    constexpr int GA = BM / 8, GB = BN / 8;
-    const int amg = tid % GA, akq = tid / GA, bng = tid % GB, bkq = tid / GB;
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < RA; ++i) {
-            if (AL == A_MK) {
-                const int v = tid + 256 * i;
-                if (v < NVA)
-                    ra[i] = *(const bf16x8 *)&A[(size_t)(m0 + v / (BK / 8)) * lda + k0 + 8 * (v % (BK / 8))];
-            } else {
-                const int kk = akq * RA + i;
-                if (kk < BK) ra[i] = *(const bf16x8 *)&A[(size_t)(k0 + kk) * lda + m0 + 8 * amg];
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            if (BL == B_NK) {
-                const int v = tid + 256 * i;
-                if (v < NVB)
-                    rb[i] = *(const bf16x8 *)&B[(size_t)(n0 + v / (BK / 8)) * ldb + k0 + 8 * (v % (BK / 8))];
-            } else {
-                const int kk = bkq * RB + i;
-                if (kk < BK) rb[i] = *(const bf16x8 *)&B[(size_t)(k0 + kk) * ldb + n0 + 8 * bng];
-            }
-        }
-    };
-    auto lstore = [&]() {
-        if (AL == A_MK) {
-#pragma unroll
-            for (int i = 0; i < RA; ++i) {
-                const int v = tid + 256 * i;
-                if (v < NVA) *(bf16x8 *)&sA[(v / (BK / 8)) * LDK + 8 * (v % (BK / 8))] = ra[i];
-            }
-        } else if (akq * RA < BK) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) store_kpack<RA>(&sA[(8 * amg + e) * LDK + akq * RA], ra, e);
-        }
-        if (BL == B_NK) {
-#pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const int v = tid + 256 * i;
-                if (v < NVB) *(bf16x8 *)&sB[(v / (BK / 8)) * LDK + 8 * (v % (BK / 8))] = rb[i];
-            }
-        } else if (bkq * RB < BK) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) store_kpack<RB>(&sB[(8 * bng + e) * LDK + bkq * RB], rb, e);
-        }
-    };
-
-    const int kslice = K / (int)gridDim.z;
-    const int kbeg = (int)blockIdx.z * kslice, kend = kbeg + kslice;
-    gload(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += BK) {
-        __syncthreads();
-        lstore();
-        __syncthreads();
-        if (k0 + BK < kend) gload(k0 + BK);
-        const int r16 = lane & 15;
-#pragma unroll
-        for (int ks = 0; ks < BK; ks += 32) {
-            const int kq = ks + 8 * (lane >> 4);
-            bf16x8 af[WM], bfr[WN];
-#pragma unroll
-            for (int i = 0; i < WM; ++i) af[i] = *(const bf16x8 *)&sA[(wm * 16 * WM + 16 * i + r16) * LDK + kq];
-#pragma unroll
-            for (int j = 0; j < WN; ++j) bfr[j] = *(const bf16x8 *)&sB[(wn * 16 * WN + 16 * j + r16) * LDK + kq];
-#pragma unroll
-            for (int i = 0; i < WM; ++i)
-#pragma unroll
-                for (int j = 0; j < WN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
-        }
-    }
-    // The B fragment is the MFMA's first operand, so the 16x16 result is the
-    // transposed tile: lane l holds row l%16 and columns 4*(l/16)..+3.
-#pragma unroll
-    for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            const int m = m0 + wm * 16 * WM + 16 * i + (lane & 15);
-            const int n = n0 + wn * 16 * WN + 16 * j + 4 * (lane >> 4);
-            epi(m, n, (int)blockIdx.z, acc[i][j]);
-        }
-}
-
-template <int AL, int BL, int WM, int WN, class Epi>
-hipError_t gemm_tile(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb, Epi epi,
-                     hipStream_t s, int splits)
-{
-    dim3 grid(N / (32 * WN), M / (32 * WM), splits);
-    if ((K / splits) % 64 == 0)
-        hipLaunchKernelGGL((gemm_kernel<AL, BL, WM, WN, 64, Epi>), grid, dim3(256), 0, s, M, N, K, A, lda,
-                           B, ldb, epi);
-    else
-        hipLaunchKernelGGL((gemm_kernel<AL, BL, WM, WN, 32, Epi>), grid, dim3(256), 0, s, M, N, K, A, lda,
-                           B, ldb, epi);
-    return hipGetLastError();
-}
-
-// Picks the tile for the shape (M % 64 == 0, N % 32 == 0, K % (32 * splits) == 0).
-template <int AL, int BL, class Epi>
-hipError_t gemm(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb, Epi epi,
-                hipStream_t s, int splits = 1)
-{
-    if (M % 64 || N % 32 || splits < 1 || K % (32 * splits)) return hipErrorInvalidValue;
-    const bool m128 = M % 128 == 0;
-    if (N % 128 == 0)
-        return m128 ? gemm_tile<AL, BL, 4, 4>(M, N, K, A, lda, B, ldb, epi, s, splits)
-                    : gemm_tile<AL, BL, 2, 4>(M, N, K, A, lda, B, ldb, epi, s, splits);
-    if (N % 64 == 0)
-        return m128 ? gemm_tile<AL, BL, 4, 2>(M, N, K, A, lda, B, ldb, epi, s, splits)
-                    : gemm_tile<AL, BL, 2, 2>(M, N, K, A, lda, B, ldb, epi, s, splits);
-    return m128 ? gemm_tile<AL, BL, 4, 1>(M, N, K, A, lda, B, ldb, epi, s, splits)
-                : gemm_tile<AL, BL, 2, 1>(M, N, K, A, lda, B, ldb, epi, s, splits);
-}
-
-// Number of K slices so that an (M x N) output with a K-long reduction
-// fills the device: about 256 workgroups, each slice at least 256 long.
-inline int split_for(int M, int N, int K)
-{
-    const int tm = M % 128 == 0 ? 128 : 64, tn = N % 128 == 0 ? 128 : N % 64 == 0 ? 64 : 32;
-    const int tiles = (M / tm) * (N / tn);
-    int sp = 1;
-    while (tiles * sp < 256 && K % (64 * sp) == 0 && K / (2 * sp) >= 256) sp *= 2;
-    return sp;
-}
-
-// Largest split_for(M, N, K) over all K: the smallest power of two that
-// brings the tile count to 256.
-inline int split_max(int M, int N)
-{
-    const int tm = M % 128 == 0 ? 128 : 64, tn = N % 128 == 0 ? 128 : N % 64 == 0 ? 64 : 32;
-    const int tiles = (M / tm) * (N / tn);
-    int sp = 1;
-    while (tiles * sp < 256) sp *= 2;
-    return sp;
-}
 
 // out[i] = sum over z of part[z * count + i] (fixed order).
 __global__ void split_reduce_kernel(int64_t count, int splits, const float *__restrict__ part, float *out)
@@ -532,6 +273,11 @@ struct SeederState {
     float *Z = nullptr, *Y = nullptr, *dZ = nullptr, *dY = nullptr, *Q = nullptr, *part = nullptr;
     float *splitbuf = nullptr;          // split-K partial weight gradients
     size_t splitbuf_floats = 0;
+    // BF16 weights in MFMA fragment order for the fused inference pass,
+    // rebuilt from Pb after the parameters change.
+    __bf16 *Wf = nullptr;
+    std::vector<int64_t> wfoff;
+    bool wf_dirty = true;
     std::vector<void *> extra;
 };
 
@@ -539,7 +285,7 @@ void seeder_free(SeederState *s)
 {
     if (!s) return;
     void *ptrs[] = {s->P, s->G, s->M, s->V, s->Pb, s->dstep, s->X0, s->Hb, s->dZb, s->dYb, s->Z,
-                    s->Y, s->dZ, s->dY, s->Q, s->part, s->splitbuf};
+                    s->Y, s->dZ, s->dY, s->Q, s->part, s->splitbuf, s->Wf};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (void *p : s->extra)
@@ -617,6 +363,44 @@ hipError_t forward(SeederState *s, int64_t rows, bool train, hipStream_t st)
     const int L = s->depth;
     return gemm<A_MK, B_NK>((int)rows, s->out_pad, s->H, in, s->H, s->Pb + s->woff[L], s->H,
                             EpiOut{s->P + s->boff[L], s->Y, s->out_pad}, st);
+}
+
+// Inference forward pass over `rows` rows of X0 into Y: the fused kernel for
+// the shapes it covers (hidden width 128, 256 or 512, padded output width
+// 64), else the layer-by-layer GEMMs.  Both give the same values.
+hipError_t forward_infer(SeederState *s, int64_t rows, hipStream_t st)
+{
+    using namespace sd;
+    const int JT = s->H / 64;
+    const bool fused = s->in_pad == 32 && s->out_pad == 64 && (JT == 2 || JT == 4 || JT == 8) &&
+                       s->depth + 1 <= MLP_MAX_LAYERS;
+    if (!fused) return forward(s, rows, false, st);
+    if (s->wf_dirty) {
+        for (int l = 0; l <= s->depth; ++l) {
+            const int N = s->lout[l], K = s->lin[l];
+            const int64_t pieces = (int64_t)(N / 16) * (K / 32) * 64;
+            hipLaunchKernelGGL(frag_layout_kernel, dim3(blocks(pieces, 256)), dim3(256), 0, st, N, K, K,
+                               (const __bf16 *)(s->Pb + s->woff[l]), l < s->depth ? 1 : 0, s->Wf + s->wfoff[l]);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        s->wf_dirty = false;
+    }
+    MlpArgs a{};
+    a.depth = s->depth;
+    a.out_pad = s->out_pad;
+    for (int l = 0; l <= s->depth; ++l) {
+        a.wf[l] = s->Wf + s->wfoff[l];
+        a.bias[l] = s->P + s->boff[l];
+    }
+    const dim3 grid((unsigned)(rows / 64)), block(256);
+    if (JT == 2)
+        hipLaunchKernelGGL((mlp_infer_kernel<2, 1>), grid, block, 0, st, a, s->X0, s->Y);
+    else if (JT == 4)
+        hipLaunchKernelGGL((mlp_infer_kernel<4, 1>), grid, block, 0, st, a, s->X0, s->Y);
+    else
+        hipLaunchKernelGGL((mlp_infer_kernel<8, 1>), grid, block, 0, st, a, s->X0, s->Y);
+    return hipGetLastError();
 }
 
 // Weight gradient dW [M][N] = A^T B reduced over `rows` (split-K + fixed-order sum).
@@ -717,7 +501,7 @@ int pk_seeder_create(pk_ctx *ctx, int32_t robot_id, int32_t K, int32_t hidden, i
     s->depth = depth;
     s->in_pad = 32;
     s->out_real = R.n * K;
-    s->out_pad = (s->out_real + 31) / 32 * 32;
+    s->out_pad = 64;   // n*K <= 64 outputs, padded to the GEMM tile's 64 rows
     s->reach = tree_reach(R);
     int64_t off = 0;
     for (int l = 0; l <= depth; ++l) {
@@ -745,6 +529,12 @@ int pk_seeder_create(pk_ctx *ctx, int32_t robot_id, int32_t K, int32_t hidden, i
     bool ok = hipMalloc(&s->P, off * 4) == hipSuccess && hipMalloc(&s->G, off * 4) == hipSuccess &&
               hipMalloc(&s->M, off * 4) == hipSuccess && hipMalloc(&s->V, off * 4) == hipSuccess &&
               hipMalloc(&s->Pb, off * 2) == hipSuccess && hipMalloc(&s->dstep, 4) == hipSuccess;
+    int64_t wfn = 0;
+    for (int l = 0; l <= depth; ++l) {
+        s->wfoff.push_back(wfn);
+        wfn += (int64_t)s->lin[l] * s->lout[l];
+    }
+    ok = ok && hipMalloc(&s->Wf, wfn * 2) == hipSuccess;
     if (!ok) {
         seeder_free(s);
         return fail(ctx, PK_ENOMEM, "pk_seeder_create: allocation failed");
@@ -857,7 +647,7 @@ int seeder_infer_into(pk_ctx *ctx, int32_t id, const float *targets, int64_t T, 
     hipLaunchKernelGGL(sd::encode_kernel, dim3(sd::blocks(rows, 256)), dim3(256), 0, st, rows, T, targets, T,
                        1.f / s->reach, s->in_pad, s->X0, (float *)nullptr);
     PK_HIP(ctx, hipGetLastError());
-    PK_HIP(ctx, forward(s, rows, false, st));
+    PK_HIP(ctx, forward_infer(s, rows, st));
     hipLaunchKernelGGL(sd::seeds_kernel, dim3(sd::blocks(T * s->K, 256)), dim3(256), 0, st, T, s->K, s->n, s->out_pad,
                        s->Y, rb->dev, seeds);
     PK_HIP(ctx, hipGetLastError());
@@ -868,15 +658,15 @@ int seeder_infer_into(pk_ctx *ctx, int32_t id, const float *targets, int64_t T, 
 
 extern "C" {
 
-// Raw network output for encoded inputs x [B][7] (device) -> y [B][7K] (device).
-int pk_seeder_forward(pk_ctx *ctx, int32_t id, const float *x, int64_t B, float *y, void *stream)
+// x [B][7] (device) -> y [B][7K] (device), fused or layer by layer.
+static int seeder_forward(pk_ctx *ctx, int32_t id, const float *x, int64_t B, float *y, hipStream_t st,
+                   bool layers, const char *who)
 {
-    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_seeder_forward: ctx is NULL");
+    if (!ctx) return fail(nullptr, PK_EINVAL, "%s: ctx is NULL", who);
     SeederState *s = seeder_of(ctx, id);
-    if (!s) return fail(ctx, PK_ENOTFOUND, "pk_seeder_forward: unknown seeder %d", id);
-    if (B < 0 || (B > 0 && (!x || !y))) return fail(ctx, PK_EINVAL, "pk_seeder_forward: bad arguments");
+    if (!s) return fail(ctx, PK_ENOTFOUND, "%s: unknown seeder %d", who, id);
+    if (B < 0 || (B > 0 && (!x || !y))) return fail(ctx, PK_EINVAL, "%s: bad arguments", who);
     if (B == 0) return PK_OK;
-    hipStream_t st = (hipStream_t)stream;
     const int64_t rows = (B + 127) / 128 * 128;
     PK_HIP(ctx, hipSetDevice(ctx->device));
     int rc = alloc_acts(ctx, s, rows);
@@ -884,11 +674,23 @@ int pk_seeder_forward(pk_ctx *ctx, int32_t id, const float *x, int64_t B, float 
     hipLaunchKernelGGL(sd::load_rows_kernel, dim3(sd::blocks(rows, 256)), dim3(256), 0, st, rows, B,
                        s->in_pad, s->n, x, nullptr, s->X0, nullptr);
     PK_HIP(ctx, hipGetLastError());
-    PK_HIP(ctx, forward(s, rows, false, st));
+    PK_HIP(ctx, layers ? forward(s, rows, false, st) : forward_infer(s, rows, st));
     hipLaunchKernelGGL(sd::store_out_kernel, dim3(sd::blocks(B, 256)), dim3(256), 0, st, B, s->out_real,
                        s->out_pad, s->Y, y);
     PK_HIP(ctx, hipGetLastError());
     return PK_OK;
+}
+
+// Raw network output for encoded inputs x [B][7] (device) -> y [B][7K] (device).
+int pk_seeder_forward(pk_ctx *ctx, int32_t id, const float *x, int64_t B, float *y, void *stream)
+{
+    return seeder_forward(ctx, id, x, B, y, (hipStream_t)stream, false, "pk_seeder_forward");
+}
+
+// The same through the layer-by-layer GEMMs.
+int pk_seeder_forward_layers(pk_ctx *ctx, int32_t id, const float *x, int64_t B, float *y, void *stream)
+{
+    return seeder_forward(ctx, id, x, B, y, (hipStream_t)stream, true, "pk_seeder_forward_layers");
 }
 
 // Loss and parameter gradients for one batch x [B][7], q [B][n] (device);
@@ -955,6 +757,7 @@ int pk_seeder_train(pk_ctx *ctx, int32_t id, const float *q_train, int64_t S, in
         e = hipGetLastError();
     }
     hipError_t e2 = hipStreamSynchronize(st);
+    s->wf_dirty = true;
     (void)hipFree(pose);
     (void)hipFree(xall);
     if (e != hipSuccess) return fail(ctx, PK_EHIP, "pk_seeder_train: %s", hipGetErrorString(e));
@@ -1022,6 +825,7 @@ int pk_seeder_load(pk_ctx *ctx, int32_t id, const char *path)
     PK_HIP(ctx, hipMemcpy(s->V, buf.data() + 2 * np, np * 4, hipMemcpyHostToDevice));
     PK_HIP(ctx, hipMemcpy(s->dstep, &hdr[6], 4, hipMemcpyHostToDevice));
     s->host_step = hdr[6];
+    s->wf_dirty = true;
     hipLaunchKernelGGL(sd::to_bf16_kernel, dim3(sd::blocks(np, 256)), dim3(256), 0, 0, np, s->P, s->Pb);
     PK_HIP(ctx, hipGetLastError());
     PK_HIP(ctx, hipDeviceSynchronize());

@@ -66,6 +66,40 @@ def test_forward_matches_bf16_oracle(ctx, arm, hidden, depth, B):
         np.testing.assert_array_equal(bg, b.astype(np.float32))
 
 
+@pytest.mark.parametrize("hidden,depth,K", [(128, 1, 8), (256, 2, 8), (512, 3, 8), (256, 2, 4),
+                                            (384, 2, 8)])
+def test_fused_forward_equals_layer_path(ctx, arm, hidden, depth, K):
+    """The fused inference kernel (activations kept on chip) takes each
+    layer's reduction in the same order as the layer-by-layer GEMMs, so the
+    two give identical outputs; also after the weights change (training).
+    K=4 has 28 real outputs of the 64 computed; hidden width 384 is a shape
+    the fused kernel leaves to the GEMMs."""
+    import paper_2505_03728_amd as pk
+    import torch
+    init = synth.mlp_init([7] + [hidden] * depth + [7 * K], 31)
+    sd = pk.Seeder(ctx, arm, K=K, hidden=hidden, depth=depth, init=init)
+    for B in (300, 1024):
+        x, _ = _inputs(B, 6 + B)
+        xd = _dev(x)
+        yf = sd.forward(xd)
+        yl = sd.forward(xd, layers=True)
+        torch.cuda.synchronize()
+        assert torch.isfinite(yf).all()
+        assert torch.equal(yf, yl), (B, float((yf - yl).abs().max()))
+        yo, _ = mlp.forward(init, x, emulate_bf16=True)
+        assert _rel(yf.cpu().numpy(), yo) <= 1e-3
+    # new weights: two training steps, then both paths again
+    q = synth.uniform_configs(synth.arm7(0), 256, 9)
+    sd.train(_dev(q.T), batch=128, epochs=1, lr=1e-2)
+    x, _ = _inputs(300, 77)
+    xd = _dev(x)
+    yf, yl = sd.forward(xd), sd.forward(xd, layers=True)
+    torch.cuda.synchronize()
+    assert torch.equal(yf, yl)
+    yo, _ = mlp.forward(sd.get(0), x, emulate_bf16=True)
+    assert _rel(yf.cpu().numpy(), yo) <= 1e-3
+
+
 @pytest.mark.parametrize("hidden,depth,B", [(128, 2, 256), (512, 3, 512)])
 def test_gradients_match_bf16_oracle(ctx, arm, hidden, depth, B):
     import paper_2505_03728_amd as pk
