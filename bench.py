@@ -490,7 +490,7 @@ def run_seeder(args):
                 roofline={"bound": "mfma", "achieved": round(fl_mlp / (ms_infer / 1e3) / 1e12, 3),
                           "peak": 2500.0, "unit": "TFLOP/s",
                           "frac": round(fl_mlp / (ms_infer / 1e3) / 1e12 / 2500.0, 5), "traffic": None,
-                          "kernel": "seeder inference (4 BF16 MFMA GEMMs + encode + seeds)",
+                          "kernel": "seeder inference (fused BF16 MFMA MLP kernel + encode + seeds)",
                           "kernel_ms": round(ms_infer, 5), "algorithmic_flops": fl_mlp})
     if not args.no_cpu:
         g = {"tree": tree, "q_star": wl["eval_q_star"], "seeds": wl["plain_seeds"], "K": K}

@@ -131,3 +131,43 @@ def test_autotune_and_oracle_sample(ctx, batch):
         print(f"{g['tree'].name}: success {np.mean((out['status'] & 0xff) == 0):.3f}")
     print(f"oracle sample: {bad} unexplained, {excused} excused")
     assert bad == 0
+
+
+def test_full_size_mixed84k_sampled(ctx):
+    """The mixed benchmark's full batch (60000 arm + 20000 hand + 4096 tree, early
+    exit, <= 50 iterations) in one scheduled graph launch with the schedule the
+    autotuner picks for it, checked on a sample of each group."""
+    import paper_2505_03728_amd as pk
+    import torch
+    wl = synth.workload("mixed84k")
+    groups = []
+    for g in wl["groups"]:
+        tree = g["tree"]
+        rid = ctx.upload(tree)
+        tg = oracle.targets_from(tree, g["q_star"])
+        groups.append({"rid": rid, "tree": tree, "tg": tg, "seeds_np": g["seeds"],
+                       "targets": targets_dev(tree, tg, DEV), "seeds": soa(g["seeds"], DEV),
+                       "K": 1, "weights": pk.Weights.from_dict(g["weights"]), "wd": g["weights"]})
+    opt = pk.Options.from_dict(wl["options"])
+    gs = _fresh(ctx, groups)
+    ctx.ik_solve_mixed(gs, opt, iters_per_launch=25, blocks_per_cu=8, use_graph=True,
+                       variants=[pk.VARIANT_LANE, pk.VARIANT_LANE, pk.VARIANT_WAVE])
+    torch.cuda.synchronize()
+    got = _host(gs)
+    rng = np.random.default_rng(17)
+    bad = excused = 0
+    for g, out in zip(groups, got):
+        st = out["status"] & 0xff
+        assert np.all(np.isin(st, [0, 1, 2]))
+        # early exit: converged problems stop at their first point within tolerance
+        np.testing.assert_array_equal(out["iters_to_tol"][st == 0], out["iters"][st == 0])
+        for p in rng.choice(g["tg"].shape[0], 12, replace=False):
+            o = oracle.lm_solve(g["tree"], g["tg"][p], g["wd"], wl["options"], g["seeds_np"][p],
+                                n_trace=wl["options"]["max_iters"])
+            v = compare_outcome(ctx, g["rid"], g["tree"], g["tg"][p], g["seeds_np"][p], g["wd"],
+                                wl["options"], out["status"][p], out["iters"][p], o)
+            bad += v == "bad"
+            excused += v == "excused"
+        print(f"{g['tree'].name}: {st.size} problems, success {np.mean(st == 0):.4f}")
+    print(f"mixed84k sample: {bad} unexplained, {excused} excused of 36")
+    assert bad == 0

@@ -57,6 +57,31 @@ def test_tree34_first_iterates_and_success(ctx):
     assert bad == 0
 
 
+def test_full_size_tree4k_sampled(ctx):
+    """The tree benchmark's workload and launch (4096 problems, 40 iterations,
+    default variant = one problem per wavefront), checked on a sample."""
+    wl = synth.workload("tree4k")
+    g = wl["groups"][0]
+    tree = g["tree"]
+    rid = ctx.upload(tree)
+    tg = oracle.targets_from(tree, g["q_star"])
+    o = wl["options"]
+    res = solve_gpu(ctx, rid, tree, tg, g["seeds"], 1, wl["weights"], o)
+    st = res["status"] & 0xff
+    assert np.all(np.isin(st, [0, 1, 2]))
+    assert np.all((res["iters"] == o["max_iters"]) | np.isin(st, [0, 2]))
+    rng = np.random.default_rng(11)
+    bad = excused = 0
+    for p in np.sort(rng.choice(tg.shape[0], 24, replace=False)):
+        ora = oracle.lm_solve(tree, tg[p], wl["weights"], o, g["seeds"][p], n_trace=o["max_iters"])
+        v = compare_outcome(ctx, rid, tree, tg[p], g["seeds"][p], wl["weights"], o, res["status"][p],
+                            res["iters"][p], ora)
+        bad += v == "bad"
+        excused += v == "excused"
+    print(f"tree4k sample: {bad} unexplained, {excused} excused of 24; success {np.mean(st == 0):.4f}")
+    assert bad == 0
+
+
 @pytest.mark.parametrize("name", ["arm7", "hand16"])
 def test_wave_matches_lane_variant(ctx, name):
     import paper_2505_03728_amd as pk
