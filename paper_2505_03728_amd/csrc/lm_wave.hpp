@@ -66,6 +66,16 @@ PK_DEV float wave_max(float v)
     return v;
 }
 
+// Orders LDS accesses across the lanes of the wavefront (one lane writes,
+// the others read): without it the compiler may treat the lanes as unrelated
+// threads and move a lane's read ahead of another lane's write.
+PK_DEV void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 PK_DEV float recip(float x) { return rcp(x); }
 PK_DEV double recip(double x) { return 1.0 / x; }
 
@@ -85,7 +95,8 @@ struct Lds {
     static constexpr int RS = JC + 64 * JS;        // [6 * MMAX] EE residual rows (current point)
     static constexpr int FR = RS + 6 * MMAX;       // [64][12] joint frames O, p (last evaluated point)
     static constexpr int EX = FR + 64 * 12;        // [MMAX][ES] EE records (last evaluated point)
-    static constexpr int FLOATS = EX + MMAX * ES;
+    static constexpr int PV = EX + MMAX * ES;      // pivot row of the elimination: DMAX + 2 values, FP64-sized
+    static constexpr int FLOATS = PV + 2 * (DMAX + 2);
 };
 // Slots of an EE record.
 enum { E_PE = 0, E_R = 4, E_RE = 12, E_LG = 24, E_M = 36, E_N = 48 };
@@ -328,61 +339,51 @@ PK_DEV T jtj_rows(const float *lds, const uint32_t (&ancp)[DMAX / 4], int lane, 
 // Solve (A + lam diag(max(A_jj, floor))) delta = -g for the tree-structured A
 // given as depth-indexed rows r and undamped diagonal dgu (consumed).
 // Returns false if a pivot is not above thresh_rel * max damped diagonal
-// (thresh_rel > 0) or not positive and finite.
+// (thresh_rel > 0) or not positive and finite.  `slot` (LDS, DMAX + 2 values
+// of T) carries each pivot row to the wave; `desc` has bit k set when this
+// lane's joint is a proper ancestor of joint k.
 template <int DMAX, typename T>
 PK_DEV bool tree_solve(T (&r)[DMAX], T dgu, T g, float lam, float dfloor, float thresh_rel,
-                       int lane, int n, int dep, uint64_t ancm, const uint32_t (&ancp)[DMAX / 4],
-                       int max_depth, float &delta)
+                       int lane, int n, int dep, uint64_t desc, const uint32_t (&ancp)[DMAX / 4],
+                       int max_depth, T *slot, float &delta)
 {
     const bool isj = lane < n;
     T dg = isj ? dgu + (T)lam * (dgu > (T)dfloor ? dgu : (T)dfloor) : (T)0;
     T thresh = 0;
     if (thresh_rel > 0.f) thresh = (T)thresh_rel * (T)wave_max((float)dg);
     T b = isj ? -g : (T)0;
-    // Leaves first: step k removes joint k from its ancestors' rows.
+    bool bad = false;
+    // Leaves first: step k removes joint k from its ancestors' rows.  Lane k
+    // puts its row, pivot and right-hand side in LDS; the other lanes read
+    // them back.  Every pivot is tested; a failed test ends the solve after
+    // the loop.
     for (int k = n - 1; k >= 0; --k) {
         const int dk = bcast_i(dep, k);
-        const T piv = bcast(dg, k);
-        if (!(piv > thresh) || !(piv < (T)INFINITY)) return false;
-        const T ip = recip(piv);
-        const bool is_anc = (bcast_u64(ancm, k) >> lane) & 1ull;
-        const T bk = bcast(b, k);
-        T sel = 0;
-        if constexpr (DMAX <= 16) {
-            T wk[DMAX];
+        wave_sync();   // the previous step's reads are done
+        if (lane == k) {
 #pragma unroll
             for (int d = 0; d < DMAX; ++d) {
                 if ((d & 3) == 0 && d >= dk) break;
-                wk[d] = bcast(r[d], k);
-                sel = dep == d ? wk[d] : sel;
+                slot[d] = r[d];
             }
-            const T c = is_anc ? sel * ip : (T)0;
-#pragma unroll
-            for (int d = 0; d < DMAX; ++d) {
-                if ((d & 3) == 0 && d >= dk) break;
-                r[d] -= c * wk[d];
-            }
-            dg -= c * sel;
-            b -= c * bk;
-        } else {
-            // Row k is not changed by its own step (k is not its own
-            // ancestor), so it is read twice instead of held in SGPRs.
-#pragma unroll
-            for (int d = 0; d < DMAX; ++d) {
-                if ((d & 3) == 0 && d >= dk) break;
-                const T w = bcast(r[d], k);
-                sel = dep == d ? w : sel;
-            }
-            const T c = is_anc ? sel * ip : (T)0;
-#pragma unroll
-            for (int d = 0; d < DMAX; ++d) {
-                if ((d & 3) == 0 && d >= dk) break;
-                r[d] -= c * bcast(r[d], k);
-            }
-            dg -= c * sel;
-            b -= c * bk;
+            slot[DMAX] = dg;
+            slot[DMAX + 1] = b;
         }
+        wave_sync();   // row k is visible to every lane
+        const T piv = slot[DMAX], bk = slot[DMAX + 1];
+        bad = bad || !(piv > thresh) || !(piv < (T)INFINITY);
+        const bool is_anc = (desc >> k) & 1ull;
+        const T sel = is_anc ? slot[dep > 0 ? dep : 0] : (T)0;
+        const T c = sel * recip(piv);
+#pragma unroll
+        for (int d = 0; d < DMAX; ++d) {
+            if ((d & 3) == 0 && d >= dk) break;
+            r[d] -= c * slot[d];
+        }
+        dg -= c * sel;
+        b -= c * bk;
     }
+    if (bad) return false;
     // Back substitution, root first: x_j = (b_j - sum_d r_j[d] x_anc(d)) / pivot_j.
     const T ipj = isj ? recip(dg) : (T)0;
     T s = 0, x = 0;
@@ -432,7 +433,7 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
     const uint32_t *arow = (const uint32_t *)rb->anc_at[jl];
 #pragma unroll
     for (int i = 0; i < DMAX / 4; ++i) ancp[i] = isj ? arow[i] : 0u;
-    const uint64_t ancm = isj ? rb->janc[jl] : 0ull;
+    const uint64_t desc = isj ? rb->jdesc[jl] : 0ull;
     const int dep = C.depth;
 
     bool fin = true;
@@ -566,7 +567,7 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
 #pragma unroll
             for (int d = 0; d < DMAX; ++d) r[d] = rows[d];
             ok = tree_solve<DMAX, float>(r, dgu, g, lam, P.damping_floor, P.pivot_rel, lane, n, dep,
-                                         ancm, ancp, max_depth, delta);
+                                         desc, ancp, max_depth, lds + L::PV, delta);
         }
         if (!ok) {
             // Re-form the damped system and gradient in FP64 from the FP32
@@ -577,7 +578,7 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
                          (double)dl * dl + (double)P.w_rest * P.w_rest;
             gd += (double)dl * rl + (double)P.w_rest * rr;
             ok = tree_solve<DMAX, double>(r, dgd, isj ? gd : 0.0, lam, P.damping_floor, 0.f, lane,
-                                          n, dep, ancm, ancp, max_depth, delta);
+                                          n, dep, desc, ancp, max_depth, (double *)(lds + L::PV), delta);
         }
         qt = q + delta;
         evaluate = ok;   // a failed solve counts as a rejected step
@@ -619,7 +620,7 @@ template <int DMAX, int MMAX>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((DMAX <= 16 && MMAX <= 4) ? 2 : 1))) void lm_wave_kernel(const RobotC *__restrict__ rb, SolveParams P)
 {
     using L = Lds<DMAX, MMAX>;
-    __shared__ float lds[L::FLOATS];
+    __shared__ __attribute__((aligned(16))) float lds[L::FLOATS];
     const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
     int64_t wi = P.queue_head ? pop_item_wave(P.queue_head) : (int64_t)blockIdx.x;
     while (wi < nact) {

@@ -265,6 +265,11 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
         for (int d = 0; d < J.depth; ++d) R.anc_at[j][d] = R.anc_at[par][d];
         R.anc_at[j][J.depth] = (uint8_t)j;
     }
+    for (int j = 0; j < n; ++j) {
+        R.jdesc[j] = 0;
+        for (int k = 0; k < n; ++k)
+            if ((R.janc[k] >> j) & 1ull) R.jdesc[j] |= 1ull << k;
+    }
     int tgt = 0, rows = 0;
     for (int k = 0; k < m; ++k) {
         const int e = t->ee_joint[k], kind = t->ee_kind[k];

@@ -42,6 +42,7 @@ struct RobotC {
     EEC e[PK_MAX_EES];
     float mid[PK_MAX_JOINTS];              // (lower + upper) / 2, the default rest pose
     uint64_t janc[PK_MAX_JOINTS];          // bit i set iff joint i is a proper ancestor of joint j
+    uint64_t jdesc[PK_MAX_JOINTS];         // bit k set iff joint j is a proper ancestor of joint k
     uint8_t anc_at[PK_MAX_JOINTS][PK_MAX_JOINTS];   // [j][d]: ancestor of j at depth d (d <= depth j; j itself at its depth)
 };
 
