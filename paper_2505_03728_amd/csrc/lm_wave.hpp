@@ -68,7 +68,9 @@ PK_DEV float wave_max(float v)
 
 // Orders LDS accesses across the lanes of the wavefront (one lane writes,
 // the others read): without it the compiler may treat the lanes as unrelated
-// threads and move a lane's read ahead of another lane's write.
+// threads and move a lane's read ahead of another lane's write.  The kernel's
+// workgroup is a single wavefront, so this is the only ordering its LDS
+// exchanges need (LDS accesses of one wavefront complete in order).
 PK_DEV void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -147,7 +149,7 @@ PK_DEV void point(const SolveParams &P, const LaneConst &C, int lane, int n, int
 #pragma unroll
             for (int u = 0; u < 3; ++u) f[9 + u] = pos[u];
         }
-        __syncthreads();
+        wave_sync();
     }
     // EE lanes: frame of the EE joint, residual, errors.
     float ecost = 0.f;
@@ -242,7 +244,7 @@ PK_DEV void jacobian(const RobotC *__restrict__ rb, const SolveParams &P, int la
 #pragma unroll
         for (int u = 0; u < 6; ++u) lds[L::RS + 6 * lane + u] = e[E_R + u];
     }
-    __syncthreads();
+    wave_sync();
     const float *f = lds + L::FR + (isj ? lane : 0) * 12;
     const float om[3] = {f[2], f[5], f[8]}, pj[3] = {f[9], f[10], f[11]};
     float *jc = lds + L::JC + lane * L::JS;
@@ -538,9 +540,9 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
                 }
             }
             if (!done && iters < iter_end) {
-                __syncthreads();
+                wave_sync();
                 jacobian<DMAX, MMAX>(rb, P, lane, n, m, lds);
-                __syncthreads();
+                wave_sync();
                 float ge;
                 dgu = jtj_rows<DMAX, MMAX, float>(lds, ancp, lane, dep, m, max_depth, rows, ge) +
                       dl * dl + P.w_rest * P.w_rest;
