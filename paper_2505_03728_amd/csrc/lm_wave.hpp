@@ -97,8 +97,8 @@ struct Lds {
     static constexpr int RS = JC + 64 * JS;        // [6 * MMAX] EE residual rows (current point)
     static constexpr int FR = RS + 6 * MMAX;       // [64][12] joint frames O, p (last evaluated point)
     static constexpr int EX = FR + 64 * 12;        // [MMAX][ES] EE records (last evaluated point)
-    static constexpr int PV = EX + MMAX * ES;      // pivot row of the elimination: DMAX + 2 values, FP64-sized
-    static constexpr int FLOATS = PV + 2 * (DMAX + 2);
+    static constexpr int PV = EX + MMAX * ES;      // pivot rows of an elimination step: DMAX + 2 values each, FP64-sized
+    static constexpr int FLOATS = PV + 2 * PK_STEP_PIVOTS * (DMAX + 2);
 };
 // Slots of an EE record.
 enum { E_PE = 0, E_R = 4, E_RE = 12, E_LG = 24, E_M = 36, E_N = 48 };
@@ -341,49 +341,64 @@ PK_DEV T jtj_rows(const float *lds, const uint32_t (&ancp)[DMAX / 4], int lane, 
 // Solve (A + lam diag(max(A_jj, floor))) delta = -g for the tree-structured A
 // given as depth-indexed rows r and undamped diagonal dgu (consumed).
 // Returns false if a pivot is not above thresh_rel * max damped diagonal
-// (thresh_rel > 0) or not positive and finite.  `slot` (LDS, DMAX + 2 values
-// of T) carries each pivot row to the wave; `desc` has bit k set when this
-// lane's joint is a proper ancestor of joint k.
+// (thresh_rel > 0) or not positive and finite.  `desc` has bit k set when
+// this lane's joint is a proper ancestor of joint k; the lane's joint is
+// pivot `pos` of elimination step `step` (-1: no joint).  Lane i's `stab`
+// holds pivot i of the schedule (bits 0-7), that pivot's depth (8-15) and
+// the first pivot of step i (16-23).  `slots` (LDS, PK_STEP_PIVOTS rows of
+// DMAX + 2 values of T) carry a step's pivot rows.
 template <int DMAX, typename T>
 PK_DEV bool tree_solve(T (&r)[DMAX], T dgu, T g, float lam, float dfloor, float thresh_rel,
-                       int lane, int n, int dep, uint64_t desc, const uint32_t (&ancp)[DMAX / 4],
-                       int max_depth, T *slot, float &delta)
+                       int lane, int n, int dep, uint64_t desc, int step, int pos, int nstep,
+                       uint32_t stab, const uint32_t (&ancp)[DMAX / 4], int max_depth, T *slots,
+                       float &delta)
 {
+    constexpr int SS = DMAX + 2;
     const bool isj = lane < n;
     T dg = isj ? dgu + (T)lam * (dgu > (T)dfloor ? dgu : (T)dfloor) : (T)0;
     T thresh = 0;
     if (thresh_rel > 0.f) thresh = (T)thresh_rel * (T)wave_max((float)dg);
     T b = isj ? -g : (T)0;
     bool bad = false;
-    // Leaves first: step k removes joint k from its ancestors' rows.  Lane k
-    // puts its row, pivot and right-hand side in LDS; the other lanes read
-    // them back.  Every pivot is tested; a failed test ends the solve after
-    // the loop.
-    for (int k = n - 1; k >= 0; --k) {
-        const int dk = bcast_i(dep, k);
+    // Leaves first, one step of mutually unrelated joints at a time: the
+    // step's pivot lanes put their rows, pivots and right-hand sides in LDS,
+    // then every lane removes from its row the pivots it is an ancestor of.
+    // Every pivot is tested; a failed test ends the solve after the loop.
+    for (int st = 0; st < nstep; ++st) {
         wave_sync();   // the previous step's reads are done
-        if (lane == k) {
+        if (step == st) {
+            // Up to 16 depths the whole row goes out, zero past the joint's
+            // own depth, so that readers need no depth-dependent branches.
+            T *sl = slots + pos * SS;
 #pragma unroll
             for (int d = 0; d < DMAX; ++d) {
-                if ((d & 3) == 0 && d >= dk) break;
-                slot[d] = r[d];
+                if (DMAX > 16 && (d & 3) == 0 && d >= dep) break;
+                sl[d] = d < dep ? r[d] : (T)0;
             }
-            slot[DMAX] = dg;
-            slot[DMAX + 1] = b;
+            sl[DMAX] = dg;
+            sl[DMAX + 1] = b;
         }
-        wave_sync();   // row k is visible to every lane
-        const T piv = slot[DMAX], bk = slot[DMAX + 1];
-        bad = bad || !(piv > thresh) || !(piv < (T)INFINITY);
-        const bool is_anc = (desc >> k) & 1ull;
-        const T sel = is_anc ? slot[dep > 0 ? dep : 0] : (T)0;
-        const T c = sel * recip(piv);
+        wave_sync();   // the step's rows are visible to every lane
+        const int i0 = (int)((unsigned)bcast_i((int)stab, st) >> 16);
+        const int i1 = st + 1 < nstep ? (int)((unsigned)bcast_i((int)stab, st + 1) >> 16) : n;
+        for (int i = i0; i < i1; ++i) {
+            const unsigned e = (unsigned)bcast_i((int)stab, i);
+            const int k = (int)(e & 0xffu), dk = (int)((e >> 8) & 0xffu);
+            const T *sk = slots + (i - i0) * SS;
+            const T piv = sk[DMAX], bk = sk[DMAX + 1];
+            bad = bad || !(piv > thresh) || !(piv < (T)INFINITY);
+            const bool is_anc = (desc >> k) & 1ull;
+            const T sk_dep = sk[dep > 0 ? dep : 0];
+            const T sel = is_anc ? sk_dep : (T)0;
+            const T c = sel * recip(piv);
 #pragma unroll
-        for (int d = 0; d < DMAX; ++d) {
-            if ((d & 3) == 0 && d >= dk) break;
-            r[d] -= c * slot[d];
+            for (int d = 0; d < DMAX; ++d) {
+                if (DMAX > 16 && (d & 3) == 0 && d >= dk) break;
+                r[d] -= c * sk[d];
+            }
+            dg -= c * sel;
+            b -= c * bk;
         }
-        dg -= c * sel;
-        b -= c * bk;
     }
     if (bad) return false;
     // Back substitution, root first: x_j = (b_j - sum_d r_j[d] x_anc(d)) / pivot_j.
@@ -436,6 +451,14 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
 #pragma unroll
     for (int i = 0; i < DMAX / 4; ++i) ancp[i] = isj ? arow[i] : 0u;
     const uint64_t desc = isj ? rb->jdesc[jl] : 0ull;
+    const int step = isj ? rb->step_of[jl] : -1, spos = isj ? rb->step_pos[jl] : 0;
+    const int nstep = rb->nstep;
+    uint32_t stab = 0;
+    if (isj) {
+        const int pj = rb->step_joint[lane];
+        stab = (uint32_t)pj | ((uint32_t)rb->j[pj].depth << 8);
+    }
+    if (lane < nstep) stab |= (uint32_t)rb->step_start[lane] << 16;
     const int dep = C.depth;
 
     bool fin = true;
@@ -569,7 +592,8 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
 #pragma unroll
             for (int d = 0; d < DMAX; ++d) r[d] = rows[d];
             ok = tree_solve<DMAX, float>(r, dgu, g, lam, P.damping_floor, P.pivot_rel, lane, n, dep,
-                                         desc, ancp, max_depth, lds + L::PV, delta);
+                                         desc, step, spos, nstep, stab, ancp, max_depth, lds + L::PV,
+                                         delta);
         }
         if (!ok) {
             // Re-form the damped system and gradient in FP64 from the FP32
@@ -580,7 +604,8 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
                          (double)dl * dl + (double)P.w_rest * P.w_rest;
             gd += (double)dl * rl + (double)P.w_rest * rr;
             ok = tree_solve<DMAX, double>(r, dgd, isj ? gd : 0.0, lam, P.damping_floor, 0.f, lane,
-                                          n, dep, desc, ancp, max_depth, (double *)(lds + L::PV), delta);
+                                          n, dep, desc, step, spos, nstep, stab, ancp, max_depth,
+                                          (double *)(lds + L::PV), delta);
         }
         qt = q + delta;
         evaluate = ok;   // a failed solve counts as a rejected step

@@ -270,6 +270,32 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
         for (int k = 0; k < n; ++k)
             if ((R.janc[k] >> j) & 1ull) R.jdesc[j] |= 1ull << k;
     }
+    // Elimination steps: joints by height (leaves 0, a parent one above its
+    // highest child), descending index within a height, at most
+    // PK_STEP_PIVOTS per step.
+    {
+        int h[PK_MAX_JOINTS] = {0};
+        int hmax = 0;
+        for (int j = n - 1; j >= 0; --j) {
+            const int par = R.j[j].parent;
+            if (par >= 0 && h[par] < h[j] + 1) h[par] = h[j] + 1;
+        }
+        for (int j = 0; j < n; ++j) hmax = h[j] > hmax ? h[j] : hmax;
+        int ns = 0, pos = 0;
+        for (int lv = 0; lv <= hmax; ++lv) {
+            int inlev = 0;
+            for (int j = n - 1; j >= 0; --j) {
+                if (h[j] != lv) continue;
+                if (inlev % PK_STEP_PIVOTS == 0) R.step_start[ns++] = (uint8_t)pos;
+                R.step_of[j] = (uint8_t)(ns - 1);
+                R.step_pos[j] = (uint8_t)(inlev % PK_STEP_PIVOTS);
+                R.step_joint[pos++] = (uint8_t)j;
+                ++inlev;
+            }
+        }
+        R.step_start[ns] = (uint8_t)pos;
+        R.nstep = ns;
+    }
     int tgt = 0, rows = 0;
     for (int k = 0; k < m; ++k) {
         const int e = t->ee_joint[k], kind = t->ee_kind[k];

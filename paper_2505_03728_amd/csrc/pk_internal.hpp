@@ -34,6 +34,8 @@ struct EEC {
     int32_t row_off;   // first residual row of this EE
 };
 
+constexpr int PK_STEP_PIVOTS = 16;   // pivots per elimination step (LDS slots)
+
 struct RobotC {
     int32_t n, m, tgt_floats, pose_rows;   // pose_rows = sum of EE row counts
     int32_t chains, chain_len, max_depth, pad;
@@ -44,6 +46,15 @@ struct RobotC {
     uint64_t janc[PK_MAX_JOINTS];          // bit i set iff joint i is a proper ancestor of joint j
     uint64_t jdesc[PK_MAX_JOINTS];         // bit k set iff joint j is a proper ancestor of joint k
     uint8_t anc_at[PK_MAX_JOINTS][PK_MAX_JOINTS];   // [j][d]: ancestor of j at depth d (d <= depth j; j itself at its depth)
+    // Elimination schedule of the tree factorization: step s removes the
+    // joints step_joint[step_start[s] .. step_start[s+1]) (at most
+    // PK_STEP_PIVOTS, none an ancestor of another, all their descendants
+    // removed in earlier steps); joint j is pivot step_pos[j] of step step_of[j].
+    int32_t nstep, pad2;
+    uint8_t step_start[PK_MAX_JOINTS + 1];
+    uint8_t step_joint[PK_MAX_JOINTS];
+    uint8_t step_of[PK_MAX_JOINTS];
+    uint8_t step_pos[PK_MAX_JOINTS];
 };
 
 // Uniform per-call data for the LM kernels (passed by value).
