@@ -181,6 +181,68 @@ PK_DEV void eval_jacobian_chain(const RobotC *__restrict__ rb, const SolveParams
     }
 }
 
+// Single-chain robots: cost and errors at q and, when the point is taken
+// (the start point, or a trial with cost below `cur`), its Jacobian and
+// residual rows into LDS from the same forward kinematics, so an accepted
+// trial is not evaluated a second time.  Returns whether it was taken.
+template <int L, int KIND>
+PK_DEV bool eval_point1(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
+                        const LaneLds &S, const float *q, bool first, float cur, float &cost, float &pcost,
+                        float *perr, float *rerr)
+{
+    using SL = Slots<1, L, KIND>;
+    constexpr int ROWS = SL::ROWS;
+    float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS];
+    PoseLog lg;
+    chain_fk<1, L, true>(rb, 0, q, om, pj, Re, pe);
+    ee_residual<KIND>(P, S, SL::TG, Re, pe, r, perr[0], rerr[0], &lg);
+    float cp = 0.f, cj = 0.f;
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) cp += r[u] * r[u];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const float over = q[j] - rb->j[j].hi, under = rb->j[j].lo - q[j];
+        const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
+        const float rr = P.w_rest * (q[j] - qr[j]);
+        cj += rl * rl + rr * rr;
+    }
+    pcost = cp;
+    cost = cp + cj;
+    const bool take = first || cost < cur;
+    if (take) {
+        float M[9], Nb[9];
+        if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) S[SL::RES + u] = r[u];
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            float lev[3] = {pe[0] - pj[i][0], pe[1] - pj[i][1], pe[2] - pj[i][2]}, v[3];
+            cross(om[i], lev, v);
+            const int base = SL::COL + i * ROWS;
+            if constexpr (KIND == PK_EE_POSE) {
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
+                    float nw = Nb[3 * u] * om[i][0] + Nb[3 * u + 1] * om[i][1] + Nb[3 * u + 2] * om[i][2];
+                    float mw = M[3 * u] * om[i][0] + M[3 * u + 1] * om[i][1] + M[3 * u + 2] * om[i][2];
+                    S[base + u] = P.w_pos * (mv + nw);
+                    S[base + 3 + u] = P.w_rot * mw;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 3; ++u) S[base + u] = P.w_pos * v[u];
+            }
+            const float over = q[i] - rb->j[i].hi, under = rb->j[i].lo - q[i];
+            const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
+            const float rr = P.w_rest * (q[i] - qr[i]);
+            const float dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
+            S[SL::DG + i] = dl * dl + P.w_rest * P.w_rest;
+            S[SL::GX + i] = dl * rl + P.w_rest * rr;
+        }
+    }
+    return take;
+}
+
 // Diagonal of J^T J (with the limit/rest terms) for joint j, from LDS.
 template <int C, int L, int KIND>
 PK_DEV float jtj_diag(const LaneLds &S, int j)
@@ -487,11 +549,13 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
         __asm__ volatile("" ::: "memory");
         bool ok = true;
         if (!first) {
-            if (need_j) {
-                // Jacobian at the current point (after an accept) -> LDS.
+            if constexpr (C > 1) {
+                if (need_j) {
+                    // Jacobian at the current point (after an accept) -> LDS.
 #pragma unroll
-                for (int c = 0; c < C; ++c) eval_jacobian_chain<C, L, KIND>(rb, P, qr, S, q, c);
-                need_j = false;
+                    for (int c = 0; c < C; ++c) eval_jacobian_chain<C, L, KIND>(rb, P, qr, S, q, c);
+                    need_j = false;
+                }
             }
             float delta[St::N];
             ok = lane_step<C, L, KIND>(P, S, lam, flags, delta);
@@ -501,7 +565,12 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
         float ct = INFINITY, pct = 0.f, pe_t[C], re_t[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) pe_t[c] = re_t[c] = 0.f;
-        if (ok) eval_cost<C, L, KIND>(rb, P, qr, S, qt, ct, pct, pe_t, re_t);
+        if constexpr (C == 1) {
+            // a taken point's Jacobian is formed here, from the same FK
+            if (ok) (void)eval_point1<L, KIND>(rb, P, qr, S, qt, first, cost, ct, pct, pe_t, re_t);
+        } else {
+            if (ok) eval_cost<C, L, KIND>(rb, P, qr, S, qt, ct, pct, pe_t, re_t);
+        }
         if (first) {
             cost = ct;
             pcost = pct;
