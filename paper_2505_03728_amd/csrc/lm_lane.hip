@@ -50,6 +50,11 @@ struct Slots {
     static constexpr int DG = RES + C * ROWS;
     static constexpr int GX = DG + C * L;
     static constexpr int TOTAL = GX + C * L;
+    // Single chains keep the FP32 normal equations of the current point
+    // instead: packed J^T J (+ diagonal terms) then J^T r, over the columns'
+    // slots, formed once per taken point and reused by rejected steps.
+    static constexpr int AG = COL;
+    static_assert(C > 1 || Star<C, L, KIND>::NA + L <= TOTAL - COL, "normal equations fit");
 };
 
 // FK along chain c at q; optionally keeps each joint's world axis and origin.
@@ -181,10 +186,69 @@ PK_DEV void eval_jacobian_chain(const RobotC *__restrict__ rb, const SolveParams
     }
 }
 
+// Single chain: Jacobian columns, EE residual rows and the limit/rest
+// diagonal terms at q into LDS, from the chain's kept FK (joint axes and
+// origins), the EE frame and its pose log.
+template <int L, int KIND>
+PK_DEV void jacobian1(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
+                      const LaneLds &S, const float *q, const float (*om)[3], const float (*pj)[3],
+                      const float *Re, const float *pe, const float *r, const PoseLog &lg)
+{
+    using SL = Slots<1, L, KIND>;
+    constexpr int ROWS = SL::ROWS;
+    float M[9], Nb[9];
+    if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
+#pragma unroll
+    for (int u = 0; u < ROWS; ++u) S[SL::RES + u] = r[u];
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        float lev[3] = {pe[0] - pj[i][0], pe[1] - pj[i][1], pe[2] - pj[i][2]}, v[3];
+        cross(om[i], lev, v);
+        const int base = SL::COL + i * ROWS;
+        if constexpr (KIND == PK_EE_POSE) {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
+                float nw = Nb[3 * u] * om[i][0] + Nb[3 * u + 1] * om[i][1] + Nb[3 * u + 2] * om[i][2];
+                float mw = M[3 * u] * om[i][0] + M[3 * u + 1] * om[i][1] + M[3 * u + 2] * om[i][2];
+                S[base + u] = P.w_pos * (mv + nw);
+                S[base + 3 + u] = P.w_rot * mw;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) S[base + u] = P.w_pos * v[u];
+        }
+        const float over = q[i] - rb->j[i].hi, under = rb->j[i].lo - q[i];
+        const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
+        const float rr = P.w_rest * (q[i] - qr[i]);
+        const float dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
+        S[SL::DG + i] = dl * dl + P.w_rest * P.w_rest;
+        S[SL::GX + i] = dl * rl + P.w_rest * rr;
+    }
+}
+
+template <int C, int L, int KIND, typename T>
+PK_DEV void form_normal(const LaneLds &S, int c, T *A, T *g);
+
+// Single chain: FP32 J^T J and J^T r from the columns in LDS, written over
+// them (AG) for the steps that follow.
+template <int L, int KIND>
+PK_DEV void cache_normal1(const LaneLds &S)
+{
+    using SL = Slots<1, L, KIND>;
+    constexpr int NA = Star<1, L, KIND>::NA;
+    float A[NA], g[L];
+    form_normal<1, L, KIND, float>(S, 0, A, g);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) S[SL::AG + i] = A[i];
+#pragma unroll
+    for (int i = 0; i < L; ++i) S[SL::AG + NA + i] = g[i];
+}
+
 // Single-chain robots: cost and errors at q and, when the point is taken
 // (the start point, or a trial with cost below `cur`), its Jacobian and
-// residual rows into LDS from the same forward kinematics, so an accepted
-// trial is not evaluated a second time.  Returns whether it was taken.
+// normal equations from the same forward kinematics, so an accepted trial is
+// not evaluated a second time.  Returns whether it was taken.
 template <int L, int KIND>
 PK_DEV bool eval_point1(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
                         const LaneLds &S, const float *q, bool first, float cur, float &cost, float &pcost,
@@ -210,51 +274,10 @@ PK_DEV bool eval_point1(const RobotC *__restrict__ rb, const SolveParams &P, con
     cost = cp + cj;
     const bool take = first || cost < cur;
     if (take) {
-        float M[9], Nb[9];
-        if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
-#pragma unroll
-        for (int u = 0; u < ROWS; ++u) S[SL::RES + u] = r[u];
-#pragma unroll
-        for (int i = 0; i < L; ++i) {
-            float lev[3] = {pe[0] - pj[i][0], pe[1] - pj[i][1], pe[2] - pj[i][2]}, v[3];
-            cross(om[i], lev, v);
-            const int base = SL::COL + i * ROWS;
-            if constexpr (KIND == PK_EE_POSE) {
-#pragma unroll
-                for (int u = 0; u < 3; ++u) {
-                    float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
-                    float nw = Nb[3 * u] * om[i][0] + Nb[3 * u + 1] * om[i][1] + Nb[3 * u + 2] * om[i][2];
-                    float mw = M[3 * u] * om[i][0] + M[3 * u + 1] * om[i][1] + M[3 * u + 2] * om[i][2];
-                    S[base + u] = P.w_pos * (mv + nw);
-                    S[base + 3 + u] = P.w_rot * mw;
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < 3; ++u) S[base + u] = P.w_pos * v[u];
-            }
-            const float over = q[i] - rb->j[i].hi, under = rb->j[i].lo - q[i];
-            const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
-            const float rr = P.w_rest * (q[i] - qr[i]);
-            const float dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
-            S[SL::DG + i] = dl * dl + P.w_rest * P.w_rest;
-            S[SL::GX + i] = dl * rl + P.w_rest * rr;
-        }
+        jacobian1<L, KIND>(rb, P, qr, S, q, om, pj, Re, pe, r, lg);
+        cache_normal1<L, KIND>(S);
     }
     return take;
-}
-
-// Diagonal of J^T J (with the limit/rest terms) for joint j, from LDS.
-template <int C, int L, int KIND>
-PK_DEV float jtj_diag(const LaneLds &S, int j)
-{
-    using SL = Slots<C, L, KIND>;
-    float d = S[SL::DG + j];
-#pragma unroll
-    for (int u = 0; u < SL::ROWS; ++u) {
-        const float v = S[SL::COL + j * SL::ROWS + u];
-        d += v * v;
-    }
-    return d;
 }
 
 // Packed block c of J^T J (+ diagonal terms) and J^T r in precision T, from
@@ -285,6 +308,35 @@ PK_DEV void form_normal(const LaneLds &S, int c, T *A, T *g)
 #pragma unroll
         for (int u = 0; u < ROWS; ++u) s += (T)col[i][u] * (T)r[u];
         g[i] = s;
+    }
+}
+
+// The same block in FP64 with one column held at a time: the other column of
+// each product is read from LDS again (the compiler may not keep it across
+// rows), which keeps the register use of this rarely taken path low.
+template <int C, int L, int KIND>
+PK_DEV void form_normal64(const LaneLds &S, int c, double *A, double *g)
+{
+    using SL = Slots<C, L, KIND>;
+    constexpr int ROWS = SL::ROWS;
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        double ci[ROWS];
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) ci[u] = (double)S[SL::COL + (c * L + i) * ROWS + u];
+#pragma unroll
+        for (int k = 0; k <= i; ++k) {
+            double s = 0;
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) s += ci[u] * (double)S[SL::COL + (c * L + k) * ROWS + u];
+            if (k == i) s += (double)S[SL::DG + c * L + i];
+            A[tri(i, k)] = s;
+        }
+        double s = (double)S[SL::GX + c * L + i];
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) s += ci[u] * (double)S[SL::RES + c * ROWS + u];
+        g[i] = s;
+        __asm__ volatile("" ::: "memory");
     }
 }
 
@@ -361,6 +413,31 @@ PK_DEV bool step_fp64(const SolveParams &P, const LaneLds &S, float lam, float *
 #pragma unroll
         for (int i = 0; i < L; ++i) delta[c * L + i] = (float)x[i];
     }
+    return ok;
+}
+
+// Single chain, FP64 re-solve: the columns at q are formed again (the same
+// FP32 values the cached normal equations came from), J^T J and J^T r in
+// FP64, then the FP32 cache is restored.
+template <int L, int KIND>
+PK_DEV bool step_fp64_1(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
+                        const LaneLds &S, const float *q, float lam, float *delta)
+{
+    using SL = Slots<1, L, KIND>;
+    constexpr int ROWS = SL::ROWS;
+    float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS], pe_err, re_err;
+    PoseLog lg;
+    chain_fk<1, L, true>(rb, 0, q, om, pj, Re, pe);
+    ee_residual<KIND>(P, S, SL::TG, Re, pe, r, pe_err, re_err, &lg);
+    jacobian1<L, KIND>(rb, P, qr, S, q, om, pj, Re, pe, r, lg);
+    __asm__ volatile("" ::: "memory");   // the FK values die before the FP64 system is formed
+    double A[Star<1, L, KIND>::NA], g[L], x[L];
+    form_normal64<1, L, KIND>(S, 0, A, g);
+    const bool ok = chol_damped<L, double>(A, (double)lam, (double)P.damping_floor, 0.0, A);
+    chol_solve_neg<L, double>(A, g, x);
+#pragma unroll
+    for (int i = 0; i < L; ++i) delta[i] = (float)x[i];
+    cache_normal1<L, KIND>(S);
     return ok;
 }
 
@@ -450,29 +527,47 @@ PK_DEV void write_nonfinite(const SolveParams &P, int64_t p, const float *q, boo
 // against the largest damped diagonal, FP64 re-solve on a small pivot.
 // False if that fails too.
 template <int C, int L, int KIND>
-PK_DEV bool lane_step(const SolveParams &P, const LaneLds &S, float lam, int &flags, float *delta)
+PK_DEV bool lane_step(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
+                      const LaneLds &S, const float *q, float lam, int &flags, float *delta)
 {
     using St = Star<C, L, KIND>;
+    using SL = Slots<C, L, KIND>;
+    // Every block first: the pivot threshold needs the largest damped
+    // diagonal over all joints, read off the formed blocks (a single chain
+    // reads its cached normal equations).
+    float Ac[C][St::NA], gc[C][L];
+    if constexpr (C == 1) {
+#pragma unroll
+        for (int i = 0; i < St::NA; ++i) Ac[0][i] = S[SL::AG + i];
+#pragma unroll
+        for (int i = 0; i < L; ++i) gc[0][i] = S[SL::AG + St::NA + i];
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) form_normal<C, L, KIND, float>(S, c, Ac[c], gc[c]);
+    }
     float dmax = 0.f;
 #pragma unroll
-    for (int j = 0; j < St::N; ++j) {
-        const float a = jtj_diag<C, L, KIND>(S, j);
-        dmax = fmaxf(dmax, a + lam * fmaxf(a, P.damping_floor));
-    }
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int i = 0; i < L; ++i) {
+            const float a = Ac[c][tri(i, i)];
+            dmax = fmaxf(dmax, a + lam * fmaxf(a, P.damping_floor));
+        }
     const float thresh = P.pivot_rel * dmax;
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        float Ac[St::NA], gc[L], x[L];
-        form_normal<C, L, KIND, float>(S, c, Ac, gc);
-        ok &= chol_damped<L, float>(Ac, lam, P.damping_floor, thresh, Ac);   // in place
-        chol_solve_neg<L, float>(Ac, gc, x);
+        float x[L];
+        ok &= chol_damped<L, float>(Ac[c], lam, P.damping_floor, thresh, Ac[c]);   // in place
+        chol_solve_neg<L, float>(Ac[c], gc[c], x);
 #pragma unroll
         for (int ii = 0; ii < L; ++ii) delta[c * L + ii] = x[ii];
     }
     if (!ok) {
         flags |= PK_FLAG_FP64;
-        ok = step_fp64<C, L, KIND>(P, S, lam, delta);
+        // a single chain re-forms its Jacobian for this (the caller does it,
+        // where fewer values are live)
+        if constexpr (C > 1) ok = step_fp64<C, L, KIND>(P, S, lam, delta);
     }
     return ok;
 }
@@ -558,7 +653,10 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
                 }
             }
             float delta[St::N];
-            ok = lane_step<C, L, KIND>(P, S, lam, flags, delta);
+            ok = lane_step<C, L, KIND>(rb, P, qr, S, q, lam, flags, delta);
+            if constexpr (C == 1) {
+                if (!ok) ok = step_fp64_1<L, KIND>(rb, P, qr, S, q, lam, delta);
+            }
 #pragma unroll
             for (int j = 0; j < St::N; ++j) qt[j] = q[j] + delta[j];
         }
