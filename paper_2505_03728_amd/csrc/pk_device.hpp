@@ -104,23 +104,29 @@ PK_DEV void cross(const float *a, const float *b, float *c)
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// Unit quaternion (w >= 0) of a rotation matrix, Shepperd's method.
+// Unit quaternion (w >= 0) of a rotation matrix, Shepperd's method: the
+// largest of |w|, |x|, |y|, |z| comes from a square root, the other three from
+// sums and differences of off-diagonal entries over it.  The case is chosen
+// per lane with selects around one square root (no divergent branches).
 PK_DEV void rot_to_quat(const float *R, float &w, float &x, float &y, float &z)
 {
-    float tr = R[0] + R[4] + R[8];
-    if (tr >= R[0] && tr >= R[4] && tr >= R[8]) {
-        float s = 2.f * sqrtf(1.f + tr), is = rcp(s);
-        w = 0.25f * s; x = (R[7] - R[5]) * is; y = (R[2] - R[6]) * is; z = (R[3] - R[1]) * is;
-    } else if (R[0] >= R[4] && R[0] >= R[8]) {
-        float s = 2.f * sqrtf(1.f + R[0] - R[4] - R[8]), is = rcp(s);
-        w = (R[7] - R[5]) * is; x = 0.25f * s; y = (R[1] + R[3]) * is; z = (R[2] + R[6]) * is;
-    } else if (R[4] >= R[8]) {
-        float s = 2.f * sqrtf(1.f + R[4] - R[0] - R[8]), is = rcp(s);
-        w = (R[2] - R[6]) * is; x = (R[1] + R[3]) * is; y = 0.25f * s; z = (R[5] + R[7]) * is;
-    } else {
-        float s = 2.f * sqrtf(1.f + R[8] - R[0] - R[4]), is = rcp(s);
-        w = (R[3] - R[1]) * is; x = (R[2] + R[6]) * is; y = (R[5] + R[7]) * is; z = 0.25f * s;
-    }
+    const float tr = R[0] + R[4] + R[8];
+    const bool c0 = tr >= R[0] && tr >= R[4] && tr >= R[8];
+    const bool c1 = !c0 && R[0] >= R[4] && R[0] >= R[8];
+    const bool c2 = !c0 && !c1 && R[4] >= R[8];
+    const float t = c0 ? 1.f + tr
+                  : c1 ? 1.f + R[0] - R[4] - R[8]
+                  : c2 ? 1.f + R[4] - R[0] - R[8]
+                       : 1.f + R[8] - R[0] - R[4];
+    const float s = 2.f * sqrtf(t), is = rcp(s), big = 0.25f * s;
+    const float d1 = (R[7] - R[5]) * is, d2 = (R[2] - R[6]) * is, d3 = (R[3] - R[1]) * is;
+    const float s1 = (R[1] + R[3]) * is, s2 = (R[2] + R[6]) * is, s3 = (R[5] + R[7]) * is;
+    // (w, x, y, z) per case: 0 (big, d1, d2, d3), 1 (d1, big, s1, s2),
+    // 2 (d2, s1, big, s3), 3 (d3, s2, s3, big)
+    w = c0 ? big : c1 ? d1 : c2 ? d2 : d3;
+    x = c0 ? d1 : c1 ? big : c2 ? s1 : s2;
+    y = c0 ? d2 : c1 ? s1 : c2 ? big : s3;
+    z = c0 ? d3 : c1 ? s2 : c2 ? s3 : big;
     if (w < 0.f) { w = -w; x = -x; y = -y; z = -z; }
     float in = rsqrtf(w * w + x * x + y * y + z * z);
     w *= in; x *= in; y *= in; z *= in;
