@@ -186,6 +186,43 @@ PK_DEV void eval_jacobian_chain(const RobotC *__restrict__ rb, const SolveParams
     }
 }
 
+// Weighted Jacobian column of a joint with world axis w and origin pj, for
+// the single EE at pe (M, Nb: the EE's right-Jacobian-inverse blocks, pose
+// EEs only).
+template <int KIND>
+PK_DEV void jac_column(const SolveParams &P, const float *M, const float *Nb, const float *w,
+                       const float *pj, const float *pe, float *col)
+{
+    float lev[3] = {pe[0] - pj[0], pe[1] - pj[1], pe[2] - pj[2]}, v[3];
+    cross(w, lev, v);
+    if constexpr (KIND == PK_EE_POSE) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
+            float nw = Nb[3 * u] * w[0] + Nb[3 * u + 1] * w[1] + Nb[3 * u + 2] * w[2];
+            float mw = M[3 * u] * w[0] + M[3 * u + 1] * w[1] + M[3 * u + 2] * w[2];
+            col[u] = P.w_pos * (mv + nw);
+            col[3 + u] = P.w_rot * mw;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) col[u] = P.w_pos * v[u];
+    }
+}
+
+// Limit and rest terms of joint i at q: its share of the normal matrix's
+// diagonal (dl^2 + w_rest^2) and of J^T r (dl rl + w_rest rr).
+PK_DEV void joint_terms(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
+                        const float *q, int i, float &dg, float &gx)
+{
+    const float over = q[i] - rb->j[i].hi, under = rb->j[i].lo - q[i];
+    const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
+    const float rr = P.w_rest * (q[i] - qr[i]);
+    const float dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
+    dg = dl * dl + P.w_rest * P.w_rest;
+    gx = dl * rl + P.w_rest * rr;
+}
+
 // Single chain: Jacobian columns, EE residual rows and the limit/rest
 // diagonal terms at q into LDS, from the chain's kept FK (joint axes and
 // origins), the EE frame and its pose log.
@@ -202,28 +239,46 @@ PK_DEV void jacobian1(const RobotC *__restrict__ rb, const SolveParams &P, const
     for (int u = 0; u < ROWS; ++u) S[SL::RES + u] = r[u];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-        float lev[3] = {pe[0] - pj[i][0], pe[1] - pj[i][1], pe[2] - pj[i][2]}, v[3];
-        cross(om[i], lev, v);
-        const int base = SL::COL + i * ROWS;
-        if constexpr (KIND == PK_EE_POSE) {
+        float col[ROWS], dg, gx;
+        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, col);
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
-                float nw = Nb[3 * u] * om[i][0] + Nb[3 * u + 1] * om[i][1] + Nb[3 * u + 2] * om[i][2];
-                float mw = M[3 * u] * om[i][0] + M[3 * u + 1] * om[i][1] + M[3 * u + 2] * om[i][2];
-                S[base + u] = P.w_pos * (mv + nw);
-                S[base + 3 + u] = P.w_rot * mw;
-            }
-        } else {
+        for (int u = 0; u < ROWS; ++u) S[SL::COL + i * ROWS + u] = col[u];
+        joint_terms(rb, P, qr, q, i, dg, gx);
+        S[SL::DG + i] = dg;
+        S[SL::GX + i] = gx;
+    }
+}
+
+// Single chain: FP32 J^T J (+ diagonal terms) and J^T r at q straight from
+// the columns as they are formed (the sums of form_normal, in its order;
+// the columns never go through LDS), into the cached normal equations (AG).
+template <int L, int KIND>
+PK_DEV void normal1(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
+                    const LaneLds &S, const float *q, const float (*om)[3], const float (*pj)[3],
+                    const float *Re, const float *pe, const float *r, const PoseLog &lg)
+{
+    using SL = Slots<1, L, KIND>;
+    constexpr int ROWS = SL::ROWS, NA = Star<1, L, KIND>::NA;
+    float M[9], Nb[9];
+    if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
+    float col[L][ROWS];
 #pragma unroll
-            for (int u = 0; u < 3; ++u) S[base + u] = P.w_pos * v[u];
+    for (int i = 0; i < L; ++i) {
+        float dg, gx;
+        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, col[i]);
+        joint_terms(rb, P, qr, q, i, dg, gx);
+#pragma unroll
+        for (int k = 0; k <= i; ++k) {
+            float a = 0.f;
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) a += col[i][u] * col[k][u];
+            if (k == i) a += dg;
+            S[SL::AG + tri(i, k)] = a;
         }
-        const float over = q[i] - rb->j[i].hi, under = rb->j[i].lo - q[i];
-        const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
-        const float rr = P.w_rest * (q[i] - qr[i]);
-        const float dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
-        S[SL::DG + i] = dl * dl + P.w_rest * P.w_rest;
-        S[SL::GX + i] = dl * rl + P.w_rest * rr;
+        float b = gx;
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) b += col[i][u] * r[u];
+        S[SL::AG + NA + i] = b;
     }
 }
 
@@ -273,10 +328,7 @@ PK_DEV bool eval_point1(const RobotC *__restrict__ rb, const SolveParams &P, con
     pcost = cp;
     cost = cp + cj;
     const bool take = first || cost < cur;
-    if (take) {
-        jacobian1<L, KIND>(rb, P, qr, S, q, om, pj, Re, pe, r, lg);
-        cache_normal1<L, KIND>(S);
-    }
+    if (take) normal1<L, KIND>(rb, P, qr, S, q, om, pj, Re, pe, r, lg);
     return take;
 }
 
