@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--targets", type=int, default=16384)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--workload", default="arm131k",
-                    choices=["arm131k", "tree4k", "mixed84k", "seeder"])
+                    choices=["arm131k", "tree4k", "mixed84k", "seeder", "beam"])
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
@@ -104,7 +104,8 @@ def main():
                                    f"--gpus {args.gpus} is not supported"}))
         sys.exit(2)
     if args.workload != "arm131k":
-        {"tree4k": run_tree, "mixed84k": run_mixed, "seeder": run_seeder}[args.workload](args)
+        {"tree4k": run_tree, "mixed84k": run_mixed, "seeder": run_seeder,
+         "beam": run_beam}[args.workload](args)
         return
     import numpy as np
     import torch
@@ -498,6 +499,86 @@ def run_seeder(args):
         res["cpu_baseline"] = {"value": rate, "unit": "solves/s", "cores": th, "kind": "oracle",
                                "sample": f"plain form: first {done} of {T} targets x {K} seeds, {el:.1f} s"}
     print(json.dumps(res), flush=True)
+
+
+
+# IK-Beam GPU times of the paper's Table II (analytic Jacobians, RTX 4090,
+# Franka Panda), ms per batch: context only (other robot and hardware).
+PAPER_BEAM_MS = {1: 3.6, 10: 3.6, 100: 4.7, 1000: 15.5, 2000: 32.8}
+
+
+def run_beam(args):
+    """IK-Beam (64 seeds, 6 iterations, 4 kept, 10 iterations) on the 7-DoF arm
+    at the paper's batch sizes; value = targets per second at batch 2000."""
+    import numpy as np
+    import torch
+
+    import paper_2505_03728_amd as pk
+    from paper_2505_03728_amd.flops import lm_flops
+    import synth
+    wl = synth.workload("beam")
+    g = wl["groups"][0]
+    tree, K, sch = g["tree"], g["K"], wl["schedule"]
+    ctx = pk.Context(0)
+    rid = ctx.upload(tree)
+    w, o = pk.Weights.from_dict(wl["weights"]), pk.Options.from_dict(wl["options"])
+    batches = {}
+    for B in wl["batches"]:
+        targets = _dev_targets(ctx, rid, tree, g["q_star"][:B])
+        seeds = torch.from_numpy(np.ascontiguousarray(g["seeds"][:B * K].T.astype(np.float32))).cuda()
+        out = ctx.alloc_beam_outputs(rid, B, K, sch["keep"])
+        ms = _time(lambda: ctx.ik_beam(rid, targets, seeds, w, o, out=out, **sch), args.steps,
+                   args.warmup)
+        pe = out["pos_err"][0].cpu().numpy() * 1e3
+        re = out["rot_err"][0].cpu().numpy()
+        batches[B] = {"ms": round(ms, 4), "success": float(out["target_success"].float().mean()),
+                      "p98_pos_err_mm": float(np.percentile(pe, 98)),
+                      "p98_rot_err_rad": float(np.percentile(re, 98)),
+                      "paper_ms_context": PAPER_BEAM_MS.get(B)}
+        print(f"# batch {B}: {ms:.4f} ms", file=sys.stderr, flush=True)
+    B = wl["batches"][-1]
+    ms = batches[B]["ms"]
+    # The dominant kernel, stage 0 (B*64 problems, 6 iterations), timed alone.
+    targets = _dev_targets(ctx, rid, tree, g["q_star"][:B])
+    seeds = torch.from_numpy(np.ascontiguousarray(g["seeds"][:B * K].T.astype(np.float32))).cuda()
+    o0 = pk.Options.from_dict(dict(wl["options"], max_iters=sch["iters0"]))
+    out0 = ctx.alloc_outputs(rid, B, K)
+    k_ms = _time(lambda: ctx.ik_solve(rid, targets, seeds, K, w, o0, out0), max(5, args.steps), 1)
+    info = ctx.robot_info(rid)
+    blocks = [info["chain_len"]] * info["chains"]
+    flops = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(out0["iters"].sum()),
+                     int(out0["accepts"].sum()), B * K)
+    ach = flops / (k_ms / 1e3) / 1e12
+    res = _line("IK-Beam targets/sec (batch 2000)", B / (ms / 1e3), "targets/s", args, ms,
+                {"workload": f"IK-Beam on the 7-DoF arm: {B} targets x {K} seeds, "
+                             f"{sch['iters0']} LM iterations, best {sch['keep']} kept, "
+                             f"{sch['iters1']} more, best returned; pose(1.0/0.5) + limit(10)",
+                 "targets": B, "schedule": sch},
+                success_rate=batches[B]["success"], batches=batches,
+                roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
+                          "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6),
+                          "traffic": None, "kernel": "lm_lane_kernel<1,7,pose> (stage 0)",
+                          "kernel_ms": round(k_ms, 5), "algorithmic_flops": flops})
+    if not args.no_cpu:
+        import oracle
+        threads = max(1, min(16, os.cpu_count() or 1))
+        done = succ = 0
+        el = 0.0
+        while done < B and el < args.cpu_seconds:
+            a, b = done, min(B, done + 100)
+            tg = oracle.targets_from(tree, g["q_star"][a:b])
+            t0 = time.perf_counter()
+            r = oracle.ik_beam(tree, tg, g["seeds"][a * K:b * K], K, sch["iters0"], sch["keep"],
+                               sch["iters1"], wl["weights"], wl["options"], threads=threads)
+            el += time.perf_counter() - t0
+            succ += int(r["success"].sum())
+            done = b
+        res["cpu_baseline"] = {"value": done / el if el else 0.0, "unit": "targets/s",
+                               "cores": threads, "kind": "oracle",
+                               "sample": f"first {done} of {B} targets in batches of 100, FP64, "
+                                         f"{el:.1f} s", "success_rate": succ / max(done, 1)}
+    print(json.dumps(res), flush=True)
+    ctx.close()
 
 
 if __name__ == "__main__":

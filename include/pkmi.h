@@ -314,6 +314,57 @@ int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t n_targets, const f
 int pk_seeder_save(pk_ctx *ctx, int32_t seeder_id, const char *path);
 int pk_seeder_load(pk_ctx *ctx, int32_t seeder_id, const char *path);
 
+/* ------------------------------------------------------------ IK-Beam
+ * Beam search over LM (Sec. V-C, runtime analysis: 64 seeds, 6 iterations on
+ * all of them, the 4 of lowest error kept for 10 more, the best returned).
+ * Per target:
+ *   1. stage 0: LM from each of its n_seeds seeds for iters0 iterations;
+ *   2. the first `keep` of them in the survivor order below;
+ *   3. stage 1: LM again from their stage-0 joints, lambda back at lambda0,
+ *      for iters1 iterations;
+ *   4. the first of the survivors' stage-1 results in the same order.
+ * Survivor order: a seed within tolerance before one that is not; among those
+ * within tolerance the lower total cost first, among the others the lower
+ * pose-only residual sum of squares; a NaN value after every number; then
+ * the lower seed index.  When no value is NaN its first element is the
+ * best-of-K choice of pk_ik_solve.
+ * The LM options apply to both stages except max_iters (iters0 / iters1).
+ * seeds (device): [n][T*n_seeds], problem t*n_seeds + k is seed k of target t.
+ * Asynchronous on `stream`; no host synchronisation inside.  Errors:
+ * PK_EINVAL for a NULL required pointer or a schedule outside the ranges
+ * below, PK_EUNSUPPORTED for T*n_seeds >= 2^31. */
+typedef struct {
+    int32_t n_seeds;                 /* 1..64 seeds per target                   */
+    int32_t iters0;                  /* >= 0, stage-0 LM iterations (paper: 6)   */
+    int32_t keep;                    /* 1..n_seeds survivors (paper: 4)          */
+    int32_t iters1;                  /* >= 0, stage-1 LM iterations (paper: 10)  */
+} pk_beam_schedule;
+
+/* Outputs (device).  best_joints is required; every other pointer may be
+ * NULL.  The stage arrays expose the intermediate results (parity checks,
+ * debugging); without them the library keeps those in its own workspace. */
+typedef struct {
+    float *best_joints;              /* [n][T] the returned solution             */
+    int32_t *best_index;             /* [T] its stage-0 seed index, 0..n_seeds-1  */
+    int32_t *target_success;         /* [T] 1 if it meets the tolerance           */
+    float *pos_err;                  /* [m][T] at best_joints                     */
+    float *rot_err;                  /* [m][T]                                    */
+    float *cost;                     /* [T] total cost at best_joints             */
+    float *stage0_joints;            /* [n][T*n_seeds]                            */
+    float *stage0_cost;              /* [T*n_seeds]                               */
+    float *stage0_pose_cost;         /* [T*n_seeds] pose-only residual sum of squares */
+    int32_t *stage0_status;          /* [T*n_seeds] PK_CONVERGED.. | flags         */
+    int32_t *kept;                   /* [T][keep] survivors' seed indices, in order */
+    float *stage1_joints;            /* [n][T*keep] problem t*keep + r: survivor r */
+    float *stage1_cost;              /* [T*keep]                                  */
+    float *stage1_pose_cost;         /* [T*keep]                                  */
+    int32_t *stage1_status;          /* [T*keep]                                  */
+} pk_beam_outputs;
+
+int pk_ik_beam(pk_ctx *ctx, int32_t robot_id, int64_t n_targets, const float *targets,
+               const float *seeds, const pk_cost_weights *w, const pk_lm_options *opt,
+               const pk_beam_schedule *sched, const pk_beam_outputs *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

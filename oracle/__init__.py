@@ -97,6 +97,7 @@ def _setup(L):
                                P(_Options), _dp, _dp, _dp, _dp, _dp, _ip, _ip, _ip, _ip,
                                C.c_int],
         "ora_best_of_k": [C.c_long, C.c_int, _ip, _dp, _dp, _ip, _ip],
+        "ora_beam_select": [C.c_long, C.c_int, C.c_int, _ip, _dp, _dp, _ip],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -371,3 +372,42 @@ def best_of_k(status, cost, pose_cost, K):
     best, succ = np.zeros(T, np.int32), np.zeros(T, np.int32)
     lib().ora_best_of_k(T, int(K), _p(st, _ip), _p(c), _p(pc), _p(best, _ip), _p(succ, _ip))
     return best, succ.astype(bool)
+
+
+def beam_select(status, cost, pose_cost, K, keep):
+    """IK-Beam survivors (Sec. V-C): per target the ``keep`` best of its K
+    seeds, best first, as seed indices [T, keep].  Order: within tolerance
+    before not; then total cost (within) or pose-only cost (not), NaN last;
+    then the lower index."""
+    st = _i(status)
+    c, pc = _d(cost), _d(pose_cost)
+    T = st.shape[0] // K
+    kept = np.zeros((T, keep), np.int32)
+    lib().ora_beam_select(T, int(K), int(keep), _p(st, _ip), _p(c), _p(pc), _p(kept, _ip))
+    return kept
+
+
+def ik_beam(tree, targets, seeds, K0, iters0, keep, iters1, w, o, threads=None):
+    """IK-Beam (Sec. V-C) in FP64.  targets [T,m,7], seeds [T*K0, n].
+
+    Stage 0: LM from every seed for ``iters0`` iterations.  The ``keep``
+    survivors per target (``beam_select``) restart LM, lambda back at its
+    initial value, from their stage-0 joints for ``iters1`` iterations.  The
+    first of the survivors' results in the same order is returned.
+    Returns the stage results, the survivors and, per target, the chosen
+    seed's index (0..K0-1), joints and success flag.
+    """
+    o0, o1 = dict(o), dict(o)
+    o0["max_iters"], o1["max_iters"] = int(iters0), int(iters1)
+    s0 = lm_solve_batch(tree, targets, seeds, K0, w, o0, threads)
+    kept = beam_select(s0["status"], s0["cost"], s0["pose_cost"], K0, keep)
+    T = kept.shape[0]
+    rows = (np.arange(T)[:, None] * K0 + kept).reshape(-1)
+    s1 = lm_solve_batch(tree, targets, s0["q"][rows], keep, w, o1, threads)
+    pick = beam_select(s1["status"], s1["cost"], s1["pose_cost"], keep, 1)[:, 0]
+    win = np.arange(T) * keep + pick
+    return {"stage0": s0, "kept": kept, "seeds1": s0["q"][rows], "stage1": s1, "pick": pick,
+            "best_index": kept[np.arange(T), pick], "best_q": s1["q"][win],
+            "success": (s1["status"][win] & 0xFF) == CONVERGED,
+            "pos_err": s1["pos_err"][win], "rot_err": s1["rot_err"][win],
+            "cost": s1["cost"][win]}

@@ -827,3 +827,48 @@ void ora_best_of_k(long T, int K, const int *status, const double *cost,
         success[t] = any;
     }
 }
+
+/* IK-Beam survivor order (Sec. V-C keeps the seeds of lowest error): seed a
+ * comes before seed b if it meets the tolerance and b does not; otherwise by
+ * the error measure of their class (total cost for seeds within tolerance,
+ * pose-only residual sum of squares for the others), a NaN after every
+ * number; then the lower seed index.  The first seed in this order is the
+ * best-of-K choice whenever no value is NaN. */
+static int beam_before(int conv_a, double va, int ka, int conv_b, double vb, int kb)
+{
+    if (conv_a != conv_b) return conv_a;
+    int na = isnan(va), nb = isnan(vb);
+    if (na != nb) return nb;
+    if (!na && va != vb) return va < vb;
+    return ka < kb;
+}
+
+/* Per target, the `keep` first of its K seeds in the survivor order, first
+ * one first: kept[t * keep + r] = seed index (0..K-1).  A plain selection:
+ * pass r takes the earliest seed not taken by passes 0..r-1. */
+void ora_beam_select(long T, int K, int keep, const int *status, const double *cost,
+                     const double *pose_cost, int *kept)
+{
+    for (long t = 0; t < T; ++t) {
+        for (int r = 0; r < keep; ++r) {
+            int b = -1;
+            int conv_b = 0;
+            double vb = 0;
+            for (int k = 0; k < K; ++k) {
+                int taken = 0;
+                for (int u = 0; u < r; ++u)
+                    if (kept[t * keep + u] == k) taken = 1;
+                if (taken) continue;
+                long p = t * K + k;
+                int conv = (status[p] & 0xff) == ORA_CONVERGED;
+                double v = conv ? cost[p] : pose_cost[p];
+                if (b < 0 || beam_before(conv, v, k, conv_b, vb, b)) {
+                    b = k;
+                    conv_b = conv;
+                    vb = v;
+                }
+            }
+            kept[t * keep + r] = b;
+        }
+    }
+}

@@ -87,6 +87,20 @@ class _SeededOutputs(C.Structure):
                 ("n_fallback", C.c_void_p)]
 
 
+class _BeamSchedule(C.Structure):
+    _fields_ = [("n_seeds", C.c_int32), ("iters0", C.c_int32), ("keep", C.c_int32),
+                ("iters1", C.c_int32)]
+
+
+_BEAM_OUT = ["best_joints", "best_index", "target_success", "pos_err", "rot_err", "cost",
+             "stage0_joints", "stage0_cost", "stage0_pose_cost", "stage0_status", "kept",
+             "stage1_joints", "stage1_cost", "stage1_pose_cost", "stage1_status"]
+
+
+class _BeamOutputs(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in _BEAM_OUT]
+
+
 class _Group(C.Structure):
     _fields_ = [("robot_id", C.c_int32), ("problem", _Problem), ("weights", _Weights),
                 ("out", _Outputs)]
@@ -139,13 +153,15 @@ def lib():
                                         C.POINTER(_Sched), vp]
         L.pk_autotune_mixed.argtypes = [vp, i32, C.POINTER(_Group), C.POINTER(_Options),
                                         C.POINTER(_Sched), C.POINTER(C.c_float), vp]
+        L.pk_ik_beam.argtypes = [vp, i32, i64, vp, vp, C.POINTER(_Weights), C.POINTER(_Options),
+                                 C.POINTER(_BeamSchedule), C.POINTER(_BeamOutputs), vp]
         for f in ["pk_create", "pk_destroy", "pk_robot_upload", "pk_robot_info", "pk_fk",
                   "pk_residual_jacobian", "pk_ik_solve", "pk_seeder_create",
                   "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward",
                   "pk_seeder_forward_layers", "pk_seeder_grad", "pk_seeder_train",
                   "pk_seeder_infer", "pk_seeder_save",
                   "pk_seeder_load", "pk_ik_solve_seeded", "pk_ik_solve_mixed",
-                  "pk_autotune_mixed"]:
+                  "pk_autotune_mixed", "pk_ik_beam"]:
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -158,7 +174,7 @@ def exported_symbols():
             "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward",
             "pk_seeder_forward_layers", "pk_seeder_grad",
             "pk_seeder_train", "pk_seeder_infer", "pk_seeder_save", "pk_seeder_load",
-            "pk_ik_solve_seeded", "pk_ik_solve_mixed", "pk_autotune_mixed"]
+            "pk_ik_solve_seeded", "pk_ik_solve_mixed", "pk_autotune_mixed", "pk_ik_beam"]
 
 
 class Weights:
@@ -384,6 +400,40 @@ class Context:
         self._call(lib().pk_autotune_mixed(self._h, len(groups), arr, C.byref(o), C.byref(sch),
                                            C.byref(ms), self.stream()))
         return sch.iters_per_launch, sch.blocks_per_cu, ms.value, list(sch.variant)[:len(groups)]
+
+    def alloc_beam_outputs(self, rid, T, n_seeds=64, keep=4, stages=False, device=None):
+        """Device tensors for ik_beam: best_joints [n, T], best_index,
+        target_success [T], pos_err / rot_err [m, T], cost [T] and, with
+        ``stages``, the stage-0 / stage-1 per-problem results and ``kept``
+        [T, keep]."""
+        torch = self._torch
+        info = self.robot_info(rid)
+        n, m = info["n"], info["m"]
+        dev = device or f"cuda:{self.device}"
+        f = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+        i = lambda *s: torch.empty(s, dtype=torch.int32, device=dev)
+        out = {"best_joints": f(n, T), "best_index": i(T), "target_success": i(T),
+               "pos_err": f(m, T), "rot_err": f(m, T), "cost": f(T)}
+        if stages:
+            N0, N1 = T * n_seeds, T * keep
+            out.update(stage0_joints=f(n, N0), stage0_cost=f(N0), stage0_pose_cost=f(N0),
+                       stage0_status=i(N0), kept=i(T, keep), stage1_joints=f(n, N1),
+                       stage1_cost=f(N1), stage1_pose_cost=f(N1), stage1_status=i(N1))
+        return out
+
+    def ik_beam(self, rid, targets, seeds, weights: Weights, options: Options, n_seeds=64,
+                iters0=6, keep=4, iters1=10, stages=False, out=None):
+        """IK-Beam (see include/pkmi.h): targets [tf, T], seeds [n, T*n_seeds];
+        out from alloc_beam_outputs (allocated here when None).  Returns out."""
+        T = targets.shape[1]
+        if out is None:
+            out = self.alloc_beam_outputs(rid, T, n_seeds, keep, stages, targets.device)
+        oo = _BeamOutputs(*[_ptr(out.get(k)) for k in _BEAM_OUT])
+        sch = _BeamSchedule(int(n_seeds), int(iters0), int(keep), int(iters1))
+        w, op = weights._c(), options._c()
+        self._call(lib().pk_ik_beam(self._h, rid, T, _ptr(targets), _ptr(seeds), C.byref(w),
+                                    C.byref(op), C.byref(sch), C.byref(oo), self.stream()))
+        return out
 
     def ik_solve(self, rid, targets, seeds, K, weights: Weights, options: Options, out):
         """targets [tf, T] and seeds [n, T*K] are cuda float32 tensors; out from

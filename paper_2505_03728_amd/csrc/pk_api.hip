@@ -196,6 +196,7 @@ int pk_destroy(pk_ctx *ctx)
         if (r.dev) (void)hipFree(r.dev);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->ws2) (void)hipFree(ctx->ws2);
+    if (ctx->ws3) (void)hipFree(ctx->ws3);
     for (auto *sd : ctx->seeders) seeder_free(sd);
     sched_free(ctx);
     delete ctx;

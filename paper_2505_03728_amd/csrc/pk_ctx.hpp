@@ -27,6 +27,8 @@ struct pk_ctx {
     size_t ws_bytes = 0;
     void *ws2 = nullptr;      // learned-seed pipeline workspace
     size_t ws2_bytes = 0;
+    void *ws3 = nullptr;      // IK-Beam workspace
+    size_t ws3_bytes = 0;
 };
 
 namespace pk {

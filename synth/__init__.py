@@ -231,7 +231,10 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
       * ``mixed84k``— 60000 arm7 + 20000 hand16 + 4096 tree34 problems, early
                       exit, rest 0.01, up to 50 iterations (per-group weights in
                       each group's ``weights``);
-      * ``seeder``  — 2M training configurations + 131072 evaluation targets.
+      * ``seeder``  — 2M training configurations + 131072 evaluation targets;
+      * ``beam``    — IK-Beam on arm7 (pose+limit): 2000 targets x 64 seeds,
+                      6 iterations, 4 kept, 10 iterations; the batch sizes
+                      1, 10, 100, 1000, 2000 are prefixes of the same draws.
     ``targets`` overrides the target count (a prefix of the same draws).
     Returns q* (configurations whose FK are the targets) and seeds; the caller
     computes the target poses with its own FK.
@@ -272,6 +275,15 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
                        "seeds": uniform_configs(r, c, ss), "weights": w})
         return {"groups": gs, "weights": _weights(w_rest=0.01),
                 "options": _options(50, early_exit=True)}
+    if name == "beam":
+        r = arm7(0)
+        T = targets or int(2000 * scale)
+        K = 64
+        return {"groups": [{"tree": r, "q_star": uniform_configs(r, T, 20), "K": K,
+                            "seeds": uniform_configs(r, T * K, 21)}],
+                "weights": _weights(), "options": _options(16),
+                "schedule": {"n_seeds": K, "iters0": 6, "keep": 4, "iters1": 10},
+                "batches": [1, 10, 100, 1000, 2000]}
     if name == "seeder":
         r = arm7(0)
         S = int(2_000_000 * scale)

@@ -92,12 +92,25 @@ def first_divergence(acc_gpu, acc_ora):
     return 0
 
 
+def at_limit(tree, q, eps=1e-6):
+    """Some joint within eps (relative to 1 + |limit|) of a limit: the limit
+    residual's kink, where whether its Jacobian row is active (the strict
+    test q > upper / q < lower) is decided by rounding (a Gauss-Newton step
+    that projects a joint back onto its limit lands on it, just inside or just
+    outside, depending on the last bits)."""
+    q = np.asarray(q, dtype=np.float64)
+    lo, hi = np.asarray(tree.lower), np.asarray(tree.upper)
+    return bool(np.any(np.abs(q - lo) <= eps * (1 + np.abs(lo))) or
+                np.any(np.abs(q - hi) <= eps * (1 + np.abs(hi))))
+
+
 def compare_outcome(ctx, rid, tree, tg, seed, w, o, status, iters, ora, variant=0):
     """'same' when the GPU's success flag (and, if both converged, iteration
     count) equals the oracle's; 'excused' when the difference traces back to
     something FP32 cannot settle (a near-tie, a final or crossing error within
-    5% of a tolerance, or a first differing decision that is FP32-fragile);
-    else 'bad'.  ora: oracle.lm_solve result with a full trace."""
+    5% of a tolerance, or a first differing decision that is FP32-fragile or
+    taken from an iterate on a joint limit's kink); else 'bad'.  ora:
+    oracle.lm_solve result with a full trace."""
     cg, co = (status & 0xff) == 0, (ora["status"] & 0xff) == 0
     if cg == co and (not cg or iters == ora["iters"]):
         return "same"
@@ -109,7 +122,13 @@ def compare_outcome(ctx, rid, tree, tg, seed, w, o, status, iters, ora, variant=
     res = solve_gpu(ctx, rid, tree, tg[None], np.asarray(seed)[None], 1, w, o,
                     trace_iters=o["max_iters"], **kw)
     t = first_divergence(res["trace_accept"][0], ora["trace_acc"])
-    return "excused" if t > 0 and fp32_fragile(tree, tg, w, o, seed, ora, t) else "bad"
+    if t == 0:
+        return "bad"
+    if fp32_fragile(tree, tg, w, o, seed, ora, t):
+        return "excused"
+    qg = np.asarray(seed) if t == 1 else res["trace_q"][0][t - 2]
+    qo = np.asarray(seed) if t == 1 else ora["trace_q"][t - 2]
+    return "excused" if at_limit(tree, qg) or at_limit(tree, qo) else "bad"
 
 
 def borderline(ora_res, p, tol_pos=1e-3, tol_rot=1e-2, frac=0.05):

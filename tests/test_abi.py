@@ -40,6 +40,8 @@ def test_null_context_errors_without_gpu():
     assert L.pk_robot_upload(None, None, None) == -1
     assert b"ctx is NULL" in L.pk_last_error(None)
     assert L.pk_destroy(None) == 0
+    assert L.pk_ik_beam(None, 0, 1, None, None, None, None, None, None, None) == -1
+    assert b"pk_ik_beam: ctx is NULL" in L.pk_last_error(None)
 
 
 def test_pack_targets_layout():

@@ -1,0 +1,191 @@
+"""GPU parity of IK-Beam (Sec. V-C) through the C ABI against the FP64 oracle.
+
+Each LM stage is held to the bar of the LM parity tests: per-problem success
+agrees with the oracle run from the same (FP32) starting joints, a
+disagreement allowed only where the oracle's trajectory has a near-tie
+(|c' - c| <= 1e-5 c), its final error is within 5% of a tolerance, or the
+first accept decision where the GPU's and the oracle's traces differ is one
+FP32 cannot settle (a step of FP32-fragile outcome, or one taken from an
+iterate within 1e-6 rad of a joint limit, where rounding decides whether the
+limit's Jacobian row is active); at batch 10, 90% of stage-0 results lie
+within 1e-3 rad of the oracle's.  Every
+decision that turns FP32 values into indices (the survivors, the pick) must
+equal the oracle's selection applied to the GPU's own FP32 stage results,
+bit for bit, and the returned joints / cost / success are exact copies of the
+picked stage-1 entry.  Position and rotation errors of the returned joints
+agree with the oracle's FK within 2e-5 m / 2e-5 rad.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import compare_outcome, soa, targets_dev
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+PAPER = {"n_seeds": 64, "iters0": 6, "keep": 4, "iters1": 10}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2505_03728_amd as pk
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def rid(ctx):
+    return ctx.upload(synth.arm7(0))
+
+
+def _case(T):
+    wl = synth.workload("beam", targets=T)
+    g = wl["groups"][0]
+    tree = g["tree"]
+    return tree, oracle.targets_from(tree, g["q_star"]), g["seeds"], wl
+
+
+def _run(ctx, rid, tree, tg, seeds, w, o, sch, variant=0):
+    import paper_2505_03728_amd as pk
+    import torch
+    kw = {"variant": variant} if variant else {}
+    out = ctx.ik_beam(rid, targets_dev(tree, tg, DEV), soa(seeds, DEV), pk.Weights.from_dict(w),
+                      pk.Options.from_dict(o, **kw), stages=True, **sch)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _check_selection(res, T, sch):
+    """Survivors and pick against the oracle's selection on the GPU's values;
+    returns the stage-1 starting joints [T*keep, n]."""
+    K, keep = sch["n_seeds"], sch["keep"]
+    kept = oracle.beam_select(res["stage0_status"], res["stage0_cost"], res["stage0_pose_cost"],
+                              K, keep)
+    np.testing.assert_array_equal(res["kept"], kept)
+    pick = oracle.beam_select(res["stage1_status"], res["stage1_cost"], res["stage1_pose_cost"],
+                              keep, 1)[:, 0]
+    win = np.arange(T) * keep + pick
+    np.testing.assert_array_equal(res["best_index"], kept[np.arange(T), pick])
+    np.testing.assert_array_equal(res["best_joints"].T, res["stage1_joints"].T[win])
+    np.testing.assert_array_equal(res["cost"], res["stage1_cost"][win])
+    np.testing.assert_array_equal(res["target_success"],
+                                  ((res["stage1_status"][win] & 0xFF) == 0).astype(np.int32))
+    rows = (np.arange(T)[:, None] * K + kept).ravel()
+    return res["stage0_joints"].T[rows]
+
+
+def _stage_agreement(ctx, rid, tree, tg, starts, Kst, status, q, w, o, iters, sample):
+    """Success agreement of sampled problems of one stage with the oracle (a
+    stage is plain LM from its starting joints, so a disagreement is judged
+    as in the LM tests: near-tie, borderline error, or a first differing
+    accept decision that FP32 cannot settle)."""
+    oo = dict(o, max_iters=iters)
+    bad, excused, close = [], 0, 0
+    for p in sample:
+        ora = oracle.lm_solve(tree, tg[p // Kst], w, oo, starts[p], n_trace=max(iters, 1))
+        cg, co = (status[p] & 0xFF) == 0, (ora["status"] & 0xFF) == 0
+        if np.abs(q[p] - ora["q"]).max() <= 1e-3:
+            close += 1
+        if cg == co:
+            continue
+        v = compare_outcome(ctx, rid, tree, tg[p // Kst], starts[p], w, oo, status[p],
+                            ora["iters"], ora)
+        if v == "bad":
+            bad.append(int(p))
+            print(f"problem {p}: gpu status {status[p]}, oracle {ora['status']} "
+                  f"pos {ora['pos_err']} rot {ora['rot_err']}")
+        else:
+            excused += 1
+    return bad, excused, close
+
+
+def _check_errors(res, tree, tg, T):
+    for t in range(T):
+        _, pe, re = oracle.residual(tree, tg[t], {"w_pos": 1.0, "w_rot": 1.0, "w_limit": 0.0,
+                                                  "w_rest": 0.0}, res["best_joints"][:, t])
+        assert abs(pe[0] - res["pos_err"][0, t]) <= 2e-5
+        assert abs(re[0] - res["rot_err"][0, t]) <= 2e-5
+
+
+@pytest.mark.parametrize("variant", [0, 2])
+def test_beam_small_batch_full_parity(ctx, rid, variant):
+    """Batch 10 (640 LM problems) with the paper's schedule, every problem of
+    both stages checked against the oracle; per-lane and wave kernels."""
+    T = 10
+    tree, tg, seeds, wl = _case(T)
+    w, o = wl["weights"], wl["options"]
+    res = _run(ctx, rid, tree, tg, seeds, w, o, PAPER, variant)
+    seeds1 = _check_selection(res, T, PAPER)
+    N0, N1 = T * 64, T * 4
+    b0, e0, c0 = _stage_agreement(ctx, rid, tree, tg, seeds, 64, res["stage0_status"],
+                                  res["stage0_joints"].T, w, o, 6, range(N0))
+    b1, e1, c1 = _stage_agreement(ctx, rid, tree, tg, seeds1, 4, res["stage1_status"],
+                                  res["stage1_joints"].T, w, o, 10, range(N1))
+    print(f"beam T={T} variant={variant}: stage 0 {len(b0)} unexplained, {e0} excused, "
+          f"{c0}/{N0} within 1e-3 rad; stage 1 {len(b1)} unexplained, {e1} excused, "
+          f"{c1}/{N1} within 1e-3 rad; success {res['target_success'].mean():.2f}")
+    assert not b0 and not b1
+    assert c0 >= 0.9 * N0
+    _check_errors(res, tree, tg, T)
+
+
+def test_beam_full_size_batch2000_sampled(ctx, rid):
+    """The largest batch of the paper's table (2000 targets x 64 seeds): all
+    selections exact, sampled problems of both stages against the oracle."""
+    T = 2000
+    tree, tg, seeds, wl = _case(T)
+    w, o = wl["weights"], wl["options"]
+    res = _run(ctx, rid, tree, tg, seeds, w, o, PAPER)
+    seeds1 = _check_selection(res, T, PAPER)
+    rng = np.random.default_rng(17)
+    s0 = np.sort(rng.choice(T * 64, 96, replace=False))
+    s1 = np.sort(rng.choice(T * 4, 48, replace=False))
+    b0, e0, _ = _stage_agreement(ctx, rid, tree, tg, seeds, 64, res["stage0_status"],
+                                 res["stage0_joints"].T, w, o, 6, s0)
+    b1, e1, _ = _stage_agreement(ctx, rid, tree, tg, seeds1, 4, res["stage1_status"],
+                                 res["stage1_joints"].T, w, o, 10, s1)
+    print(f"beam T=2000: stage 0 {len(b0)} unexplained / {e0} excused of {len(s0)}, stage 1 "
+          f"{len(b1)} / {e1} of {len(s1)}; success {res['target_success'].mean():.4f}")
+    assert not b0 and not b1
+    _check_errors(res, tree, tg, 16)
+
+
+def test_beam_batch_one_and_degenerate_schedules(ctx, rid):
+    import paper_2505_03728_amd as pk
+    tree, tg, seeds, wl = _case(3)
+    w, o = wl["weights"], wl["options"]
+    # batch 1
+    r = _run(ctx, rid, tree, tg[:1], seeds[:64], w, o, PAPER)
+    _check_selection(r, 1, PAPER)
+    # iters0 = 0, keep everything: stage 0 returns the seeds, ranked by their cost
+    sch = {"n_seeds": 64, "iters0": 0, "keep": 64, "iters1": 3}
+    r = _run(ctx, rid, tree, tg, seeds, w, o, sch)
+    np.testing.assert_array_equal(r["stage0_joints"].T, seeds.astype(np.float32))
+    s1 = _check_selection(r, 3, sch)
+    assert sorted(r["kept"][0]) == list(range(64))
+    # iters1 = 0: the result is the first survivor's stage-0 joints
+    sch = {"n_seeds": 64, "iters0": 6, "keep": 4, "iters1": 0}
+    r = _run(ctx, rid, tree, tg, seeds, w, o, sch)
+    s1 = _check_selection(r, 3, sch)
+    np.testing.assert_array_equal(r["stage1_joints"].T, s1)
+    # one seed, kept: LM, then LM again from its result
+    sd = seeds.reshape(3, 64, -1)[:, 0]
+    sch = {"n_seeds": 1, "iters0": 4, "keep": 1, "iters1": 4}
+    r = _run(ctx, rid, tree, tg, sd, w, o, sch)
+    _check_selection(r, 3, sch)
+    np.testing.assert_array_equal(r["best_index"], 0)
+    # argument errors
+    for bad in [{"n_seeds": 65, "keep": 4}, {"n_seeds": 8, "keep": 0}, {"n_seeds": 8, "keep": 9},
+                {"n_seeds": 8, "keep": 2, "iters0": -1}]:
+        sch = dict(PAPER, **bad)
+        with pytest.raises(pk.PkError) as e:
+            _run(ctx, rid, tree, tg, seeds[:3 * min(sch["n_seeds"], 64)], w, o, sch)
+        assert e.value.code == -1
+    # T = 0 is a no-op
+    import torch
+    out = ctx.ik_beam(rid, torch.empty((7, 0), device=DEV), torch.empty((7, 0), device=DEV),
+                      pk.Weights(), pk.Options())
+    assert out["best_joints"].shape == (7, 0)
