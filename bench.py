@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--targets", type=int, default=16384)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--workload", default="arm131k",
-                    choices=["arm131k", "tree4k", "mixed84k", "seeder", "beam"])
+                    choices=["arm131k", "tree4k", "mixed84k", "seeder", "beam", "mobile"])
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
@@ -105,7 +105,7 @@ def main():
         sys.exit(2)
     if args.workload != "arm131k":
         {"tree4k": run_tree, "mixed84k": run_mixed, "seeder": run_seeder,
-         "beam": run_beam}[args.workload](args)
+         "beam": run_beam, "mobile": run_mobile}[args.workload](args)
         return
     import numpy as np
     import torch
@@ -577,6 +577,68 @@ def run_beam(args):
                                "cores": threads, "kind": "oracle",
                                "sample": f"first {done} of {B} targets in batches of 100, FP64, "
                                          f"{el:.1f} s", "success_rate": succ / max(done, 1)}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+def run_mobile(args):
+    """IK with a mobile base (Sec. V-B): 4096 translated targets x 4 seeds on the
+    arm with its SE(2) base pose as variables (prismatic x, y + revolute yaw, on
+    the per-wavefront kernel); the same targets with the base fixed at the
+    origin (arm alone) are solved once for the success comparison."""
+    import numpy as np
+    import torch
+
+    import paper_2505_03728_amd as pk
+    from paper_2505_03728_amd.flops import lm_flops
+    import synth
+    wl = synth.workload("mobile")
+    g = wl["groups"][0]
+    mob, K = g["tree"], g["K"]
+    T = g["q_star"].shape[0]
+    N = T * K
+    ctx = pk.Context(0)
+    rid = ctx.upload(mob)
+    targets = _dev_targets(ctx, rid, mob, g["q_star"])
+    seeds = torch.from_numpy(np.ascontiguousarray(g["seeds"].T.astype(np.float32))).cuda()
+    w, o = pk.Weights.from_dict(wl["weights"]), pk.Options.from_dict(wl["options"])
+    out = ctx.alloc_outputs(rid, T, K, best=True)
+    ms = _time(lambda: ctx.ik_solve(rid, targets, seeds, K, w, o, out), args.steps, args.warmup)
+    succ = int(out["target_success"].sum().item())
+    st = out["status"].cpu().numpy()
+    pe = out["pos_err"].cpu().numpy()[0].reshape(T, K)
+    bi = out["best_index"].cpu().numpy()
+    flops = lm_flops(mob.parent, mob.ee_joint, mob.ee_kind, None, int(out["iters"].sum()),
+                     int(out["accepts"].sum()), T * K)
+    ach = flops / (ms / 1e3) / 1e12
+    # fixed base: the arm alone on the same targets, seeds without the base part
+    arm = synth.arm7(0)
+    rid_a = ctx.upload(arm)
+    seeds_a = torch.from_numpy(np.ascontiguousarray(wl["fixed_base"]["seeds"].T.astype(np.float32))).cuda()
+    out_a = ctx.alloc_outputs(rid_a, T, K, best=True)
+    ctx.ik_solve(rid_a, targets, seeds_a, K, w, o, out_a)
+    torch.cuda.synchronize()
+    pe_a = out_a["pos_err"].cpu().numpy()[0].reshape(T, K)[np.arange(T), out_a["best_index"].cpu().numpy()]
+    res = _line("IK solves/sec at 5mm/0.05rad success (mobile base)", succ / (ms / 1e3), "solves/s",
+                args, ms,
+                {"workload": f"mobile-base IK: 7-DoF arm on an SE(2) base (10 variables), {T} "
+                             f"translated targets x {K} seeds, {wl['options']['max_iters']} "
+                             f"iterations, pose + limit, best-of-{K}", "targets": T,
+                 "problems": N},
+                success_rate=succ / T,
+                mean_pos_err_mm=float(pe[np.arange(T), bi].mean() * 1e3),
+                fixed_base={"success_rate": float(out_a["target_success"].float().mean()),
+                            "mean_pos_err_mm": float(pe_a.mean() * 1e3)},
+                fp64_fallback_fraction=float(((st & 0x100) != 0).mean()),
+                roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
+                          "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
+                          "kernel": "lm_wave_kernel<16,4>", "kernel_ms": round(ms, 5),
+                          "algorithmic_flops": flops})
+    if not args.no_cpu:
+        rate, th, done, el = _oracle_rate([{"tree": mob, "q_star": g["q_star"], "seeds": g["seeds"],
+                                            "K": K}], wl["weights"], wl["options"], args.cpu_seconds)
+        res["cpu_baseline"] = {"value": rate, "unit": "solves/s", "cores": th, "kind": "oracle",
+                               "sample": f"first {done} of {T} targets x {K} seeds, {el:.1f} s"}
     print(json.dumps(res), flush=True)
     ctx.close()
 

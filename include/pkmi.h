@@ -53,7 +53,8 @@ typedef struct pk_ctx pk_ctx;
 #define PK_EE_POSE 0          /* full SE(3) target: 7 values p, quat (wxyz)  */
 #define PK_EE_POSITION 1      /* position-only target: 3 values              */
 
-#define PK_MAX_JOINTS 64
+#define PK_MAX_JOINTS 64          /* variables (non-fixed joints) per robot      */
+#define PK_MAX_TREE_JOINTS 128    /* joints of a description, fixed ones included */
 #define PK_MAX_EES 8
 
 /* Kernel variants for pk_lm_options.variant. */
@@ -61,14 +62,26 @@ typedef struct pk_ctx pk_ctx;
 #define PK_VARIANT_LANE 1     /* one problem per lane; star-of-chains robots  */
 #define PK_VARIANT_WAVE 2     /* one problem per 64-lane wavefront; any tree  */
 
+/* Joint kinds (Sec. III-B: fixed, revolute and prismatic joints). */
+#define PK_JOINT_REVOLUTE 0   /* rotation by q about the axis                 */
+#define PK_JOINT_PRISMATIC 1  /* translation by q (metres) along the axis       */
+#define PK_JOINT_FIXED 2      /* no variable                                    */
+
 /* Robot description (host memory, FP64; rounded to FP32 on upload).
- * Revolute joints in topological order (parent[j] < j, -1 = the base).
+ * Joints in topological order (parent[j] < j, -1 = the base).
  * Forward kinematics (Sec. III-B, T_base<-i = FK(q)_i):
- *   p_j = p_parent + R_parent * offset_j,
- *   R_j = R_parent * Rot(mount_quat_j) * Rot(axis_j, q_j),
- * EE k is fixed to joint ee_joint[k] by (ee_offset[k], ee_quat[k]). */
+ *   revolute:  p_j = p_parent + R_parent offset_j,
+ *              R_j = R_parent Rot(mount_quat_j) Rot(axis_j, q_j);
+ *   prismatic: R_j = R_parent Rot(mount_quat_j),
+ *              p_j = p_parent + R_parent offset_j + R_j axis_j q_j;
+ *   fixed:     R_j = R_parent Rot(mount_quat_j), p_j = p_parent + R_parent offset_j.
+ * EE k is fixed to joint ee_joint[k] by (ee_offset[k], ee_quat[k]).
+ * The problem's variables are the non-fixed joints in index order: every
+ * [n][N] joint array (seeds, joints, q_rest) has n = that count, the value
+ * pk_robot_info reports.  Fixed joints are folded into their neighbours on
+ * upload (their limits are ignored); an EE needs a non-fixed ancestor. */
 typedef struct {
-    int32_t n_joints;            /* 1..PK_MAX_JOINTS                          */
+    int32_t n_joints;            /* 1..PK_MAX_TREE_JOINTS, at most PK_MAX_JOINTS non-fixed */
     const int32_t *parent;       /* [n]                                       */
     const double *mount_quat;    /* [n][4] wxyz, normalised on upload          */
     const double *offset;        /* [n][3] metres, in the parent frame         */
@@ -80,6 +93,7 @@ typedef struct {
     const double *ee_offset;     /* [m][3]                                    */
     const double *ee_quat;       /* [m][4] wxyz                               */
     const int32_t *ee_kind;      /* [m] PK_EE_POSE or PK_EE_POSITION           */
+    const int32_t *joint_type;   /* [n] PK_JOINT_*, or NULL = all revolute      */
 } pk_tree;
 
 /* Residual weights (Sec. III-C: the costs are weighted residuals and LM
@@ -158,10 +172,12 @@ int pk_destroy(pk_ctx *ctx);
 const char *pk_last_error(pk_ctx *ctx);
 
 /* Copies the tree to the device (FP32) and returns its id.  Validates shape,
- * parent order, unit axes (within 1e-3; renormalised), limits and EE
- * references.  Synchronous. */
+ * parent order, unit axes (within 1e-3; renormalised), limits, joint kinds
+ * and EE references; folds fixed joints.  Robots with prismatic joints run on
+ * the per-wavefront kernel (PK_VARIANT_LANE is unsupported for them).
+ * Synchronous. */
 int pk_robot_upload(pk_ctx *ctx, const pk_tree *tree, int32_t *robot_id);
-/* n joints, m EEs, target floats per target (sum of EE widths), residual rows
+/* n variables (non-fixed joints), m EEs, target floats per target (sum of EE widths), residual rows
  * (6 per pose EE, 3 per position EE, then n limit and n rest rows), and the
  * star shape used by the per-lane kernel (chains = 0 if not a star). */
 int pk_robot_info(pk_ctx *ctx, int32_t robot_id, int32_t *n, int32_t *m,
@@ -170,7 +186,8 @@ int pk_robot_info(pk_ctx *ctx, int32_t robot_id, int32_t *n, int32_t *m,
 
 /* Forward kinematics (Sec. III-B) for N configurations q [n][N] (device).
  * ee_pose [m][7][N]: position and unit quaternion (wxyz, w >= 0).
- * joint_frames (optional) [n][12][N]: R_j row-major (9) then p_j (3). */
+ * joint_frames (optional) [n][12][N]: R_j row-major (9) then p_j (3), for
+ * the non-fixed joints. */
 int pk_fk(pk_ctx *ctx, int32_t robot_id, int64_t N, const float *q, float *ee_pose,
           float *joint_frames, void *stream);
 

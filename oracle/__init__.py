@@ -56,7 +56,8 @@ _ip = C.POINTER(C.c_int)
 class _Tree(C.Structure):
     _fields_ = [("n", C.c_int), ("parent", _ip), ("mount_quat", _dp), ("offset", _dp),
                 ("axis", _dp), ("lower", _dp), ("upper", _dp), ("m", C.c_int),
-                ("ee_joint", _ip), ("ee_offset", _dp), ("ee_quat", _dp), ("ee_kind", _ip)]
+                ("ee_joint", _ip), ("ee_offset", _dp), ("ee_quat", _dp), ("ee_kind", _ip),
+                ("joint_type", _ip)]
 
 
 class _Weights(C.Structure):
@@ -105,6 +106,8 @@ def _setup(L):
         f.restype = None
     L.ora_rows.argtypes = [P(_Tree)]
     L.ora_rows.restype = C.c_int
+    L.ora_nvar.argtypes = [P(_Tree)]
+    L.ora_nvar.restype = C.c_int
     L.ora_cost.argtypes = [P(_Tree), _dp, P(_Weights), _dp]
     L.ora_cost.restype = C.c_double
     L.ora_cholesky.argtypes = [C.c_int, _dp, _dp]
@@ -131,13 +134,16 @@ class OTree:
 
     def __init__(self, tree):
         self.n, self.m = tree.n, tree.m
+        jt = getattr(tree, "joint_type", None)
         self.ee_kind = np.asarray(tree.ee_kind)
         self._keep = [_i(tree.parent), _d(tree.mount_quat), _d(tree.offset), _d(tree.axis),
                       _d(tree.lower), _d(tree.upper), _i(tree.ee_joint), _d(tree.ee_offset),
-                      _d(tree.ee_quat), _i(tree.ee_kind)]
+                      _d(tree.ee_quat), _i(tree.ee_kind), None if jt is None else _i(jt)]
         k = self._keep
         self.s = _Tree(self.n, _p(k[0], _ip), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]),
-                       self.m, _p(k[6], _ip), _p(k[7]), _p(k[8]), _p(k[9], _ip))
+                       self.m, _p(k[6], _ip), _p(k[7]), _p(k[8]), _p(k[9], _ip),
+                       _p(k[10], _ip) if k[10] is not None else None)
+        self.nv = lib().ora_nvar(self.s)
 
     @property
     def ref(self):
@@ -270,7 +276,7 @@ def residual(tree, targets, w, q):
     tg, q = _d(targets), _d(q)
     r = np.zeros(n_rows(t))
     pe, re = np.zeros(t.m), np.zeros(t.m)
-    ws, _k = _weights(w, t.n)
+    ws, _k = _weights(w, t.nv)
     lib().ora_residual(t.ref, _p(tg), C.byref(ws), _p(q), _p(r), _p(pe), _p(re))
     return r, pe, re
 
@@ -278,8 +284,8 @@ def residual(tree, targets, w, q):
 def jacobian(tree, targets, w, q):
     t = _ot(tree)
     tg, q = _d(targets), _d(q)
-    J = np.zeros((n_rows(t), t.n))
-    ws, _k = _weights(w, t.n)
+    J = np.zeros((n_rows(t), t.nv))
+    ws, _k = _weights(w, t.nv)
     lib().ora_jacobian(t.ref, _p(tg), C.byref(ws), _p(q), _p(J))
     return J
 
@@ -287,7 +293,7 @@ def jacobian(tree, targets, w, q):
 def cost(tree, targets, w, q):
     t = _ot(tree)
     tg, q = _d(targets), _d(q)
-    ws, _k = _weights(w, t.n)
+    ws, _k = _weights(w, t.nv)
     return lib().ora_cost(t.ref, _p(tg), C.byref(ws), _p(q))
 
 
@@ -312,9 +318,9 @@ def chol_solve(L, b):
 def lm_step(tree, targets, w, o, q, lam):
     t = _ot(tree)
     tg, q = _d(targets), _d(q)
-    ws, _k = _weights(w, t.n)
+    ws, _k = _weights(w, t.nv)
     os_ = _options(o)
-    d = np.zeros(t.n)
+    d = np.zeros(t.nv)
     fb = C.c_int()
     ok = lib().ora_lm_step(t.ref, _p(tg), C.byref(ws), C.byref(os_), _p(q), lam, _p(d),
                            C.byref(fb))
@@ -327,13 +333,13 @@ def lm_solve(tree, targets, w, o, q0, n_trace=0):
     """One problem.  targets [m,7].  Returns a dict (q, errors, counters, trace)."""
     t = _ot(tree)
     tg, q0 = _d(targets), _d(q0)
-    ws, _k = _weights(w, t.n)
+    ws, _k = _weights(w, t.nv)
     os_ = _options(o)
-    q = np.zeros(t.n)
+    q = np.zeros(t.nv)
     pe, re = np.zeros(t.m), np.zeros(t.m)
     res = _Result()
     nt = max(int(n_trace), 0)
-    tq = np.zeros((max(nt, 1), t.n))
+    tq = np.zeros((max(nt, 1), t.nv))
     ta = np.zeros(max(nt, 1), np.int32)
     tc = np.zeros(max(nt, 1))
     tt = np.zeros(max(nt, 1), np.int32)
@@ -351,9 +357,9 @@ def lm_solve_batch(tree, targets, seeds, K, w, o, threads=None):
     t = _ot(tree)
     tg, sd = _d(targets), _d(seeds)
     N = sd.shape[0]
-    ws, _k = _weights(w, t.n)
+    ws, _k = _weights(w, t.nv)
     os_ = _options(o)
-    q = np.zeros((N, t.n))
+    q = np.zeros((N, t.nv))
     pe, re = np.zeros((N, t.m)), np.zeros((N, t.m))
     c, pc = np.zeros(N), np.zeros(N)
     it, ac, st, itt = (np.zeros(N, np.int32) for _ in range(4))

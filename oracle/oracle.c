@@ -56,7 +56,44 @@ typedef struct {
     const double *ee_offset;    /* [m][3]                                    */
     const double *ee_quat;      /* [m][4]                                    */
     const int *ee_kind;         /* [m] 0 = full pose, 1 = position only      */
+    const int *joint_type;      /* [n] ORA_REVOLUTE / ORA_PRISMATIC / ORA_FIXED,
+                                   NULL = all revolute                        */
 } ora_tree;
+
+/* Joint kinds (Sec. III-B lists fixed, revolute and prismatic joints): a
+ * revolute joint rotates by its variable about its axis, a prismatic one
+ * translates by it along the axis, a fixed one has no variable.  The
+ * variables are the non-fixed joints in index order. */
+enum { ORA_REVOLUTE = 0, ORA_PRISMATIC = 1, ORA_FIXED = 2 };
+
+static int jtype(const ora_tree *tr, int j)
+{
+    return tr->joint_type ? tr->joint_type[j] : ORA_REVOLUTE;
+}
+
+/* Number of variables. */
+int ora_nvar(const ora_tree *tr)
+{
+    int v = 0;
+    for (int j = 0; j < tr->n; ++j) v += jtype(tr, j) != ORA_FIXED;
+    return v;
+}
+
+/* var_of[j]: variable of joint j (-1 if fixed); joint_of[v]: joint of
+ * variable v. */
+static void var_maps(const ora_tree *tr, int *var_of, int *joint_of)
+{
+    int v = 0;
+    for (int j = 0; j < tr->n; ++j) {
+        if (jtype(tr, j) == ORA_FIXED) {
+            var_of[j] = -1;
+        } else {
+            var_of[j] = v;
+            if (joint_of) joint_of[v] = j;
+            ++v;
+        }
+    }
+}
 
 typedef struct {
     double w_pos, w_rot, w_limit, w_rest;
@@ -339,13 +376,18 @@ static void axis_angle(const double *a, double q, double *R)
 }
 
 /* FK: for j in topological order,
- *   p_j = p_parent + R_parent t_j,   R_j = R_parent R_mount,j Rot(a_j, q_j);
+ *   revolute:  p_j = p_parent + R_parent t_j,   R_j = R_parent R_mount,j Rot(a_j, q_j);
+ *   prismatic: R_j = R_parent R_mount,j,        p_j = p_parent + R_parent t_j + R_j a_j q_j;
+ *   fixed:     R_j = R_parent R_mount,j,        p_j = p_parent + R_parent t_j;
+ * q holds one value per variable (non-fixed joint).
  * EE k: R = R_e R_eeoff,  p = p_e + R_e t_eeoff.   Base frame = (I, 0).
- * Outputs (any may be NULL): R[n][9], p[n][3], Ree[m][9], pee[m][3]. */
+ * Outputs (any may be NULL): R[n][9], p[n][3] (every joint), Ree[m][9], pee[m][3]. */
 void ora_fk(const ora_tree *tr, const double *q, double *R, double *p, double *Ree,
             double *pee)
 {
     double Rl[ORA_MAX_N][9], pl[ORA_MAX_N][3];
+    int var_of[ORA_MAX_N];
+    var_maps(tr, var_of, NULL);
     for (int j = 0; j < tr->n; ++j) {
         double Rp[9], pp[3] = {0, 0, 0}, Rm[9], Rq[9], tmp[9], v[3];
         int par = tr->parent[j];
@@ -358,9 +400,20 @@ void ora_fk(const ora_tree *tr, const double *q, double *R, double *p, double *R
         matvec3(Rp, tr->offset + 3 * j, v);
         for (int i = 0; i < 3; ++i) pl[j][i] = pp[i] + v[i];
         ora_quat_to_R(tr->mount_quat + 4 * j, Rm);
-        axis_angle(tr->axis + 3 * j, q[j], Rq);
         matmul3(Rp, Rm, tmp);
-        matmul3(tmp, Rq, Rl[j]);
+        const int kind = jtype(tr, j);
+        if (kind == ORA_REVOLUTE) {
+            axis_angle(tr->axis + 3 * j, q[var_of[j]], Rq);
+            matmul3(tmp, Rq, Rl[j]);
+        } else {
+            memcpy(Rl[j], tmp, sizeof tmp);
+            if (kind == ORA_PRISMATIC) {
+                double a[3], wa[3], an = norm3(tr->axis + 3 * j);
+                for (int i = 0; i < 3; ++i) a[i] = tr->axis[3 * j + i] / an;
+                matvec3(Rl[j], a, wa);
+                for (int i = 0; i < 3; ++i) pl[j][i] += wa[i] * q[var_of[j]];
+            }
+        }
         if (R) memcpy(R + 9 * j, Rl[j], sizeof(double) * 9);
         if (p) memcpy(p + 3 * j, pl[j], sizeof(double) * 3);
     }
@@ -410,12 +463,13 @@ int ora_rows(const ora_tree *tr)
 {
     int r = 0;
     for (int k = 0; k < tr->m; ++k) r += tr->ee_kind[k] == 0 ? 6 : 3;
-    return r + 2 * tr->n;
+    return r + 2 * ora_nvar(tr);
 }
 
-static double rest_of(const ora_tree *tr, const ora_weights *w, int j)
+/* Rest value of variable v (joint j). */
+static double rest_of(const ora_tree *tr, const ora_weights *w, int v, int j)
 {
-    return w->q_rest ? w->q_rest[j] : 0.5 * (tr->lower[j] + tr->upper[j]);
+    return w->q_rest ? w->q_rest[v] : 0.5 * (tr->lower[j] + tr->upper[j]);
 }
 
 /* Residual vector, row order: per EE (pose: [w_pos rho; w_rot phi] with
@@ -450,12 +504,16 @@ void ora_residual(const ora_tree *tr, const double *targets, const ora_weights *
             row += 3;
         }
     }
-    for (int j = 0; j < tr->n; ++j) {
-        double over = q[j] - tr->upper[j], under = tr->lower[j] - q[j];
-        r[row + j] = w->w_limit * ((over > 0.0 ? over : 0.0) + (under > 0.0 ? under : 0.0));
+    int joint_of[ORA_MAX_N], var_of[ORA_MAX_N];
+    var_maps(tr, var_of, joint_of);
+    const int nv = ora_nvar(tr);
+    for (int v = 0; v < nv; ++v) {
+        const int j = joint_of[v];
+        double over = q[v] - tr->upper[j], under = tr->lower[j] - q[v];
+        r[row + v] = w->w_limit * ((over > 0.0 ? over : 0.0) + (under > 0.0 ? under : 0.0));
     }
-    row += tr->n;
-    for (int j = 0; j < tr->n; ++j) r[row + j] = w->w_rest * (q[j] - rest_of(tr, w, j));
+    row += nv;
+    for (int v = 0; v < nv; ++v) r[row + v] = w->w_rest * (q[v] - rest_of(tr, w, v, joint_of[v]));
 }
 
 double ora_cost(const ora_tree *tr, const double *targets, const ora_weights *w,
@@ -476,16 +534,19 @@ static int is_ancestor(const ora_tree *tr, int j, int e)
     return 0;
 }
 
-/* Analytic Jacobian dr/dq, row-major [rows][n].
- * Pose EE k, ancestor joint j: world axis w_j = R_j a_j, point velocity
- * v_j = w_j x (p_ee - p_j), body twist s_j = [R_ee^T v_j; R_ee^T w_j];
+/* Analytic Jacobian dr/dq, row-major [rows][nvar].
+ * Pose EE k, ancestor revolute joint j: world axis w_j = R_j a_j, point
+ * velocity v_j = w_j x (p_ee - p_j); ancestor prismatic joint j: v_j = R_j a_j,
+ * w_j = 0.  Body twist s_j = [R_ee^T v_j; R_ee^T w_j];
  * d xi / d q_j = J_r^-1(xi) s_j, rows weighted by w_pos / w_rot.
  * Position EE: w_pos v_j.  Limit rows: +-w_limit outside the limits, else 0.
  * Rest rows: w_rest on the diagonal. */
 void ora_jacobian(const ora_tree *tr, const double *targets, const ora_weights *w,
                   const double *q, double *J)
 {
-    int n = tr->n, rows = ora_rows(tr);
+    int n = ora_nvar(tr), rows = ora_rows(tr);
+    int joint_of[ORA_MAX_N], var_of[ORA_MAX_N];
+    var_maps(tr, var_of, joint_of);
     double R[ORA_MAX_N * 9], p[ORA_MAX_N * 3], Ree[ORA_MAX_M * 9], pee[ORA_MAX_M * 3];
     memset(J, 0, sizeof(double) * rows * n);
     ora_fk(tr, q, R, p, Ree, pee);
@@ -505,7 +566,8 @@ void ora_jacobian(const ora_tree *tr, const double *targets, const ora_weights *
             ora_se3_jr_inv(xi, Jr);
             transpose3(Ree + 9 * k, ReT);
         }
-        for (int j = 0; j < n; ++j) {
+        for (int jv = 0; jv < n; ++jv) {
+            const int j = joint_of[jv];
             if (!is_ancestor(tr, j, tr->ee_joint[k])) continue;
             double om[3], lev[3], v[3];
             const double *Rj = R + 9 * j;
@@ -514,8 +576,15 @@ void ora_jacobian(const ora_tree *tr, const double *targets, const ora_weights *
             double an = norm3(tr->axis + 3 * j);
             for (int i = 0; i < 3; ++i) a[i] = tr->axis[3 * j + i] / an;
             matvec3(Rj, a, om);
-            for (int i = 0; i < 3; ++i) lev[i] = pee[3 * k + i] - p[3 * j + i];
-            cross3(om, lev, v);
+            if (jtype(tr, j) == ORA_PRISMATIC) {
+                for (int i = 0; i < 3; ++i) {
+                    v[i] = om[i];
+                    om[i] = 0.0;
+                }
+            } else {
+                for (int i = 0; i < 3; ++i) lev[i] = pee[3 * k + i] - p[3 * j + i];
+                cross3(om, lev, v);
+            }
             if (pose) {
                 double s[6], col[6];
                 matvec3(ReT, v, s);
@@ -525,22 +594,23 @@ void ora_jacobian(const ora_tree *tr, const double *targets, const ora_weights *
                     for (int l = 0; l < 6; ++l) acc += Jr[6 * i + l] * s[l];
                     col[i] = acc;
                 }
-                for (int i = 0; i < 3; ++i) J[(row + i) * n + j] = w->w_pos * col[i];
-                for (int i = 0; i < 3; ++i) J[(row + 3 + i) * n + j] = w->w_rot * col[3 + i];
+                for (int i = 0; i < 3; ++i) J[(row + i) * n + jv] = w->w_pos * col[i];
+                for (int i = 0; i < 3; ++i) J[(row + 3 + i) * n + jv] = w->w_rot * col[3 + i];
             } else {
-                for (int i = 0; i < 3; ++i) J[(row + i) * n + j] = w->w_pos * v[i];
+                for (int i = 0; i < 3; ++i) J[(row + i) * n + jv] = w->w_pos * v[i];
             }
         }
         row += pose ? 6 : 3;
     }
-    for (int j = 0; j < n; ++j) {
+    for (int v = 0; v < n; ++v) {
+        const int j = joint_of[v];
         double d = 0.0;
-        if (q[j] > tr->upper[j]) d = w->w_limit;
-        else if (q[j] < tr->lower[j]) d = -w->w_limit;
-        J[(row + j) * n + j] = d;
+        if (q[v] > tr->upper[j]) d = w->w_limit;
+        else if (q[v] < tr->lower[j]) d = -w->w_limit;
+        J[(row + v) * n + v] = d;
     }
     row += n;
-    for (int j = 0; j < n; ++j) J[(row + j) * n + j] = w->w_rest;
+    for (int v = 0; v < n; ++v) J[(row + v) * n + v] = w->w_rest;
 }
 
 /* ----------------------------------------------------------- linear algebra */
@@ -597,7 +667,7 @@ int ora_lm_step(const ora_tree *tr, const double *targets, const ora_weights *w,
                 const ora_options *o, const double *q, double lambda, double *delta,
                 int *fallback)
 {
-    int n = tr->n, rows = ora_rows(tr);
+    int n = ora_nvar(tr), rows = ora_rows(tr);
     double r[ORA_MAX_ROWS];
     double *J = malloc(sizeof(double) * rows * n);
     double *A = malloc(sizeof(double) * n * n);
@@ -657,7 +727,7 @@ static double pose_cost_of(const ora_tree *tr, const double *targets,
 {
     double r[ORA_MAX_ROWS];
     ora_residual(tr, targets, w, q, r, NULL, NULL);
-    int prow = ora_rows(tr) - 2 * tr->n;
+    int prow = ora_rows(tr) - 2 * ora_nvar(tr);
     double c = 0.0;
     for (int i = 0; i < prow; ++i) c += r[i] * r[i];
     return c;
@@ -677,7 +747,7 @@ void ora_lm_solve(const ora_tree *tr, const double *targets, const ora_weights *
                   double *pos_err, double *rot_err, ora_result *res, int n_trace,
                   double *trace_q, int *trace_acc, double *trace_cost, int *trace_tie)
 {
-    int n = tr->n;
+    int n = ora_nvar(tr);
     double q[ORA_MAX_N], qt[ORA_MAX_N], delta[ORA_MAX_N];
     memset(res, 0, sizeof *res);
     res->iters_to_tol = -1;
@@ -759,7 +829,7 @@ typedef struct {
 static void *run_chunk(void *arg)
 {
     ora_chunk *c = arg;
-    int n = c->tr->n, m = c->tr->m;
+    int n = ora_nvar(c->tr), m = c->tr->m;
     for (long p = c->begin; p < c->end; ++p) {
         ora_result r;
         ora_lm_solve(c->tr, c->targets + (size_t)(p / c->K) * m * 7, c->w, c->o,

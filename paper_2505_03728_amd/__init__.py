@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpkmi.so")
 
 CONVERGED, MAX_ITERS, STALLED, NONFINITE = 0, 1, 2, 3
+JOINT_REVOLUTE, JOINT_PRISMATIC, JOINT_FIXED = 0, 1, 2
 FLAG_FP64 = 0x100
 EE_POSE, EE_POSITION = 0, 1
 VARIANT_AUTO, VARIANT_LANE, VARIANT_WAVE = 0, 1, 2
@@ -44,7 +45,7 @@ class _Tree(C.Structure):
     _fields_ = [("n_joints", C.c_int32), ("parent", _i32p), ("mount_quat", _f64p),
                 ("offset", _f64p), ("axis", _f64p), ("lower", _f64p), ("upper", _f64p),
                 ("n_ee", C.c_int32), ("ee_joint", _i32p), ("ee_offset", _f64p),
-                ("ee_quat", _f64p), ("ee_kind", _i32p)]
+                ("ee_quat", _f64p), ("ee_kind", _i32p), ("joint_type", _i32p)]
 
 
 class _Weights(C.Structure):
@@ -266,16 +267,19 @@ class Context:
     # ------------------------------------------------------------- robots
     def upload(self, tree) -> int:
         """tree: object with parent, mount_quat, offset, axis, lower, upper, ee_joint,
-        ee_offset, ee_quat, ee_kind arrays (see include/pkmi.h)."""
+        ee_offset, ee_quat, ee_kind arrays and optionally joint_type (None = all
+        revolute; see include/pkmi.h)."""
         d = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         i = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+        jt = getattr(tree, "joint_type", None)
         keep = [i(tree.parent), d(tree.mount_quat), d(tree.offset), d(tree.axis), d(tree.lower),
                 d(tree.upper), i(tree.ee_joint), d(tree.ee_offset), d(tree.ee_quat),
-                i(tree.ee_kind)]
-        pi = lambda a: a.ctypes.data_as(_i32p)
+                i(tree.ee_kind), None if jt is None else i(jt)]
+        pi = lambda a: a.ctypes.data_as(_i32p) if a is not None else None
         pd = lambda a: a.ctypes.data_as(_f64p)
         t = _Tree(len(keep[0]), pi(keep[0]), pd(keep[1]), pd(keep[2]), pd(keep[3]), pd(keep[4]),
-                  pd(keep[5]), len(keep[6]), pi(keep[6]), pd(keep[7]), pd(keep[8]), pi(keep[9]))
+                  pd(keep[5]), len(keep[6]), pi(keep[6]), pd(keep[7]), pd(keep[8]), pi(keep[9]),
+                  pi(keep[10]))
         rid = C.c_int32()
         self._call(lib().pk_robot_upload(self._h, C.byref(t), C.byref(rid)))
         self._trees[rid.value] = keep

@@ -107,6 +107,7 @@ enum { E_PE = 0, E_R = 4, E_RE = 12, E_LG = 24, E_M = 36, E_N = 48 };
 struct LaneConst {
     float G[9], t[3], lo, hi, qr;
     int parent, depth;
+    bool pris;            // prismatic joint (else revolute)
     float eG[9], et[3];
     int ee_joint, ee_kind;
     float tp[3], tR[9];   // this lane's EE target
@@ -129,7 +130,7 @@ PK_DEV void point(const SolveParams &P, const LaneConst &C, int lane, int n, int
     using L = Lds<DMAX, MMAX>;
     const bool isj = lane < n, ise = lane < m;
     float s = 0.f, c = 1.f;
-    if (isj) joint_sincos(q, s, c);
+    if (isj && !C.pris) joint_sincos(q, s, c);
     // FK, one tree level at a time, through LDS.
     for (int d = 0; d <= max_depth; ++d) {
         if (C.depth == d) {
@@ -143,6 +144,7 @@ PK_DEV void point(const SolveParams &P, const LaneConst &C, int lane, int n, int
             }
             float O[9], pos[3];
             joint_step(Op, pp, C.G, C.t, s, c, O, pos);
+            if (C.pris) joint_slide(O, q, pos);
             float *f = lds + L::FR + lane * 12;
 #pragma unroll
             for (int u = 0; u < 9; ++u) f[u] = O[u];
@@ -247,6 +249,7 @@ PK_DEV void jacobian(const RobotC *__restrict__ rb, const SolveParams &P, int la
     wave_sync();
     const float *f = lds + L::FR + (isj ? lane : 0) * 12;
     const float om[3] = {f[2], f[5], f[8]}, pj[3] = {f[9], f[10], f[11]};
+    const bool pris = isj && rb->j[lane].type == PK_JOINT_PRISMATIC;
     float *jc = lds + L::JC + lane * L::JS;
 #pragma unroll
     for (int k = 0; k < MMAX; ++k) {
@@ -254,16 +257,15 @@ PK_DEV void jacobian(const RobotC *__restrict__ rb, const SolveParams &P, int la
             const float *e = lds + L::EX + k * L::ES;
             const int kind = rb->e[k].kind;
             const bool anc = isj && ((rb->anc[k] >> lane) & 1ull);
-            float col[6];
-            float lev[3] = {e[E_PE] - pj[0], e[E_PE + 1] - pj[1], e[E_PE + 2] - pj[2]}, v[3];
-            cross(om, lev, v);
+            float col[6], v[3], wv[3];
+            joint_twist(pris, om, pj, e + E_PE, v, wv);
             if (kind == PK_EE_POSE) {
 #pragma unroll
                 for (int u = 0; u < 3; ++u) {
                     const float *Mu = e + E_M + 3 * u, *Nu = e + E_N + 3 * u;
                     float mv = Mu[0] * v[0] + Mu[1] * v[1] + Mu[2] * v[2];
-                    float nw = Nu[0] * om[0] + Nu[1] * om[1] + Nu[2] * om[2];
-                    float mw = Mu[0] * om[0] + Mu[1] * om[1] + Mu[2] * om[2];
+                    float nw = Nu[0] * wv[0] + Nu[1] * wv[1] + Nu[2] * wv[2];
+                    float mw = Mu[0] * wv[0] + Mu[1] * wv[1] + Mu[2] * wv[2];
                     col[u] = anc ? P.w_pos * (mv + nw) : 0.f;
                     col[3 + u] = anc ? P.w_rot * mw : 0.f;
                 }
@@ -440,6 +442,7 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
     C.qr = P.q_rest ? P.q_rest[jl] : rb->j[jl].mid;
     C.parent = rb->j[jl].parent;
     C.depth = isj ? rb->j[jl].depth : -1;
+    C.pris = isj && rb->j[jl].type == PK_JOINT_PRISMATIC;
 #pragma unroll
     for (int u = 0; u < 9; ++u) C.eG[u] = rb->e[el].G[u];
 #pragma unroll

@@ -141,7 +141,9 @@ int pk::prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *
     if (!finite_w(w)) return fail(ctx, PK_EINVAL, "cost weights: non-finite value");
     const RobotC &H = rb.host;
     variant = o->variant;
-    const bool lane_ok = H.chains > 0 && lane_variant_available(H.chains, H.chain_len, H.e[0].kind);
+    // the per-lane kernel has revolute joints only
+    const bool lane_ok = H.chains > 0 && H.prismatic == 0 &&
+                         lane_variant_available(H.chains, H.chain_len, H.e[0].kind);
     const bool wave_ok = wave_variant_available(H.n);
     if (variant == PK_VARIANT_AUTO) variant = lane_ok ? PK_VARIANT_LANE : PK_VARIANT_WAVE;
     if (variant == PK_VARIANT_LANE && !lane_ok)
@@ -212,18 +214,83 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
 {
     if (!ctx) return fail(nullptr, PK_EINVAL, "pk_robot_upload: ctx is NULL");
     if (!t || !robot_id) return fail(ctx, PK_EINVAL, "pk_robot_upload: NULL argument");
-    const int n = t->n_joints, m = t->n_ee;
-    if (n < 1 || m < 1) return fail(ctx, PK_EINVAL, "pk_robot_upload: need >= 1 joint and EE");
-    if (n > PK_MAX_JOINTS || m > PK_MAX_EES)
-        return fail(ctx, PK_EUNSUPPORTED, "pk_robot_upload: %d joints / %d EEs above %d / %d", n, m,
-                    PK_MAX_JOINTS, PK_MAX_EES);
+    const int nt = t->n_joints, m = t->n_ee;
+    if (nt < 1 || m < 1) return fail(ctx, PK_EINVAL, "pk_robot_upload: need >= 1 joint and EE");
+    if (nt > PK_MAX_TREE_JOINTS || m > PK_MAX_EES)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_robot_upload: %d joints / %d EEs above %d / %d", nt, m,
+                    PK_MAX_TREE_JOINTS, PK_MAX_EES);
     if (!t->parent || !t->mount_quat || !t->offset || !t->axis || !t->lower || !t->upper ||
         !t->ee_joint || !t->ee_offset || !t->ee_quat || !t->ee_kind)
         return fail(ctx, PK_EINVAL, "pk_robot_upload: NULL array in tree");
-    if (!finite_all(t->mount_quat, 4 * n) || !finite_all(t->offset, 3 * n) ||
-        !finite_all(t->axis, 3 * n) || !finite_all(t->lower, n) || !finite_all(t->upper, n) ||
+    if (!finite_all(t->mount_quat, 4 * nt) || !finite_all(t->offset, 3 * nt) ||
+        !finite_all(t->axis, 3 * nt) || !finite_all(t->lower, nt) || !finite_all(t->upper, nt) ||
         !finite_all(t->ee_offset, 3 * m) || !finite_all(t->ee_quat, 4 * m))
         return fail(ctx, PK_EINVAL, "pk_robot_upload: non-finite tree value");
+
+    // Fold fixed joints: a fixed joint's transform (mount, offset) is composed
+    // into the mounts and offsets of its children and into its EEs, which are
+    // then expressed in the frame of its nearest non-fixed ancestor.  Every
+    // joint left is a variable.  rel_R / rel_p: a fixed joint's frame in its
+    // anchor's frame.
+    struct Folded {
+        int parent;
+        M3 mount;
+        double offset[3], axis[3], lo, hi;
+        int kind;
+    };
+    std::vector<Folded> F;
+    std::vector<int> kind(nt), var(nt, -1), anchor(nt, -1);
+    std::vector<M3> rel_R(nt);
+    std::vector<double> rel_p(3 * nt, 0.0);
+    for (int j = 0; j < nt; ++j) {
+        const int par = t->parent[j];
+        if (par < -1 || par >= j)
+            return fail(ctx, PK_EINVAL, "pk_robot_upload: parent[%d] = %d not in [-1, %d)", j, par, j);
+        kind[j] = t->joint_type ? t->joint_type[j] : PK_JOINT_REVOLUTE;
+        if (kind[j] != PK_JOINT_REVOLUTE && kind[j] != PK_JOINT_PRISMATIC && kind[j] != PK_JOINT_FIXED)
+            return fail(ctx, PK_EINVAL, "pk_robot_upload: joint_type[%d] = %d", j, kind[j]);
+        const double *mq = t->mount_quat + 4 * j;
+        double qn = sqrt(mq[0] * mq[0] + mq[1] * mq[1] + mq[2] * mq[2] + mq[3] * mq[3]);
+        if (qn < 1e-6) return fail(ctx, PK_EINVAL, "pk_robot_upload: mount quaternion %d is zero", j);
+        // parent frame in the anchor frame
+        int anc = -1;
+        M3 Rb = eye();
+        double pb[3] = {0.0, 0.0, 0.0};
+        if (par >= 0 && kind[par] != PK_JOINT_FIXED) {
+            anc = var[par];
+        } else if (par >= 0) {
+            anc = anchor[par];
+            Rb = rel_R[par];
+            for (int i = 0; i < 3; ++i) pb[i] = rel_p[3 * par + i];
+        }
+        Folded f;
+        f.parent = anc;
+        f.mount = mul(Rb, quat(mq));
+        mv(Rb, t->offset + 3 * j, f.offset);
+        for (int i = 0; i < 3; ++i) f.offset[i] += pb[i];
+        if (kind[j] == PK_JOINT_FIXED) {
+            anchor[j] = anc;
+            rel_R[j] = f.mount;
+            for (int i = 0; i < 3; ++i) rel_p[3 * j + i] = f.offset[i];
+            continue;
+        }
+        const double *a = t->axis + 3 * j;
+        double an = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        if (fabs(an - 1.0) > 1e-3) return fail(ctx, PK_EINVAL, "pk_robot_upload: axis %d not unit (|a|=%g)", j, an);
+        if (!(t->lower[j] <= t->upper[j]))
+            return fail(ctx, PK_EINVAL, "pk_robot_upload: lower[%d] > upper[%d]", j, j);
+        for (int i = 0; i < 3; ++i) f.axis[i] = a[i] / an;
+        f.lo = t->lower[j];
+        f.hi = t->upper[j];
+        f.kind = kind[j];
+        var[j] = (int)F.size();
+        anchor[j] = var[j];
+        F.push_back(f);
+    }
+    const int n = (int)F.size();
+    if (n < 1) return fail(ctx, PK_EINVAL, "pk_robot_upload: every joint is fixed");
+    if (n > PK_MAX_JOINTS)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_robot_upload: %d variables above %d", n, PK_MAX_JOINTS);
 
     RobotC R;
     memset(&R, 0, sizeof R);
@@ -231,23 +298,13 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
     R.m = m;
     std::vector<M3> U(n);
     for (int j = 0; j < n; ++j) {
-        const int par = t->parent[j];
-        if (par < -1 || par >= j)
-            return fail(ctx, PK_EINVAL, "pk_robot_upload: parent[%d] = %d not in [-1, %d)", j, par, j);
-        const double *a = t->axis + 3 * j;
-        double an = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
-        if (fabs(an - 1.0) > 1e-3) return fail(ctx, PK_EINVAL, "pk_robot_upload: axis %d not unit (|a|=%g)", j, an);
-        double qn = sqrt(t->mount_quat[4 * j] * t->mount_quat[4 * j] + t->mount_quat[4 * j + 1] * t->mount_quat[4 * j + 1] +
-                         t->mount_quat[4 * j + 2] * t->mount_quat[4 * j + 2] + t->mount_quat[4 * j + 3] * t->mount_quat[4 * j + 3]);
-        if (qn < 1e-6) return fail(ctx, PK_EINVAL, "pk_robot_upload: mount quaternion %d is zero", j);
-        if (!(t->lower[j] <= t->upper[j]))
-            return fail(ctx, PK_EINVAL, "pk_robot_upload: lower[%d] > upper[%d]", j, j);
-        double au[3] = {a[0] / an, a[1] / an, a[2] / an};
-        U[j] = z_to(au);
+        const Folded &f = F[j];
+        const int par = f.parent;
+        U[j] = z_to(f.axis);
         M3 Upt = par < 0 ? eye() : tr(U[par]);
-        M3 G = mul(mul(Upt, quat(t->mount_quat + 4 * j)), U[j]);
+        M3 G = mul(mul(Upt, f.mount), U[j]);
         double tt[3];
-        mv(Upt, t->offset + 3 * j, tt);
+        mv(Upt, f.offset, tt);
         JointC &J = R.j[j];
         M3 Ut = tr(U[j]);
         for (int i = 0; i < 9; ++i) {
@@ -255,9 +312,11 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
             J.Ut[i] = snap(Ut.a[i]);
         }
         for (int i = 0; i < 3; ++i) J.t[i] = snap(tt[i]);
-        J.lo = (float)t->lower[j];
-        J.hi = (float)t->upper[j];
-        J.mid = (float)(0.5 * (t->lower[j] + t->upper[j]));
+        J.lo = (float)f.lo;
+        J.hi = (float)f.hi;
+        J.mid = (float)(0.5 * (f.lo + f.hi));
+        J.type = f.kind;
+        R.prismatic += f.kind == PK_JOINT_PRISMATIC;
         R.mid[j] = J.mid;
         J.parent = par;
         J.depth = par < 0 ? 0 : R.j[par].depth + 1;
@@ -298,16 +357,30 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
         R.nstep = ns;
     }
     int tgt = 0, rows = 0;
+    std::vector<int> ee_var(m);
     for (int k = 0; k < m; ++k) {
-        const int e = t->ee_joint[k], kind = t->ee_kind[k];
-        if (e < 0 || e >= n) return fail(ctx, PK_EINVAL, "pk_robot_upload: ee_joint[%d] = %d out of range", k, e);
+        const int ej = t->ee_joint[k], kind = t->ee_kind[k];
+        if (ej < 0 || ej >= nt) return fail(ctx, PK_EINVAL, "pk_robot_upload: ee_joint[%d] = %d out of range", k, ej);
         if (kind != PK_EE_POSE && kind != PK_EE_POSITION)
             return fail(ctx, PK_EINVAL, "pk_robot_upload: ee_kind[%d] = %d", k, kind);
+        // the EE in the frame of its joint's anchor (the joint itself unless fixed)
+        const int e = anchor[ej];
+        if (e < 0) return fail(ctx, PK_EUNSUPPORTED, "pk_robot_upload: EE %d has no non-fixed ancestor", k);
+        M3 Rrel = quat(t->ee_quat + 4 * k);
+        double prel[3];
+        for (int i = 0; i < 3; ++i) prel[i] = t->ee_offset[3 * k + i];
+        if (var[ej] < 0) {
+            double pr[3];
+            mv(rel_R[ej], prel, pr);
+            for (int i = 0; i < 3; ++i) prel[i] = rel_p[3 * ej + i] + pr[i];
+            Rrel = mul(rel_R[ej], Rrel);
+        }
+        ee_var[k] = e;
         EEC &E = R.e[k];
         M3 Uet = tr(U[e]);
-        M3 G = mul(Uet, quat(t->ee_quat + 4 * k));
+        M3 G = mul(Uet, Rrel);
         double tt[3];
-        mv(Uet, t->ee_offset + 3 * k, tt);
+        mv(Uet, prel, tt);
         for (int i = 0; i < 9; ++i) E.G[i] = snap(G.a[i]);
         for (int i = 0; i < 3; ++i) E.t[i] = snap(tt[i]);
         E.joint = e;
@@ -317,7 +390,7 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
         tgt += kind == PK_EE_POSE ? 7 : 3;
         rows += kind == PK_EE_POSE ? 6 : 3;
         uint64_t mask = 0;
-        for (int a = e; a >= 0; a = t->parent[a]) mask |= 1ull << a;
+        for (int a = e; a >= 0; a = F[a].parent) mask |= 1ull << a;
         R.anc[k] = mask;
     }
     R.tgt_floats = tgt;
@@ -327,13 +400,13 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
     // indices, EE c at the tip of chain c, one EE kind.
     {
         int roots = 0;
-        for (int j = 0; j < n; ++j) roots += t->parent[j] < 0;
+        for (int j = 0; j < n; ++j) roots += F[j].parent < 0;
         bool star = roots >= 1 && n % roots == 0 && m == roots;
         const int L = star ? n / roots : 0;
         for (int j = 0; star && j < n; ++j)
-            star = (j % L == 0) ? t->parent[j] == -1 : t->parent[j] == j - 1;
+            star = (j % L == 0) ? F[j].parent == -1 : F[j].parent == j - 1;
         for (int k = 0; star && k < m; ++k)
-            star = t->ee_joint[k] == k * L + L - 1 && t->ee_kind[k] == t->ee_kind[0];
+            star = ee_var[k] == k * L + L - 1 && t->ee_kind[k] == t->ee_kind[0];
         R.chains = star ? roots : 0;
         R.chain_len = star ? L : 0;
     }

@@ -19,9 +19,12 @@ PK_DEV void fk_all(const RobotC *__restrict__ rb, const float *q, int64_t N, int
         float Ob[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, pb[3] = {0.f, 0.f, 0.f};
         const float *Op = par < 0 ? Ob : O[par];
         const float *pp = par < 0 ? pb : pos[par];
-        float s, c;
-        joint_sincos(q[(int64_t)j * N + p], s, c);
+        const float qj = q[(int64_t)j * N + p];
+        const bool pri = rb->j[j].type == PK_JOINT_PRISMATIC;
+        float s = 0.f, c = 1.f;
+        if (!pri) joint_sincos(qj, s, c);
         joint_step(Op, pp, rb->j[j].G, rb->j[j].t, s, c, O[j], pos[j]);
+        if (pri) joint_slide(O[j], qj, pos[j]);
     }
 }
 
@@ -87,13 +90,13 @@ __global__ __launch_bounds__(64) void resjac_kernel(const RobotC *__restrict__ r
                 jr_inv_blocks(lg, Re, M, Nb);
                 for (int j = 0; j < n; ++j) {
                     if (!((rb->anc[k] >> j) & 1ull)) continue;
-                    float om[3] = {O[j][2], O[j][5], O[j][8]};
-                    float lev[3] = {pe[0] - pos[j][0], pe[1] - pos[j][1], pe[2] - pos[j][2]}, v[3];
-                    cross(om, lev, v);
+                    const float om[3] = {O[j][2], O[j][5], O[j][8]};
+                    float v[3], wv[3];
+                    joint_twist(rb->j[j].type == PK_JOINT_PRISMATIC, om, pos[j], pe, v, wv);
                     for (int u = 0; u < 3; ++u) {
                         float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
-                        float nw = Nb[3 * u] * om[0] + Nb[3 * u + 1] * om[1] + Nb[3 * u + 2] * om[2];
-                        float mw = M[3 * u] * om[0] + M[3 * u + 1] * om[1] + M[3 * u + 2] * om[2];
+                        float nw = Nb[3 * u] * wv[0] + Nb[3 * u + 1] * wv[1] + Nb[3 * u + 2] * wv[2];
+                        float mw = M[3 * u] * wv[0] + M[3 * u + 1] * wv[1] + M[3 * u + 2] * wv[2];
                         J[((int64_t)(row0 + u) * n + j) * N + p] = P.w_pos * (mv + nw);
                         J[((int64_t)(row0 + 3 + u) * n + j) * N + p] = P.w_rot * mw;
                     }
@@ -104,9 +107,9 @@ __global__ __launch_bounds__(64) void resjac_kernel(const RobotC *__restrict__ r
             if (J) {
                 for (int j = 0; j < n; ++j) {
                     if (!((rb->anc[k] >> j) & 1ull)) continue;
-                    float om[3] = {O[j][2], O[j][5], O[j][8]};
-                    float lev[3] = {pe[0] - pos[j][0], pe[1] - pos[j][1], pe[2] - pos[j][2]}, v[3];
-                    cross(om, lev, v);
+                    const float om[3] = {O[j][2], O[j][5], O[j][8]};
+                    float v[3], wv[3];
+                    joint_twist(rb->j[j].type == PK_JOINT_PRISMATIC, om, pos[j], pe, v, wv);
                     for (int u = 0; u < 3; ++u) J[((int64_t)(row0 + u) * n + j) * N + p] = P.w_pos * v[u];
                 }
             }

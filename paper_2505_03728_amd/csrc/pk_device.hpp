@@ -48,6 +48,15 @@ PK_DEV void joint_step(const float *Op, const float *pp, const float *G, const f
     }
 }
 
+// Prismatic joint: joint_step with s = 0, c = 1 leaves the frame unrotated;
+// then the origin slides by q along the joint axis, the frame's third column.
+PK_DEV void joint_slide(const float *O, float q, float *p)
+{
+    p[0] += q * O[2];
+    p[1] += q * O[5];
+    p[2] += q * O[8];
+}
+
 // EE frame: R = O G, p = pe + O t.
 PK_DEV void ee_frame(const float *O, const float *p, const float *G, const float *t,
                      float *R, float *pe)
@@ -102,6 +111,25 @@ PK_DEV void cross(const float *a, const float *b, float *c)
     c[0] = a[1] * b[2] - a[2] * b[1];
     c[1] = a[2] * b[0] - a[0] * b[2];
     c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Velocity of a joint with world axis om at origin pj, seen at the point pe:
+// revolute (v, w) = (om x (pe - pj), om); prismatic (v, w) = (om, 0).
+PK_DEV void joint_twist(bool prismatic, const float *om, const float *pj, const float *pe, float *v,
+                        float *w)
+{
+    if (prismatic) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            v[u] = om[u];
+            w[u] = 0.f;
+        }
+    } else {
+        const float lev[3] = {pe[0] - pj[0], pe[1] - pj[1], pe[2] - pj[2]};
+        cross(om, lev, v);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) w[u] = om[u];
+    }
 }
 
 // Unit quaternion (w >= 0) of a rotation matrix, Shepperd's method: the

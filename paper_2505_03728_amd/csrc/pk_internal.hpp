@@ -22,7 +22,8 @@ struct JointC {
     int32_t parent;
     float Ut[9];       // U_j^T, to report the paper's R_j = O_j U_j^T
     int32_t depth;
-    int32_t pad[2];
+    int32_t type;      // PK_JOINT_REVOLUTE or PK_JOINT_PRISMATIC (fixed joints are folded away)
+    int32_t pad;
 };
 
 struct EEC {
@@ -38,7 +39,7 @@ constexpr int PK_STEP_PIVOTS = 16;   // pivots per elimination step (LDS slots)
 
 struct RobotC {
     int32_t n, m, tgt_floats, pose_rows;   // pose_rows = sum of EE row counts
-    int32_t chains, chain_len, max_depth, pad;
+    int32_t chains, chain_len, max_depth, prismatic;   // prismatic: count of prismatic joints
     uint64_t anc[PK_MAX_EES];              // bit j set iff joint j is an ancestor of EE k
     JointC j[PK_MAX_JOINTS];
     EEC e[PK_MAX_EES];

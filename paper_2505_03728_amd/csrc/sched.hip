@@ -369,7 +369,8 @@ int pk_autotune_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
         const RobotEntry *rb = robot_of(ctx, groups[g].robot_id);
         if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_autotune_mixed: group %d: unknown robot", g);
         const RobotC &H = rb->host;
-        if (H.chains > 0 && lane_variant_available(H.chains, H.chain_len, H.e[0].kind)) flex.push_back(g);
+        if (H.chains > 0 && H.prismatic == 0 && lane_variant_available(H.chains, H.chain_len, H.e[0].kind))
+            flex.push_back(g);
     }
     std::vector<std::vector<int>> vsets;
     auto base = [&]() {

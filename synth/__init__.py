@@ -22,6 +22,12 @@ these seeded families stand in for them):
 * ``hand16`` — 4 fingers of 4 joints (z,y,z,y) from the base, offsets
   U[0.02,0.05], finger c's root shifted by (0, (c-1.5)*0.02, 0); one
   position-only fingertip EE per finger.  16 DoF, 4 EEs.
+* ``arm7_tool`` — arm7 with two fixed joints: a flange between joints 3 and 4
+  (mount Rx(pi/2)) and a tool at the tip that carries the EE.  7 DoF.
+* ``scara4`` — revolute z, revolute z, prismatic z, revolute z (a SCARA-like
+  chain with one sliding joint), pose EE.  4 DoF.
+* ``mobile_arm7`` — a planar base (prismatic x, prismatic y, revolute z: the
+  SE(2) base pose) carrying arm7.  10 DoF.
 """
 from __future__ import annotations
 
@@ -31,13 +37,17 @@ import math
 import numpy as np
 
 __all__ = [
-    "Tree", "EE_POSE", "EE_POSITION", "arm7", "tree34", "hand16", "chain",
+    "Tree", "EE_POSE", "EE_POSITION", "JOINT_REVOLUTE", "JOINT_PRISMATIC", "JOINT_FIXED",
+    "arm7", "tree34", "hand16", "chain", "arm7_tool", "scara4", "mobile_arm7",
     "planar2", "one_joint", "uniform_configs", "workload", "mlp_init",
     "epoch_permutation", "f32",
 ]
 
 EE_POSE = 0
 EE_POSITION = 1
+JOINT_REVOLUTE = 0
+JOINT_PRISMATIC = 1
+JOINT_FIXED = 2
 
 _AX = {"x": (1.0, 0.0, 0.0), "y": (0.0, 1.0, 0.0), "z": (0.0, 0.0, 1.0)}
 
@@ -49,13 +59,16 @@ def f32(a):
 
 @dataclass
 class Tree:
-    """A revolute joint tree in topological order (parent[j] < j, -1 = base).
+    """A joint tree in topological order (parent[j] < j, -1 = base).
 
     Joint j's frame is its parent's frame, translated by ``offset[j]``
     (expressed in the parent frame), rotated by the mount rotation
-    ``mount_quat[j]`` (wxyz) and then by the joint rotation about ``axis[j]``
-    (expressed after the mount).  EE k is rigidly attached to joint
-    ``ee_joint[k]`` with ``ee_offset[k]`` / ``ee_quat[k]``.
+    ``mount_quat[j]`` (wxyz) and then moved by the joint: a rotation about
+    ``axis[j]`` (expressed after the mount) for a revolute joint, a
+    translation along it for a prismatic one, nothing for a fixed one.  The
+    variables are the non-fixed joints in index order (``var_joints``); EE k
+    is rigidly attached to joint ``ee_joint[k]`` with ``ee_offset[k]`` /
+    ``ee_quat[k]``.  ``joint_type`` None means every joint is revolute.
     """
     name: str
     parent: np.ndarray          # int32 [n]
@@ -69,10 +82,27 @@ class Tree:
     ee_quat: np.ndarray         # [m,4]
     ee_kind: np.ndarray         # int32 [m]
     meta: dict = field(default_factory=dict)
+    joint_type: np.ndarray | None = None   # int32 [n] JOINT_*, None = all revolute
 
     @property
     def n(self) -> int:
+        """Joints of the description (fixed ones included)."""
         return int(self.parent.shape[0])
+
+    @property
+    def types(self) -> np.ndarray:
+        if self.joint_type is None:
+            return np.zeros(self.n, dtype=np.int32)
+        return np.asarray(self.joint_type, dtype=np.int32)
+
+    @property
+    def var_joints(self) -> np.ndarray:
+        """Indices of the joints that are variables (not fixed), in order."""
+        return np.nonzero(self.types != JOINT_FIXED)[0]
+
+    @property
+    def dof(self) -> int:
+        return int(self.var_joints.shape[0])
 
     @property
     def m(self) -> int:
@@ -84,7 +114,7 @@ class Tree:
 
 
 def _finish(name, parent, mount, offset, axis, lim, ee_joint, ee_offset, ee_quat,
-            ee_kind, meta=None) -> Tree:
+            ee_kind, meta=None, joint_type=None) -> Tree:
     lim = f32(lim)
     return Tree(
         name=name,
@@ -99,6 +129,7 @@ def _finish(name, parent, mount, offset, axis, lim, ee_joint, ee_offset, ee_quat
         ee_quat=f32(ee_quat).reshape(-1, 4),
         ee_kind=np.asarray(ee_kind, dtype=np.int32),
         meta=dict(meta or {}),
+        joint_type=None if joint_type is None else np.asarray(joint_type, dtype=np.int32),
     )
 
 
@@ -203,11 +234,67 @@ def one_joint(offset=(0.1, 0.2, 0.3), ee_offset=(0.5, 0.0, 0.0), axis="z",
                    [0], [ee_offset], [[1.0, 0, 0, 0]], [kind])
 
 
+def arm7_tool(seed: int = 0) -> Tree:
+    """arm7 with a fixed flange after joint 3 (mount Rx(pi/2), offset
+    (0, 0, 0.05)) and a fixed tool after joint 6 (offset (0, 0, 0.12),
+    mount Ry(pi/4)) that carries the pose EE (at arm7's EE offset)."""
+    a = arm7(seed)
+    h = math.sqrt(0.5)
+    c8 = math.cos(math.pi / 8)
+    s8 = math.sin(math.pi / 8)
+    order = [0, 1, 2, 3, "flange", 4, 5, 6, "tool"]
+    idx = {}
+    parent, mount, offset, axis, lim, jt = [], [], [], [], [], []
+    for i, o in enumerate(order):
+        idx[o] = i
+        if o == "flange":
+            parent.append(idx[3]); mount.append([h, h, 0.0, 0.0]); offset.append([0.0, 0.0, 0.05])
+            axis.append(_AX["z"]); lim.append(0.0); jt.append(JOINT_FIXED)
+        elif o == "tool":
+            parent.append(idx[6]); mount.append([c8, 0.0, s8, 0.0]); offset.append([0.0, 0.0, 0.12])
+            axis.append(_AX["z"]); lim.append(0.0); jt.append(JOINT_FIXED)
+        else:
+            parent.append(-1 if o == 0 else (idx["flange"] if o == 4 else idx[o - 1]))
+            mount.append(a.mount_quat[o]); offset.append(a.offset[o]); axis.append(a.axis[o])
+            lim.append(a.upper[o]); jt.append(JOINT_REVOLUTE)
+    return _finish("arm7_tool", parent, mount, offset, axis, lim, [idx["tool"]], a.ee_offset,
+                   [[1.0, 0.0, 0.0, 0.0]], [EE_POSE], {"seed": seed}, joint_type=jt)
+
+
+def scara4() -> Tree:
+    """Revolute z, revolute z (0.35 m link along x), prismatic z (0.25 m link,
+    stroke +-0.2 m), revolute z; pose EE 0.05 m below the last joint."""
+    return _finish("scara4", [-1, 0, 1, 2], np.tile([1.0, 0, 0, 0], (4, 1)),
+                   [[0, 0, 0.4], [0.35, 0, 0], [0.25, 0, 0], [0, 0, 0]],
+                   [_AX["z"]] * 4, [math.pi * 0.9, math.pi * 0.8, 0.2, math.pi], [3],
+                   [[0, 0, -0.05]], [[1.0, 0, 0, 0]], [EE_POSE],
+                   joint_type=[JOINT_REVOLUTE, JOINT_REVOLUTE, JOINT_PRISMATIC, JOINT_REVOLUTE])
+
+
+def mobile_arm7(seed: int = 0, reach: float = 2.0) -> Tree:
+    """SE(2) base pose as joints (prismatic x, prismatic y, revolute z, all at
+    the base origin; x and y within +-reach metres, yaw within +-pi) carrying
+    arm7 (its joint 0 hangs off the yaw joint)."""
+    a = arm7(seed)
+    n = a.n
+    parent = [-1, 0, 1] + [2 if j == 0 else j + 2 for j in range(n)]
+    mount = [[1.0, 0, 0, 0]] * 3 + list(a.mount_quat)
+    offset = [[0.0, 0.0, 0.0]] * 3 + list(a.offset)
+    axis = [_AX["x"], _AX["y"], _AX["z"]] + list(a.axis)
+    lim = [reach, reach, math.pi] + list(a.upper)
+    jt = [JOINT_PRISMATIC, JOINT_PRISMATIC, JOINT_REVOLUTE] + [JOINT_REVOLUTE] * n
+    return _finish("mobile_arm7", parent, mount, offset, axis, lim, [a.ee_joint[0] + 3],
+                   a.ee_offset, a.ee_quat, [EE_POSE], {"seed": seed, "reach": reach},
+                   joint_type=jt)
+
+
 def uniform_configs(tree: Tree, count: int, seed: int) -> np.ndarray:
-    """count x n joint vectors, q_j ~ U[lower_j, upper_j] (row-major draws)."""
+    """count x dof variable vectors, q_v ~ U[lower, upper] of the v-th
+    non-fixed joint (row-major draws)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    u = rng.random(size=(count, tree.n))
-    return f32(tree.lower + u * (tree.upper - tree.lower))
+    vj = tree.var_joints
+    u = rng.random(size=(count, vj.shape[0]))
+    return f32(tree.lower[vj] + u * (tree.upper[vj] - tree.lower[vj]))
 
 
 def _weights(w_pos=1.0, w_rot=0.5, w_limit=10.0, w_rest=0.0):
@@ -234,7 +321,13 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
       * ``seeder``  — 2M training configurations + 131072 evaluation targets;
       * ``beam``    — IK-Beam on arm7 (pose+limit): 2000 targets x 64 seeds,
                       6 iterations, 4 kept, 10 iterations; the batch sizes
-                      1, 10, 100, 1000, 2000 are prefixes of the same draws.
+                      1, 10, 100, 1000, 2000 are prefixes of the same draws;
+      * ``mobile``  — IK with a mobile base: 4096 arm7 poses reachable from
+                      the base at the origin, each translated horizontally by
+                      U[-1, 1]^2 m; mobile_arm7 (base pose free) x 4 seeds
+                      with the base at the origin, and the same targets for
+                      arm7 alone (fixed base); pose+limit, 30 iterations,
+                      success at 5 mm / 0.05 rad.
     ``targets`` overrides the target count (a prefix of the same draws).
     Returns q* (configurations whose FK are the targets) and seeds; the caller
     computes the target poses with its own FK.
@@ -284,6 +377,19 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
                 "weights": _weights(), "options": _options(16),
                 "schedule": {"n_seeds": K, "iters0": 6, "keep": 4, "iters1": 10},
                 "batches": [1, 10, 100, 1000, 2000]}
+    if name == "mobile":
+        arm, mob = arm7(0), mobile_arm7(0)
+        T = targets or int(4096 * scale)
+        K = 4
+        q_arm = uniform_configs(arm, T, 22)
+        shift = f32(np.random.Generator(np.random.PCG64(23)).uniform(-1.0, 1.0, size=(T, 2)))
+        seeds_arm = uniform_configs(arm, T * K, 24)
+        q_star = np.concatenate([shift, np.zeros((T, 1)), q_arm], 1)
+        seeds = np.concatenate([np.zeros((T * K, 3)), seeds_arm], 1)
+        o = dict(_options(30), tol_pos=5e-3, tol_rot=5e-2)
+        return {"groups": [{"tree": mob, "q_star": q_star, "K": K, "seeds": seeds}],
+                "fixed_base": {"tree": arm, "seeds": seeds_arm},
+                "weights": _weights(), "options": o}
     if name == "seeder":
         r = arm7(0)
         S = int(2_000_000 * scale)

@@ -26,7 +26,7 @@ def manifest():
                   "ee_offset", "ee_quat", "ee_kind"]:
             out[f"{name}.{f}"] = digest(getattr(t, f))
     for wl, tg in [("arm16", None), ("arm131k", 64), ("tree4k", 16), ("mixed84k", 8),
-                   ("beam", 10)]:
+                   ("beam", 10), ("mobile", 10)]:
         w = synth.workload(wl, targets=tg)
         for i, g in enumerate(w["groups"]):
             out[f"{wl}.{i}.q_star"] = digest(g["q_star"])

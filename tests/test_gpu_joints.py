@@ -1,0 +1,219 @@
+"""GPU parity for fixed and prismatic joints (Sec. III-B) through the C ABI.
+
+Robots: arm7 with a fixed flange and a fixed tool (folded on upload, then a
+single revolute chain for the per-lane kernel), a SCARA-like chain with one
+prismatic joint and a 7-DoF arm on an SE(2) base (prismatic x, prismatic y,
+revolute yaw), both on the per-wavefront kernel.  Tolerances as in the LM
+parity tests: FK within 1e-5 m / 1e-5 rad, Jacobian within 1e-4 relative,
+per-problem LM success agreeing with the oracle except where FP32 cannot
+settle the outcome.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import compare_outcome, quat_to_R, rot_angle, soa, solve_gpu, targets_dev
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+ROBOTS = {"arm7_tool": synth.arm7_tool(0), "scara4": synth.scara4(),
+          "mobile_arm7": synth.mobile_arm7(0)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2505_03728_amd as pk
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def rids(ctx):
+    return {k: ctx.upload(t) for k, t in ROBOTS.items()}
+
+
+def test_upload_shapes(ctx, rids):
+    info = ctx.robot_info(rids["arm7_tool"])
+    assert info["n"] == 7 and info["chains"] == 1 and info["chain_len"] == 7
+    info = ctx.robot_info(rids["scara4"])
+    assert info["n"] == 4
+    info = ctx.robot_info(rids["mobile_arm7"])
+    assert info["n"] == 10 and info["rows"] == 6 + 2 * 10
+
+
+@pytest.mark.parametrize("name", list(ROBOTS))
+def test_fk_parity(ctx, rids, name):
+    import torch
+    tree = ROBOTS[name]
+    N = 517
+    q = synth.uniform_configs(tree, N, 301)
+    q[::7] *= 1.3
+    ee, fr = ctx.fk(rids[name], soa(q, DEV), frames=True)
+    torch.cuda.synchronize()
+    ee, fr = ee.cpu().numpy().astype(np.float64), fr.cpu().numpy().astype(np.float64)
+    vj = tree.var_joints
+    worst_p = worst_r = 0.0
+    for p in range(0, N, 3):
+        R, pos, Re, pe = oracle.fk(tree, q[p])
+        for k in range(tree.m):
+            worst_p = max(worst_p, np.abs(ee[k, :3, p] - pe[k]).max())
+            worst_r = max(worst_r, rot_angle(Re[k], quat_to_R(ee[k, 3:, p])))
+        for v, j in enumerate(vj):
+            worst_p = max(worst_p, np.abs(fr[v, 9:, p] - pos[j]).max())
+            worst_r = max(worst_r, np.abs(fr[v, :9, p].reshape(3, 3) - R[j]).max())
+    print(f"{name}: FK max |dp| = {worst_p:.2e} m, max rot err = {worst_r:.2e} rad")
+    assert worst_p <= 1e-5 and worst_r <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(ROBOTS))
+def test_residual_jacobian_parity(ctx, rids, name):
+    import paper_2505_03728_amd as pk
+    import torch
+    tree = ROBOTS[name]
+    N = 257
+    q = synth.uniform_configs(tree, N, 302)
+    rng = np.random.default_rng(3)
+    tq = q + rng.normal(size=q.shape) * np.logspace(-6, -0.5, N)[:, None]
+    tg = oracle.targets_from(tree, tq)
+    q[::5, 0] = tree.upper[tree.var_joints[0]] + 0.2          # limit rows active
+    w = {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 10.0, "w_rest": 0.01, "q_rest": None}
+    r, J = ctx.residual_jacobian(rids[name], targets_dev(tree, tg, DEV), soa(q, DEV), 1,
+                                 pk.Weights.from_dict(w))
+    torch.cuda.synchronize()
+    r, J = r.cpu().numpy().astype(np.float64), J.cpu().numpy().astype(np.float64)
+    worst_r = worst_j = 0.0
+    for p in range(N):
+        ro, _, re = oracle.residual(tree, tg[p], w, q[p])
+        if np.any(re > np.pi - 0.05):
+            continue
+        Jo = oracle.jacobian(tree, tg[p], w, q[p])
+        worst_r = max(worst_r, np.abs(r[:, p] - ro).max())
+        worst_j = max(worst_j, np.linalg.norm(J[:, :, p] - Jo) / max(np.linalg.norm(Jo), 1e-6))
+    print(f"{name}: max |dr| = {worst_r:.2e}, max rel J err = {worst_j:.2e}")
+    assert worst_r <= 2e-5 and worst_j <= 1e-4
+
+
+@pytest.mark.parametrize("name,variant", [("arm7_tool", 1), ("arm7_tool", 2), ("scara4", 0),
+                                          ("mobile_arm7", 0)])
+def test_lm_success_agreement(ctx, rids, name, variant):
+    """Pose + limit + rest (0.01); the mobile arm without the rest term: its
+    10 variables leave a 4-dimensional null space of the pose, along which a
+    rest term makes the last iterations a creep of relative cost decreases
+    near 1e-3 on a damped system of condition ~1e5, accept decisions FP32
+    cannot reproduce (the case that showed it: problem 13 parts at iteration
+    20 with its pose still converged on the GPU)."""
+    tree = ROBOTS[name]
+    T, K = 48, 2
+    tg = oracle.targets_from(tree, synth.uniform_configs(tree, T, 303))
+    seeds = synth.uniform_configs(tree, T * K, 304)
+    w = {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 10.0,
+         "w_rest": 0.0 if name == "mobile_arm7" else 0.01}
+    o = {"max_iters": 30, "lambda0": 1e-3, "nu_up": 10.0, "nu_down": 10.0, "lambda_min": 1e-10,
+         "lambda_max": 1e10, "early_exit": False, "tol_pos": 1e-3, "tol_rot": 1e-2,
+         "damping_floor": 1e-6, "pivot_rel": 1e-6}
+    kw = {"variant": variant} if variant else {}
+    res = solve_gpu(ctx, rids[name], tree, tg, seeds, K, w, o, **kw)
+    bad, excused = [], 0
+    for p in range(T * K):
+        ora = oracle.lm_solve(tree, tg[p // K], w, o, seeds[p], n_trace=30)
+        v = compare_outcome(ctx, rids[name], tree, tg[p // K], seeds[p], w, o, res["status"][p],
+                            res["iters"][p], ora, variant=variant)
+        if v == "bad":
+            bad.append(p)
+        excused += v == "excused"
+    conv = ((res["status"] & 0xFF) == 0).mean()
+    print(f"{name} variant {variant}: success {conv:.3f}, {excused} excused, unexplained {bad}")
+    assert not bad
+
+
+def test_fixed_joint_robot_matches_its_folded_arm(ctx, rids):
+    """arm7_tool folds into a revolute chain of 7: the per-lane and the wave
+    kernels solve it, and their success flags agree with each other."""
+    tree = ROBOTS["arm7_tool"]
+    T = 64
+    tg = oracle.targets_from(tree, synth.uniform_configs(tree, T, 305))
+    seeds = synth.uniform_configs(tree, T, 306)
+    w = {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 10.0, "w_rest": 0.01}
+    o = {"max_iters": 40, "lambda0": 1e-3, "nu_up": 10.0, "nu_down": 10.0, "lambda_min": 1e-10,
+         "lambda_max": 1e10, "early_exit": False, "tol_pos": 1e-3, "tol_rot": 1e-2,
+         "damping_floor": 1e-6, "pivot_rel": 1e-6}
+    a = solve_gpu(ctx, rids["arm7_tool"], tree, tg, seeds, 1, w, o, variant=1)
+    b = solve_gpu(ctx, rids["arm7_tool"], tree, tg, seeds, 1, w, o, variant=2)
+    ora = oracle.lm_solve_batch(tree, tg, seeds, 1, w, o)
+    sa, sb = (a["status"] & 0xFF) == 0, (b["status"] & 0xFF) == 0
+    so = (ora["status"] & 0xFF) == 0
+    print(f"arm7_tool single seed success: lane {sa.mean():.3f}, wave {sb.mean():.3f}, "
+          f"oracle {so.mean():.3f}")
+    assert abs(sa.mean() - so.mean()) <= 0.05 and abs(sb.mean() - so.mean()) <= 0.05
+    assert (sa == sb).mean() >= 0.9
+
+
+def test_upload_errors_and_lane_variant(ctx, rids):
+    import copy
+
+    import paper_2505_03728_amd as pk
+    tree = copy.deepcopy(ROBOTS["scara4"])
+    tree.joint_type = np.array([0, 0, 7, 0], np.int32)
+    with pytest.raises(pk.PkError) as e:
+        ctx.upload(tree)
+    assert e.value.code == -1
+    # an EE whose joints up to the base are all fixed
+    t2 = copy.deepcopy(ROBOTS["scara4"])
+    t2.joint_type = np.array([2, 0, 1, 0], np.int32)
+    t2.ee_joint = np.array([0], np.int32)
+    with pytest.raises(pk.PkError) as e:
+        ctx.upload(t2)
+    assert e.value.code == -2
+    # prismatic robots have no per-lane kernel
+    tree = ROBOTS["scara4"]
+    tg = oracle.targets_from(tree, synth.uniform_configs(tree, 4, 1))
+    with pytest.raises(pk.PkError) as e:
+        solve_gpu(ctx, rids["scara4"], tree, tg, synth.uniform_configs(tree, 4, 2), 1,
+                  {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 10.0, "w_rest": 0.0},
+                  {"max_iters": 5, "lambda0": 1e-3, "nu_up": 10.0, "nu_down": 10.0,
+                   "lambda_min": 1e-10, "lambda_max": 1e10, "early_exit": False, "tol_pos": 1e-3,
+                   "tol_rot": 1e-2, "damping_floor": 1e-6, "pivot_rel": 1e-6}, variant=1)
+    assert e.value.code == -2
+
+
+def test_mobile_base_workload(ctx, rids):
+    """Sec. V-B: arm poses reachable from the base at the origin, moved
+    horizontally by up to 1 m, solved with the SE(2) base pose as variables.
+
+    The robot is redundant (10 variables for a 6-D pose) and has no rest
+    term here, so the damped normal matrix is conditioned by 1 / lambda along
+    the pose's null space: once lambda falls below ~1e-6 the FP32 Jacobian's
+    rounding (~1e-7 relative) moves the null-space part of the step by O(1),
+    and the FP32 and FP64 runs reach different points of the solution set.
+    What is unique is compared instead: every success the GPU reports is a
+    valid solution by the oracle's FK (errors within the tolerance plus
+    1e-5), and the success rates per problem and per target agree within 4
+    points.  Best-of-K succeeds on more targets than the same solve with the
+    base fixed at the origin (the arm alone)."""
+    wl = synth.workload("mobile", targets=128)
+    g = wl["groups"][0]
+    mob, K = g["tree"], g["K"]
+    T = g["q_star"].shape[0]
+    tg = oracle.targets_from(mob, g["q_star"])
+    w, o = wl["weights"], wl["options"]
+    res = solve_gpu(ctx, rids["mobile_arm7"], mob, tg, g["seeds"], K, w, o, best=True)
+    ora = oracle.lm_solve_batch(mob, tg, g["seeds"], K, w, o)
+    conv_g = (res["status"] & 0xFF) == 0
+    conv_o = (ora["status"] & 0xFF) == 0
+    for p in np.nonzero(conv_g)[0]:
+        _, pe, re = oracle.residual(mob, tg[p // K], w, res["q"][p].astype(np.float64))
+        assert pe[0] <= o["tol_pos"] + 1e-5 and re[0] <= o["tol_rot"] + 1e-5, (p, pe, re)
+    _, succ_o = oracle.best_of_k(ora["status"], ora["cost"], ora["pose_cost"], K)
+    sm = res["target_success"].mean()
+    arm = synth.arm7(0)
+    rid_arm = ctx.upload(arm)
+    fixed = solve_gpu(ctx, rid_arm, arm, tg, wl["fixed_base"]["seeds"], K, w, o, best=True)
+    sf = fixed["target_success"].mean()
+    print(f"mobile base: per problem {conv_g.mean():.3f} (oracle {conv_o.mean():.3f}), per target "
+          f"{sm:.3f} (oracle {succ_o.mean():.3f}); fixed base {sf:.3f}")
+    assert abs(conv_g.mean() - conv_o.mean()) <= 0.04
+    assert abs(sm - succ_o.mean()) <= 0.04
+    assert sm > sf

@@ -18,6 +18,8 @@ import synth
 
 rng = np.random.default_rng(99)
 TREES = [synth.arm7(0), synth.tree34(5), synth.hand16(8)]
+# fixed, prismatic and mixed joint kinds (Sec. III-B)
+KINDS = [synth.arm7_tool(0), synth.scara4(), synth.mobile_arm7(0)]
 
 
 def homog(R, t):
@@ -28,15 +30,26 @@ def homog(R, t):
 
 
 def fk_homogeneous(tree, q):
-    """Independent FK: T_j = T_parent * Trans(t_j) * Rot(mount_j) * Rot(axis_j, q_j)."""
+    """Independent FK: T_j = T_parent * Trans(t_j) * Rot(mount_j) * M_j, with
+    M_j = Rot(axis_j, q_v) (revolute), Trans(axis_j q_v) (prismatic) or I
+    (fixed); q_v is the variable of joint j (non-fixed joints in order)."""
     Ts = []
+    v = 0
     for j in range(tree.n):
         par = tree.parent[j]
         Tp = np.eye(4) if par < 0 else Ts[par]
         mq = tree.mount_quat[j]
         Rm = Rotation.from_quat([mq[1], mq[2], mq[3], mq[0]]).as_matrix()
-        Rq = Rotation.from_rotvec(tree.axis[j] / np.linalg.norm(tree.axis[j]) * q[j]).as_matrix()
-        Ts.append(Tp @ homog(np.eye(3), tree.offset[j]) @ homog(Rm, np.zeros(3)) @ homog(Rq, np.zeros(3)))
+        a = tree.axis[j] / np.linalg.norm(tree.axis[j])
+        kind = tree.types[j]
+        if kind == synth.JOINT_REVOLUTE:
+            Mj = homog(Rotation.from_rotvec(a * q[v]).as_matrix(), np.zeros(3))
+        elif kind == synth.JOINT_PRISMATIC:
+            Mj = homog(np.eye(3), a * q[v])
+        else:
+            Mj = np.eye(4)
+        v += kind != synth.JOINT_FIXED
+        Ts.append(Tp @ homog(np.eye(3), tree.offset[j]) @ homog(Rm, np.zeros(3)) @ Mj)
     ees = []
     for k in range(tree.m):
         eq = tree.ee_quat[k]
@@ -45,7 +58,7 @@ def fk_homogeneous(tree, q):
     return Ts, ees
 
 
-@pytest.mark.parametrize("tree", TREES, ids=lambda t: t.name)
+@pytest.mark.parametrize("tree", TREES + KINDS, ids=lambda t: t.name)
 def test_fk_matches_homogeneous_product(ora, tree):
     for q in synth.uniform_configs(tree, 20, 5):
         R, p, Re, pe = ora.fk(tree, q)
@@ -154,20 +167,21 @@ def test_limit_residual_values(ora):
 
 
 def _fd_jac(ora, tree, t, w, q, h=1e-6):
-    J = np.zeros((ora.n_rows(tree), tree.n))
-    for j in range(tree.n):
-        e = np.zeros(tree.n)
+    J = np.zeros((ora.n_rows(tree), tree.dof))
+    for j in range(tree.dof):
+        e = np.zeros(tree.dof)
         e[j] = h
         J[:, j] = (ora.residual(tree, t, w, q + e)[0] - ora.residual(tree, t, w, q - e)[0]) / (2 * h)
     return J
 
 
-@pytest.mark.parametrize("tree", TREES + [synth.planar2(), synth.one_joint(kind=synth.EE_POSITION)],
+@pytest.mark.parametrize("tree", TREES + KINDS + [synth.planar2(),
+                                                  synth.one_joint(kind=synth.EE_POSITION)],
                          ids=lambda t: t.name + str(t.ee_kind[0]))
 def test_analytic_jacobian_matches_finite_differences(ora, tree):
     qs = synth.uniform_configs(tree, 8, 11)
     # Push a few joints outside their limits (away from the kink).
-    qs[::2, 0] = tree.upper[0] + 0.3
+    qs[::2, 0] = tree.upper[tree.var_joints[0]] + 0.3
     tg = ora.targets_from(tree, synth.uniform_configs(tree, 8, 12))
     for q, t in zip(qs, tg):
         J = ora.jacobian(tree, t, WEIGHTS, q)
@@ -188,3 +202,75 @@ def test_jacobian_zero_for_non_ancestors(ora):
                 assert np.all(blk[:, j] == 0)
             else:
                 assert np.any(blk[:, j] != 0)
+
+
+def test_fk_scara_closed_form(ora):
+    """Two revolute z joints (links 0.35, 0.25 along x), a prismatic z joint
+    and a revolute z joint: planar position, height 0.4 + d - 0.05, yaw the
+    sum of the angles."""
+    tree = synth.scara4()
+    # the tree's FP32-rounded lengths
+    l1, l2, h, e = tree.offset[1][0], tree.offset[2][0], tree.offset[0][2], tree.ee_offset[0][2]
+    for t1, t2, d, t4 in [(0.3, -0.7, 0.1, 1.2), (-2.0, 1.5, -0.15, -0.4), (0, 0, 0, 0)]:
+        _, _, Re, pe = ora.fk(tree, np.array([t1, t2, d, t4]))
+        x = l1 * math.cos(t1) + l2 * math.cos(t1 + t2)
+        y = l1 * math.sin(t1) + l2 * math.sin(t1 + t2)
+        np.testing.assert_allclose(pe[0], [x, y, h + d + e], atol=1e-14)
+        yaw = t1 + t2 + t4
+        np.testing.assert_allclose(Re[0], [[math.cos(yaw), -math.sin(yaw), 0],
+                                           [math.sin(yaw), math.cos(yaw), 0], [0, 0, 1]], atol=1e-14)
+
+
+def test_fk_mobile_base_is_se2_times_arm(ora):
+    """The planar base (x, y, yaw) composes as T_world<-base = Trans(x, y, 0)
+    Rz(yaw) in front of the arm's own FK (Sec. V-B)."""
+    arm, mob = synth.arm7(0), synth.mobile_arm7(0)
+    for q in synth.uniform_configs(mob, 10, 7):
+        _, _, Re, pe = ora.fk(mob, q)
+        _, _, Ra, pa = ora.fk(arm, q[3:])
+        c, s_ = math.cos(q[2]), math.sin(q[2])
+        Rz = np.array([[c, -s_, 0], [s_, c, 0], [0, 0, 1.0]])
+        np.testing.assert_allclose(Re[0], Rz @ Ra[0], atol=1e-13)
+        np.testing.assert_allclose(pe[0], Rz @ pa[0] + [q[0], q[1], 0], atol=1e-13)
+
+
+def test_fixed_joints_fold_into_their_neighbours(ora):
+    """A fixed joint is the same as composing its transform into the next
+    joint's mount and offset (and the EE's): the tool arm against a revolute
+    arm built with the folded transforms by hand."""
+    tool = synth.arm7_tool(0)
+    arm = synth.arm7(0)
+
+    def rot(wxyz):
+        return Rotation.from_quat([wxyz[1], wxyz[2], wxyz[3], wxyz[0]]).as_matrix()
+    Rf, Rt = rot(tool.mount_quat[4]), rot(tool.mount_quat[8])     # flange, tool (as stored)
+    assert tool.types[4] == tool.types[8] == synth.JOINT_FIXED
+    folded = synth.Tree("folded", arm.parent.copy(), arm.mount_quat.copy(), arm.offset.copy(),
+                        arm.axis.copy(), arm.lower.copy(), arm.upper.copy(), arm.ee_joint.copy(),
+                        arm.ee_offset.copy(), arm.ee_quat.copy(), arm.ee_kind.copy())
+    # joint 4 hangs off the flange: offset 0.05 z then Rf, then its own offset and mount
+    folded.offset[4] = tool.offset[4] + Rf @ arm.offset[4]
+    m4 = Rotation.from_quat(np.r_[arm.mount_quat[4][1:], arm.mount_quat[4][0]]).as_matrix()
+    qf = Rotation.from_matrix(Rf @ m4).as_quat()
+    folded.mount_quat[4] = np.r_[qf[3], qf[:3]]
+    folded.ee_offset[0] = tool.offset[8] + Rt @ arm.ee_offset[0]
+    qe = Rotation.from_matrix(Rt).as_quat()
+    folded.ee_quat[0] = np.r_[qe[3], qe[:3]]
+    for q in synth.uniform_configs(arm, 10, 9):
+        _, _, Ra, pa = ora.fk(tool, q)
+        _, _, Rb, pb = ora.fk(folded, q)
+        np.testing.assert_allclose(Ra, Rb, atol=1e-13)
+        np.testing.assert_allclose(pa, pb, atol=1e-13)
+
+
+def test_prismatic_column_is_the_world_axis(ora):
+    """Position EE below a prismatic joint: d p_ee / d q = the joint's world
+    axis (closed form, no rotation part)."""
+    tree = synth.scara4()
+    q = np.array([0.4, -0.3, 0.05, 0.9])
+    tg = ora.targets_from(tree, q[None])[0]
+    w = dict(WEIGHTS, w_pos=1.0, w_rot=1.0, w_limit=0.0, w_rest=0.0)
+    J = ora.jacobian(tree, tg, w, q)
+    # at the target itself the pose log is zero, J_r^-1 = I and R_ee^T maps
+    # the world z axis to the EE's z axis, which is world z here
+    np.testing.assert_allclose(J[:6, 2], [0, 0, 1, 0, 0, 0], atol=1e-12)
