@@ -76,10 +76,16 @@ typedef struct pk_ctx pk_ctx;
  *              p_j = p_parent + R_parent offset_j + R_j axis_j q_j;
  *   fixed:     R_j = R_parent Rot(mount_quat_j), p_j = p_parent + R_parent offset_j.
  * EE k is fixed to joint ee_joint[k] by (ee_offset[k], ee_quat[k]).
- * The problem's variables are the non-fixed joints in index order: every
- * [n][N] joint array (seeds, joints, q_rest) has n = that count, the value
- * pk_robot_info reports.  Fixed joints are folded into their neighbours on
- * upload (their limits are ignored); an EE needs a non-fixed ancestor. */
+ * A mimic joint (mimic_joint[j] >= 0) is revolute or prismatic but follows
+ * its driver: q_j = mimic_multiplier[j] * q_driver + mimic_offset[j]; its
+ * Jacobian column adds into the driver's.  The driver must be a non-fixed,
+ * non-mimic joint, and every EE below a mimic joint must be below its
+ * driver too (so the structure of J^T J is that of the tree).
+ * The problem's variables are the joints that are neither fixed nor mimic,
+ * in index order: every [n][N] joint array (seeds, joints, q_rest) has n =
+ * that count, the value pk_robot_info reports.  Fixed joints are folded into
+ * their neighbours on upload (their limits are ignored, as are a mimic
+ * joint's); an EE needs a non-fixed ancestor. */
 typedef struct {
     int32_t n_joints;            /* 1..PK_MAX_TREE_JOINTS, at most PK_MAX_JOINTS non-fixed */
     const int32_t *parent;       /* [n]                                       */
@@ -94,6 +100,9 @@ typedef struct {
     const double *ee_quat;       /* [m][4] wxyz                               */
     const int32_t *ee_kind;      /* [m] PK_EE_POSE or PK_EE_POSITION           */
     const int32_t *joint_type;   /* [n] PK_JOINT_*, or NULL = all revolute      */
+    const int32_t *mimic_joint;  /* [n] driver joint index or -1; NULL = none   */
+    const double *mimic_multiplier; /* [n] (read where mimic_joint >= 0)       */
+    const double *mimic_offset;  /* [n]                                        */
 } pk_tree;
 
 /* Residual weights (Sec. III-C: the costs are weighted residuals and LM
@@ -173,11 +182,12 @@ const char *pk_last_error(pk_ctx *ctx);
 
 /* Copies the tree to the device (FP32) and returns its id.  Validates shape,
  * parent order, unit axes (within 1e-3; renormalised), limits, joint kinds
- * and EE references; folds fixed joints.  Robots with prismatic joints run on
- * the per-wavefront kernel (PK_VARIANT_LANE is unsupported for them).
+ * and EE references; folds fixed joints.  Robots with prismatic or mimic
+ * joints run on the per-wavefront kernel (PK_VARIANT_LANE is unsupported for
+ * them).
  * Synchronous. */
 int pk_robot_upload(pk_ctx *ctx, const pk_tree *tree, int32_t *robot_id);
-/* n variables (non-fixed joints), m EEs, target floats per target (sum of EE widths), residual rows
+/* n variables (joints neither fixed nor mimic), m EEs, target floats per target (sum of EE widths), residual rows
  * (6 per pose EE, 3 per position EE, then n limit and n rest rows), and the
  * star shape used by the per-lane kernel (chains = 0 if not a star). */
 int pk_robot_info(pk_ctx *ctx, int32_t robot_id, int32_t *n, int32_t *m,
@@ -187,7 +197,7 @@ int pk_robot_info(pk_ctx *ctx, int32_t robot_id, int32_t *n, int32_t *m,
 /* Forward kinematics (Sec. III-B) for N configurations q [n][N] (device).
  * ee_pose [m][7][N]: position and unit quaternion (wxyz, w >= 0).
  * joint_frames (optional) [n][12][N]: R_j row-major (9) then p_j (3), for
- * the non-fixed joints. */
+ * the joints that are variables. */
 int pk_fk(pk_ctx *ctx, int32_t robot_id, int64_t N, const float *q, float *ee_pose,
           float *joint_frames, void *stream);
 

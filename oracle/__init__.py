@@ -57,7 +57,8 @@ class _Tree(C.Structure):
     _fields_ = [("n", C.c_int), ("parent", _ip), ("mount_quat", _dp), ("offset", _dp),
                 ("axis", _dp), ("lower", _dp), ("upper", _dp), ("m", C.c_int),
                 ("ee_joint", _ip), ("ee_offset", _dp), ("ee_quat", _dp), ("ee_kind", _ip),
-                ("joint_type", _ip)]
+                ("joint_type", _ip), ("mimic_joint", _ip), ("mimic_mult", _dp),
+                ("mimic_offset", _dp)]
 
 
 class _Weights(C.Structure):
@@ -135,14 +136,19 @@ class OTree:
     def __init__(self, tree):
         self.n, self.m = tree.n, tree.m
         jt = getattr(tree, "joint_type", None)
+        mj = getattr(tree, "mimic_joint", None)
         self.ee_kind = np.asarray(tree.ee_kind)
         self._keep = [_i(tree.parent), _d(tree.mount_quat), _d(tree.offset), _d(tree.axis),
                       _d(tree.lower), _d(tree.upper), _i(tree.ee_joint), _d(tree.ee_offset),
-                      _d(tree.ee_quat), _i(tree.ee_kind), None if jt is None else _i(jt)]
+                      _d(tree.ee_quat), _i(tree.ee_kind), None if jt is None else _i(jt),
+                      None if mj is None else _i(mj),
+                      None if mj is None else _d(tree.mimic_multiplier),
+                      None if mj is None else _d(tree.mimic_offset)]
         k = self._keep
+        opt = lambda a, t: _p(a, t) if a is not None else None
         self.s = _Tree(self.n, _p(k[0], _ip), _p(k[1]), _p(k[2]), _p(k[3]), _p(k[4]), _p(k[5]),
                        self.m, _p(k[6], _ip), _p(k[7]), _p(k[8]), _p(k[9], _ip),
-                       _p(k[10], _ip) if k[10] is not None else None)
+                       opt(k[10], _ip), opt(k[11], _ip), opt(k[12], _dp), opt(k[13], _dp))
         self.nv = lib().ora_nvar(self.s)
 
     @property

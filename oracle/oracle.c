@@ -58,12 +58,17 @@ typedef struct {
     const int *ee_kind;         /* [m] 0 = full pose, 1 = position only      */
     const int *joint_type;      /* [n] ORA_REVOLUTE / ORA_PRISMATIC / ORA_FIXED,
                                    NULL = all revolute                        */
+    const int *mimic_joint;     /* [n] driver of a mimic joint or -1; NULL = none */
+    const double *mimic_mult;   /* [n] q_j = mult * q_driver + offset           */
+    const double *mimic_offset; /* [n]                                         */
 } ora_tree;
 
-/* Joint kinds (Sec. III-B lists fixed, revolute and prismatic joints): a
- * revolute joint rotates by its variable about its axis, a prismatic one
- * translates by it along the axis, a fixed one has no variable.  The
- * variables are the non-fixed joints in index order. */
+/* Joint kinds (Sec. III-B lists fixed, revolute, prismatic and mimic
+ * joints): a revolute joint rotates by its value about its axis, a prismatic
+ * one translates by it along the axis, a fixed one has no value.  A mimic
+ * joint (revolute or prismatic) takes mult * (its driver's value) + offset.
+ * The variables are the joints that are neither fixed nor mimic, in index
+ * order. */
 enum { ORA_REVOLUTE = 0, ORA_PRISMATIC = 1, ORA_FIXED = 2 };
 
 static int jtype(const ora_tree *tr, int j)
@@ -71,21 +76,26 @@ static int jtype(const ora_tree *tr, int j)
     return tr->joint_type ? tr->joint_type[j] : ORA_REVOLUTE;
 }
 
+static int mimic_of(const ora_tree *tr, int j)
+{
+    return tr->mimic_joint ? tr->mimic_joint[j] : -1;
+}
+
 /* Number of variables. */
 int ora_nvar(const ora_tree *tr)
 {
     int v = 0;
-    for (int j = 0; j < tr->n; ++j) v += jtype(tr, j) != ORA_FIXED;
+    for (int j = 0; j < tr->n; ++j) v += jtype(tr, j) != ORA_FIXED && mimic_of(tr, j) < 0;
     return v;
 }
 
-/* var_of[j]: variable of joint j (-1 if fixed); joint_of[v]: joint of
- * variable v. */
+/* var_of[j]: variable of joint j (-1 if fixed or mimic); joint_of[v]: joint
+ * of variable v. */
 static void var_maps(const ora_tree *tr, int *var_of, int *joint_of)
 {
     int v = 0;
     for (int j = 0; j < tr->n; ++j) {
-        if (jtype(tr, j) == ORA_FIXED) {
+        if (jtype(tr, j) == ORA_FIXED || mimic_of(tr, j) >= 0) {
             var_of[j] = -1;
         } else {
             var_of[j] = v;
@@ -389,6 +399,11 @@ void ora_fk(const ora_tree *tr, const double *q, double *R, double *p, double *R
     int var_of[ORA_MAX_N];
     var_maps(tr, var_of, NULL);
     for (int j = 0; j < tr->n; ++j) {
+        /* joint value: its variable, or the mimic rule on its driver's */
+        const int src = mimic_of(tr, j);
+        double qj = 0.0;
+        if (src >= 0) qj = tr->mimic_mult[j] * q[var_of[src]] + tr->mimic_offset[j];
+        else if (var_of[j] >= 0) qj = q[var_of[j]];
         double Rp[9], pp[3] = {0, 0, 0}, Rm[9], Rq[9], tmp[9], v[3];
         int par = tr->parent[j];
         if (par < 0) {
@@ -403,7 +418,7 @@ void ora_fk(const ora_tree *tr, const double *q, double *R, double *p, double *R
         matmul3(Rp, Rm, tmp);
         const int kind = jtype(tr, j);
         if (kind == ORA_REVOLUTE) {
-            axis_angle(tr->axis + 3 * j, q[var_of[j]], Rq);
+            axis_angle(tr->axis + 3 * j, qj, Rq);
             matmul3(tmp, Rq, Rl[j]);
         } else {
             memcpy(Rl[j], tmp, sizeof tmp);
@@ -411,7 +426,7 @@ void ora_fk(const ora_tree *tr, const double *q, double *R, double *p, double *R
                 double a[3], wa[3], an = norm3(tr->axis + 3 * j);
                 for (int i = 0; i < 3; ++i) a[i] = tr->axis[3 * j + i] / an;
                 matvec3(Rl[j], a, wa);
-                for (int i = 0; i < 3; ++i) pl[j][i] += wa[i] * q[var_of[j]];
+                for (int i = 0; i < 3; ++i) pl[j][i] += wa[i] * qj;
             }
         }
         if (R) memcpy(R + 9 * j, Rl[j], sizeof(double) * 9);
@@ -553,7 +568,7 @@ void ora_jacobian(const ora_tree *tr, const double *targets, const ora_weights *
     int row = 0;
     for (int k = 0; k < tr->m; ++k) {
         const double *tg = targets + 7 * k;
-        double Jr[36], ReT[9];
+        double Jr[36] = {0}, ReT[9] = {0};
         int pose = tr->ee_kind[k] == 0;
         if (pose) {
             double Rt[9], RtT[9], RE[9], tE[3], xi[6];
@@ -566,9 +581,13 @@ void ora_jacobian(const ora_tree *tr, const double *targets, const ora_weights *
             ora_se3_jr_inv(xi, Jr);
             transpose3(Ree + 9 * k, ReT);
         }
-        for (int jv = 0; jv < n; ++jv) {
-            const int j = joint_of[jv];
-            if (!is_ancestor(tr, j, tr->ee_joint[k])) continue;
+        for (int j = 0; j < tr->n; ++j) {
+            if (jtype(tr, j) == ORA_FIXED || !is_ancestor(tr, j, tr->ee_joint[k])) continue;
+            /* column of joint j, added into its variable's (a mimic joint's
+             * into its driver's, times the multiplier) */
+            const int src = mimic_of(tr, j);
+            const int jv = src >= 0 ? var_of[src] : var_of[j];
+            const double mul = src >= 0 ? tr->mimic_mult[j] : 1.0;
             double om[3], lev[3], v[3];
             const double *Rj = R + 9 * j;
             double a[3];
@@ -594,10 +613,10 @@ void ora_jacobian(const ora_tree *tr, const double *targets, const ora_weights *
                     for (int l = 0; l < 6; ++l) acc += Jr[6 * i + l] * s[l];
                     col[i] = acc;
                 }
-                for (int i = 0; i < 3; ++i) J[(row + i) * n + jv] = w->w_pos * col[i];
-                for (int i = 0; i < 3; ++i) J[(row + 3 + i) * n + jv] = w->w_rot * col[3 + i];
+                for (int i = 0; i < 3; ++i) J[(row + i) * n + jv] += mul * w->w_pos * col[i];
+                for (int i = 0; i < 3; ++i) J[(row + 3 + i) * n + jv] += mul * w->w_rot * col[3 + i];
             } else {
-                for (int i = 0; i < 3; ++i) J[(row + i) * n + jv] = w->w_pos * v[i];
+                for (int i = 0; i < 3; ++i) J[(row + i) * n + jv] += mul * w->w_pos * v[i];
             }
         }
         row += pose ? 6 : 3;

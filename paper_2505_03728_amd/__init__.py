@@ -45,7 +45,8 @@ class _Tree(C.Structure):
     _fields_ = [("n_joints", C.c_int32), ("parent", _i32p), ("mount_quat", _f64p),
                 ("offset", _f64p), ("axis", _f64p), ("lower", _f64p), ("upper", _f64p),
                 ("n_ee", C.c_int32), ("ee_joint", _i32p), ("ee_offset", _f64p),
-                ("ee_quat", _f64p), ("ee_kind", _i32p), ("joint_type", _i32p)]
+                ("ee_quat", _f64p), ("ee_kind", _i32p), ("joint_type", _i32p),
+                ("mimic_joint", _i32p), ("mimic_multiplier", _f64p), ("mimic_offset", _f64p)]
 
 
 class _Weights(C.Structure):
@@ -268,18 +269,22 @@ class Context:
     def upload(self, tree) -> int:
         """tree: object with parent, mount_quat, offset, axis, lower, upper, ee_joint,
         ee_offset, ee_quat, ee_kind arrays and optionally joint_type (None = all
-        revolute; see include/pkmi.h)."""
+        revolute) and mimic_joint / mimic_multiplier / mimic_offset (see
+        include/pkmi.h)."""
         d = lambda a: np.ascontiguousarray(a, dtype=np.float64)
         i = lambda a: np.ascontiguousarray(a, dtype=np.int32)
         jt = getattr(tree, "joint_type", None)
+        mj = getattr(tree, "mimic_joint", None)
         keep = [i(tree.parent), d(tree.mount_quat), d(tree.offset), d(tree.axis), d(tree.lower),
                 d(tree.upper), i(tree.ee_joint), d(tree.ee_offset), d(tree.ee_quat),
-                i(tree.ee_kind), None if jt is None else i(jt)]
+                i(tree.ee_kind), None if jt is None else i(jt), None if mj is None else i(mj),
+                None if mj is None else d(tree.mimic_multiplier),
+                None if mj is None else d(tree.mimic_offset)]
         pi = lambda a: a.ctypes.data_as(_i32p) if a is not None else None
-        pd = lambda a: a.ctypes.data_as(_f64p)
+        pd = lambda a: a.ctypes.data_as(_f64p) if a is not None else None
         t = _Tree(len(keep[0]), pi(keep[0]), pd(keep[1]), pd(keep[2]), pd(keep[3]), pd(keep[4]),
                   pd(keep[5]), len(keep[6]), pi(keep[6]), pd(keep[7]), pd(keep[8]), pi(keep[9]),
-                  pi(keep[10]))
+                  pi(keep[10]), pi(keep[11]), pd(keep[12]), pd(keep[13]))
         rid = C.c_int32()
         self._call(lib().pk_robot_upload(self._h, C.byref(t), C.byref(rid)))
         self._trees[rid.value] = keep

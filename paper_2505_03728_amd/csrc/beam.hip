@@ -140,7 +140,7 @@ extern "C" int pk_ik_beam(pk_ctx *ctx, int32_t robot_id, int64_t T, const float 
     if (rc) return rc;
     rc = prepare_solve(ctx, *rb, w, &o1, P1, v1);
     if (rc) return rc;
-    const int n = rb->host.n, m = rb->host.m;
+    const int n = rb->host.nv, m = rb->host.m;
     PK_HIP(ctx, hipSetDevice(ctx->device));
 
     // Workspace (4-byte words) for whatever the caller did not provide.

@@ -71,6 +71,14 @@ PK_DEV float wave_max(float v)
 // threads and move a lane's read ahead of another lane's write.  The kernel's
 // workgroup is a single wavefront, so this is the only ordering its LDS
 // exchanges need (LDS accesses of one wavefront complete in order).
+// A mimic lane's value from its driver lane's (every lane takes part in the
+// exchange; the others keep theirs).
+PK_DEV float mimic_rule(float q, int src, float a, float b)
+{
+    const float qd = __shfl(q, src < 0 ? 0 : src, 64);
+    return src >= 0 ? a * qd + b : q;
+}
+
 PK_DEV void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -108,6 +116,7 @@ struct LaneConst {
     float G[9], t[3], lo, hi, qr;
     int parent, depth;
     bool pris;            // prismatic joint (else revolute)
+    bool var;             // the joint is a variable (not a mimic joint)
     float eG[9], et[3];
     int ee_joint, ee_kind;
     float tp[3], tR[9];   // this lane's EE target
@@ -198,7 +207,7 @@ PK_DEV void point(const SolveParams &P, const LaneConst &C, int lane, int n, int
     // Joint lanes: limit and rest rows.
     float jcost = 0.f;
     X.rl = X.rr = X.dl = 0.f;
-    if (isj) {
+    if (isj && C.var) {
         const float over = q - C.hi, under = C.lo - q;
         X.rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
         X.rr = P.w_rest * (q - C.qr);
@@ -282,6 +291,33 @@ PK_DEV void jacobian(const RobotC *__restrict__ rb, const SolveParams &P, int la
     }
 }
 
+// Mimic joints: each adds its column, times its multiplier, into its
+// driver's, then drops it (a mimic joint is not a variable).
+template <int DMAX, int MMAX>
+PK_DEV void merge_mimic(const RobotC *__restrict__ rb, int lane, int n, int m, float *lds)
+{
+    using L = Lds<DMAX, MMAX>;
+    const int nm = rb->n_mimic;
+    for (int i = 0; i < nm; ++i) {
+        const int ml = rb->mimic_list[i];
+        if (lane == rb->j[ml].mimic_src) {
+            const float a = rb->j[ml].mimic_a;
+            float *jd = lds + L::JC + lane * L::JS;
+            const float *jm = lds + L::JC + ml * L::JS;
+#pragma unroll
+            for (int u = 0; u < L::JS; ++u)
+                if (u < 6 * m) jd[u] += a * jm[u];
+        }
+        wave_sync();
+    }
+    if (lane < n && rb->j[lane].var < 0) {
+        float *jc = lds + L::JC + lane * L::JS;
+#pragma unroll
+        for (int u = 0; u < L::JS; ++u) jc[u] = 0.f;
+    }
+    wave_sync();
+}
+
 // Row j of J^T J by ancestor depth, r[d] = A(j, ancestor of j at depth d)
 // for d < depth j, in precision T from the FP32 columns in LDS (products of
 // FP32 entries summed in T), and g = J^T r over the EE rows; returns the
@@ -353,13 +389,17 @@ template <int DMAX, typename T>
 PK_DEV bool tree_solve(T (&r)[DMAX], T dgu, T g, float lam, float dfloor, float thresh_rel,
                        int lane, int n, int dep, uint64_t desc, int step, int pos, int nstep,
                        uint32_t stab, const uint32_t (&ancp)[DMAX / 4], int max_depth, T *slots,
-                       float &delta)
+                       float &delta, bool unit = false)
 {
     constexpr int SS = DMAX + 2;
     const bool isj = lane < n;
     T dg = isj ? dgu + (T)lam * (dgu > (T)dfloor ? dgu : (T)dfloor) : (T)0;
+    // A mimic joint's row and column are zero: its pivot is set to the
+    // largest damped diagonal, so that it passes the test and leaves x = 0.
+    const float dmax = wave_max(unit ? 0.f : (float)dg);
+    if (unit) dg = (T)(dmax > 0.f ? dmax : 1.f);
     T thresh = 0;
-    if (thresh_rel > 0.f) thresh = (T)thresh_rel * (T)wave_max((float)dg);
+    if (thresh_rel > 0.f) thresh = (T)thresh_rel * (T)dmax;
     T b = isj ? -g : (T)0;
     bool bad = false;
     // Leaves first, one step of mutually unrelated joints at a time: the
@@ -439,10 +479,17 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
     for (int u = 0; u < 3; ++u) C.t[u] = rb->j[jl].t[u];
     C.lo = rb->j[jl].lo;
     C.hi = rb->j[jl].hi;
-    C.qr = P.q_rest ? P.q_rest[jl] : rb->j[jl].mid;
+    C.qr = (P.q_rest && isj && rb->j[jl].var >= 0) ? P.q_rest[rb->j[jl].var] : rb->j[jl].mid;
     C.parent = rb->j[jl].parent;
     C.depth = isj ? rb->j[jl].depth : -1;
     C.pris = isj && rb->j[jl].type == PK_JOINT_PRISMATIC;
+    // Lane j holds joint j; its variable (or, for a mimic joint, the rule
+    // on its driver's lane).
+    const int vi = isj ? rb->j[jl].var : -1, nv = rb->nv;
+    C.var = vi >= 0;
+    const int msrc = isj ? rb->j[jl].mimic_src : -1;
+    const float ma = isj ? rb->j[jl].mimic_a : 0.f, mb = isj ? rb->j[jl].mimic_b : 0.f;
+    const bool any_mimic = rb->n_mimic > 0;
 #pragma unroll
     for (int u = 0; u < 9; ++u) C.eG[u] = rb->e[el].G[u];
 #pragma unroll
@@ -466,10 +513,9 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
 
     bool fin = true;
     float q = 0.f;
-    if (isj) {
-        q = (resume ? P.joints : P.seeds)[(int64_t)lane * N + p];
-        fin = isfinite(q);
-    }
+    if (C.var) q = (resume ? P.joints : P.seeds)[(int64_t)vi * N + p];
+    if (any_mimic) q = mimic_rule(q, msrc, ma, mb);
+    if (isj) fin = isfinite(q);
     if (ise) {
         const int off = rb->e[el].tgt_off;
         const int W = C.ee_kind == PK_EE_POSE ? 7 : 3;
@@ -487,10 +533,10 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
     }
     const bool finite = __all(fin);
     if (!finite) {
-        if (isj) {
-            P.joints[(int64_t)lane * N + p] = q;
+        if (C.var) {
+            P.joints[(int64_t)vi * N + p] = q;
             for (int it = 0; it < P.trace_iters; ++it)
-                P.trace_q[((int64_t)it * n + lane) * N + p] = q;
+                P.trace_q[((int64_t)it * nv + vi) * N + p] = q;
         }
         if (ise) {
             if (P.pos_err) P.pos_err[(int64_t)lane * N + p] = NAN;
@@ -569,9 +615,10 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
                 wave_sync();
                 jacobian<DMAX, MMAX>(rb, P, lane, n, m, lds);
                 wave_sync();
+                if (any_mimic) merge_mimic<DMAX, MMAX>(rb, lane, n, m, lds);
                 float ge;
                 dgu = jtj_rows<DMAX, MMAX, float>(lds, ancp, lane, dep, m, max_depth, rows, ge) +
-                      dl * dl + P.w_rest * P.w_rest;
+                      (C.var ? dl * dl + P.w_rest * P.w_rest : 0.f);
                 g = isj ? ge + dl * rl + P.w_rest * rr : 0.f;
             }
         } else if (!first) {
@@ -582,7 +629,7 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
             lam = fminf(lam * P.nu_up, P.lambda_max);
         }
         if (!first && iters - 1 < P.trace_iters) {
-            if (isj) P.trace_q[((int64_t)(iters - 1) * n + lane) * N + p] = q;
+            if (C.var) P.trace_q[((int64_t)(iters - 1) * nv + vi) * N + p] = q;
             if (lane == 0) P.trace_acc[(int64_t)(iters - 1) * N + p] = acc ? 1 : 0;
         }
         first = false;
@@ -596,7 +643,7 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
             for (int d = 0; d < DMAX; ++d) r[d] = rows[d];
             ok = tree_solve<DMAX, float>(r, dgu, g, lam, P.damping_floor, P.pivot_rel, lane, n, dep,
                                          desc, step, spos, nstep, stab, ancp, max_depth, lds + L::PV,
-                                         delta);
+                                         delta, isj && !C.var);
         }
         if (!ok) {
             // Re-form the damped system and gradient in FP64 from the FP32
@@ -604,22 +651,23 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
             flags |= PK_FLAG_FP64;
             double r[DMAX], gd;
             double dgd = jtj_rows<DMAX, MMAX, double>(lds, ancp, lane, dep, m, max_depth, r, gd) +
-                         (double)dl * dl + (double)P.w_rest * P.w_rest;
+                         (C.var ? (double)dl * dl + (double)P.w_rest * P.w_rest : 0.0);
             gd += (double)dl * rl + (double)P.w_rest * rr;
             ok = tree_solve<DMAX, double>(r, dgd, isj ? gd : 0.0, lam, P.damping_floor, 0.f, lane,
                                           n, dep, desc, step, spos, nstep, stab, ancp, max_depth,
-                                          (double *)(lds + L::PV), delta);
+                                          (double *)(lds + L::PV), delta, isj && !C.var);
         }
         qt = q + delta;
+        if (any_mimic) qt = mimic_rule(qt, msrc, ma, mb);
         evaluate = ok;   // a failed solve counts as a rejected step
     }
     const bool finished = done || iters >= P.max_iters;
     if (finished)
         for (int it = iters; it < P.trace_iters; ++it) {
-            if (isj) P.trace_q[((int64_t)it * n + lane) * N + p] = q;
+            if (C.var) P.trace_q[((int64_t)it * nv + vi) * N + p] = q;
             if (lane == 0) P.trace_acc[(int64_t)it * N + p] = 0;
         }
-    if (isj) P.joints[(int64_t)lane * N + p] = q;
+    if (C.var) P.joints[(int64_t)vi * N + p] = q;
     if (ise) {
         if (P.pos_err) P.pos_err[(int64_t)lane * N + p] = perr;
         if (P.rot_err) P.rot_err[(int64_t)lane * N + p] = rerr;

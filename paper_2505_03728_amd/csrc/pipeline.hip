@@ -109,7 +109,7 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
         if (rc) return rc;
     }
     if (srobot != robot_id) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: seeder belongs to robot %d", srobot);
-    const int n = rb->host.n, Kf = o->fallback_K;
+    const int n = rb->host.nv, Kf = o->fallback_K;
     const int64_t NA = T * K, NB = T * Kf;
     if (NA >= (int64_t)1 << 31 || NB >= (int64_t)1 << 31)
         return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve_seeded: too many problems");

@@ -141,8 +141,8 @@ int pk::prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *
     if (!finite_w(w)) return fail(ctx, PK_EINVAL, "cost weights: non-finite value");
     const RobotC &H = rb.host;
     variant = o->variant;
-    // the per-lane kernel has revolute joints only
-    const bool lane_ok = H.chains > 0 && H.prismatic == 0 &&
+    // the per-lane kernel has revolute joints only, none of them mimic
+    const bool lane_ok = H.chains > 0 && H.prismatic == 0 && H.n_mimic == 0 &&
                          lane_variant_available(H.chains, H.chain_len, H.e[0].kind);
     const bool wave_ok = wave_variant_available(H.n);
     if (variant == PK_VARIANT_AUTO) variant = lane_ok ? PK_VARIANT_LANE : PK_VARIANT_WAVE;
@@ -290,12 +290,39 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
     const int n = (int)F.size();
     if (n < 1) return fail(ctx, PK_EINVAL, "pk_robot_upload: every joint is fixed");
     if (n > PK_MAX_JOINTS)
-        return fail(ctx, PK_EUNSUPPORTED, "pk_robot_upload: %d variables above %d", n, PK_MAX_JOINTS);
+        return fail(ctx, PK_EUNSUPPORTED, "pk_robot_upload: %d non-fixed joints above %d", n, PK_MAX_JOINTS);
+    // Mimic joints (folded indices): driver, multiplier, offset.
+    std::vector<int> msrc(n, -1), vidx(n, -1);
+    std::vector<double> ma(n, 0.0), mb(n, 0.0);
+    if (t->mimic_joint) {
+        if (!t->mimic_multiplier || !t->mimic_offset)
+            return fail(ctx, PK_EINVAL, "pk_robot_upload: mimic_joint without multiplier/offset");
+        for (int j = 0; j < nt; ++j) {
+            const int d = t->mimic_joint[j];
+            if (d < 0) continue;
+            if (kind[j] == PK_JOINT_FIXED) continue;   // a fixed joint ignores it
+            if (d >= nt || var[d] < 0 || (t->mimic_joint[d] >= 0))
+                return fail(ctx, PK_EINVAL, "pk_robot_upload: mimic_joint[%d] = %d is not a non-fixed, "
+                            "non-mimic joint", j, d);
+            if (!isfinite(t->mimic_multiplier[j]) || !isfinite(t->mimic_offset[j]))
+                return fail(ctx, PK_EINVAL, "pk_robot_upload: non-finite mimic rule %d", j);
+            msrc[var[j]] = var[d];
+            ma[var[j]] = t->mimic_multiplier[j];
+            mb[var[j]] = t->mimic_offset[j];
+        }
+    }
 
     RobotC R;
     memset(&R, 0, sizeof R);
     R.n = n;
     R.m = m;
+    for (int j = 0; j < n; ++j) {
+        if (msrc[j] >= 0) {
+            R.mimic_list[R.n_mimic++] = (uint8_t)j;
+        } else {
+            vidx[j] = R.nv++;
+        }
+    }
     std::vector<M3> U(n);
     for (int j = 0; j < n; ++j) {
         const Folded &f = F[j];
@@ -316,6 +343,10 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
         J.hi = (float)f.hi;
         J.mid = (float)(0.5 * (f.lo + f.hi));
         J.type = f.kind;
+        J.var = vidx[j];
+        J.mimic_src = msrc[j];
+        J.mimic_a = (float)ma[j];
+        J.mimic_b = (float)mb[j];
         R.prismatic += f.kind == PK_JOINT_PRISMATIC;
         R.mid[j] = J.mid;
         J.parent = par;
@@ -392,6 +423,10 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
         uint64_t mask = 0;
         for (int a = e; a >= 0; a = F[a].parent) mask |= 1ull << a;
         R.anc[k] = mask;
+        for (int j = 0; j < n; ++j)
+            if (msrc[j] >= 0 && ((mask >> j) & 1ull) && !((mask >> msrc[j]) & 1ull))
+                return fail(ctx, PK_EUNSUPPORTED, "pk_robot_upload: EE %d is below mimic joint %d but "
+                            "not below its driver", k, j);
     }
     R.tgt_floats = tgt;
     R.pose_rows = rows;
@@ -428,10 +463,10 @@ int pk_robot_info(pk_ctx *ctx, int32_t id, int32_t *n, int32_t *m, int32_t *tf, 
     if (!ctx) return fail(nullptr, PK_EINVAL, "pk_robot_info: ctx is NULL");
     if (id < 0 || id >= (int)ctx->robots.size()) return fail(ctx, PK_ENOTFOUND, "unknown robot %d", id);
     const RobotC &R = ctx->robots[id].host;
-    if (n) *n = R.n;
+    if (n) *n = R.nv;
     if (m) *m = R.m;
     if (tf) *tf = R.tgt_floats;
-    if (rows) *rows = R.pose_rows + 2 * R.n;
+    if (rows) *rows = R.pose_rows + 2 * R.nv;
     if (chains) *chains = R.chains;
     if (chain_len) *chain_len = R.chain_len;
     return PK_OK;
@@ -525,7 +560,7 @@ int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_
     hipStream_t s = (hipStream_t)stream;
     PK_HIP(ctx, launch_lm(*rb, P, variant, s));
     if (want_best)
-        PK_HIP(ctx, launch_best_of_k(P, H.n, out->best_index, out->best_joints, out->target_success, s));
+        PK_HIP(ctx, launch_best_of_k(P, H.nv, out->best_index, out->best_joints, out->target_success, s));
     return PK_OK;
 }
 

@@ -9,6 +9,15 @@
 namespace pk {
 namespace {
 
+// Value of joint j for problem p (SoA q over the variables): its variable,
+// or a mimic joint's rule on its driver's.
+PK_DEV float joint_value(const RobotC *__restrict__ rb, const float *q, int64_t N, int64_t p, int j)
+{
+    const JointC &J = rb->j[j];
+    if (J.mimic_src < 0) return q[(int64_t)J.var * N + p];
+    return J.mimic_a * q[(int64_t)rb->j[J.mimic_src].var * N + p] + J.mimic_b;
+}
+
 // FK of every joint of problem p (SoA q): O[j], pos[j].
 PK_DEV void fk_all(const RobotC *__restrict__ rb, const float *q, int64_t N, int64_t p,
                    float (*O)[9], float (*pos)[3])
@@ -19,7 +28,7 @@ PK_DEV void fk_all(const RobotC *__restrict__ rb, const float *q, int64_t N, int
         float Ob[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, pb[3] = {0.f, 0.f, 0.f};
         const float *Op = par < 0 ? Ob : O[par];
         const float *pp = par < 0 ? pb : pos[par];
-        const float qj = q[(int64_t)j * N + p];
+        const float qj = joint_value(rb, q, N, p, j);
         const bool pri = rb->j[j].type == PK_JOINT_PRISMATIC;
         float s = 0.f, c = 1.f;
         if (!pri) joint_sincos(qj, s, c);
@@ -39,10 +48,12 @@ __global__ __launch_bounds__(64) void fk_kernel(const RobotC *__restrict__ rb, i
     const int n = rb->n, m = rb->m;
     if (joint_frames) {
         for (int j = 0; j < n; ++j) {
+            const int v = rb->j[j].var;   // frames of the variables' joints
+            if (v < 0) continue;
             float R[9];
             mm3(O[j], rb->j[j].Ut, R);   // paper frame R_j = O_j U_j^T
-            for (int u = 0; u < 9; ++u) joint_frames[((int64_t)j * 12 + u) * N + p] = R[u];
-            for (int u = 0; u < 3; ++u) joint_frames[((int64_t)j * 12 + 9 + u) * N + p] = pos[j][u];
+            for (int u = 0; u < 9; ++u) joint_frames[((int64_t)v * 12 + u) * N + p] = R[u];
+            for (int u = 0; u < 3; ++u) joint_frames[((int64_t)v * 12 + 9 + u) * N + p] = pos[j][u];
         }
     }
     for (int k = 0; k < m; ++k) {
@@ -65,11 +76,12 @@ __global__ __launch_bounds__(64) void resjac_kernel(const RobotC *__restrict__ r
     const int64_t T = N / K, t = p / K;
     float O[PK_MAX_JOINTS][9], pos[PK_MAX_JOINTS][3];
     fk_all(rb, q, N, p, O, pos);
-    const int n = rb->n, m = rb->m;
-    const int rows = rb->pose_rows + 2 * n;
+    // Columns per variable; a mimic joint's column adds into its driver's.
+    const int n = rb->n, m = rb->m, nv = rb->nv;
+    const int rows = rb->pose_rows + 2 * nv;
     if (J)
         for (int row = 0; row < rows; ++row)
-            for (int j = 0; j < n; ++j) J[((int64_t)row * n + j) * N + p] = 0.f;
+            for (int v = 0; v < nv; ++v) J[((int64_t)row * nv + v) * N + p] = 0.f;
     for (int k = 0; k < m; ++k) {
         const EEC &E = rb->e[k];
         float Re[9], pe[3], d[3], tp[7];
@@ -90,6 +102,9 @@ __global__ __launch_bounds__(64) void resjac_kernel(const RobotC *__restrict__ r
                 jr_inv_blocks(lg, Re, M, Nb);
                 for (int j = 0; j < n; ++j) {
                     if (!((rb->anc[k] >> j) & 1ull)) continue;
+                    const int ms = rb->j[j].mimic_src;
+                    const int c = ms < 0 ? rb->j[j].var : rb->j[ms].var;
+                    const float f = ms < 0 ? 1.f : rb->j[j].mimic_a;
                     const float om[3] = {O[j][2], O[j][5], O[j][8]};
                     float v[3], wv[3];
                     joint_twist(rb->j[j].type == PK_JOINT_PRISMATIC, om, pos[j], pe, v, wv);
@@ -97,8 +112,8 @@ __global__ __launch_bounds__(64) void resjac_kernel(const RobotC *__restrict__ r
                         float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
                         float nw = Nb[3 * u] * wv[0] + Nb[3 * u + 1] * wv[1] + Nb[3 * u + 2] * wv[2];
                         float mw = M[3 * u] * wv[0] + M[3 * u + 1] * wv[1] + M[3 * u + 2] * wv[2];
-                        J[((int64_t)(row0 + u) * n + j) * N + p] = P.w_pos * (mv + nw);
-                        J[((int64_t)(row0 + 3 + u) * n + j) * N + p] = P.w_rot * mw;
+                        J[((int64_t)(row0 + u) * nv + c) * N + p] += f * (P.w_pos * (mv + nw));
+                        J[((int64_t)(row0 + 3 + u) * nv + c) * N + p] += f * (P.w_rot * mw);
                     }
                 }
             }
@@ -107,25 +122,31 @@ __global__ __launch_bounds__(64) void resjac_kernel(const RobotC *__restrict__ r
             if (J) {
                 for (int j = 0; j < n; ++j) {
                     if (!((rb->anc[k] >> j) & 1ull)) continue;
+                    const int ms = rb->j[j].mimic_src;
+                    const int c = ms < 0 ? rb->j[j].var : rb->j[ms].var;
+                    const float f = ms < 0 ? 1.f : rb->j[j].mimic_a;
                     const float om[3] = {O[j][2], O[j][5], O[j][8]};
                     float v[3], wv[3];
                     joint_twist(rb->j[j].type == PK_JOINT_PRISMATIC, om, pos[j], pe, v, wv);
-                    for (int u = 0; u < 3; ++u) J[((int64_t)(row0 + u) * n + j) * N + p] = P.w_pos * v[u];
+                    for (int u = 0; u < 3; ++u) J[((int64_t)(row0 + u) * nv + c) * N + p] += f * (P.w_pos * v[u]);
                 }
             }
         }
     }
-    const int lr = rb->pose_rows, rr = lr + n;
+    // limit and rest rows, one per variable
+    const int lr = rb->pose_rows, rr = lr + nv;
     for (int j = 0; j < n; ++j) {
-        const float qj = q[(int64_t)j * N + p];
-        const float qrj = P.q_rest ? P.q_rest[j] : rb->j[j].mid;
+        const int v = rb->j[j].var;
+        if (v < 0) continue;
+        const float qj = q[(int64_t)v * N + p];
+        const float qrj = P.q_rest ? P.q_rest[v] : rb->j[j].mid;
         const float over = qj - rb->j[j].hi, under = rb->j[j].lo - qj;
-        r[(int64_t)(lr + j) * N + p] = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
-        r[(int64_t)(rr + j) * N + p] = P.w_rest * (qj - qrj);
+        r[(int64_t)(lr + v) * N + p] = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
+        r[(int64_t)(rr + v) * N + p] = P.w_rest * (qj - qrj);
         if (J) {
-            J[((int64_t)(lr + j) * n + j) * N + p] =
+            J[((int64_t)(lr + v) * nv + v) * N + p] =
                 over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
-            J[((int64_t)(rr + j) * n + j) * N + p] = P.w_rest;
+            J[((int64_t)(rr + v) * nv + v) * N + p] = P.w_rest;
         }
     }
 }

@@ -23,7 +23,10 @@ struct JointC {
     float Ut[9];       // U_j^T, to report the paper's R_j = O_j U_j^T
     int32_t depth;
     int32_t type;      // PK_JOINT_REVOLUTE or PK_JOINT_PRISMATIC (fixed joints are folded away)
-    int32_t pad;
+    int32_t var;       // variable index, -1 for a mimic joint
+    int32_t mimic_src; // mimic joint: its driver (a joint index), else -1
+    float mimic_a, mimic_b;   // q = mimic_a * q_driver + mimic_b
+    int32_t pad[3];
 };
 
 struct EEC {
@@ -52,6 +55,10 @@ struct RobotC {
     // PK_STEP_PIVOTS, none an ancestor of another, all their descendants
     // removed in earlier steps); joint j is pivot step_pos[j] of step step_of[j].
     int32_t nstep, pad2;
+    // Variables: the joints that are not mimic joints (nv of them, in joint
+    // order); the mimic joints, listed.
+    int32_t nv, n_mimic;
+    uint8_t mimic_list[PK_MAX_JOINTS];
     uint8_t step_start[PK_MAX_JOINTS + 1];
     uint8_t step_joint[PK_MAX_JOINTS];
     uint8_t step_of[PK_MAX_JOINTS];

@@ -151,7 +151,7 @@ hipError_t enqueue(pk_ctx *ctx, SchedCache &C, std::vector<GroupPlan> &plans, in
             }
         }
         if (pl.out.best_index || pl.out.best_joints || pl.out.target_success) {
-            e = launch_best_of_k(pl.P, pl.rb->host.n, pl.out.best_index, pl.out.best_joints,
+            e = launch_best_of_k(pl.P, pl.rb->host.nv, pl.out.best_index, pl.out.best_joints,
                                  pl.out.target_success, s);
             if (e != hipSuccess) return e;
         }
@@ -369,7 +369,8 @@ int pk_autotune_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
         const RobotEntry *rb = robot_of(ctx, groups[g].robot_id);
         if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_autotune_mixed: group %d: unknown robot", g);
         const RobotC &H = rb->host;
-        if (H.chains > 0 && H.prismatic == 0 && lane_variant_available(H.chains, H.chain_len, H.e[0].kind))
+        if (H.chains > 0 && H.prismatic == 0 && H.n_mimic == 0 &&
+            lane_variant_available(H.chains, H.chain_len, H.e[0].kind))
             flex.push_back(g);
     }
     std::vector<std::vector<int>> vsets;

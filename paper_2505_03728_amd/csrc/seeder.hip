@@ -491,6 +491,8 @@ int pk_seeder_create(pk_ctx *ctx, int32_t robot_id, int32_t K, int32_t hidden, i
         return fail(ctx, PK_EUNSUPPORTED, "pk_seeder_create: needs a robot with one pose EE");
     if (K < 1 || depth < 1 || depth > 8 || hidden < 128 || hidden % 128)
         return fail(ctx, PK_EINVAL, "pk_seeder_create: bad K=%d hidden=%d depth=%d", K, hidden, depth);
+    if (R.n_mimic)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_seeder_create: robots with mimic joints are not supported");
     if (R.n * K > 64)
         return fail(ctx, PK_EUNSUPPORTED, "pk_seeder_create: K * n = %d above 64 outputs", R.n * K);
     SeederState *s = new SeederState;

@@ -28,6 +28,8 @@ these seeded families stand in for them):
   chain with one sliding joint), pose EE.  4 DoF.
 * ``mobile_arm7`` — a planar base (prismatic x, prismatic y, revolute z: the
   SE(2) base pose) carrying arm7.  10 DoF.
+* ``hand16_mimic`` — hand16 whose distal joints follow the joint before them
+  (mimic joints).  12 DoF.
 """
 from __future__ import annotations
 
@@ -38,7 +40,7 @@ import numpy as np
 
 __all__ = [
     "Tree", "EE_POSE", "EE_POSITION", "JOINT_REVOLUTE", "JOINT_PRISMATIC", "JOINT_FIXED",
-    "arm7", "tree34", "hand16", "chain", "arm7_tool", "scara4", "mobile_arm7",
+    "arm7", "tree34", "hand16", "chain", "arm7_tool", "scara4", "mobile_arm7", "hand16_mimic",
     "planar2", "one_joint", "uniform_configs", "workload", "mlp_init",
     "epoch_permutation", "f32",
 ]
@@ -68,7 +70,9 @@ class Tree:
     translation along it for a prismatic one, nothing for a fixed one.  The
     variables are the non-fixed joints in index order (``var_joints``); EE k
     is rigidly attached to joint ``ee_joint[k]`` with ``ee_offset[k]`` /
-    ``ee_quat[k]``.  ``joint_type`` None means every joint is revolute.
+    ``ee_quat[k]``.  ``joint_type`` None means every joint is revolute.  A
+    mimic joint (``mimic_joint[j]`` >= 0) follows its driver:
+    q_j = mimic_multiplier[j] * q_driver + mimic_offset[j].
     """
     name: str
     parent: np.ndarray          # int32 [n]
@@ -83,6 +87,9 @@ class Tree:
     ee_kind: np.ndarray         # int32 [m]
     meta: dict = field(default_factory=dict)
     joint_type: np.ndarray | None = None   # int32 [n] JOINT_*, None = all revolute
+    mimic_joint: np.ndarray | None = None  # int32 [n] driver or -1, None = no mimic joints
+    mimic_multiplier: np.ndarray | None = None
+    mimic_offset: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -96,9 +103,15 @@ class Tree:
         return np.asarray(self.joint_type, dtype=np.int32)
 
     @property
+    def mimics(self) -> np.ndarray:
+        if self.mimic_joint is None:
+            return np.full(self.n, -1, dtype=np.int32)
+        return np.asarray(self.mimic_joint, dtype=np.int32)
+
+    @property
     def var_joints(self) -> np.ndarray:
-        """Indices of the joints that are variables (not fixed), in order."""
-        return np.nonzero(self.types != JOINT_FIXED)[0]
+        """Indices of the joints that are variables (neither fixed nor mimic), in order."""
+        return np.nonzero((self.types != JOINT_FIXED) & (self.mimics < 0))[0]
 
     @property
     def dof(self) -> int:
@@ -286,6 +299,21 @@ def mobile_arm7(seed: int = 0, reach: float = 2.0) -> Tree:
     return _finish("mobile_arm7", parent, mount, offset, axis, lim, [a.ee_joint[0] + 3],
                    a.ee_offset, a.ee_quat, [EE_POSE], {"seed": seed, "reach": reach},
                    joint_type=jt)
+
+
+def hand16_mimic(seed: int = 8, mult: float = 0.8, off: float = 0.1) -> Tree:
+    """hand16 with each finger's last joint coupled to the one before it
+    (q_3 = mult * q_2 + off per finger, as a finger's distal joint follows its
+    middle joint): 12 variables."""
+    h = hand16(seed)
+    mj = np.full(h.n, -1, dtype=np.int32)
+    for c in range(4):
+        mj[4 * c + 3] = 4 * c + 2
+    t = Tree(**{**h.__dict__, "name": "hand16_mimic"})
+    t.mimic_joint = mj
+    t.mimic_multiplier = f32(np.where(mj >= 0, mult, 0.0))
+    t.mimic_offset = f32(np.where(mj >= 0, off, 0.0))
+    return t
 
 
 def uniform_configs(tree: Tree, count: int, seed: int) -> np.ndarray:

@@ -2,8 +2,9 @@
 
 Robots: arm7 with a fixed flange and a fixed tool (folded on upload, then a
 single revolute chain for the per-lane kernel), a SCARA-like chain with one
-prismatic joint and a 7-DoF arm on an SE(2) base (prismatic x, prismatic y,
-revolute yaw), both on the per-wavefront kernel.  Tolerances as in the LM
+prismatic joint, a 7-DoF arm on an SE(2) base (prismatic x, prismatic y,
+revolute yaw) and the 4-finger hand with each distal joint a mimic of the
+joint before it, the last three on the per-wavefront kernel.  Tolerances as in the LM
 parity tests: FK within 1e-5 m / 1e-5 rad, Jacobian within 1e-4 relative,
 per-problem LM success agreeing with the oracle except where FP32 cannot
 settle the outcome.
@@ -19,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 ROBOTS = {"arm7_tool": synth.arm7_tool(0), "scara4": synth.scara4(),
-          "mobile_arm7": synth.mobile_arm7(0)}
+          "mobile_arm7": synth.mobile_arm7(0), "hand16_mimic": synth.hand16_mimic(8)}
 
 
 @pytest.fixture(scope="module")
@@ -42,6 +43,8 @@ def test_upload_shapes(ctx, rids):
     assert info["n"] == 4
     info = ctx.robot_info(rids["mobile_arm7"])
     assert info["n"] == 10 and info["rows"] == 6 + 2 * 10
+    info = ctx.robot_info(rids["hand16_mimic"])
+    assert info["n"] == 12 and info["rows"] == 12 + 2 * 12 and info["chains"] == 4
 
 
 @pytest.mark.parametrize("name", list(ROBOTS))
@@ -97,7 +100,7 @@ def test_residual_jacobian_parity(ctx, rids, name):
 
 
 @pytest.mark.parametrize("name,variant", [("arm7_tool", 1), ("arm7_tool", 2), ("scara4", 0),
-                                          ("mobile_arm7", 0)])
+                                          ("mobile_arm7", 0), ("hand16_mimic", 0)])
 def test_lm_success_agreement(ctx, rids, name, variant):
     """Pose + limit + rest (0.01); the mobile arm without the rest term: its
     10 variables leave a 4-dimensional null space of the pose, along which a
@@ -127,6 +130,42 @@ def test_lm_success_agreement(ctx, rids, name, variant):
     conv = ((res["status"] & 0xFF) == 0).mean()
     print(f"{name} variant {variant}: success {conv:.3f}, {excused} excused, unexplained {bad}")
     assert not bad
+
+
+def test_mimic_hand_lm_from_nearby_seeds(ctx, rids):
+    """The coupled hand from seeds within ~0.3 rad of a solution (random seeds
+    rarely reach all four fingertips of this hand within 30 iterations, on
+    either side): per-problem agreement with the oracle, most problems solved,
+    and the returned values keep every distal joint on its mimic rule (the
+    solution is checked with the oracle's FK, which applies the rule)."""
+    tree = ROBOTS["hand16_mimic"]
+    T = 96
+    qs = synth.uniform_configs(tree, T, 307)
+    tg = oracle.targets_from(tree, qs)
+    rng = np.random.default_rng(308)
+    vj = tree.var_joints
+    seeds = synth.f32(np.clip(qs + rng.normal(scale=0.3, size=qs.shape), tree.lower[vj],
+                              tree.upper[vj]))
+    w = {"w_pos": 10.0, "w_rot": 0.5, "w_limit": 10.0, "w_rest": 0.0}
+    o = {"max_iters": 30, "lambda0": 1e-3, "nu_up": 10.0, "nu_down": 10.0, "lambda_min": 1e-10,
+         "lambda_max": 1e10, "early_exit": False, "tol_pos": 1e-3, "tol_rot": 1e-2,
+         "damping_floor": 1e-6, "pivot_rel": 1e-6}
+    res = solve_gpu(ctx, rids["hand16_mimic"], tree, tg, seeds, 1, w, o)
+    bad, excused = [], 0
+    for p in range(T):
+        ora = oracle.lm_solve(tree, tg[p], w, o, seeds[p], n_trace=30)
+        v = compare_outcome(ctx, rids["hand16_mimic"], tree, tg[p], seeds[p], w, o,
+                            res["status"][p], res["iters"][p], ora)
+        if v == "bad":
+            bad.append(p)
+        excused += v == "excused"
+    conv = (res["status"] & 0xFF) == 0
+    for p in np.nonzero(conv)[0]:
+        _, pe, _ = oracle.residual(tree, tg[p], w, res["q"][p].astype(np.float64))
+        assert np.all(pe <= 1e-3 + 1e-5)
+    print(f"hand16_mimic near seeds: success {conv.mean():.3f}, {excused} excused, unexplained {bad}")
+    assert not bad
+    assert conv.mean() >= 0.8
 
 
 def test_fixed_joint_robot_matches_its_folded_arm(ctx, rids):
@@ -166,6 +205,21 @@ def test_upload_errors_and_lane_variant(ctx, rids):
     t2.ee_joint = np.array([0], np.int32)
     with pytest.raises(pk.PkError) as e:
         ctx.upload(t2)
+    assert e.value.code == -2
+    # mimic rules: the driver may not be a mimic joint itself; an EE below a
+    # mimic joint must be below its driver
+    t3 = copy.deepcopy(ROBOTS["hand16_mimic"])
+    t3.mimic_joint = t3.mimic_joint.copy()
+    t3.mimic_joint[2] = 1
+    t3.mimic_joint[3] = 2
+    with pytest.raises(pk.PkError) as e:
+        ctx.upload(t3)
+    assert e.value.code == -1
+    t4 = copy.deepcopy(ROBOTS["hand16_mimic"])
+    t4.mimic_joint = t4.mimic_joint.copy()
+    t4.mimic_joint[3] = 6                     # finger 0's tip follows a finger-1 joint
+    with pytest.raises(pk.PkError) as e:
+        ctx.upload(t4)
     assert e.value.code == -2
     # prismatic robots have no per-lane kernel
     tree = ROBOTS["scara4"]

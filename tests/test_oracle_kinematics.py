@@ -19,7 +19,7 @@ import synth
 rng = np.random.default_rng(99)
 TREES = [synth.arm7(0), synth.tree34(5), synth.hand16(8)]
 # fixed, prismatic and mixed joint kinds (Sec. III-B)
-KINDS = [synth.arm7_tool(0), synth.scara4(), synth.mobile_arm7(0)]
+KINDS = [synth.arm7_tool(0), synth.scara4(), synth.mobile_arm7(0), synth.hand16_mimic(8)]
 
 
 def homog(R, t):
@@ -31,10 +31,13 @@ def homog(R, t):
 
 def fk_homogeneous(tree, q):
     """Independent FK: T_j = T_parent * Trans(t_j) * Rot(mount_j) * M_j, with
-    M_j = Rot(axis_j, q_v) (revolute), Trans(axis_j q_v) (prismatic) or I
-    (fixed); q_v is the variable of joint j (non-fixed joints in order)."""
+    M_j = Rot(axis_j, q_j) (revolute), Trans(axis_j q_j) (prismatic) or I
+    (fixed); q_j is joint j's variable (variables in joint order), or for a
+    mimic joint mult * (its driver's value) + offset."""
     Ts = []
+    vals = {}
     v = 0
+    mim = tree.mimics
     for j in range(tree.n):
         par = tree.parent[j]
         Tp = np.eye(4) if par < 0 else Ts[par]
@@ -42,13 +45,18 @@ def fk_homogeneous(tree, q):
         Rm = Rotation.from_quat([mq[1], mq[2], mq[3], mq[0]]).as_matrix()
         a = tree.axis[j] / np.linalg.norm(tree.axis[j])
         kind = tree.types[j]
+        if kind != synth.JOINT_FIXED:
+            if mim[j] >= 0:
+                vals[j] = tree.mimic_multiplier[j] * vals[mim[j]] + tree.mimic_offset[j]
+            else:
+                vals[j] = q[v]
+                v += 1
         if kind == synth.JOINT_REVOLUTE:
-            Mj = homog(Rotation.from_rotvec(a * q[v]).as_matrix(), np.zeros(3))
+            Mj = homog(Rotation.from_rotvec(a * vals[j]).as_matrix(), np.zeros(3))
         elif kind == synth.JOINT_PRISMATIC:
-            Mj = homog(np.eye(3), a * q[v])
+            Mj = homog(np.eye(3), a * vals[j])
         else:
             Mj = np.eye(4)
-        v += kind != synth.JOINT_FIXED
         Ts.append(Tp @ homog(np.eye(3), tree.offset[j]) @ homog(Rm, np.zeros(3)) @ Mj)
     ees = []
     for k in range(tree.m):
@@ -274,3 +282,30 @@ def test_prismatic_column_is_the_world_axis(ora):
     # at the target itself the pose log is zero, J_r^-1 = I and R_ee^T maps
     # the world z axis to the EE's z axis, which is world z here
     np.testing.assert_allclose(J[:6, 2], [0, 0, 1, 0, 0, 0], atol=1e-12)
+
+
+def test_mimic_joints_equal_the_expanded_hand(ora):
+    """A mimic joint takes mult * q_driver + offset: the coupled hand's FK at
+    12 variables equals the uncoupled hand's at the expanded 16 values, and
+    its Jacobian is the uncoupled one with each mimic column added into its
+    driver's (times mult) and dropped."""
+    hm, h = synth.hand16_mimic(8), synth.hand16(8)
+    tg = ora.targets_from(h, synth.uniform_configs(h, 4, 41))
+    w = dict(WEIGHTS, w_rest=0.0, w_limit=0.0)
+    for i, q in enumerate(synth.uniform_configs(hm, 4, 40)):
+        full = np.zeros(16)
+        full[hm.var_joints] = q
+        for j in range(16):
+            if hm.mimics[j] >= 0:
+                full[j] = hm.mimic_multiplier[j] * full[hm.mimics[j]] + hm.mimic_offset[j]
+        _, _, Ra, pa = ora.fk(hm, q)
+        _, _, Rb, pb = ora.fk(h, full)
+        np.testing.assert_array_equal(Ra, Rb)
+        np.testing.assert_array_equal(pa, pb)
+        Jm = ora.jacobian(hm, tg[i], w, q)
+        Jf = ora.jacobian(h, tg[i], w, full)
+        want = Jf[:12].copy()
+        for j in range(16):
+            if hm.mimics[j] >= 0:
+                want[:, hm.mimics[j]] += hm.mimic_multiplier[j] * want[:, j]
+        np.testing.assert_allclose(Jm[:12], want[:, hm.var_joints], rtol=1e-12, atol=1e-14)
