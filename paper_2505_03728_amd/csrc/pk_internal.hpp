@@ -26,8 +26,9 @@ struct JointC {
     int32_t var;       // variable index, -1 for a mimic joint
     int32_t mimic_src; // mimic joint: its driver (a joint index), else -1
     float mimic_a, mimic_b;   // q = mimic_a * q_driver + mimic_b
-    int32_t pad[3];
+    int32_t pad;       // 128 bytes per joint: every joint's fields keep the same alignment
 };
+static_assert(sizeof(JointC) == 128, "JointC is 128 bytes");
 
 struct EEC {
     float G[9];        // U_e^T R_eeoff
