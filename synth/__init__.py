@@ -355,7 +355,12 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
                       U[-1, 1]^2 m; mobile_arm7 (base pose free) x 4 seeds
                       with the base at the origin, and the same targets for
                       arm7 alone (fixed base); pose+limit, 30 iterations,
-                      success at 5 mm / 0.05 rad.
+                      success at 5 mm / 0.05 rad;
+      * ``traj``    — trajectory optimisation on arm7: 1024 trajectories of
+                      32 timesteps (dt 0.05 s) between the poses of two
+                      random configurations, initialised by linear
+                      interpolation between perturbed endpoint
+                      configurations plus a sine bump; 20 iterations.
     ``targets`` overrides the target count (a prefix of the same draws).
     Returns q* (configurations whose FK are the targets) and seeds; the caller
     computes the target poses with its own FK.
@@ -418,6 +423,25 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
         return {"groups": [{"tree": mob, "q_star": q_star, "K": K, "seeds": seeds}],
                 "fixed_base": {"tree": arm, "seeds": seeds_arm},
                 "weights": _weights(), "options": o}
+    if name == "traj":
+        r = arm7(0)
+        B = targets or int(1024 * scale)
+        T = 32
+        qa = uniform_configs(r, B, 25)
+        qb = uniform_configs(r, B, 26)
+        rng = np.random.Generator(np.random.PCG64(27))
+        ea = rng.normal(0.0, 0.05, size=(B, r.dof))
+        eb = rng.normal(0.0, 0.05, size=(B, r.dof))
+        u = rng.normal(0.0, 1.0, size=(B, r.dof))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        s_ = np.linspace(0.0, 1.0, T)[None, :, None]
+        init = ((1 - s_) * (qa + ea)[:, None, :] + s_ * (qb + eb)[:, None, :] +
+                0.3 * np.sin(np.pi * s_) * u[:, None, :])
+        costs = {"T": T, "dt": 0.05, "w_pos": 10.0, "w_rot": 5.0, "w_limit": 10.0,
+                 "w_smooth": 0.1, "w_vel": 1.0, "vmax": [2.0] * r.dof, "w_acc": 0.05,
+                 "w_jerk": 0.01}
+        return {"tree": r, "start_q": qa, "goal_q": qb, "init": f32(init), "costs": costs,
+                "options": _options(20)}
     if name == "seeder":
         r = arm7(0)
         S = int(2_000_000 * scale)

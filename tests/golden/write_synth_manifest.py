@@ -31,6 +31,8 @@ def manifest():
         for i, g in enumerate(w["groups"]):
             out[f"{wl}.{i}.q_star"] = digest(g["q_star"])
             out[f"{wl}.{i}.seeds"] = digest(g["seeds"])
+    tr = synth.workload("traj", targets=4)
+    out["traj.init"] = digest(tr["init"])
     out["mlp_init.small"] = digest(np.concatenate([np.r_[W.ravel(), b] for W, b in
                                                    synth.mlp_init([7, 16, 16, 14], 18)]))
     out["perm.100.e0"] = digest(synth.epoch_permutation(100, 19, 0))
