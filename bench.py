@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--targets", type=int, default=16384)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--workload", default="arm131k",
-                    choices=["arm131k", "tree4k", "mixed84k", "seeder", "beam", "mobile"])
+                    choices=["arm131k", "tree4k", "mixed84k", "seeder", "beam", "mobile", "traj"])
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
@@ -105,7 +105,7 @@ def main():
         sys.exit(2)
     if args.workload != "arm131k":
         {"tree4k": run_tree, "mixed84k": run_mixed, "seeder": run_seeder,
-         "beam": run_beam, "mobile": run_mobile}[args.workload](args)
+         "beam": run_beam, "mobile": run_mobile, "traj": run_traj}[args.workload](args)
         return
     import numpy as np
     import torch
@@ -639,6 +639,78 @@ def run_mobile(args):
                                             "K": K}], wl["weights"], wl["options"], args.cpu_seconds)
         res["cpu_baseline"] = {"value": rate, "unit": "solves/s", "cores": th, "kind": "oracle",
                                "sample": f"first {done} of {T} targets x {K} seeds, {el:.1f} s"}
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+FP64_VALU_PEAK = 78.6       # TFLOP/s, MI355X FP64 vector (datasheet)
+
+
+def traj_solve_flops(V, hb):
+    """Algorithmic FLOPs of one damped band solve: band Cholesky (column scale
+    and trailing update) plus the two triangular solves, V variables,
+    half-bandwidth hb (divisions and square roots counted as one)."""
+    f = 0
+    for j in range(V):
+        w = min(hb, V - 1 - j)
+        f += 1 + w + w * (w + 1) + 4 * w + 2
+    return f
+
+
+def run_traj(args):
+    """Trajectory optimisation: 1024 arm trajectories x 32 timesteps, 20 LM
+    iterations, one wavefront per trajectory (banded FP64 normal equations)."""
+    import numpy as np
+    import torch
+
+    import paper_2505_03728_amd as pk
+    import synth
+    wl = synth.workload("traj")
+    tree, c, o = wl["tree"], wl["costs"], wl["options"]
+    B, T, n = wl["init"].shape
+    ctx = pk.Context(0)
+    rid = ctx.upload(tree)
+    st = _dev_targets(ctx, rid, tree, wl["start_q"])
+    gl = _dev_targets(ctx, rid, tree, wl["goal_q"])
+    init = torch.from_numpy(np.ascontiguousarray(wl["init"], dtype=np.float32)).cuda()
+    vmax = torch.tensor(c["vmax"], dtype=torch.float32, device="cuda")
+    opt = pk.Options.from_dict(o)
+    out = ctx.traj_solve(rid, st, gl, init, c, opt, vmax=vmax)
+    ms = _time(lambda: ctx.traj_solve(rid, st, gl, init, c, opt, vmax=vmax, out=out), args.steps,
+               args.warmup)
+    succ = float(((out["status"] & 0xFF) == 0).float().mean())
+    iters = int(out["iters"].sum())
+    flops = iters * traj_solve_flops(T * n, 4 * n)
+    ach = flops / (ms / 1e3) / 1e12
+    res = _line("optimised trajectories/sec", B / (ms / 1e3), "trajectories/s", args, ms,
+                {"workload": f"trajectory optimisation on the 7-DoF arm: {B} trajectories x {T} "
+                             f"timesteps (dt {c['dt']} s), start/goal pose + limit + smoothness + "
+                             f"velocity limit + five-point acceleration and jerk, "
+                             f"{o['max_iters']} LM iterations", "trajectories": B, "timesteps": T},
+                dtype="f64 (normal equations) / f32 (kinematics)", success_rate=succ,
+                roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP64_VALU_PEAK,
+                          "unit": "TFLOP/s", "frac": round(ach / FP64_VALU_PEAK, 6), "traffic": None,
+                          "kernel": "traj_kernel<7>", "kernel_ms": round(ms, 5),
+                          "algorithmic_flops": flops,
+                          "count": "band Cholesky + two triangular solves per LM iteration"})
+    if not args.no_cpu:
+        import oracle
+        from oracle import traj
+        from threadpoolctl import threadpool_limits
+        st_o = oracle.targets_from(tree, wl["start_q"])
+        gl_o = oracle.targets_from(tree, wl["goal_q"])
+        done = 0
+        el = 0.0
+        with threadpool_limits(1):
+            while done < B and el < args.cpu_seconds:
+                t0 = time.perf_counter()
+                traj.lm_solve(tree, st_o[done], gl_o[done], c, o, wl["init"][done])
+                el += time.perf_counter() - t0
+                done += 1
+        res["cpu_baseline"] = {"value": done / el if el else 0.0, "unit": "trajectories/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {done} of {B} trajectories, FP64 dense LM "
+                                         f"(numpy, one thread), {el:.1f} s"}
     print(json.dumps(res), flush=True)
     ctx.close()
 

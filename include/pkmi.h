@@ -392,6 +392,55 @@ int pk_ik_beam(pk_ctx *ctx, int32_t robot_id, int64_t n_targets, const float *ta
                const float *seeds, const pk_cost_weights *w, const pk_lm_options *opt,
                const pk_beam_schedule *sched, const pk_beam_outputs *out, void *stream);
 
+/* ------------------------------------------------- trajectory optimisation
+ * LM over trajectories of T configurations (Sec. II: each configuration
+ * interacts only with its temporal neighbours; Sec. III-C costs).  Per
+ * trajectory the variables are q_0 .. q_{T-1} (n each, time-major) and the
+ * weighted residual rows are
+ *   start pose: log(T_start^-1 T_ee(q_0)) as in pk_cost_weights (w_pos, w_rot),
+ *   goal pose:  the same at q_{T-1},
+ *   limits:     w_limit (max(0, q - upper) + max(0, lower - q)) at every t,
+ *   smoothness: w_smooth (q_t - q_{t-1}), t = 1 .. T-1,
+ *   velocity:   w_vel max(0, |q_t - q_{t-1}| - vmax dt), t = 1 .. T-1,
+ *   acceleration: w_acc (-q_{t-2} + 16 q_{t-1} - 30 q_t + 16 q_{t+1} - q_{t+2}) / (12 dt^2),
+ *   jerk:       w_jerk (-q_{t-2} + 2 q_{t-1} - 2 q_{t+1} + q_{t+2}) / (2 dt^3),
+ *               both t = 2 .. T-3 (five-point stencils).
+ * The LM controller is pk_ik_solve's (pk_lm_options; success = both
+ * endpoint poses within tol_pos / tol_rot).  J^T J is banded with
+ * half-bandwidth 4n; it is formed and factored in FP64 (a pivot not above
+ * pivot_rel times the largest damped diagonal rejects the step).  Robots: one chain of 4, 6, 7 or 10 joints (revolute or
+ * prismatic, no mimic joints) with one pose EE; T >= 5 and T * n <= 256.
+ * Asynchronous on `stream`.  Errors: PK_EINVAL (NULL pointer, bad sizes or
+ * costs), PK_EUNSUPPORTED (robot shape). */
+typedef struct {
+    int64_t B;                       /* trajectories                              */
+    int32_t T;                       /* timesteps                                 */
+    const float *start;              /* device [7][B]: p, quaternion wxyz          */
+    const float *goal;               /* device [7][B]                              */
+    const float *init;               /* device [B][T][n] initial trajectories      */
+} pk_traj_problem;
+
+typedef struct {
+    float dt;                        /* seconds between configurations            */
+    float w_pos, w_rot;              /* start / goal pose rows                    */
+    float w_limit, w_smooth, w_vel, w_acc, w_jerk;
+    const float *vmax;               /* device [n] velocity limits, or NULL: no velocity rows */
+} pk_traj_costs;
+
+typedef struct {
+    float *traj;                     /* [B][T][n] required                        */
+    float *cost;                     /* [B] final sum of squared residuals        */
+    int32_t *iters;                  /* [B]                                       */
+    int32_t *accepts;                /* [B]                                       */
+    int32_t *status;                 /* [B] PK_CONVERGED / PK_MAX_ITERS / PK_STALLED */
+    float *pos_err;                  /* [2][B] start, goal                        */
+    float *rot_err;                  /* [2][B]                                    */
+} pk_traj_outputs;
+
+int pk_traj_solve(pk_ctx *ctx, int32_t robot_id, const pk_traj_problem *problem,
+                  const pk_traj_costs *costs, const pk_lm_options *opt,
+                  const pk_traj_outputs *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -103,6 +103,23 @@ class _BeamOutputs(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in _BEAM_OUT]
 
 
+class _TrajProblem(C.Structure):
+    _fields_ = [("B", C.c_int64), ("T", C.c_int32), ("start", C.c_void_p), ("goal", C.c_void_p),
+                ("init", C.c_void_p)]
+
+
+class _TrajCosts(C.Structure):
+    _fields_ = [(k, C.c_float) for k in ["dt", "w_pos", "w_rot", "w_limit", "w_smooth", "w_vel",
+                                         "w_acc", "w_jerk"]] + [("vmax", C.c_void_p)]
+
+
+_TRAJ_OUT = ["traj", "cost", "iters", "accepts", "status", "pos_err", "rot_err"]
+
+
+class _TrajOutputs(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in _TRAJ_OUT]
+
+
 class _Group(C.Structure):
     _fields_ = [("robot_id", C.c_int32), ("problem", _Problem), ("weights", _Weights),
                 ("out", _Outputs)]
@@ -157,13 +174,15 @@ def lib():
                                         C.POINTER(_Sched), C.POINTER(C.c_float), vp]
         L.pk_ik_beam.argtypes = [vp, i32, i64, vp, vp, C.POINTER(_Weights), C.POINTER(_Options),
                                  C.POINTER(_BeamSchedule), C.POINTER(_BeamOutputs), vp]
+        L.pk_traj_solve.argtypes = [vp, i32, C.POINTER(_TrajProblem), C.POINTER(_TrajCosts),
+                                    C.POINTER(_Options), C.POINTER(_TrajOutputs), vp]
         for f in ["pk_create", "pk_destroy", "pk_robot_upload", "pk_robot_info", "pk_fk",
                   "pk_residual_jacobian", "pk_ik_solve", "pk_seeder_create",
                   "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward",
                   "pk_seeder_forward_layers", "pk_seeder_grad", "pk_seeder_train",
                   "pk_seeder_infer", "pk_seeder_save",
                   "pk_seeder_load", "pk_ik_solve_seeded", "pk_ik_solve_mixed",
-                  "pk_autotune_mixed", "pk_ik_beam"]:
+                  "pk_autotune_mixed", "pk_ik_beam", "pk_traj_solve"]:
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -176,7 +195,8 @@ def exported_symbols():
             "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward",
             "pk_seeder_forward_layers", "pk_seeder_grad",
             "pk_seeder_train", "pk_seeder_infer", "pk_seeder_save", "pk_seeder_load",
-            "pk_ik_solve_seeded", "pk_ik_solve_mixed", "pk_autotune_mixed", "pk_ik_beam"]
+            "pk_ik_solve_seeded", "pk_ik_solve_mixed", "pk_autotune_mixed", "pk_ik_beam",
+            "pk_traj_solve"]
 
 
 class Weights:
@@ -442,6 +462,30 @@ class Context:
         w, op = weights._c(), options._c()
         self._call(lib().pk_ik_beam(self._h, rid, T, _ptr(targets), _ptr(seeds), C.byref(w),
                                     C.byref(op), C.byref(sch), C.byref(oo), self.stream()))
+        return out
+
+    def traj_solve(self, rid, start, goal, init, costs: dict, options: Options, vmax=None,
+                   out=None):
+        """Trajectory optimisation (see include/pkmi.h): start / goal [7, B] poses,
+        init [B, T, n] (cuda float32); costs: dt, w_pos, w_rot, w_limit, w_smooth,
+        w_vel, w_acc, w_jerk; vmax: cuda [n] or None.  Returns a dict of device
+        tensors traj [B, T, n], cost, iters, accepts, status [B], pos_err /
+        rot_err [2, B]."""
+        torch = self._torch
+        B, T, n = init.shape
+        dev = init.device
+        if out is None:
+            f = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+            i = lambda *s: torch.empty(s, dtype=torch.int32, device=dev)
+            out = {"traj": f(B, T, n), "cost": f(B), "iters": i(B), "accepts": i(B),
+                   "status": i(B), "pos_err": f(2, B), "rot_err": f(2, B)}
+        pr = _TrajProblem(B, T, _ptr(start), _ptr(goal), _ptr(init))
+        c = _TrajCosts(*[float(costs[k]) for k in ["dt", "w_pos", "w_rot", "w_limit", "w_smooth",
+                                                    "w_vel", "w_acc", "w_jerk"]], _ptr(vmax))
+        oo = _TrajOutputs(*[_ptr(out.get(k)) for k in _TRAJ_OUT])
+        op = options._c()
+        self._call(lib().pk_traj_solve(self._h, rid, C.byref(pr), C.byref(c), C.byref(op),
+                                       C.byref(oo), self.stream()))
         return out
 
     def ik_solve(self, rid, targets, seeds, K, weights: Weights, options: Options, out):

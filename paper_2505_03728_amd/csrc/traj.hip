@@ -1,0 +1,512 @@
+// Trajectory optimisation: LM over a trajectory of T configurations of a
+// single-chain robot (Sec. II: a configuration interacts only with its
+// temporal neighbours, so the normal equations are banded).  One trajectory
+// per 64-lane wavefront:
+//   * lanes 0 and 1 run FK, the pose log and the pose Jacobian at the first
+//     and the last configuration (start and goal pose costs);
+//   * every lane takes its share of the T*n variables for the limit,
+//     smoothness, velocity-limit and five-point acceleration/jerk terms;
+//   * J^T J is banded (half-bandwidth 4n in time-major order): it is formed
+//     straight into a band in LDS, damped, factored by a right-looking band
+//     Cholesky (the trailing update of each column spread over the lanes)
+//     and solved, all in FP64: the jerk rows outweigh the smoothness rows by
+//     ~1e5 in J^T J, and at that conditioning an FP32 factorisation steers LM
+//     off the FP64 path (FP64 FMAs issue at the unpacked FP32 rate).
+#include <string.h>
+
+#include <cmath>
+
+#include "pk_ctx.hpp"
+#include "pk_device.hpp"
+
+namespace pk {
+namespace {
+
+constexpr int TRAJ_VMAX = 256;   // T * n variables per trajectory
+
+struct TrajParams {
+    int64_t B;
+    int T;
+    float dt, w_pos, w_rot, w_limit, w_smooth, w_vel, w_acc, w_jerk;
+    const float *vmax;                 // [n] or null (no velocity-limit term)
+    const float *start, *goal;         // [7][B]: p, quaternion wxyz
+    const float *init;                 // [B][T][n]
+    float *out;                        // [B][T][n]
+    float *cost, *pos_err, *rot_err;   // [B], [2][B], [2][B]
+    int32_t *iters, *accepts, *status;
+    float lambda0, nu_up, nu_down, lambda_min, lambda_max, tol_pos, tol_rot, damping_floor,
+        pivot_rel;
+    int max_iters, early_exit;
+};
+
+// Five-point stencils on offsets -2..2: second derivative times dt^2 and
+// third derivative times dt^3.
+__constant__ float ACC5[5] = {-1.f / 12.f, 16.f / 12.f, -30.f / 12.f, 16.f / 12.f, -1.f / 12.f};
+__constant__ float JERK5[5] = {-0.5f, 1.f, 0.f, -1.f, 0.5f};
+
+template <int NJ>
+struct TrajLds {
+    static constexpr int HB = 4 * NJ, W = HB + 1;
+    static constexpr int NPAIR = HB * (HB + 1) / 2;
+    double band[TRAJ_VMAX * W];
+    double b[TRAJ_VMAX];
+    float Q[TRAJ_VMAX], Qt[TRAJ_VMAX];
+    float J0[6 * NJ], J1[6 * NJ], r0[6], r1[6];        // pose rows at the current point
+    float Jt0[6 * NJ], Jt1[6 * NJ], rt0[6], rt1[6];    // ... at the trial point
+    float err[4], errt[4];                             // pos/rot errors (start, goal)
+    uint8_t pair[2 * NPAIR];                           // (di, dk), 1 <= dk <= di <= HB
+};
+
+PK_DEV float wsum(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+PK_DEV float wmax(float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// FK of the chain at q (NJ values), the pose residual rows against target
+// tp (p, quaternion) and, with jac, the weighted pose Jacobian [6][NJ].
+template <int NJ>
+PK_DEV void endpoint(const RobotC *__restrict__ rb, const TrajParams &P, const float *q,
+                     const float *tp, float *r6, float *J, float &perr, float &rerr)
+{
+    float O[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, p[3] = {0.f, 0.f, 0.f};
+    float om[NJ][3], pj[NJ][3];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        const bool pri = rb->j[i].type == PK_JOINT_PRISMATIC;
+        float s = 0.f, c = 1.f, On[9], pn[3];
+        if (!pri) joint_sincos(q[i], s, c);
+        joint_step(O, p, rb->j[i].G, rb->j[i].t, s, c, On, pn);
+        if (pri) joint_slide(On, q[i], pn);
+#pragma unroll
+        for (int u = 0; u < 9; ++u) O[u] = On[u];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            p[u] = pn[u];
+            om[i][u] = O[3 * u + 2];
+            pj[i][u] = p[u];
+        }
+    }
+    float Re[9], pe[3], Rt[9], d[3];
+    ee_frame(O, p, rb->e[0].G, rb->e[0].t, Re, pe);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) d[u] = pe[u] - tp[u];
+    perr = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    quat_to_rot(tp[3], tp[4], tp[5], tp[6], Rt);
+    const PoseLog lg = pose_log(Rt, Re, d);
+    rerr = lg.theta;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        r6[u] = P.w_pos * lg.rho[u];
+        r6[3 + u] = P.w_rot * lg.phi[u];
+    }
+    float M[9], Nb[9];
+    jr_inv_blocks(lg, Re, M, Nb);
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        float v[3], w[3];
+        joint_twist(rb->j[i].type == PK_JOINT_PRISMATIC, om[i], pj[i], pe, v, w);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
+            const float nw = Nb[3 * u] * w[0] + Nb[3 * u + 1] * w[1] + Nb[3 * u + 2] * w[2];
+            const float mw = M[3 * u] * w[0] + M[3 * u + 1] * w[1] + M[3 * u + 2] * w[2];
+            J[u * NJ + i] = P.w_pos * (mv + nw);
+            J[(3 + u) * NJ + i] = P.w_rot * mw;
+        }
+    }
+}
+
+// Per-variable pieces at Q: limit residual and derivative, and the
+// velocity-limit residual and sign of the step into timestep t.
+template <int NJ>
+PK_DEV void limit_row(const RobotC *__restrict__ rb, const TrajParams &P, float q, int i, float &rl,
+                      float &dl)
+{
+    const float over = q - rb->j[i].hi, under = rb->j[i].lo - q;
+    rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
+    dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
+}
+
+PK_DEV void vel_row(const TrajParams &P, const float *Q, int v, int n, int i, float &rv, float &sv)
+{
+    const float d = Q[v] - Q[v - n];
+    const float ex = fabsf(d) - P.vmax[i] * P.dt;
+    rv = ex > 0.f ? P.w_vel * ex : 0.f;
+    sv = ex > 0.f ? (d > 0.f ? P.w_vel : -P.w_vel) : 0.f;
+}
+
+PK_DEV float acc_row(const TrajParams &P, const float *Q, int v, int n)
+{
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a += ACC5[k] * Q[v + (k - 2) * n];
+    return a * (P.w_acc / (P.dt * P.dt));
+}
+
+PK_DEV float jerk_row(const TrajParams &P, const float *Q, int v, int n)
+{
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a += JERK5[k] * Q[v + (k - 2) * n];
+    return a * (P.w_jerk / (P.dt * P.dt * P.dt));
+}
+
+// Sum of squares of the non-pose rows at Q (every lane; wave total).
+template <int NJ>
+PK_DEV float path_cost(const RobotC *__restrict__ rb, const TrajParams &P, const float *Q, int lane)
+{
+    const int T = P.T, V = T * NJ;
+    float s = 0.f;
+    for (int v = lane; v < V; v += 64) {
+        const int t = v / NJ, i = v - t * NJ;
+        float rl, dl;
+        limit_row<NJ>(rb, P, Q[v], i, rl, dl);
+        s += rl * rl;
+        if (t >= 1) {
+            const float rs = P.w_smooth * (Q[v] - Q[v - NJ]);
+            s += rs * rs;
+            if (P.vmax) {
+                float rv, sv;
+                vel_row(P, Q, v, NJ, i, rv, sv);
+                s += rv * rv;
+            }
+        }
+        if (t >= 2 && t <= T - 3) {
+            const float ra = acc_row(P, Q, v, NJ), rj = jerk_row(P, Q, v, NJ);
+            s += ra * ra + rj * rj;
+        }
+    }
+    return wsum(s);
+}
+
+// Band of A + lambda diag(max(A_vv, floor)) and the right-hand side -J^T r at
+// the current point, in precision T: A(v, v - k) at band[v * W + k].
+template <int NJ, typename T>
+PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, const TrajLds<NJ> &S,
+                        float lam, int lane, T *band, T *rhs)
+{
+    constexpr int W = TrajLds<NJ>::W;
+    const int TT = P.T, V = TT * NJ;
+    const T ws2 = (T)P.w_smooth * (T)P.w_smooth;
+    const T sa = (T)P.w_acc / ((T)P.dt * (T)P.dt), sj = (T)P.w_jerk / ((T)P.dt * (T)P.dt * (T)P.dt);
+    for (int e = lane; e < V * W; e += 64) {
+        const int v = e / W, k = e - v * W;
+        const int u = v - k;
+        T a = 0;
+        if (u >= 0) {
+            const int t = v / NJ, i = v - t * NJ;
+            const int t2 = u / NJ, i2 = u - t2 * NJ;
+            if (i2 == i) {
+                const int dtk = t - t2;   // 0..4
+                if (dtk == 0) {
+                    float rl, dl;
+                    limit_row<NJ>(rb, P, S.Q[v], i, rl, dl);
+                    a += (T)dl * (T)dl;
+                }
+                // smoothness rows q_tau - q_{tau-1}, tau = 1..T-1
+                if (dtk == 0) a += (t >= 1 ? ws2 : (T)0) + (t <= TT - 2 ? ws2 : (T)0);
+                if (dtk == 1) a -= ws2;
+                // velocity-limit rows, where active
+                if (P.vmax) {
+                    float rv, sv, rv1 = 0.f, sv1 = 0.f;
+                    rv = sv = 0.f;
+                    if (t >= 1) vel_row(P, S.Q, v, NJ, i, rv, sv);
+                    if (t + 1 <= TT - 1) vel_row(P, S.Q, v + NJ, NJ, i, rv1, sv1);
+                    if (dtk == 0) a += (T)sv * (T)sv + (T)sv1 * (T)sv1;
+                    if (dtk == 1) a -= (T)sv * (T)sv;
+                }
+                // acceleration and jerk rows centred at tc = 2..T-3
+                for (int tc = t - 2; tc <= t2 + 2; ++tc) {
+                    if (tc < 2 || tc > TT - 3) continue;
+                    const int o1 = t - tc + 2, o2 = t2 - tc + 2;
+                    a += sa * sa * (T)ACC5[o1] * (T)ACC5[o2] + sj * sj * (T)JERK5[o1] * (T)JERK5[o2];
+                }
+            }
+            if (t2 == t && (t == 0 || t == TT - 1)) {
+                const float *J = t == 0 ? S.J0 : S.J1;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) a += (T)J[r * NJ + i] * (T)J[r * NJ + i2];
+            }
+            if (k == 0) a += (T)lam * (a > (T)P.damping_floor ? a : (T)P.damping_floor);
+        }
+        band[e] = a;
+    }
+    for (int v = lane; v < V; v += 64) {
+        const int t = v / NJ, i = v - t * NJ;
+        T g = 0;
+        float rl, dl;
+        limit_row<NJ>(rb, P, S.Q[v], i, rl, dl);
+        g += (T)dl * (T)rl;
+        if (t >= 1) g += (T)P.w_smooth * (T)P.w_smooth * ((T)S.Q[v] - (T)S.Q[v - NJ]);
+        if (t <= TT - 2) g -= (T)P.w_smooth * (T)P.w_smooth * ((T)S.Q[v + NJ] - (T)S.Q[v]);
+        if (P.vmax) {
+            float rv, sv;
+            if (t >= 1) {
+                vel_row(P, S.Q, v, NJ, i, rv, sv);
+                g += (T)sv * (T)rv;
+            }
+            if (t <= TT - 2) {
+                vel_row(P, S.Q, v + NJ, NJ, i, rv, sv);
+                g -= (T)sv * (T)rv;
+            }
+        }
+        for (int tc = t - 2; tc <= t + 2; ++tc) {
+            if (tc < 2 || tc > TT - 3) continue;
+            const int o = t - tc + 2, vc = tc * NJ + i;
+            g += sa * (T)ACC5[o] * (T)acc_row(P, S.Q, vc, NJ) + sj * (T)JERK5[o] * (T)jerk_row(P, S.Q, vc, NJ);
+        }
+        if (t == 0 || t == TT - 1) {
+            const float *J = t == 0 ? S.J0 : S.J1;
+            const float *r = t == 0 ? S.r0 : S.r1;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) g += (T)J[q * NJ + i] * (T)r[q];
+        }
+        rhs[v] = -g;
+    }
+}
+
+// In-place band Cholesky of band (half-bandwidth HB) and the solve of
+// L L^T x = rhs (x over rhs).  A pivot not above thresh_rel times the largest
+// damped diagonal fails the factorisation (returns false).
+template <int NJ, typename T>
+PK_DEV bool band_solve(T *band, T *rhs, int V, float thresh_rel, const uint8_t *pair, int lane)
+{
+    constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W, NPAIR = TrajLds<NJ>::NPAIR;
+    float mx = 0.f;
+    for (int v = lane; v < V; v += 64) mx = fmaxf(mx, (float)band[v * W]);
+    const T thresh = (T)thresh_rel * (T)wmax(mx);
+    bool bad = false;
+    __syncthreads();
+    for (int j = 0; j < V; ++j) {
+        T d = band[j * W];
+        if (!(d > thresh) || !(d < (T)INFINITY)) {
+            bad = true;
+            d = 1;
+        }
+        const T ljj = sqrt(d), inv = (T)1 / ljj;
+        __syncthreads();
+        if (lane == 0) band[j * W] = ljj;
+        for (int r = lane + 1; r <= HB; r += 64)
+            if (j + r < V) band[(j + r) * W + r] *= inv;
+        __syncthreads();
+        for (int p = lane; p < NPAIR; p += 64) {
+            const int di = pair[2 * p], dk = pair[2 * p + 1];
+            const int i = j + di;
+            if (i < V) band[i * W + (di - dk)] -= band[i * W + di] * band[(j + dk) * W + dk];
+        }
+        __syncthreads();
+    }
+    if (bad) return false;
+    for (int j = 0; j < V; ++j) {
+        const T y = rhs[j] / band[j * W];
+        __syncthreads();
+        for (int r = lane + 1; r <= HB; r += 64)
+            if (j + r < V) rhs[j + r] -= band[(j + r) * W + r] * y;
+        if (lane == 0) rhs[j] = y;
+        __syncthreads();
+    }
+    for (int j = V - 1; j >= 0; --j) {
+        const T x = rhs[j] / band[j * W];
+        __syncthreads();
+        for (int r = lane + 1; r <= HB; r += 64)
+            if (j - r >= 0) rhs[j - r] -= band[j * W + r] * x;
+        if (lane == 0) rhs[j] = x;
+        __syncthreads();
+    }
+    return true;
+}
+
+template <int NJ>
+__global__ __launch_bounds__(64) void traj_kernel(const RobotC *__restrict__ rb, TrajParams P)
+{
+    using L = TrajLds<NJ>;
+    __shared__ L S;
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    if (b >= P.B) return;   // uniform per workgroup
+    const int TT = P.T, V = TT * NJ;
+    for (int p = lane; p < L::NPAIR; p += 64) {
+        // p-th pair (di, dk) in row-major order of the triangle 1 <= dk <= di <= HB
+        int di = 1, rem = p;
+        while (rem >= di) {
+            rem -= di;
+            ++di;
+        }
+        S.pair[2 * p] = (uint8_t)di;
+        S.pair[2 * p + 1] = (uint8_t)(rem + 1);
+    }
+    const float *src = P.init + b * (int64_t)V;
+    for (int v = lane; v < V; v += 64) S.Q[v] = src[v];
+    __syncthreads();
+
+    float tgt[7];
+    const float *tplane = lane == 0 ? P.start : P.goal;
+#pragma unroll
+    for (int u = 0; u < 7; ++u) tgt[u] = tplane[(int64_t)u * P.B + b];
+
+    int iters = 0, accepts = 0;
+    bool stalled = false, done = false, first = true, evaluate = true;
+    float lam = P.lambda0, cost = 0.f;
+    // Each pass evaluates one point (first the initial trajectory, then each
+    // trial), takes or rejects it, then forms and solves the next step; a
+    // failed solve is a rejected trial.  All decisions are wave-uniform.
+    for (;;) {
+        bool acc = false;
+        if (evaluate) {
+            const float *Qe = first ? S.Q : S.Qt;
+            if (lane < 2) {
+                float q[NJ], perr, rerr;
+                const int t = lane == 0 ? 0 : TT - 1;
+#pragma unroll
+                for (int i = 0; i < NJ; ++i) q[i] = Qe[t * NJ + i];
+                endpoint<NJ>(rb, P, q, tgt, lane == 0 ? S.rt0 : S.rt1, lane == 0 ? S.Jt0 : S.Jt1,
+                             perr, rerr);
+                S.errt[lane] = perr;
+                S.errt[2 + lane] = rerr;
+            }
+            const float pc = path_cost<NJ>(rb, P, Qe, lane);
+            __syncthreads();
+            float pose = 0.f;
+#pragma unroll
+            for (int u = 0; u < 6; ++u) pose += S.rt0[u] * S.rt0[u] + S.rt1[u] * S.rt1[u];
+            const float ct = pc + pose;
+            acc = first || ct < cost;
+            if (acc) {
+                if (!first)
+                    for (int v = lane; v < V; v += 64) S.Q[v] = S.Qt[v];
+                for (int e = lane; e < 6 * NJ; e += 64) {
+                    S.J0[e] = S.Jt0[e];
+                    S.J1[e] = S.Jt1[e];
+                }
+                if (lane < 6) {
+                    S.r0[lane] = S.rt0[lane];
+                    S.r1[lane] = S.rt1[lane];
+                }
+                if (lane < 4) S.err[lane] = S.errt[lane];
+                cost = ct;
+            }
+        }
+        if (!first) {
+            ++iters;
+            if (acc) {
+                lam = fmaxf(lam / P.nu_down, P.lambda_min);
+                ++accepts;
+            } else {
+                if (lam >= P.lambda_max) {
+                    stalled = true;
+                    done = true;
+                }
+                lam = fminf(lam * P.nu_up, P.lambda_max);
+            }
+        }
+        if (acc && P.early_exit && S.errt[0] <= P.tol_pos && S.errt[1] <= P.tol_pos &&
+            S.errt[2] <= P.tol_rot && S.errt[3] <= P.tol_rot)
+            done = true;
+        first = false;
+        __syncthreads();
+        if (done || iters >= P.max_iters) break;
+        // damped step from the current point (a pivot test failure is a
+        // rejected trial, as when the IK re-solve fails)
+        form_system<NJ, double>(rb, P, S, lam, lane, S.band, S.b);
+        __syncthreads();
+        const bool ok = band_solve<NJ, double>(S.band, S.b, V, P.pivot_rel, S.pair, lane);
+        for (int v = lane; v < V; v += 64) S.Qt[v] = S.Q[v] + (ok ? (float)S.b[v] : 0.f);
+        evaluate = ok;
+        __syncthreads();
+    }
+    float *dst = P.out + b * (int64_t)V;
+    for (int v = lane; v < V; v += 64) dst[v] = S.Q[v];
+    if (lane == 0) {
+        const bool meets = S.err[0] <= P.tol_pos && S.err[1] <= P.tol_pos && S.err[2] <= P.tol_rot &&
+                           S.err[3] <= P.tol_rot;
+        if (P.cost) P.cost[b] = cost;
+        if (P.iters) P.iters[b] = iters;
+        if (P.accepts) P.accepts[b] = accepts;
+        if (P.status) P.status[b] = meets ? PK_CONVERGED : (stalled ? PK_STALLED : PK_MAX_ITERS);
+        if (P.pos_err) {
+            P.pos_err[b] = S.err[0];
+            P.pos_err[P.B + b] = S.err[1];
+        }
+        if (P.rot_err) {
+            P.rot_err[b] = S.err[2];
+            P.rot_err[P.B + b] = S.err[3];
+        }
+    }
+}
+
+inline bool traj_variant(int n) { return n == 4 || n == 6 || n == 7 || n == 10; }
+
+hipError_t launch_traj(const RobotC *rb, int n, const TrajParams &P, hipStream_t s)
+{
+    const dim3 grid((unsigned)P.B), block(64);
+    switch (n) {
+    case 4: hipLaunchKernelGGL(traj_kernel<4>, grid, block, 0, s, rb, P); break;
+    case 6: hipLaunchKernelGGL(traj_kernel<6>, grid, block, 0, s, rb, P); break;
+    case 7: hipLaunchKernelGGL(traj_kernel<7>, grid, block, 0, s, rb, P); break;
+    case 10: hipLaunchKernelGGL(traj_kernel<10>, grid, block, 0, s, rb, P); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace pk
+
+using namespace pk;
+
+extern "C" int pk_traj_solve(pk_ctx *ctx, int32_t robot_id, const pk_traj_problem *pr,
+                             const pk_traj_costs *c, const pk_lm_options *o,
+                             const pk_traj_outputs *out, void *stream)
+{
+    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_traj_solve: ctx is NULL");
+    RobotEntry *rb = robot_of(ctx, robot_id);
+    if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_traj_solve: unknown robot %d", robot_id);
+    if (!pr || !c || !o || !out) return fail(ctx, PK_EINVAL, "pk_traj_solve: NULL argument");
+    const RobotC &H = rb->host;
+    const int n = H.n;
+    if (H.chains != 1 || H.m != 1 || H.e[0].kind != PK_EE_POSE || H.n_mimic != 0 || !traj_variant(n))
+        return fail(ctx, PK_EUNSUPPORTED, "pk_traj_solve: needs a single chain of 4, 6, 7 or 10 "
+                    "non-mimic joints with one pose EE");
+    if (pr->B < 0 || pr->T < 5 || (int64_t)pr->T * n > TRAJ_VMAX)
+        return fail(ctx, PK_EINVAL, "pk_traj_solve: B=%lld T=%d (need T >= 5, T * n <= %d)",
+                    (long long)pr->B, pr->T, TRAJ_VMAX);
+    if (pr->B == 0) return PK_OK;
+    if (pr->B >= (int64_t)1 << 31) return fail(ctx, PK_EUNSUPPORTED, "pk_traj_solve: B too large");
+    if (!pr->start || !pr->goal || !pr->init || !out->traj)
+        return fail(ctx, PK_EINVAL, "pk_traj_solve: NULL start/goal/init/traj");
+    if (!(c->dt > 0) || !std::isfinite(c->w_pos) || !std::isfinite(c->w_rot) ||
+        !std::isfinite(c->w_limit) || !std::isfinite(c->w_smooth) || !std::isfinite(c->w_vel) ||
+        !std::isfinite(c->w_acc) || !std::isfinite(c->w_jerk))
+        return fail(ctx, PK_EINVAL, "pk_traj_solve: bad costs");
+    if (o->max_iters < 0 || !(o->lambda0 > 0) || !(o->nu_up > 1) || !(o->nu_down > 1) ||
+        !(o->lambda_min > 0) || !(o->lambda_max >= o->lambda_min) || !(o->damping_floor > 0) ||
+        !(o->pivot_rel >= 0))
+        return fail(ctx, PK_EINVAL, "pk_traj_solve: invalid LM options");
+    PK_HIP(ctx, hipSetDevice(ctx->device));
+    TrajParams P;
+    memset(&P, 0, sizeof P);
+    P.B = pr->B;
+    P.T = pr->T;
+    P.dt = c->dt;
+    P.w_pos = c->w_pos; P.w_rot = c->w_rot; P.w_limit = c->w_limit; P.w_smooth = c->w_smooth;
+    P.w_vel = c->w_vel; P.w_acc = c->w_acc; P.w_jerk = c->w_jerk; P.vmax = c->vmax;
+    P.start = pr->start; P.goal = pr->goal; P.init = pr->init;
+    P.out = out->traj; P.cost = out->cost; P.pos_err = out->pos_err; P.rot_err = out->rot_err;
+    P.iters = out->iters; P.accepts = out->accepts; P.status = out->status;
+    P.lambda0 = o->lambda0; P.nu_up = o->nu_up; P.nu_down = o->nu_down;
+    P.lambda_min = o->lambda_min; P.lambda_max = o->lambda_max;
+    P.tol_pos = o->tol_pos; P.tol_rot = o->tol_rot;
+    P.damping_floor = o->damping_floor; P.pivot_rel = o->pivot_rel;
+    P.max_iters = o->max_iters; P.early_exit = o->early_exit ? 1 : 0;
+    PK_HIP(ctx, launch_traj(rb->dev, n, P, (hipStream_t)stream));
+    return PK_OK;
+}
