@@ -40,9 +40,9 @@ struct TrajParams {
 };
 
 // Five-point stencils on offsets -2..2: second derivative times dt^2 and
-// third derivative times dt^3.
-__constant__ float ACC5[5] = {-1.f / 12.f, 16.f / 12.f, -30.f / 12.f, 16.f / 12.f, -1.f / 12.f};
-__constant__ float JERK5[5] = {-0.5f, 1.f, 0.f, -1.f, 0.5f};
+// third derivative times dt^3 (copied to LDS per workgroup).
+constexpr float ACC5[5] = {-1.f / 12.f, 16.f / 12.f, -30.f / 12.f, 16.f / 12.f, -1.f / 12.f};
+constexpr float JERK5[5] = {-0.5f, 1.f, 0.f, -1.f, 0.5f};
 
 template <int NJ>
 struct TrajLds {
@@ -54,7 +54,9 @@ struct TrajLds {
     float J0[6 * NJ], J1[6 * NJ], r0[6], r1[6];        // pose rows at the current point
     float Jt0[6 * NJ], Jt1[6 * NJ], rt0[6], rt1[6];    // ... at the trial point
     float err[4], errt[4];                             // pos/rot errors (start, goal)
-    uint8_t pair[2 * NPAIR];                           // (di, dk), 1 <= dk <= di <= HB
+    // per-joint limits and allowed step, the stencils: read per band entry,
+    // so they sit in LDS rather than behind lane-indexed global loads
+    float lo[NJ], hi[NJ], vdt[NJ], acc5[5], jerk5[5];
 };
 
 PK_DEV float wsum(float v)
@@ -128,18 +130,19 @@ PK_DEV void endpoint(const RobotC *__restrict__ rb, const TrajParams &P, const f
 // Per-variable pieces at Q: limit residual and derivative, and the
 // velocity-limit residual and sign of the step into timestep t.
 template <int NJ>
-PK_DEV void limit_row(const RobotC *__restrict__ rb, const TrajParams &P, float q, int i, float &rl,
-                      float &dl)
+PK_DEV void limit_row(const TrajLds<NJ> &S, const TrajParams &P, float q, int i, float &rl, float &dl)
 {
-    const float over = q - rb->j[i].hi, under = rb->j[i].lo - q;
+    const float over = q - S.hi[i], under = S.lo[i] - q;
     rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
     dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
 }
 
-PK_DEV void vel_row(const TrajParams &P, const float *Q, int v, int n, int i, float &rv, float &sv)
+template <int NJ>
+PK_DEV void vel_row(const TrajLds<NJ> &S, const TrajParams &P, const float *Q, int v, int i, float &rv,
+                    float &sv)
 {
-    const float d = Q[v] - Q[v - n];
-    const float ex = fabsf(d) - P.vmax[i] * P.dt;
+    const float d = Q[v] - Q[v - NJ];
+    const float ex = fabsf(d) - S.vdt[i];
     rv = ex > 0.f ? P.w_vel * ex : 0.f;
     sv = ex > 0.f ? (d > 0.f ? P.w_vel : -P.w_vel) : 0.f;
 }
@@ -162,21 +165,21 @@ PK_DEV float jerk_row(const TrajParams &P, const float *Q, int v, int n)
 
 // Sum of squares of the non-pose rows at Q (every lane; wave total).
 template <int NJ>
-PK_DEV float path_cost(const RobotC *__restrict__ rb, const TrajParams &P, const float *Q, int lane)
+PK_DEV float path_cost(const TrajLds<NJ> &S, const TrajParams &P, const float *Q, int lane)
 {
     const int T = P.T, V = T * NJ;
     float s = 0.f;
     for (int v = lane; v < V; v += 64) {
         const int t = v / NJ, i = v - t * NJ;
         float rl, dl;
-        limit_row<NJ>(rb, P, Q[v], i, rl, dl);
+        limit_row<NJ>(S, P, Q[v], i, rl, dl);
         s += rl * rl;
         if (t >= 1) {
             const float rs = P.w_smooth * (Q[v] - Q[v - NJ]);
             s += rs * rs;
             if (P.vmax) {
                 float rv, sv;
-                vel_row(P, Q, v, NJ, i, rv, sv);
+                vel_row<NJ>(S, P, Q, v, i, rv, sv);
                 s += rv * rv;
             }
         }
@@ -209,7 +212,7 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
                 const int dtk = t - t2;   // 0..4
                 if (dtk == 0) {
                     float rl, dl;
-                    limit_row<NJ>(rb, P, S.Q[v], i, rl, dl);
+                    limit_row<NJ>(S, P, S.Q[v], i, rl, dl);
                     a += (T)dl * (T)dl;
                 }
                 // smoothness rows q_tau - q_{tau-1}, tau = 1..T-1
@@ -219,8 +222,8 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
                 if (P.vmax) {
                     float rv, sv, rv1 = 0.f, sv1 = 0.f;
                     rv = sv = 0.f;
-                    if (t >= 1) vel_row(P, S.Q, v, NJ, i, rv, sv);
-                    if (t + 1 <= TT - 1) vel_row(P, S.Q, v + NJ, NJ, i, rv1, sv1);
+                    if (t >= 1) vel_row<NJ>(S, P, S.Q, v, i, rv, sv);
+                    if (t + 1 <= TT - 1) vel_row<NJ>(S, P, S.Q, v + NJ, i, rv1, sv1);
                     if (dtk == 0) a += (T)sv * (T)sv + (T)sv1 * (T)sv1;
                     if (dtk == 1) a -= (T)sv * (T)sv;
                 }
@@ -228,7 +231,7 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
                 for (int tc = t - 2; tc <= t2 + 2; ++tc) {
                     if (tc < 2 || tc > TT - 3) continue;
                     const int o1 = t - tc + 2, o2 = t2 - tc + 2;
-                    a += sa * sa * (T)ACC5[o1] * (T)ACC5[o2] + sj * sj * (T)JERK5[o1] * (T)JERK5[o2];
+                    a += sa * sa * (T)S.acc5[o1] * (T)S.acc5[o2] + sj * sj * (T)S.jerk5[o1] * (T)S.jerk5[o2];
                 }
             }
             if (t2 == t && (t == 0 || t == TT - 1)) {
@@ -244,25 +247,25 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
         const int t = v / NJ, i = v - t * NJ;
         T g = 0;
         float rl, dl;
-        limit_row<NJ>(rb, P, S.Q[v], i, rl, dl);
+        limit_row<NJ>(S, P, S.Q[v], i, rl, dl);
         g += (T)dl * (T)rl;
         if (t >= 1) g += (T)P.w_smooth * (T)P.w_smooth * ((T)S.Q[v] - (T)S.Q[v - NJ]);
         if (t <= TT - 2) g -= (T)P.w_smooth * (T)P.w_smooth * ((T)S.Q[v + NJ] - (T)S.Q[v]);
         if (P.vmax) {
             float rv, sv;
             if (t >= 1) {
-                vel_row(P, S.Q, v, NJ, i, rv, sv);
+                vel_row<NJ>(S, P, S.Q, v, i, rv, sv);
                 g += (T)sv * (T)rv;
             }
             if (t <= TT - 2) {
-                vel_row(P, S.Q, v + NJ, NJ, i, rv, sv);
+                vel_row<NJ>(S, P, S.Q, v + NJ, i, rv, sv);
                 g -= (T)sv * (T)rv;
             }
         }
         for (int tc = t - 2; tc <= t + 2; ++tc) {
             if (tc < 2 || tc > TT - 3) continue;
             const int o = t - tc + 2, vc = tc * NJ + i;
-            g += sa * (T)ACC5[o] * (T)acc_row(P, S.Q, vc, NJ) + sj * (T)JERK5[o] * (T)jerk_row(P, S.Q, vc, NJ);
+            g += sa * (T)S.acc5[o] * (T)acc_row(P, S.Q, vc, NJ) + sj * (T)S.jerk5[o] * (T)jerk_row(P, S.Q, vc, NJ);
         }
         if (t == 0 || t == TT - 1) {
             const float *J = t == 0 ? S.J0 : S.J1;
@@ -277,10 +280,31 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
 // In-place band Cholesky of band (half-bandwidth HB) and the solve of
 // L L^T x = rhs (x over rhs).  A pivot not above thresh_rel times the largest
 // damped diagonal fails the factorisation (returns false).
-template <int NJ, typename T>
-PK_DEV bool band_solve(T *band, T *rhs, int V, float thresh_rel, const uint8_t *pair, int lane)
+template <int NJ>
+constexpr int pairs_per_lane() { return (TrajLds<NJ>::NPAIR + 63) / 64; }
+
+// This lane's entries of the trailing-update triangle, (di | dk << 8), 0 past
+// the end: pair p = lane + 64 m in row-major order of 1 <= dk <= di <= HB.
+template <int NJ>
+PK_DEV void lane_pairs(int lane, int (&mp)[pairs_per_lane<NJ>()])
 {
-    constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W, NPAIR = TrajLds<NJ>::NPAIR;
+#pragma unroll
+    for (int m = 0; m < pairs_per_lane<NJ>(); ++m) {
+        const int p = lane + 64 * m;
+        int di = 1, rem = p;
+        while (rem >= di) {
+            rem -= di;
+            ++di;
+        }
+        mp[m] = p < TrajLds<NJ>::NPAIR ? (di | ((rem + 1) << 8)) : 0;
+    }
+}
+
+template <int NJ, typename T>
+PK_DEV bool band_solve(T *band, T *rhs, int V, float thresh_rel, const int (&mp)[pairs_per_lane<NJ>()],
+                       int lane)
+{
+    constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W;
     float mx = 0.f;
     for (int v = lane; v < V; v += 64) mx = fmaxf(mx, (float)band[v * W]);
     const T thresh = (T)thresh_rel * (T)wmax(mx);
@@ -298,10 +322,11 @@ PK_DEV bool band_solve(T *band, T *rhs, int V, float thresh_rel, const uint8_t *
         for (int r = lane + 1; r <= HB; r += 64)
             if (j + r < V) band[(j + r) * W + r] *= inv;
         __syncthreads();
-        for (int p = lane; p < NPAIR; p += 64) {
-            const int di = pair[2 * p], dk = pair[2 * p + 1];
+#pragma unroll
+        for (int m = 0; m < pairs_per_lane<NJ>(); ++m) {
+            const int di = mp[m] & 0xff, dk = mp[m] >> 8;
             const int i = j + di;
-            if (i < V) band[i * W + (di - dk)] -= band[i * W + di] * band[(j + dk) * W + dk];
+            if (di && i < V) band[i * W + (di - dk)] -= band[i * W + di] * band[(j + dk) * W + dk];
         }
         __syncthreads();
     }
@@ -334,18 +359,19 @@ __global__ __launch_bounds__(64) void traj_kernel(const RobotC *__restrict__ rb,
     const int64_t b = blockIdx.x;
     if (b >= P.B) return;   // uniform per workgroup
     const int TT = P.T, V = TT * NJ;
-    for (int p = lane; p < L::NPAIR; p += 64) {
-        // p-th pair (di, dk) in row-major order of the triangle 1 <= dk <= di <= HB
-        int di = 1, rem = p;
-        while (rem >= di) {
-            rem -= di;
-            ++di;
-        }
-        S.pair[2 * p] = (uint8_t)di;
-        S.pair[2 * p + 1] = (uint8_t)(rem + 1);
-    }
+    int mp[pairs_per_lane<NJ>()];
+    lane_pairs<NJ>(lane, mp);
     const float *src = P.init + b * (int64_t)V;
     for (int v = lane; v < V; v += 64) S.Q[v] = src[v];
+    if (lane < NJ) {
+        S.lo[lane] = rb->j[lane].lo;
+        S.hi[lane] = rb->j[lane].hi;
+        S.vdt[lane] = P.vmax ? P.vmax[lane] * P.dt : 0.f;
+    }
+    if (lane < 5) {
+        S.acc5[lane] = ACC5[lane];
+        S.jerk5[lane] = JERK5[lane];
+    }
     __syncthreads();
 
     float tgt[7];
@@ -373,7 +399,7 @@ __global__ __launch_bounds__(64) void traj_kernel(const RobotC *__restrict__ rb,
                 S.errt[lane] = perr;
                 S.errt[2 + lane] = rerr;
             }
-            const float pc = path_cost<NJ>(rb, P, Qe, lane);
+            const float pc = path_cost<NJ>(S, P, Qe, lane);
             __syncthreads();
             float pose = 0.f;
 #pragma unroll
@@ -418,7 +444,7 @@ __global__ __launch_bounds__(64) void traj_kernel(const RobotC *__restrict__ rb,
         // rejected trial, as when the IK re-solve fails)
         form_system<NJ, double>(rb, P, S, lam, lane, S.band, S.b);
         __syncthreads();
-        const bool ok = band_solve<NJ, double>(S.band, S.b, V, P.pivot_rel, S.pair, lane);
+        const bool ok = band_solve<NJ, double>(S.band, S.b, V, P.pivot_rel, mp, lane);
         for (int v = lane; v < V; v += 64) S.Qt[v] = S.Q[v] + (ok ? (float)S.b[v] : 0.f);
         evaluate = ok;
         __syncthreads();
