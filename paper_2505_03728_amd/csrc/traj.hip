@@ -23,6 +23,7 @@ namespace pk {
 namespace {
 
 constexpr int TRAJ_VMAX = 256;   // T * n variables per trajectory
+constexpr int TRAJ_THREADS = 256; // four wavefronts per trajectory
 
 struct TrajParams {
     int64_t B;
@@ -57,6 +58,7 @@ struct TrajLds {
     // per-joint limits and allowed step, the stencils: read per band entry,
     // so they sit in LDS rather than behind lane-indexed global loads
     float lo[NJ], hi[NJ], vdt[NJ], acc5[5], jerk5[5];
+    float red[4];                                      // per-wavefront partials of a reduction
 };
 
 PK_DEV float wsum(float v)
@@ -71,6 +73,35 @@ PK_DEV float wmax(float v)
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
     return v;
+}
+
+// Sum and maximum over the workgroup (four wavefronts): butterflies within
+// each wavefront, then the four partials through LDS, added in one order so
+// that every thread gets the same value.
+PK_DEV float block_sum(float v, float *red)
+{
+    v = wsum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+PK_DEV float block_max(float v, float *red)
+{
+    v = wmax(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// Ordering of LDS accesses among the lanes of one wavefront.
+PK_DEV void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // FK of the chain at q (NJ values), the pose residual rows against target
@@ -165,11 +196,11 @@ PK_DEV float jerk_row(const TrajParams &P, const float *Q, int v, int n)
 
 // Sum of squares of the non-pose rows at Q (every lane; wave total).
 template <int NJ>
-PK_DEV float path_cost(const TrajLds<NJ> &S, const TrajParams &P, const float *Q, int lane)
+PK_DEV float path_cost(TrajLds<NJ> &S, const TrajParams &P, const float *Q, int lane)
 {
     const int T = P.T, V = T * NJ;
     float s = 0.f;
-    for (int v = lane; v < V; v += 64) {
+    for (int v = lane; v < V; v += TRAJ_THREADS) {
         const int t = v / NJ, i = v - t * NJ;
         float rl, dl;
         limit_row<NJ>(S, P, Q[v], i, rl, dl);
@@ -188,7 +219,7 @@ PK_DEV float path_cost(const TrajLds<NJ> &S, const TrajParams &P, const float *Q
             s += ra * ra + rj * rj;
         }
     }
-    return wsum(s);
+    return block_sum(s, S.red);
 }
 
 // Band of A + lambda diag(max(A_vv, floor)) and the right-hand side -J^T r at
@@ -201,7 +232,7 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
     const int TT = P.T, V = TT * NJ;
     const T ws2 = (T)P.w_smooth * (T)P.w_smooth;
     const T sa = (T)P.w_acc / ((T)P.dt * (T)P.dt), sj = (T)P.w_jerk / ((T)P.dt * (T)P.dt * (T)P.dt);
-    for (int e = lane; e < V * W; e += 64) {
+    for (int e = lane; e < V * W; e += TRAJ_THREADS) {
         const int v = e / W, k = e - v * W;
         const int u = v - k;
         T a = 0;
@@ -243,7 +274,7 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
         }
         band[e] = a;
     }
-    for (int v = lane; v < V; v += 64) {
+    for (int v = lane; v < V; v += TRAJ_THREADS) {
         const int t = v / NJ, i = v - t * NJ;
         T g = 0;
         float rl, dl;
@@ -281,16 +312,17 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
 // L L^T x = rhs (x over rhs).  A pivot not above thresh_rel times the largest
 // damped diagonal fails the factorisation (returns false).
 template <int NJ>
-constexpr int pairs_per_lane() { return (TrajLds<NJ>::NPAIR + 63) / 64; }
+constexpr int pairs_per_lane() { return (TrajLds<NJ>::NPAIR + TRAJ_THREADS - 1) / TRAJ_THREADS; }
 
-// This lane's entries of the trailing-update triangle, (di | dk << 8), 0 past
-// the end: pair p = lane + 64 m in row-major order of 1 <= dk <= di <= HB.
+// This thread's entries of the trailing-update triangle, (di | dk << 8), 0
+// past the end: pair p = lane + TRAJ_THREADS m in row-major order of
+// 1 <= dk <= di <= HB.
 template <int NJ>
 PK_DEV void lane_pairs(int lane, int (&mp)[pairs_per_lane<NJ>()])
 {
 #pragma unroll
     for (int m = 0; m < pairs_per_lane<NJ>(); ++m) {
-        const int p = lane + 64 * m;
+        const int p = lane + TRAJ_THREADS * m;
         int di = 1, rem = p;
         while (rem >= di) {
             rem -= di;
@@ -302,12 +334,12 @@ PK_DEV void lane_pairs(int lane, int (&mp)[pairs_per_lane<NJ>()])
 
 template <int NJ, typename T>
 PK_DEV bool band_solve(T *band, T *rhs, int V, float thresh_rel, const int (&mp)[pairs_per_lane<NJ>()],
-                       int lane)
+                       int lane, float *red)
 {
     constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W;
     float mx = 0.f;
-    for (int v = lane; v < V; v += 64) mx = fmaxf(mx, (float)band[v * W]);
-    const T thresh = (T)thresh_rel * (T)wmax(mx);
+    for (int v = lane; v < V; v += TRAJ_THREADS) mx = fmaxf(mx, (float)band[v * W]);
+    const T thresh = (T)thresh_rel * (T)block_max(mx, red);
     bool bad = false;
     __syncthreads();
     for (int j = 0; j < V; ++j) {
@@ -319,8 +351,7 @@ PK_DEV bool band_solve(T *band, T *rhs, int V, float thresh_rel, const int (&mp)
         const T ljj = sqrt(d), inv = (T)1 / ljj;
         __syncthreads();
         if (lane == 0) band[j * W] = ljj;
-        for (int r = lane + 1; r <= HB; r += 64)
-            if (j + r < V) band[(j + r) * W + r] *= inv;
+        if (lane >= 1 && lane <= HB && j + lane < V) band[(j + lane) * W + lane] *= inv;
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < pairs_per_lane<NJ>(); ++m) {
@@ -331,27 +362,30 @@ PK_DEV bool band_solve(T *band, T *rhs, int V, float thresh_rel, const int (&mp)
         __syncthreads();
     }
     if (bad) return false;
-    for (int j = 0; j < V; ++j) {
-        const T y = rhs[j] / band[j * W];
-        __syncthreads();
-        for (int r = lane + 1; r <= HB; r += 64)
-            if (j + r < V) rhs[j + r] -= band[(j + r) * W + r] * y;
-        if (lane == 0) rhs[j] = y;
-        __syncthreads();
+    // Triangular solves on the first wavefront alone (HB <= 63 lanes take
+    // part), ordered by wavefront-scope fences instead of workgroup barriers.
+    if (lane < 64) {
+        for (int j = 0; j < V; ++j) {
+            const T y = rhs[j] / band[j * W];
+            wave_sync();
+            if (lane >= 1 && lane <= HB && j + lane < V) rhs[j + lane] -= band[(j + lane) * W + lane] * y;
+            if (lane == 0) rhs[j] = y;
+            wave_sync();
+        }
+        for (int j = V - 1; j >= 0; --j) {
+            const T x = rhs[j] / band[j * W];
+            wave_sync();
+            if (lane >= 1 && lane <= HB && j - lane >= 0) rhs[j - lane] -= band[j * W + lane] * x;
+            if (lane == 0) rhs[j] = x;
+            wave_sync();
+        }
     }
-    for (int j = V - 1; j >= 0; --j) {
-        const T x = rhs[j] / band[j * W];
-        __syncthreads();
-        for (int r = lane + 1; r <= HB; r += 64)
-            if (j - r >= 0) rhs[j - r] -= band[j * W + r] * x;
-        if (lane == 0) rhs[j] = x;
-        __syncthreads();
-    }
+    __syncthreads();
     return true;
 }
 
 template <int NJ>
-__global__ __launch_bounds__(64) void traj_kernel(const RobotC *__restrict__ rb, TrajParams P)
+__global__ __launch_bounds__(TRAJ_THREADS) void traj_kernel(const RobotC *__restrict__ rb, TrajParams P)
 {
     using L = TrajLds<NJ>;
     __shared__ L S;
@@ -362,7 +396,7 @@ __global__ __launch_bounds__(64) void traj_kernel(const RobotC *__restrict__ rb,
     int mp[pairs_per_lane<NJ>()];
     lane_pairs<NJ>(lane, mp);
     const float *src = P.init + b * (int64_t)V;
-    for (int v = lane; v < V; v += 64) S.Q[v] = src[v];
+    for (int v = lane; v < V; v += TRAJ_THREADS) S.Q[v] = src[v];
     if (lane < NJ) {
         S.lo[lane] = rb->j[lane].lo;
         S.hi[lane] = rb->j[lane].hi;
@@ -408,8 +442,8 @@ __global__ __launch_bounds__(64) void traj_kernel(const RobotC *__restrict__ rb,
             acc = first || ct < cost;
             if (acc) {
                 if (!first)
-                    for (int v = lane; v < V; v += 64) S.Q[v] = S.Qt[v];
-                for (int e = lane; e < 6 * NJ; e += 64) {
+                    for (int v = lane; v < V; v += TRAJ_THREADS) S.Q[v] = S.Qt[v];
+                for (int e = lane; e < 6 * NJ; e += TRAJ_THREADS) {
                     S.J0[e] = S.Jt0[e];
                     S.J1[e] = S.Jt1[e];
                 }
@@ -444,13 +478,13 @@ __global__ __launch_bounds__(64) void traj_kernel(const RobotC *__restrict__ rb,
         // rejected trial, as when the IK re-solve fails)
         form_system<NJ, double>(rb, P, S, lam, lane, S.band, S.b);
         __syncthreads();
-        const bool ok = band_solve<NJ, double>(S.band, S.b, V, P.pivot_rel, mp, lane);
-        for (int v = lane; v < V; v += 64) S.Qt[v] = S.Q[v] + (ok ? (float)S.b[v] : 0.f);
+        const bool ok = band_solve<NJ, double>(S.band, S.b, V, P.pivot_rel, mp, lane, S.red);
+        for (int v = lane; v < V; v += TRAJ_THREADS) S.Qt[v] = S.Q[v] + (ok ? (float)S.b[v] : 0.f);
         evaluate = ok;
         __syncthreads();
     }
     float *dst = P.out + b * (int64_t)V;
-    for (int v = lane; v < V; v += 64) dst[v] = S.Q[v];
+    for (int v = lane; v < V; v += TRAJ_THREADS) dst[v] = S.Q[v];
     if (lane == 0) {
         const bool meets = S.err[0] <= P.tol_pos && S.err[1] <= P.tol_pos && S.err[2] <= P.tol_rot &&
                            S.err[3] <= P.tol_rot;
@@ -473,7 +507,7 @@ inline bool traj_variant(int n) { return n == 4 || n == 6 || n == 7 || n == 10; 
 
 hipError_t launch_traj(const RobotC *rb, int n, const TrajParams &P, hipStream_t s)
 {
-    const dim3 grid((unsigned)P.B), block(64);
+    const dim3 grid((unsigned)P.B), block(TRAJ_THREADS);
     switch (n) {
     case 4: hipLaunchKernelGGL(traj_kernel<4>, grid, block, 0, s, rb, P); break;
     case 6: hipLaunchKernelGGL(traj_kernel<6>, grid, block, 0, s, rb, P); break;
