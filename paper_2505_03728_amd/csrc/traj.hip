@@ -51,6 +51,7 @@ struct TrajLds {
     static constexpr int NPAIR = HB * (HB + 1) / 2;
     double band[TRAJ_VMAX * W];
     double b[TRAJ_VMAX];
+    double invd[TRAJ_VMAX];                            // 1 / D_j of the L D L^T factorisation
     float Q[TRAJ_VMAX], Qt[TRAJ_VMAX];
     float J0[6 * NJ], J1[6 * NJ], r0[6], r1[6];        // pose rows at the current point
     float Jt0[6 * NJ], Jt1[6 * NJ], rt0[6], rt1[6];    // ... at the trial point
@@ -94,14 +95,6 @@ PK_DEV float block_max(float v, float *red)
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-}
-
-// Ordering of LDS accesses among the lanes of one wavefront.
-PK_DEV void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // FK of the chain at q (NJ values), the pose residual rows against target
@@ -308,9 +301,10 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
     }
 }
 
-// In-place band Cholesky of band (half-bandwidth HB) and the solve of
-// L L^T x = rhs (x over rhs).  A pivot not above thresh_rel times the largest
-// damped diagonal fails the factorisation (returns false).
+// In-place band L D L^T factorisation of band (half-bandwidth HB, unit L)
+// and the solve of L D L^T x = rhs (x over rhs).  A pivot D_j not above
+// thresh_rel times the largest damped diagonal fails the factorisation
+// (returns false).
 template <int NJ>
 constexpr int pairs_per_lane() { return (TrajLds<NJ>::NPAIR + TRAJ_THREADS - 1) / TRAJ_THREADS; }
 
@@ -332,52 +326,165 @@ PK_DEV void lane_pairs(int lane, int (&mp)[pairs_per_lane<NJ>()])
     }
 }
 
-template <int NJ, typename T>
-PK_DEV bool band_solve(T *band, T *rhs, int V, float thresh_rel, const int (&mp)[pairs_per_lane<NJ>()],
-                       int lane, float *red)
+// Value of v in lane l (l uniform) broadcast to the wavefront.
+PK_DEV double readlane_d(double v, int l)
 {
-    constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W;
+    const long long u = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 1 / d for a positive normal d: the hardware reciprocal estimate refined by
+// two Newton-Raphson steps r <- r + r (1 - d r), each of which squares the
+// relative error.
+PK_DEV double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+// Right-looking L D L^T without square roots: after column j, band[j * W]
+// holds D_j and band[i * W + (i - j)] the unscaled column D_j L_ij; the
+// trailing update subtracts a_ij a_kj / D_j.  The column itself is never
+// rewritten, so the update of column j reads only entries it does not write
+// and one workgroup barrier per column orders the steps; a thread issues all
+// of its loads together with the pivot's so that one LDS round trip and the
+// reciprocal make up the column's latency.  The two triangular solves run on
+// the first wavefront with the right-hand side in registers (lane l holds
+// entries l, l + 64, ...): per chunk of CH steps the lanes read their
+// coefficients at once, then each step broadcasts the finished entry with
+// readlane and the lanes holding the next HB entries take their update, with
+// no memory access or branch on that dependent chain.
+template <int NJ, typename T>
+PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
+                       const int (&mp)[pairs_per_lane<NJ>()], int lane, float *red)
+{
+    constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W, PPL = pairs_per_lane<NJ>();
+    constexpr int NS = TRAJ_VMAX / 64, CH = 8;
     float mx = 0.f;
     for (int v = lane; v < V; v += TRAJ_THREADS) mx = fmaxf(mx, (float)band[v * W]);
     const T thresh = (T)thresh_rel * (T)block_max(mx, red);
     bool bad = false;
-    __syncthreads();
     for (int j = 0; j < V; ++j) {
+        // addresses clamped into the band so that every load is issued
+        // unconditionally (padding pairs and rows past V store nothing)
+        T ai[PPL], ak[PPL], at[PPL];
+        int tgt[PPL];
+#pragma unroll
+        for (int m = 0; m < PPL; ++m) {
+            const int di = mp[m] & 0xff, dk = mp[m] >> 8;
+            const int i = min(j + di, V - 1), k = min(j + dk, V - 1);
+            tgt[m] = di && j + di < V ? i * W + (di - dk) : -1;
+            ai[m] = band[i * W + di];
+            ak[m] = band[k * W + dk];
+            at[m] = band[i * W + (di - dk)];
+        }
         T d = band[j * W];
         if (!(d > thresh) || !(d < (T)INFINITY)) {
             bad = true;
             d = 1;
         }
-        const T ljj = sqrt(d), inv = (T)1 / ljj;
-        __syncthreads();
-        if (lane == 0) band[j * W] = ljj;
-        if (lane >= 1 && lane <= HB && j + lane < V) band[(j + lane) * W + lane] *= inv;
-        __syncthreads();
+        const T inv = recip(d);
+        if (lane == 0) invd[j] = inv;
 #pragma unroll
-        for (int m = 0; m < pairs_per_lane<NJ>(); ++m) {
-            const int di = mp[m] & 0xff, dk = mp[m] >> 8;
-            const int i = j + di;
-            if (di && i < V) band[i * W + (di - dk)] -= band[i * W + di] * band[(j + dk) * W + dk];
-        }
+        for (int m = 0; m < PPL; ++m)
+            if (tgt[m] >= 0) band[tgt[m]] = at[m] - ai[m] * (ak[m] * inv);
         __syncthreads();
     }
     if (bad) return false;
-    // Triangular solves on the first wavefront alone (HB <= 63 lanes take
-    // part), ordered by wavefront-scope fences instead of workgroup barriers.
     if (lane < 64) {
-        for (int j = 0; j < V; ++j) {
-            const T y = rhs[j] / band[j * W];
-            wave_sync();
-            if (lane >= 1 && lane <= HB && j + lane < V) rhs[j + lane] -= band[(j + lane) * W + lane] * y;
-            if (lane == 0) rhs[j] = y;
-            wave_sync();
+        T x[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int i = 64 * s + lane;
+            x[s] = i < V ? rhs[i] : (T)0;
         }
-        for (int j = V - 1; j >= 0; --j) {
-            const T x = rhs[j] / band[j * W];
-            wave_sync();
-            if (lane >= 1 && lane <= HB && j - lane >= 0) rhs[j - lane] -= band[j * W + lane] * x;
-            if (lane == 0) rhs[j] = x;
-            wave_sync();
+        // L y = rhs: the entry finished at step j updates i in (j, j + HB] by
+        // -L_ij y_j.  This lane's candidate i sits in slot s = j / 64 when
+        // lane > j % 64 (coefficient cs), else in slot s + 1 (cn).  Steps at
+        // j >= V broadcast an entry that stays 0 and carry no coefficient.
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+#pragma unroll 1
+            for (int l0 = 0; l0 < 64; l0 += CH) {
+                const int j0 = 64 * s + l0;
+                if (j0 >= V) break;
+                T cs[CH], cn[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {   // loads first, all in flight together
+                    const int j = j0 + u, l = l0 + u;
+                    const int i = 64 * s + lane + (lane > l ? 0 : 64);
+                    const bool ok = j < V && i < V && i - j <= HB;
+                    cs[u] = band[ok ? i * W + (i - j) : 0];
+                    cn[u] = invd[j < V ? j : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int j = j0 + u, l = l0 + u;
+                    const bool up = lane > l;
+                    const int i = 64 * s + lane + (up ? 0 : 64);
+                    const bool ok = j < V && i < V && i - j <= HB;
+                    const T c = cs[u] * cn[u];
+                    cs[u] = ok && up ? c : (T)0;
+                    cn[u] = ok && !up ? c : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const T y = readlane_d(x[s], l0 + u);
+                    x[s] -= cs[u] * y;
+                    if (s + 1 < NS) x[s + 1] -= cn[u] * y;
+                }
+            }
+        }
+        // D z = y
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int i = 64 * s + lane;
+            if (i < V) x[s] *= invd[i];
+        }
+        // L^T x = z: the entry finished at step j updates i in [j - HB, j)
+        // by -L_ji x_j; the candidate i sits in slot s when lane < j % 64
+        // (cs), else in slot s - 1 (cp).
+#pragma unroll
+        for (int s = NS - 1; s >= 0; --s) {
+#pragma unroll 1
+            for (int l0 = 64 - CH; l0 >= 0; l0 -= CH) {
+                const int jt = 64 * s + l0;
+                if (jt >= V) continue;
+                T cs[CH], cp[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {   // loads first, all in flight together
+                    const int l = l0 + CH - 1 - u, j = 64 * s + l;
+                    const int i = 64 * s + lane - (lane < l ? 0 : 64);
+                    const bool ok = j < V && i >= 0 && j - i <= HB;
+                    cs[u] = band[ok ? j * W + (j - i) : 0];
+                    cp[u] = invd[ok ? i : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int l = l0 + CH - 1 - u, j = 64 * s + l;
+                    const bool dn = lane < l;
+                    const int i = 64 * s + lane - (dn ? 0 : 64);
+                    const bool ok = j < V && i >= 0 && j - i <= HB;
+                    const T c = cs[u] * cp[u];
+                    cs[u] = ok && dn ? c : (T)0;
+                    cp[u] = ok && !dn ? c : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const T y = readlane_d(x[s], l0 + CH - 1 - u);
+                    x[s] -= cs[u] * y;
+                    if (s > 0) x[s - 1] -= cp[u] * y;
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int i = 64 * s + lane;
+            if (i < V) rhs[i] = x[s];
         }
     }
     __syncthreads();
@@ -478,7 +585,7 @@ __global__ __launch_bounds__(TRAJ_THREADS) void traj_kernel(const RobotC *__rest
         // rejected trial, as when the IK re-solve fails)
         form_system<NJ, double>(rb, P, S, lam, lane, S.band, S.b);
         __syncthreads();
-        const bool ok = band_solve<NJ, double>(S.band, S.b, V, P.pivot_rel, mp, lane, S.red);
+        const bool ok = band_solve<NJ, double>(S.band, S.b, S.invd, V, P.pivot_rel, mp, lane, S.red);
         for (int v = lane; v < V; v += TRAJ_THREADS) S.Qt[v] = S.Q[v] + (ok ? (float)S.b[v] : 0.f);
         evaluate = ok;
         __syncthreads();
