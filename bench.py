@@ -659,7 +659,8 @@ def traj_solve_flops(V, hb):
 
 def run_traj(args):
     """Trajectory optimisation: 1024 arm trajectories x 32 timesteps, 20 LM
-    iterations, one wavefront per trajectory (banded FP64 normal equations)."""
+    iterations, one workgroup of four wavefronts per trajectory (banded FP64
+    normal equations, blocked L D L^T)."""
     import numpy as np
     import torch
 

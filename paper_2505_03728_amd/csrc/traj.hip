@@ -60,6 +60,11 @@ struct TrajLds {
     // so they sit in LDS rather than behind lane-indexed global loads
     float lo[NJ], hi[NJ], vdt[NJ], acc5[5], jerk5[5];
     float red[4];                                      // per-wavefront partials of a reduction
+    // the part of the normal matrix that does not depend on the trajectory:
+    // smoothness and the two stencils, A(t, t - dtk) per joint at t * 5 + dtk
+    double ctab[5 * (TRAJ_VMAX / NJ)];
+    float racc[TRAJ_VMAX], rjerk[TRAJ_VMAX];          // stencil rows at the current point
+    int fail;                                          // a pivot failed in the factorisation
 };
 
 PK_DEV float wsum(float v)
@@ -218,13 +223,19 @@ PK_DEV float path_cost(TrajLds<NJ> &S, const TrajParams &P, const float *Q, int 
 // Band of A + lambda diag(max(A_vv, floor)) and the right-hand side -J^T r at
 // the current point, in precision T: A(v, v - k) at band[v * W + k].
 template <int NJ, typename T>
-PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, const TrajLds<NJ> &S,
+PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, TrajLds<NJ> &S,
                         float lam, int lane, T *band, T *rhs)
 {
     constexpr int W = TrajLds<NJ>::W;
     const int TT = P.T, V = TT * NJ;
-    const T ws2 = (T)P.w_smooth * (T)P.w_smooth;
     const T sa = (T)P.w_acc / ((T)P.dt * (T)P.dt), sj = (T)P.w_jerk / ((T)P.dt * (T)P.dt * (T)P.dt);
+    for (int v = lane; v < V; v += TRAJ_THREADS) {
+        const int t = v / NJ;
+        if (t >= 2 && t <= TT - 3) {
+            S.racc[v] = acc_row(P, S.Q, v, NJ);
+            S.rjerk[v] = jerk_row(P, S.Q, v, NJ);
+        }
+    }
     for (int e = lane; e < V * W; e += TRAJ_THREADS) {
         const int v = e / W, k = e - v * W;
         const int u = v - k;
@@ -234,28 +245,20 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
             const int t2 = u / NJ, i2 = u - t2 * NJ;
             if (i2 == i) {
                 const int dtk = t - t2;   // 0..4
+                a = (T)S.ctab[t * 5 + dtk];
                 if (dtk == 0) {
                     float rl, dl;
                     limit_row<NJ>(S, P, S.Q[v], i, rl, dl);
                     a += (T)dl * (T)dl;
                 }
-                // smoothness rows q_tau - q_{tau-1}, tau = 1..T-1
-                if (dtk == 0) a += (t >= 1 ? ws2 : (T)0) + (t <= TT - 2 ? ws2 : (T)0);
-                if (dtk == 1) a -= ws2;
-                // velocity-limit rows, where active
-                if (P.vmax) {
+                // velocity-limit rows q_tau - q_{tau-1}, where active
+                if (P.vmax && dtk <= 1) {
                     float rv, sv, rv1 = 0.f, sv1 = 0.f;
                     rv = sv = 0.f;
                     if (t >= 1) vel_row<NJ>(S, P, S.Q, v, i, rv, sv);
-                    if (t + 1 <= TT - 1) vel_row<NJ>(S, P, S.Q, v + NJ, i, rv1, sv1);
+                    if (dtk == 0 && t + 1 <= TT - 1) vel_row<NJ>(S, P, S.Q, v + NJ, i, rv1, sv1);
                     if (dtk == 0) a += (T)sv * (T)sv + (T)sv1 * (T)sv1;
-                    if (dtk == 1) a -= (T)sv * (T)sv;
-                }
-                // acceleration and jerk rows centred at tc = 2..T-3
-                for (int tc = t - 2; tc <= t2 + 2; ++tc) {
-                    if (tc < 2 || tc > TT - 3) continue;
-                    const int o1 = t - tc + 2, o2 = t2 - tc + 2;
-                    a += sa * sa * (T)S.acc5[o1] * (T)S.acc5[o2] + sj * sj * (T)S.jerk5[o1] * (T)S.jerk5[o2];
+                    else a -= (T)sv * (T)sv;
                 }
             }
             if (t2 == t && (t == 0 || t == TT - 1)) {
@@ -267,6 +270,7 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
         }
         band[e] = a;
     }
+    __syncthreads();   // stencil rows
     for (int v = lane; v < V; v += TRAJ_THREADS) {
         const int t = v / NJ, i = v - t * NJ;
         T g = 0;
@@ -289,7 +293,7 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, cons
         for (int tc = t - 2; tc <= t + 2; ++tc) {
             if (tc < 2 || tc > TT - 3) continue;
             const int o = t - tc + 2, vc = tc * NJ + i;
-            g += sa * (T)S.acc5[o] * (T)acc_row(P, S.Q, vc, NJ) + sj * (T)S.jerk5[o] * (T)jerk_row(P, S.Q, vc, NJ);
+            g += sa * (T)S.acc5[o] * (T)S.racc[vc] + sj * (T)S.jerk5[o] * (T)S.rjerk[vc];
         }
         if (t == 0 || t == TT - 1) {
             const float *J = t == 0 ? S.J0 : S.J1;
@@ -346,98 +350,104 @@ PK_DEV double recip(double d)
     return r;
 }
 
-// Right-looking L D L^T without square roots: after column j, band[j * W]
-// holds D_j and band[i * W + (i - j)] the unscaled column D_j L_ij; the
-// trailing update subtracts a_ij a_kj / D_j.  The column itself is never
-// rewritten, so the update of column j reads only entries it does not write
-// and one workgroup barrier per column orders the steps; a thread issues all
-// of its loads together with the pivot's so that one LDS round trip and the
-// reciprocal make up the column's latency.  The two triangular solves run on
-// the first wavefront with the right-hand side in registers (lane l holds
-// entries l, l + 64, ...): per chunk of CH steps the lanes read their
-// coefficients at once, then each step broadcasts the finished entry with
-// readlane and the lanes holding the next HB entries take their update, with
-// no memory access or branch on that dependent chain.
+// Band L D L^T without square roots (unit L), blocked by timestep: after
+// the factorisation band[j * W] holds D_j and band[i * W + (i - j)] the
+// unscaled entry D_j L_ij, with invd[j] = 1 / D_j.  Each block step of NJ
+// columns eliminates its window (the block's rows and the HB rows below it,
+// at most 64) on the first wavefront in registers, carrying the right-hand
+// side along as one more column (the forward substitution L y = rhs), then
+// all threads apply the rank-NJ update of the trailing triangle: two
+// workgroup barriers per NJ columns.  The backward solve L^T x = D^-1 y runs
+// on the first wavefront with the vector in registers (lane l holds entries
+// l, l + 64, ...): per chunk of CH steps the lanes read their coefficients
+// at once, then each step broadcasts the finished entry with readlane and the
+// lanes holding the previous HB entries take their update, with no memory
+// access or branch on that dependent chain.
 template <int NJ, typename T>
 PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
-                       const int (&mp)[pairs_per_lane<NJ>()], int lane, float *red)
+                       const int (&mp)[pairs_per_lane<NJ>()], int lane, float *red, int *fail)
 {
     constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W, PPL = pairs_per_lane<NJ>();
-    constexpr int NS = TRAJ_VMAX / 64, CH = 8;
+    constexpr int NS = TRAJ_VMAX / 64, CH = 8, NR = NJ + HB;
+    static_assert(NR <= 64, "a block step's window fits one wavefront");
     float mx = 0.f;
     for (int v = lane; v < V; v += TRAJ_THREADS) mx = fmaxf(mx, (float)band[v * W]);
     const T thresh = (T)thresh_rel * (T)block_max(mx, red);
-    bool bad = false;
-    for (int j = 0; j < V; ++j) {
-        // addresses clamped into the band so that every load is issued
-        // unconditionally (padding pairs and rows past V store nothing)
-        T ai[PPL], ak[PPL], at[PPL];
-        int tgt[PPL];
+    if (lane == 0) *fail = 0;
+    for (int c0 = 0; c0 < V; c0 += NJ) {
+        // Block step over columns c0 .. c0 + NJ - 1.  Lane r of the first
+        // wavefront holds row R = c0 + r of the window (the block's rows
+        // and the HB rows below) restricted to the block's columns, x[cc]
+        // = A(R, c0 + cc), 0 outside the band; the NJ elimination steps run
+        // in registers, each broadcasting its pivot row's column with
+        // readlane.
+        if (lane < 64) {
+            const int R = c0 + lane;
+            const bool live = lane < NR && R < V;
+            T x[NJ];
+#pragma unroll
+            for (int cc = 0; cc < NJ; ++cc) {
+                const int k = R - (c0 + cc);
+                x[cc] = live && k >= 0 && k <= HB ? band[R * W + k] : (T)0;
+            }
+            T bv = live ? rhs[R] : (T)0;   // right-hand side as one more column
+            bool bad = false;
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                T d = readlane_d(x[jj], jj);
+                if (!(d > thresh) || !(d < (T)INFINITY)) {
+                    bad = true;
+                    d = 1;
+                }
+                const T inv = recip(d);
+                if (lane == 0) invd[c0 + jj] = inv;
+                const T ell = lane > jj ? x[jj] : (T)0;   // unscaled D_jj L_(R, jj)
+#pragma unroll
+                for (int cc = jj + 1; cc < NJ; ++cc) x[cc] -= ell * (readlane_d(x[jj], cc) * inv);
+                bv -= ell * (readlane_d(bv, jj) * inv);
+            }
+#pragma unroll
+            for (int cc = 0; cc < NJ; ++cc) {
+                const int k = R - (c0 + cc);
+                if (live && k >= 0 && k <= HB) band[R * W + k] = x[cc];
+            }
+            if (live) rhs[R] = bv;
+            if (bad && lane == 0) *fail = 1;
+        }
+        __syncthreads();
+        // rank-NJ update of the trailing triangle: rows R >= R2 of the HB
+        // rows below the block, A(R, R2) -= sum_cc A(R, cc) A(R2, cc) / D_cc
+        // (unscaled entries); addresses are clamped into the band so that
+        // every load is issued unconditionally.
+        T dinv[NJ];
+#pragma unroll
+        for (int cc = 0; cc < NJ; ++cc) dinv[cc] = invd[c0 + cc];
 #pragma unroll
         for (int m = 0; m < PPL; ++m) {
             const int di = mp[m] & 0xff, dk = mp[m] >> 8;
-            const int i = min(j + di, V - 1), k = min(j + dk, V - 1);
-            tgt[m] = di && j + di < V ? i * W + (di - dk) : -1;
-            ai[m] = band[i * W + di];
-            ak[m] = band[k * W + dk];
-            at[m] = band[i * W + (di - dk)];
-        }
-        T d = band[j * W];
-        if (!(d > thresh) || !(d < (T)INFINITY)) {
-            bad = true;
-            d = 1;
-        }
-        const T inv = recip(d);
-        if (lane == 0) invd[j] = inv;
+            const int R = c0 + NJ - 1 + di, R2 = c0 + NJ - 1 + dk;
+            const bool ok = di && R < V;
+            const int Rc = min(R, V - 1), R2c = min(R2, V - 1);
+            T acc = 0;
 #pragma unroll
-        for (int m = 0; m < PPL; ++m)
-            if (tgt[m] >= 0) band[tgt[m]] = at[m] - ai[m] * (ak[m] * inv);
+            for (int cc = 0; cc < NJ; ++cc) {
+                const int k1 = NJ - 1 + di - cc, k2 = NJ - 1 + dk - cc;
+                const T a1 = band[Rc * W + min(k1, HB)], a2 = band[R2c * W + min(k2, HB)];
+                acc += (k1 <= HB ? a1 : (T)0) * (k2 <= HB ? a2 : (T)0) * dinv[cc];
+            }
+            if (ok) band[R * W + (di - dk)] -= acc;
+        }
         __syncthreads();
     }
-    if (bad) return false;
+    if (*fail) return false;
+    // rhs now holds y of L y = rhs (forward substitution rode along with the
+    // elimination)
     if (lane < 64) {
         T x[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int i = 64 * s + lane;
             x[s] = i < V ? rhs[i] : (T)0;
-        }
-        // L y = rhs: the entry finished at step j updates i in (j, j + HB] by
-        // -L_ij y_j.  This lane's candidate i sits in slot s = j / 64 when
-        // lane > j % 64 (coefficient cs), else in slot s + 1 (cn).  Steps at
-        // j >= V broadcast an entry that stays 0 and carry no coefficient.
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-#pragma unroll 1
-            for (int l0 = 0; l0 < 64; l0 += CH) {
-                const int j0 = 64 * s + l0;
-                if (j0 >= V) break;
-                T cs[CH], cn[CH];
-#pragma unroll
-                for (int u = 0; u < CH; ++u) {   // loads first, all in flight together
-                    const int j = j0 + u, l = l0 + u;
-                    const int i = 64 * s + lane + (lane > l ? 0 : 64);
-                    const bool ok = j < V && i < V && i - j <= HB;
-                    cs[u] = band[ok ? i * W + (i - j) : 0];
-                    cn[u] = invd[j < V ? j : 0];
-                }
-#pragma unroll
-                for (int u = 0; u < CH; ++u) {
-                    const int j = j0 + u, l = l0 + u;
-                    const bool up = lane > l;
-                    const int i = 64 * s + lane + (up ? 0 : 64);
-                    const bool ok = j < V && i < V && i - j <= HB;
-                    const T c = cs[u] * cn[u];
-                    cs[u] = ok && up ? c : (T)0;
-                    cn[u] = ok && !up ? c : (T)0;
-                }
-#pragma unroll
-                for (int u = 0; u < CH; ++u) {
-                    const T y = readlane_d(x[s], l0 + u);
-                    x[s] -= cs[u] * y;
-                    if (s + 1 < NS) x[s + 1] -= cn[u] * y;
-                }
-            }
         }
         // D z = y
 #pragma unroll
@@ -492,7 +502,7 @@ PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
 }
 
 template <int NJ>
-__global__ __launch_bounds__(TRAJ_THREADS) void traj_kernel(const RobotC *__restrict__ rb, TrajParams P)
+__global__ __launch_bounds__(TRAJ_THREADS, NJ <= 7 ? 2 : 1) void traj_kernel(const RobotC *__restrict__ rb, TrajParams P)
 {
     using L = TrajLds<NJ>;
     __shared__ L S;
@@ -512,6 +522,25 @@ __global__ __launch_bounds__(TRAJ_THREADS) void traj_kernel(const RobotC *__rest
     if (lane < 5) {
         S.acc5[lane] = ACC5[lane];
         S.jerk5[lane] = JERK5[lane];
+    }
+    {
+        // smoothness rows q_tau - q_{tau-1} (tau = 1..T-1), then the
+        // acceleration and jerk rows centred at tc = 2..T-3
+        const double ws2 = (double)P.w_smooth * (double)P.w_smooth;
+        const double sa = (double)P.w_acc / ((double)P.dt * (double)P.dt);
+        const double sj = (double)P.w_jerk / ((double)P.dt * (double)P.dt * (double)P.dt);
+        for (int x = lane; x < 5 * P.T; x += TRAJ_THREADS) {
+            const int t = x / 5, dtk = x - 5 * t, t2 = t - dtk;
+            double a = 0;
+            if (dtk == 0) a += (t >= 1 ? ws2 : 0.0) + (t <= P.T - 2 ? ws2 : 0.0);
+            if (dtk == 1) a -= ws2;
+            for (int tc = t - 2; tc <= t2 + 2; ++tc) {
+                if (tc < 2 || tc > P.T - 3) continue;
+                const int o1 = t - tc + 2, o2 = t2 - tc + 2;
+                a += sa * sa * (double)ACC5[o1] * (double)ACC5[o2] + sj * sj * (double)JERK5[o1] * (double)JERK5[o2];
+            }
+            S.ctab[x] = a;
+        }
     }
     __syncthreads();
 
@@ -585,7 +614,7 @@ __global__ __launch_bounds__(TRAJ_THREADS) void traj_kernel(const RobotC *__rest
         // rejected trial, as when the IK re-solve fails)
         form_system<NJ, double>(rb, P, S, lam, lane, S.band, S.b);
         __syncthreads();
-        const bool ok = band_solve<NJ, double>(S.band, S.b, S.invd, V, P.pivot_rel, mp, lane, S.red);
+        const bool ok = band_solve<NJ, double>(S.band, S.b, S.invd, V, P.pivot_rel, mp, lane, S.red, &S.fail);
         for (int v = lane; v < V; v += TRAJ_THREADS) S.Qt[v] = S.Q[v] + (ok ? (float)S.b[v] : 0.f);
         evaluate = ok;
         __syncthreads();
