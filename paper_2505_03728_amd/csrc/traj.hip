@@ -394,11 +394,10 @@ PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
             bool bad = false;
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) {
-                T d = readlane_d(x[jj], jj);
-                if (!(d > thresh) || !(d < (T)INFINITY)) {
-                    bad = true;
-                    d = 1;
-                }
+                // a failed pivot discards the whole factorisation, so the
+                // test stays off the dependent chain
+                const T d = readlane_d(x[jj], jj);
+                bad |= !(d > thresh) || !(d < (T)INFINITY);
                 const T inv = recip(d);
                 if (lane == 0) invd[c0 + jj] = inv;
                 const T ell = lane > jj ? x[jj] : (T)0;   // unscaled D_jj L_(R, jj)
@@ -428,13 +427,19 @@ PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
             const int R = c0 + NJ - 1 + di, R2 = c0 + NJ - 1 + dk;
             const bool ok = di && R < V;
             const int Rc = min(R, V - 1), R2c = min(R2, V - 1);
-            T acc = 0;
+            T term[NJ];
 #pragma unroll
             for (int cc = 0; cc < NJ; ++cc) {
                 const int k1 = NJ - 1 + di - cc, k2 = NJ - 1 + dk - cc;
                 const T a1 = band[Rc * W + min(k1, HB)], a2 = band[R2c * W + min(k2, HB)];
-                acc += (k1 <= HB ? a1 : (T)0) * (k2 <= HB ? a2 : (T)0) * dinv[cc];
+                term[cc] = (k1 <= HB ? a1 : (T)0) * dinv[cc] * (k2 <= HB ? a2 : (T)0);
             }
+            // pairwise sum: a short dependent chain
+#pragma unroll
+            for (int w = 1; w < NJ; w *= 2)
+#pragma unroll
+                for (int cc = 0; cc + w < NJ; cc += 2 * w) term[cc] += term[cc + w];
+            const T acc = term[0];
             if (ok) band[R * W + (di - dk)] -= acc;
         }
         __syncthreads();
