@@ -647,9 +647,10 @@ FP64_VALU_PEAK = 78.6       # TFLOP/s, MI355X FP64 vector (datasheet)
 
 
 def traj_solve_flops(V, hb):
-    """Algorithmic FLOPs of one damped band solve: band Cholesky (column scale
-    and trailing update) plus the two triangular solves, V variables,
-    half-bandwidth hb (divisions and square roots counted as one)."""
+    """Algorithmic FLOPs of one damped band solve, counted as a band Cholesky
+    (column scale and trailing update) plus the two triangular solves, V
+    variables, half-bandwidth hb (divisions and square roots counted as one;
+    the kernel's L D L^T has the same count up to lower-order terms)."""
     f = 0
     for j in range(V):
         w = min(hb, V - 1 - j)
@@ -693,7 +694,7 @@ def run_traj(args):
                           "unit": "TFLOP/s", "frac": round(ach / FP64_VALU_PEAK, 6), "traffic": None,
                           "kernel": "traj_kernel<7>", "kernel_ms": round(ms, 5),
                           "algorithmic_flops": flops,
-                          "count": "band Cholesky + two triangular solves per LM iteration"})
+                          "count": "band factorisation (Cholesky count) + two triangular solves per LM iteration"})
     if not args.no_cpu:
         import oracle
         from oracle import traj

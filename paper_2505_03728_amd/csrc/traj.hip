@@ -1,17 +1,17 @@
 // Trajectory optimisation: LM over a trajectory of T configurations of a
 // single-chain robot (Sec. II: a configuration interacts only with its
 // temporal neighbours, so the normal equations are banded).  One trajectory
-// per 64-lane wavefront:
+// per workgroup of four wavefronts:
 //   * lanes 0 and 1 run FK, the pose log and the pose Jacobian at the first
 //     and the last configuration (start and goal pose costs);
-//   * every lane takes its share of the T*n variables for the limit,
+//   * every thread takes its share of the T*n variables for the limit,
 //     smoothness, velocity-limit and five-point acceleration/jerk terms;
 //   * J^T J is banded (half-bandwidth 4n in time-major order): it is formed
-//     straight into a band in LDS, damped, factored by a right-looking band
-//     Cholesky (the trailing update of each column spread over the lanes)
-//     and solved, all in FP64: the jerk rows outweigh the smoothness rows by
-//     ~1e5 in J^T J, and at that conditioning an FP32 factorisation steers LM
-//     off the FP64 path (FP64 FMAs issue at the unpacked FP32 rate).
+//     straight into a band in LDS, damped, factored by a band L D L^T
+//     blocked by timestep and solved, all in FP64: the jerk rows outweigh
+//     the smoothness rows by ~1e5 in J^T J, and at that conditioning an FP32
+//     factorisation steers LM off the FP64 path (FP64 FMAs issue at the
+//     unpacked FP32 rate).
 #include <string.h>
 
 #include <cmath>
