@@ -309,24 +309,74 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, Traj
 // and the solve of L D L^T x = rhs (x over rhs).  A pivot D_j not above
 // thresh_rel times the largest damped diagonal fails the factorisation
 // (returns false).
+// The trailing triangle of a block step at c0: entries (R, R2) =
+// (c0 + NJ - 1 + di, c0 + NJ - 1 + dk), 1 <= dk <= di <= HB, in two parts:
+// A (dk <= NJ: the next block's columns, which its elimination needs) and B
+// (dk > NJ).  A is spread over the workgroup, B over wavefronts 1..3.
 template <int NJ>
-constexpr int pairs_per_lane() { return (TrajLds<NJ>::NPAIR + TRAJ_THREADS - 1) / TRAJ_THREADS; }
+struct Pairs {
+    static constexpr int HB = TrajLds<NJ>::HB;
+    static constexpr int NA = NJ * (HB + 1) - NJ * (NJ + 1) / 2;
+    static constexpr int NB = (HB - NJ) * (HB - NJ + 1) / 2;
+    static constexpr int PA = (NA + TRAJ_THREADS - 1) / TRAJ_THREADS;
+    static constexpr int PB = (NB + TRAJ_THREADS - 64 - 1) / (TRAJ_THREADS - 64);
+};
 
-// This thread's entries of the trailing-update triangle, (di | dk << 8), 0
-// past the end: pair p = lane + TRAJ_THREADS m in row-major order of
-// 1 <= dk <= di <= HB.
-template <int NJ>
-PK_DEV void lane_pairs(int lane, int (&mp)[pairs_per_lane<NJ>()])
+// Entries p = t + stride m of the part with dk in [dlo, HB], listed dk-major
+// (di = dk .. HB within a dk), packed di | dk << 8; 0 for t < 0 and past total.
+template <int NJ, int M>
+PK_DEV void part_pairs(int t, int stride, int dlo, int total, int (&mp)[M])
 {
+    constexpr int HB = TrajLds<NJ>::HB;
 #pragma unroll
-    for (int m = 0; m < pairs_per_lane<NJ>(); ++m) {
-        const int p = lane + TRAJ_THREADS * m;
-        int di = 1, rem = p;
-        while (rem >= di) {
-            rem -= di;
-            ++di;
+    for (int m = 0; m < M; ++m) {
+        const int p = t + stride * m;
+        int dk = dlo, rem = p;
+        while (dk <= HB && rem >= HB - dk + 1) {
+            rem -= HB - dk + 1;
+            ++dk;
         }
-        mp[m] = p < TrajLds<NJ>::NPAIR ? (di | ((rem + 1) << 8)) : 0;
+        mp[m] = t >= 0 && p < total ? ((dk + rem) | (dk << 8)) : 0;
+    }
+}
+
+// Rank-NJ update of the listed entries of the trailing triangle of the block
+// step at c0: A(R, R2) -= sum_cc A(R, cc) A(R2, cc) / D_cc over the block's
+// columns (unscaled entries).  Addresses are clamped into the band so that
+// every load is issued unconditionally; padding entries store nothing.
+template <int NJ, typename T, int M>
+PK_DEV void trail(T *band, const T *invd, int V, int c0_, const int (&mp)[M])
+{
+    constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W;
+    // the block offset as an opaque uniform value: addresses are recomputed
+    // per block step rather than carried as induction variables across the
+    // factorisation (which spilled them)
+    const int c0 = __builtin_amdgcn_readfirstlane(c0_);
+    T dinv[NJ];
+#pragma unroll
+    for (int cc = 0; cc < NJ; ++cc) dinv[cc] = invd[c0 + cc];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        // likewise for the pair: its offsets are derived here, not hoisted
+        int pm = mp[m];
+        asm volatile("" : "+v"(pm));
+        const int di = pm & 0xff, dk = pm >> 8;
+        const int R = c0 + NJ - 1 + di, R2 = c0 + NJ - 1 + dk;
+        const bool ok = di && R < V;
+        const int Rc = min(R, V - 1), R2c = min(R2, V - 1);
+        T term[NJ];
+#pragma unroll
+        for (int cc = 0; cc < NJ; ++cc) {
+            const int k1 = NJ - 1 + di - cc, k2 = NJ - 1 + dk - cc;
+            const T a1 = band[Rc * W + min(k1, HB)], a2 = band[R2c * W + min(k2, HB)];
+            term[cc] = (k1 <= HB ? a1 : (T)0) * dinv[cc] * (k2 <= HB ? a2 : (T)0);
+        }
+        // pairwise sum: a short dependent chain
+#pragma unroll
+        for (int w = 1; w < NJ; w *= 2)
+#pragma unroll
+            for (int cc = 0; cc + w < NJ; cc += 2 * w) term[cc] += term[cc + w];
+        if (ok) band[R * W + (di - dk)] -= term[0];
     }
 }
 
@@ -365,9 +415,10 @@ PK_DEV double recip(double d)
 // access or branch on that dependent chain.
 template <int NJ, typename T>
 PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
-                       const int (&mp)[pairs_per_lane<NJ>()], int lane, float *red, int *fail)
+                       const int (&mpa)[Pairs<NJ>::PA], const int (&mpb)[Pairs<NJ>::PB], int lane,
+                       float *red, int *fail)
 {
-    constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W, PPL = pairs_per_lane<NJ>();
+    constexpr int HB = TrajLds<NJ>::HB, W = TrajLds<NJ>::W;
     constexpr int NS = TRAJ_VMAX / 64, CH = 8, NR = NJ + HB;
     static_assert(NR <= 64, "a block step's window fits one wavefront");
     float mx = 0.f;
@@ -381,7 +432,11 @@ PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
         // = A(R, c0 + cc), 0 outside the band; the NJ elimination steps run
         // in registers, each broadcasting its pivot row's column with
         // readlane.
-        if (lane < 64) {
+        if (lane >= 64) {
+            // meanwhile: part B of the previous block (entries beyond this
+            // block's columns, which the elimination does not touch)
+            if (c0 > 0) trail<NJ, T>(band, invd, V, c0 - NJ, mpb);
+        } else {
             const int R = c0 + lane;
             const bool live = lane < NR && R < V;
             T x[NJ];
@@ -414,34 +469,7 @@ PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
             if (bad && lane == 0) *fail = 1;
         }
         __syncthreads();
-        // rank-NJ update of the trailing triangle: rows R >= R2 of the HB
-        // rows below the block, A(R, R2) -= sum_cc A(R, cc) A(R2, cc) / D_cc
-        // (unscaled entries); addresses are clamped into the band so that
-        // every load is issued unconditionally.
-        T dinv[NJ];
-#pragma unroll
-        for (int cc = 0; cc < NJ; ++cc) dinv[cc] = invd[c0 + cc];
-#pragma unroll
-        for (int m = 0; m < PPL; ++m) {
-            const int di = mp[m] & 0xff, dk = mp[m] >> 8;
-            const int R = c0 + NJ - 1 + di, R2 = c0 + NJ - 1 + dk;
-            const bool ok = di && R < V;
-            const int Rc = min(R, V - 1), R2c = min(R2, V - 1);
-            T term[NJ];
-#pragma unroll
-            for (int cc = 0; cc < NJ; ++cc) {
-                const int k1 = NJ - 1 + di - cc, k2 = NJ - 1 + dk - cc;
-                const T a1 = band[Rc * W + min(k1, HB)], a2 = band[R2c * W + min(k2, HB)];
-                term[cc] = (k1 <= HB ? a1 : (T)0) * dinv[cc] * (k2 <= HB ? a2 : (T)0);
-            }
-            // pairwise sum: a short dependent chain
-#pragma unroll
-            for (int w = 1; w < NJ; w *= 2)
-#pragma unroll
-                for (int cc = 0; cc + w < NJ; cc += 2 * w) term[cc] += term[cc + w];
-            const T acc = term[0];
-            if (ok) band[R * W + (di - dk)] -= acc;
-        }
+        trail<NJ, T>(band, invd, V, c0, mpa);   // part A of this block
         __syncthreads();
     }
     if (*fail) return false;
@@ -515,8 +543,9 @@ __global__ __launch_bounds__(TRAJ_THREADS, NJ <= 7 ? 2 : 1) void traj_kernel(con
     const int64_t b = blockIdx.x;
     if (b >= P.B) return;   // uniform per workgroup
     const int TT = P.T, V = TT * NJ;
-    int mp[pairs_per_lane<NJ>()];
-    lane_pairs<NJ>(lane, mp);
+    int mpa[Pairs<NJ>::PA], mpb[Pairs<NJ>::PB];
+    part_pairs<NJ>(lane, TRAJ_THREADS, 1, Pairs<NJ>::NA, mpa);
+    part_pairs<NJ>(lane - 64, TRAJ_THREADS - 64, NJ + 1, Pairs<NJ>::NB, mpb);
     const float *src = P.init + b * (int64_t)V;
     for (int v = lane; v < V; v += TRAJ_THREADS) S.Q[v] = src[v];
     if (lane < NJ) {
@@ -619,7 +648,7 @@ __global__ __launch_bounds__(TRAJ_THREADS, NJ <= 7 ? 2 : 1) void traj_kernel(con
         // rejected trial, as when the IK re-solve fails)
         form_system<NJ, double>(rb, P, S, lam, lane, S.band, S.b);
         __syncthreads();
-        const bool ok = band_solve<NJ, double>(S.band, S.b, S.invd, V, P.pivot_rel, mp, lane, S.red, &S.fail);
+        const bool ok = band_solve<NJ, double>(S.band, S.b, S.invd, V, P.pivot_rel, mpa, mpb, lane, S.red, &S.fail);
         for (int v = lane; v < V; v += TRAJ_THREADS) S.Qt[v] = S.Q[v] + (ok ? (float)S.b[v] : 0.f);
         evaluate = ok;
         __syncthreads();
