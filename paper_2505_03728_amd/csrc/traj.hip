@@ -406,8 +406,10 @@ PK_DEV double recip(double d)
 // columns eliminates its window (the block's rows and the HB rows below it,
 // at most 64) on the first wavefront in registers, carrying the right-hand
 // side along as one more column (the forward substitution L y = rhs), then
-// all threads apply the rank-NJ update of the trailing triangle: two
-// workgroup barriers per NJ columns.  The backward solve L^T x = D^-1 y runs
+// all threads apply the part of the block's rank-NJ trailing update that
+// falls in the next block's columns; the rest of it runs on wavefronts 1..3
+// while wavefront 0 eliminates the next block (look-ahead: the two touch
+// disjoint entries).  Two workgroup barriers per NJ columns.  The backward solve L^T x = D^-1 y runs
 // on the first wavefront with the vector in registers (lane l holds entries
 // l, l + 64, ...): per chunk of CH steps the lanes read their coefficients
 // at once, then each step broadcasts the finished entry with readlane and the
