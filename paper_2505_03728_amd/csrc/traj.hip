@@ -307,10 +307,6 @@ PK_DEV void form_system(const RobotC *__restrict__ rb, const TrajParams &P, Traj
     }
 }
 
-// In-place band L D L^T factorisation of band (half-bandwidth HB, unit L)
-// and the solve of L D L^T x = rhs (x over rhs).  A pivot D_j not above
-// thresh_rel times the largest damped diagonal fails the factorisation
-// (returns false).
 // The trailing triangle of a block step at c0: entries (R, R2) =
 // (c0 + NJ - 1 + di, c0 + NJ - 1 + dk), 1 <= dk <= di <= HB, in two parts:
 // A (dk <= NJ: the next block's columns, which its elimination needs) and B
@@ -402,21 +398,26 @@ PK_DEV double recip(double d)
     return fma(r, fma(-d, r, 1.0), r);
 }
 
-// Band L D L^T without square roots (unit L), blocked by timestep: after
-// the factorisation band[j * W] holds D_j and band[i * W + (i - j)] the
-// unscaled entry D_j L_ij, with invd[j] = 1 / D_j.  Each block step of NJ
-// columns eliminates its window (the block's rows and the HB rows below it,
-// at most 64) on the first wavefront in registers, carrying the right-hand
-// side along as one more column (the forward substitution L y = rhs), then
-// all threads apply the part of the block's rank-NJ trailing update that
-// falls in the next block's columns; the rest of it runs on wavefronts 1..3
-// while wavefront 0 eliminates the next block (look-ahead: the two touch
-// disjoint entries).  Two workgroup barriers per NJ columns.  The backward solve L^T x = D^-1 y runs
-// on the first wavefront with the vector in registers (lane l holds entries
-// l, l + 64, ...): per chunk of CH steps the lanes read their coefficients
-// at once, then each step broadcasts the finished entry with readlane and the
-// lanes holding the previous HB entries take their update, with no memory
-// access or branch on that dependent chain.
+// In-place band L D L^T factorisation of band (half-bandwidth HB, unit L)
+// and the solve of L D L^T x = rhs (x over rhs).  A pivot D_j not above
+// thresh_rel times the largest damped diagonal fails the factorisation
+// (returns false).
+//
+// No square roots; blocked by timestep: after the factorisation band[j * W]
+// holds D_j and band[i * W + (i - j)] the unscaled entry D_j L_ij, with
+// invd[j] = 1 / D_j.  Each block step of NJ columns eliminates its window
+// (the block's rows and the HB rows below it, at most 64) on the first
+// wavefront in registers, carrying the right-hand side along as one more
+// column (the forward substitution L y = rhs); then all threads apply the
+// part of the block's rank-NJ trailing update that falls in the next block's
+// columns, and the rest of it runs on wavefronts 1..3 while wavefront 0
+// eliminates the next block (look-ahead: the two touch disjoint entries).
+// Two workgroup barriers per NJ columns.  The backward solve L^T x = D^-1 y
+// runs on the first wavefront with the vector in registers (lane l holds
+// entries l, l + 64, ...): per chunk of CH steps the lanes read their
+// coefficients at once, then each step broadcasts the finished entry with
+// readlane and the lanes holding the previous HB entries take their update,
+// with no memory access or branch on that dependent chain.
 template <int NJ, typename T>
 PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
                        const int (&mpa)[Pairs<NJ>::PA], const int (&mpb)[Pairs<NJ>::PB], int lane,
@@ -538,8 +539,11 @@ PK_DEV bool band_solve(T *band, T *rhs, T *invd, int V, float thresh_rel,
     return true;
 }
 
+// Two workgroups per CU where their LDS fits (up to 7 joints), which also
+// holds the register budget to 256 per lane.
 template <int NJ>
-__global__ __launch_bounds__(TRAJ_THREADS, NJ <= 7 ? 2 : 1) void traj_kernel(const RobotC *__restrict__ rb, TrajParams P)
+__global__ __launch_bounds__(TRAJ_THREADS, NJ <= 7 ? 2 : 1) void traj_kernel(const RobotC *__restrict__ rb,
+                                                                             TrajParams P)
 {
     using L = TrajLds<NJ>;
     __shared__ L S;
@@ -575,7 +579,8 @@ __global__ __launch_bounds__(TRAJ_THREADS, NJ <= 7 ? 2 : 1) void traj_kernel(con
             for (int tc = t - 2; tc <= t2 + 2; ++tc) {
                 if (tc < 2 || tc > P.T - 3) continue;
                 const int o1 = t - tc + 2, o2 = t2 - tc + 2;
-                a += sa * sa * (double)ACC5[o1] * (double)ACC5[o2] + sj * sj * (double)JERK5[o1] * (double)JERK5[o2];
+                a += sa * sa * (double)ACC5[o1] * (double)ACC5[o2] +
+                     sj * sj * (double)JERK5[o1] * (double)JERK5[o2];
             }
             S.ctab[x] = a;
         }
@@ -592,7 +597,7 @@ __global__ __launch_bounds__(TRAJ_THREADS, NJ <= 7 ? 2 : 1) void traj_kernel(con
     float lam = P.lambda0, cost = 0.f;
     // Each pass evaluates one point (first the initial trajectory, then each
     // trial), takes or rejects it, then forms and solves the next step; a
-    // failed solve is a rejected trial.  All decisions are wave-uniform.
+    // failed solve is a rejected trial.  All decisions are workgroup-uniform.
     for (;;) {
         bool acc = false;
         if (evaluate) {
@@ -652,7 +657,8 @@ __global__ __launch_bounds__(TRAJ_THREADS, NJ <= 7 ? 2 : 1) void traj_kernel(con
         // rejected trial, as when the IK re-solve fails)
         form_system<NJ, double>(rb, P, S, lam, lane, S.band, S.b);
         __syncthreads();
-        const bool ok = band_solve<NJ, double>(S.band, S.b, S.invd, V, P.pivot_rel, mpa, mpb, lane, S.red, &S.fail);
+        const bool ok =
+            band_solve<NJ, double>(S.band, S.b, S.invd, V, P.pivot_rel, mpa, mpb, lane, S.red, &S.fail);
         for (int v = lane; v < V; v += TRAJ_THREADS) S.Qt[v] = S.Q[v] + (ok ? (float)S.b[v] : 0.f);
         evaluate = ok;
         __syncthreads();
