@@ -362,19 +362,27 @@ PK_DEV void trail(T *band, const T *invd, int V, int c0_, const int (&mp)[M])
         const int R = c0 + NJ - 1 + di, R2 = c0 + NJ - 1 + dk;
         const bool ok = di && R < V;
         const int Rc = min(R, V - 1), R2c = min(R2, V - 1);
+        // every load first (the target included), so that they are in flight
+        // together; the band-edge selects come after
+        T a1[NJ], a2[NJ];
+#pragma unroll
+        for (int cc = 0; cc < NJ; ++cc) {
+            a1[cc] = band[Rc * W + min(NJ - 1 + di - cc, HB)];
+            a2[cc] = band[R2c * W + min(NJ - 1 + dk - cc, HB)];
+        }
+        const T tv = band[Rc * W + (di - dk)];
         T term[NJ];
 #pragma unroll
         for (int cc = 0; cc < NJ; ++cc) {
             const int k1 = NJ - 1 + di - cc, k2 = NJ - 1 + dk - cc;
-            const T a1 = band[Rc * W + min(k1, HB)], a2 = band[R2c * W + min(k2, HB)];
-            term[cc] = (k1 <= HB ? a1 : (T)0) * dinv[cc] * (k2 <= HB ? a2 : (T)0);
+            term[cc] = (k1 <= HB ? a1[cc] : (T)0) * dinv[cc] * (k2 <= HB ? a2[cc] : (T)0);
         }
         // pairwise sum: a short dependent chain
 #pragma unroll
         for (int w = 1; w < NJ; w *= 2)
 #pragma unroll
             for (int cc = 0; cc + w < NJ; cc += 2 * w) term[cc] += term[cc + w];
-        if (ok) band[R * W + (di - dk)] -= term[0];
+        if (ok) band[R * W + (di - dk)] = tv - term[0];
     }
 }
 
