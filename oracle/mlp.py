@@ -88,25 +88,33 @@ def backward(params, cache, dy, emulate_bf16=False):
 
 
 class Adam:
+    """Adam (Kingma & Ba 2015, Algorithm 1): per parameter array
+        m_t = b1 m_{t-1} + (1 - b1) g_t,   v_t = b2 v_{t-1} + (1 - b2) g_t^2,
+        theta_t = theta_{t-1} - lr (m_t / (1 - b1^t)) / (sqrt(v_t / (1 - b2^t)) + eps).
+    The moments ``m[layer][0|1]`` / ``v[layer][0|1]`` (weights, bias) start at
+    zero; ``t`` counts the steps taken."""
+
     def __init__(self, params, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.lr, self.b1, self.b2, self.eps = lr, b1, b2, eps
-        self.m = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
-        self.v = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+        self.m = [[np.zeros(np.shape(W)), np.zeros(np.shape(b))] for W, b in params]
+        self.v = [[np.zeros(np.shape(W)), np.zeros(np.shape(b))] for W, b in params]
         self.t = 0
 
     def step(self, params, grads):
+        """New parameters [(W, b)] after one step with gradients [(dW, db)]."""
         self.t += 1
         c1 = 1.0 - self.b1 ** self.t
         c2 = 1.0 - self.b2 ** self.t
         out = []
-        for i, ((W, b), (gW, gb)) in enumerate(zip(params, grads)):
+        for i, (layer, glayer) in enumerate(zip(params, grads)):
             new = []
-            for j, (p, g) in enumerate(((W, gW), (b, gb))):
-                m = self.b1 * self.m[i][j] + (1 - self.b1) * g
-                v = self.b2 * self.v[i][j] + (1 - self.b2) * g * g
-                self.m[i] = tuple(m if jj == j else self.m[i][jj] for jj in range(2))
-                self.v[i] = tuple(v if jj == j else self.v[i][jj] for jj in range(2))
-                new.append(p - self.lr * (m / c1) / (np.sqrt(v / c2) + self.eps))
+            for j in range(2):
+                g = np.asarray(glayer[j], dtype=np.float64)
+                self.m[i][j] = self.b1 * self.m[i][j] + (1 - self.b1) * g
+                self.v[i][j] = self.b2 * self.v[i][j] + (1 - self.b2) * g * g
+                mhat = self.m[i][j] / c1
+                vhat = self.v[i][j] / c2
+                new.append(layer[j] - self.lr * mhat / (np.sqrt(vhat) + self.eps))
             out.append(tuple(new))
         return out
 
