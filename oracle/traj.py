@@ -117,7 +117,9 @@ def lm_solve(tree, start, goal, c, o, Q0):
     (<= lambda_max; a reject at lambda_max stalls); every trial is one
     iteration; with early_exit the run stops once both endpoint poses are
     within tolerance.  Returns the trajectory, cost, counters and status
-    (CONVERGED when both endpoint poses meet the tolerance at the end)."""
+    (CONVERGED when both endpoint poses meet the tolerance at the end), the
+    accept sequence and, per iteration, whether its decision was a near-tie
+    (|c' - c| <= 1e-5 c, as the IK oracle flags them)."""
     Q = np.array(Q0, np.float64)
     T, n = Q.shape
     cst = cost(tree, start, goal, c, Q)
@@ -130,7 +132,7 @@ def lm_solve(tree, start, goal, c, o, Q0):
         return bool(np.all(pe <= o["tol_pos"]) and np.all(re <= o["tol_rot"]))
 
     done = o["early_exit"] and meets(Q)
-    trace = []
+    trace, ties = [], []
     while not done and iters < o["max_iters"]:
         r = residual(tree, start, goal, c, Q)
         J = jacobian(tree, start, goal, c, Q)
@@ -141,6 +143,7 @@ def lm_solve(tree, start, goal, c, o, Q0):
         Qt = Q + d.reshape(T, n)
         ct = cost(tree, start, goal, c, Qt)
         iters += 1
+        ties.append(int(np.isfinite(ct) and abs(ct - cst) <= 1e-5 * cst))
         if ct < cst:
             Q, cst = Qt, ct
             lam = max(lam / o["nu_down"], o["lambda_min"])
@@ -158,4 +161,5 @@ def lm_solve(tree, start, goal, c, o, Q0):
     pe, re = endpoint_errors(tree, start, goal, Q)
     status = oracle.CONVERGED if ok else (oracle.STALLED if stalled else oracle.MAX_ITERS)
     return {"Q": Q, "cost": cst, "iters": iters, "accepts": accepts, "status": status,
-            "pos_err": pe, "rot_err": re, "trace_acc": np.array(trace, np.int32)}
+            "pos_err": pe, "rot_err": re, "trace_acc": np.array(trace, np.int32),
+            "trace_tie": np.array(ties, np.int32)}

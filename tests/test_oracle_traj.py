@@ -124,3 +124,8 @@ def test_smoothness_only_optimum_is_a_straight_line():
     line = (1 - s) * Q[0] + s * Q[-1]
     np.testing.assert_allclose(Q, line, atol=1e-4)
     assert res["cost"] < traj.cost(ARM, st, gl, c, Q0)
+    # one accept flag and one near-tie flag per iteration (this run's
+    # decisions all move the cost by more than 1e-5 of itself)
+    assert len(res["trace_acc"]) == len(res["trace_tie"]) == res["iters"] == 60
+    assert set(np.unique(res["trace_acc"])) <= {0, 1} and not res["trace_tie"].any()
+    assert res["accepts"] == res["trace_acc"].sum()
