@@ -171,6 +171,8 @@ typedef struct {
     int32_t trace_iters;         /* 0..64                                      */
     float *trace_q;              /* [trace_iters][n][N]                        */
     int32_t *trace_accept;       /* [trace_iters][N]                           */
+    float *pose_cost;            /* [N] pose-only residual sum of squares (the
+                                    best-of-K key of targets no seed solved)   */
 } pk_ik_outputs;
 
 /* Context on one device (ordinal as seen by HIP).  Allocates the context's
@@ -411,7 +413,7 @@ int pk_ik_beam(pk_ctx *ctx, int32_t robot_id, int64_t n_targets, const float *ta
  * pivot_rel times the largest damped diagonal rejects the step).  Robots: one chain of 4, 6, 7 or 10 joints (revolute or
  * prismatic, no mimic joints) with one pose EE; T >= 5 and T * n <= 256.
  * Asynchronous on `stream`.  Errors: PK_EINVAL (NULL pointer, bad sizes or
- * costs), PK_EUNSUPPORTED (robot shape). */
+ * costs, w_vel != 0 without vmax), PK_EUNSUPPORTED (robot shape). */
 typedef struct {
     int64_t B;                       /* trajectories                              */
     int32_t T;                       /* timesteps                                 */
@@ -424,7 +426,8 @@ typedef struct {
     float dt;                        /* seconds between configurations            */
     float w_pos, w_rot;              /* start / goal pose rows                    */
     float w_limit, w_smooth, w_vel, w_acc, w_jerk;
-    const float *vmax;               /* device [n] velocity limits, or NULL: no velocity rows */
+    const float *vmax;               /* device [n] velocity limits; NULL only with
+                                        w_vel == 0 (no velocity rows), else PK_EINVAL */
 } pk_traj_costs;
 
 typedef struct {

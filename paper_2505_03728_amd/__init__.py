@@ -72,7 +72,7 @@ class _Outputs(C.Structure):
                 ("status", C.c_void_p), ("iters_to_tol", C.c_void_p),
                 ("best_index", C.c_void_p), ("best_joints", C.c_void_p),
                 ("target_success", C.c_void_p), ("trace_iters", C.c_int32),
-                ("trace_q", C.c_void_p), ("trace_accept", C.c_void_p)]
+                ("trace_q", C.c_void_p), ("trace_accept", C.c_void_p), ("pose_cost", C.c_void_p)]
 
 
 class _SeededOptions(C.Structure):
@@ -255,6 +255,29 @@ def _ptr(t):
     return None if t is None else t.data_ptr()
 
 
+def _check(t, name, shape, dtype="float32", device=None):
+    """Raises PkError (PK_EINVAL) unless ``t`` is a contiguous tensor of
+    ``dtype`` and ``shape`` (None entries match any size) on ``device``: the
+    kernels index these buffers by the sizes the call passes, so a mismatch
+    would read or write past them."""
+    import torch
+    want = getattr(torch, dtype)
+    if not isinstance(t, torch.Tensor):
+        raise PkError(-1, f"{name}: expected a tensor")
+    if t.dtype != want:
+        raise PkError(-1, f"{name}: dtype {t.dtype}, expected {want}")
+    if device is not None and t.device != device:
+        raise PkError(-1, f"{name}: on {t.device}, expected {device}")
+    if t.device.type != "cuda":
+        raise PkError(-1, f"{name}: must be a device tensor")
+    if not t.is_contiguous():
+        raise PkError(-1, f"{name}: must be contiguous")
+    if len(t.shape) != len(shape) or any(w is not None and int(a) != int(w)
+                                         for a, w in zip(t.shape, shape)):
+        raise PkError(-1, f"{name}: shape {tuple(t.shape)}, expected "
+                          f"{tuple('*' if w is None else w for w in shape)}")
+
+
 class Context:
     """One library context on one HIP device."""
 
@@ -350,7 +373,7 @@ class Context:
         out = {"joints": f(n, N)}
         if full:
             out.update(pos_err=f(m, N), rot_err=f(m, N), cost=f(N), iters=i(N), accepts=i(N),
-                       status=i(N), iters_to_tol=i(N))
+                       status=i(N), iters_to_tol=i(N), pose_cost=f(N))
         if best:
             out.update(best_index=i(T), best_joints=f(n, T), target_success=i(T))
         if trace_iters:
@@ -370,6 +393,9 @@ class Context:
         info = self.robot_info(rid)
         dev = targets.device
         K = seeder.K
+        _check(targets, "targets", (info["target_floats"], T))
+        if fallback_K:
+            _check(fallback_seeds, "fallback_seeds", (info["n"], T * int(fallback_K)), device=dev)
         i = lambda *s: torch.empty(s, dtype=torch.int32, device=dev)
         out = {"best_joints": torch.empty((info["n"], T), dtype=torch.float32, device=dev),
                "target_success": i(T), "source": i(T), "iters_to_tol": i(T), "n_fallback": i(1)}
@@ -390,18 +416,41 @@ class Context:
         return out
 
     @staticmethod
+    def _check_ik(info, targets, seeds, T, K, out=None):
+        """Shapes, dtypes and device of a batch and its outputs (as in
+        alloc_outputs) against the robot's sizes."""
+        n, m, N = info["n"], info["m"], T * K
+        dev = targets.device
+        _check(targets, "targets", (info["target_floats"], T))
+        _check(seeds, "seeds", (n, N), device=dev)
+        if out is None:
+            return
+        tr = int(out.get("_trace_iters", 0))
+        shapes = {"joints": ((n, N), "float32"), "pos_err": ((m, N), "float32"),
+                  "rot_err": ((m, N), "float32"), "cost": ((N,), "float32"),
+                  "iters": ((N,), "int32"), "accepts": ((N,), "int32"), "status": ((N,), "int32"),
+                  "iters_to_tol": ((N,), "int32"), "best_index": ((T,), "int32"),
+                  "best_joints": ((n, T), "float32"), "target_success": ((T,), "int32"),
+                  "trace_q": ((tr, n, N), "float32"), "trace_accept": ((tr, N), "int32"),
+                  "pose_cost": ((N,), "float32")}
+        for k, (shp, dt) in shapes.items():
+            if out.get(k) is not None:
+                _check(out[k], k, shp, dt, device=dev)
+
+    @staticmethod
     def _outputs_c(out):
         return _Outputs(*[_ptr(out.get(k)) for k in ["joints", "pos_err", "rot_err", "cost", "iters",
                                                       "accepts", "status", "iters_to_tol",
                                                       "best_index", "best_joints",
                                                       "target_success"]],
                         int(out.get("_trace_iters", 0)), _ptr(out.get("trace_q")),
-                        _ptr(out.get("trace_accept")))
+                        _ptr(out.get("trace_accept")), _ptr(out.get("pose_cost")))
 
     def _groups_c(self, groups):
         arr = (_Group * len(groups))()
         for i, g in enumerate(groups):
             T = g["targets"].shape[1]
+            self._check_ik(self.robot_info(g["rid"]), g["targets"], g["seeds"], T, g["K"], g["out"])
             arr[i] = _Group(g["rid"], _Problem(T, g["K"], _ptr(g["targets"]), _ptr(g["seeds"])),
                             g["weights"]._c(), self._outputs_c(g["out"]))
         return arr
@@ -455,6 +504,7 @@ class Context:
         """IK-Beam (see include/pkmi.h): targets [tf, T], seeds [n, T*n_seeds];
         out from alloc_beam_outputs (allocated here when None).  Returns out."""
         T = targets.shape[1]
+        self._check_ik(self.robot_info(rid), targets, seeds, T, int(n_seeds))
         if out is None:
             out = self.alloc_beam_outputs(rid, T, n_seeds, keep, stages, targets.device)
         oo = _BeamOutputs(*[_ptr(out.get(k)) for k in _BEAM_OUT])
@@ -472,13 +522,29 @@ class Context:
         tensors traj [B, T, n], cost, iters, accepts, status [B], pos_err /
         rot_err [2, B]."""
         torch = self._torch
+        info = self.robot_info(rid)
+        if init.dim() != 3:
+            raise PkError(-1, f"init: shape {tuple(init.shape)}, expected (B, T, n)")
         B, T, n = init.shape
+        if n != info["n"]:
+            raise PkError(-1, f"init: last dimension {n}, the robot has {info['n']} variables")
         dev = init.device
+        _check(init, "init", (B, T, n))
+        _check(start, "start", (7, B), device=dev)
+        _check(goal, "goal", (7, B), device=dev)
+        if vmax is not None:
+            _check(vmax, "vmax", (n,), device=dev)
         if out is None:
             f = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
             i = lambda *s: torch.empty(s, dtype=torch.int32, device=dev)
             out = {"traj": f(B, T, n), "cost": f(B), "iters": i(B), "accepts": i(B),
                    "status": i(B), "pos_err": f(2, B), "rot_err": f(2, B)}
+        shapes = {"traj": (B, T, n), "cost": (B,), "iters": (B,), "accepts": (B,), "status": (B,),
+                  "pos_err": (2, B), "rot_err": (2, B)}
+        for k, shp in shapes.items():
+            if out.get(k) is not None:
+                _check(out[k], k, shp, "int32" if k in ("iters", "accepts", "status") else "float32",
+                       device=dev)
         pr = _TrajProblem(B, T, _ptr(start), _ptr(goal), _ptr(init))
         c = _TrajCosts(*[float(costs[k]) for k in ["dt", "w_pos", "w_rot", "w_limit", "w_smooth",
                                                     "w_vel", "w_acc", "w_jerk"]], _ptr(vmax))
@@ -491,7 +557,11 @@ class Context:
     def ik_solve(self, rid, targets, seeds, K, weights: Weights, options: Options, out):
         """targets [tf, T] and seeds [n, T*K] are cuda float32 tensors; out from
         alloc_outputs (missing keys are passed as NULL)."""
+        info = self.robot_info(rid)
+        if targets.dim() != 2:
+            raise PkError(-1, f"targets: shape {tuple(targets.shape)}, expected (floats, T)")
         T = targets.shape[1]
+        self._check_ik(info, targets, seeds, T, K, out)
         pr = _Problem(T, K, _ptr(targets), _ptr(seeds))
         o = self._outputs_c(out)
         w, op = weights._c(), options._c()

@@ -566,7 +566,7 @@ PK_DEV void write_nonfinite(const SolveParams &P, int64_t p, const float *q, boo
         if (P.rot_err) P.rot_err[c * N + p] = NAN;
     }
     if (P.cost) P.cost[p] = NAN;
-    P.pose_cost[p] = NAN;
+    if (P.pose_cost) P.pose_cost[p] = NAN;
     if (P.iters) P.iters[p] = 0;
     if (P.accepts) P.accepts[p] = 0;
     if (P.status) P.status[p] = PK_NONFINITE;
@@ -643,7 +643,7 @@ PK_DEV void write_result(const SolveParams &P, int64_t p, const float *q, float 
         if (P.rot_err) P.rot_err[c * N + p] = rerr[c];
     }
     if (P.cost) P.cost[p] = cost;
-    P.pose_cost[p] = pcost;
+    if (P.pose_cost) P.pose_cost[p] = pcost;
     if (P.iters) P.iters[p] = iters;
     if (P.accepts) P.accepts[p] = accepts;
     if (P.status)

@@ -544,7 +544,7 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
         }
         if (lane == 0) {
             if (P.cost) P.cost[p] = NAN;
-            P.pose_cost[p] = NAN;
+            if (P.pose_cost) P.pose_cost[p] = NAN;
             if (P.iters) P.iters[p] = 0;
             if (P.accepts) P.accepts[p] = 0;
             if (P.status) P.status[p] = PK_NONFINITE;
@@ -674,7 +674,7 @@ PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
     }
     if (lane == 0) {
         if (P.cost) P.cost[p] = cost;
-        P.pose_cost[p] = pcost;
+        if (P.pose_cost) P.pose_cost[p] = pcost;
         if (P.iters) P.iters[p] = iters;
         if (P.accepts) P.accepts[p] = accepts;
         if (P.status)

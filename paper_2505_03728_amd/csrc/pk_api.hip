@@ -541,17 +541,19 @@ int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_
 
     PK_HIP(ctx, hipSetDevice(ctx->device));
     const bool want_best = out->best_index || out->best_joints || out->target_success;
-    // Workspace: pose-only cost always; total cost and status when best-of-K
-    // needs them and the caller did not ask for them.
-    size_t need = (size_t)N * 4 * 3;
-    int rc = ensure_ws(ctx, need);
-    if (rc) return rc;
-    float *ws_f = (float *)ctx->ws;
+    // Workspace: pose-only cost, total cost and status when best-of-K needs
+    // them and the caller did not ask for them.
+    float *ws_f = nullptr;
+    if (want_best && !(out->pose_cost && out->cost && out->status)) {
+        int rc = ensure_ws(ctx, (size_t)N * 4 * 3);
+        if (rc) return rc;
+        ws_f = (float *)ctx->ws;
+    }
 
     P.K = pr->K; P.N = N; P.T = pr->n_targets;
     P.targets = pr->targets; P.seeds = pr->seeds;
     P.joints = out->joints; P.pos_err = out->pos_err; P.rot_err = out->rot_err;
-    P.pose_cost = ws_f;
+    P.pose_cost = out->pose_cost ? out->pose_cost : (want_best ? ws_f : nullptr);
     P.cost = out->cost ? out->cost : (want_best ? ws_f + N : nullptr);
     P.status = out->status ? out->status : (want_best ? (int32_t *)(ws_f + 2 * N) : nullptr);
     P.iters = out->iters; P.accepts = out->accepts; P.iters_to_tol = out->iters_to_tol;

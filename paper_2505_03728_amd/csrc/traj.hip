@@ -735,6 +735,8 @@ extern "C" int pk_traj_solve(pk_ctx *ctx, int32_t robot_id, const pk_traj_proble
         !std::isfinite(c->w_limit) || !std::isfinite(c->w_smooth) || !std::isfinite(c->w_vel) ||
         !std::isfinite(c->w_acc) || !std::isfinite(c->w_jerk))
         return fail(ctx, PK_EINVAL, "pk_traj_solve: bad costs");
+    if (c->w_vel != 0.f && !c->vmax)
+        return fail(ctx, PK_EINVAL, "pk_traj_solve: w_vel != 0 needs vmax (velocity limits)");
     if (o->max_iters < 0 || !(o->lambda0 > 0) || !(o->nu_up > 1) || !(o->nu_down > 1) ||
         !(o->lambda_min > 0) || !(o->lambda_max >= o->lambda_min) || !(o->damping_floor > 0) ||
         !(o->pivot_rel >= 0))

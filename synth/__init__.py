@@ -354,8 +354,9 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
                       the base at the origin, each translated horizontally by
                       U[-1, 1]^2 m; mobile_arm7 (base pose free) x 4 seeds
                       with the base at the origin, and the same targets for
-                      arm7 alone (fixed base); pose+limit, 30 iterations,
-                      success at 5 mm / 0.05 rad;
+                      arm7 alone (fixed base); pose+limit+rest(0.01), up to
+                      30 iterations with early exit, success at 5 mm /
+                      0.05 rad;
       * ``traj``    — trajectory optimisation on arm7: 1024 trajectories of
                       32 timesteps (dt 0.05 s) between the poses of two
                       random configurations, initialised by linear
@@ -419,10 +420,10 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
         seeds_arm = uniform_configs(arm, T * K, 24)
         q_star = np.concatenate([shift, np.zeros((T, 1)), q_arm], 1)
         seeds = np.concatenate([np.zeros((T * K, 3)), seeds_arm], 1)
-        o = dict(_options(30), tol_pos=5e-3, tol_rot=5e-2)
+        o = dict(_options(30, early_exit=True), tol_pos=5e-3, tol_rot=5e-2)
         return {"groups": [{"tree": mob, "q_star": q_star, "K": K, "seeds": seeds}],
                 "fixed_base": {"tree": arm, "seeds": seeds_arm},
-                "weights": _weights(), "options": o}
+                "weights": _weights(w_rest=0.01), "options": o}
     if name == "traj":
         r = arm7(0)
         B = targets or int(1024 * scale)

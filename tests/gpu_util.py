@@ -60,13 +60,45 @@ def borderline_at(tree, tg, w, trace_q, it, tol_pos=1e-3, tol_rot=1e-2, frac=0.0
                 np.any((np.abs(re - tol_rot) <= frac * tol_rot) & pose))
 
 
-def fp32_fragile(tree, tg, w, o, seed, ora, t, rel_tie=1e-5, eps_step=1e-6):
+def _chol32_solve(A, g, pivot_rel):
+    """FP32 Cholesky of A (float32, with the library's pivot test: every
+    pivot above pivot_rel times the largest diagonal, and finite) and the
+    step -A^-1 g in FP32.  Returns (step, ok)."""
+    n = A.shape[0]
+    L = np.zeros_like(A)
+    thresh = np.float32(pivot_rel) * np.max(np.diag(A))
+    for k in range(n):
+        d = np.float32(A[k, k] - np.dot(L[k, :k], L[k, :k]))
+        if not (d > thresh) or not np.isfinite(d):
+            return None, False
+        L[k, k] = np.sqrt(d)
+        for i in range(k + 1, n):
+            L[i, k] = np.float32(A[i, k] - np.dot(L[i, :k], L[k, :k])) / L[k, k]
+    y = np.zeros(n, np.float32)
+    for i in range(n):
+        y[i] = (np.float32(-g[i]) - np.dot(L[i, :i], y[:i])) / L[i, i]
+    x = np.zeros(n, np.float32)
+    for i in range(n - 1, -1, -1):
+        x[i] = (y[i] - np.dot(L[i + 1:, i], x[i + 1:])) / L[i, i]
+    return x, True
+
+
+# Accuracy of an FP32 residual relative to its unit scale (metres, radians):
+# about 16 ulps of 1.
+FP32_RES_ERR = 2.0 ** -20
+
+
+def fp32_replay_flips(tree, tg, w, o, seed, ora, t):
     """Whether the oracle's accept decision at iteration t (1-based) is one
-    FP32 cannot settle.  Replays the oracle to the state before iteration t
-    (its trace and lambda schedule), forms the damped system there in FP64 and
-    compares |c' - c| with rel_tie * c plus the first-order change of c' that
-    a relative step error of eps_step * cond(A_lambda) causes; eps_step is the
-    relative accuracy of an FP32-formed Jacobian (about 16 ulps)."""
+    that FP32 arithmetic does not reproduce.  The step is replayed on the host
+    from the oracle's state before iteration t (its trace and lambda
+    schedule): residual and Jacobian rounded to FP32, the damped normal
+    equations formed and Cholesky-solved in FP32 (with the pivot test, and
+    the FP64 re-solve from the FP32 Jacobian when it fails), the trial point
+    rounded to FP32.  The replayed decision c(q + d32) < c(q) (costs in FP64)
+    flips the oracle's, or the two costs are closer than an FP32 cost
+    evaluation can tell apart (residuals good to FP32_RES_ERR of their unit
+    scale): 2 (sqrt c + sqrt c') FP32_RES_ERR + 4 (c + c') 2^-24."""
     import oracle
     q = np.asarray(seed, dtype=np.float64) if t == 1 else ora["trace_q"][t - 2]
     lam = o["lambda0"]
@@ -75,12 +107,25 @@ def fp32_fragile(tree, tg, w, o, seed, ora, t, rel_tie=1e-5, eps_step=1e-6):
             min(lam * o["nu_up"], o["lambda_max"])
     r, _, _ = oracle.residual(tree, tg, w, q)
     J = oracle.jacobian(tree, tg, w, q)
-    A = J.T @ J
-    g = J.T @ r
-    Al = A + lam * np.diag(np.maximum(np.diag(A), o["damping_floor"]))
-    d = np.linalg.solve(Al, -g)
-    c, ct = oracle.cost(tree, tg, w, q), oracle.cost(tree, tg, w, q + d)
-    return bool(abs(ct - c) <= rel_tie * c + eps_step * np.linalg.cond(Al) * 2 * abs(g @ d))
+    J32, r32 = J.astype(np.float32), r.astype(np.float32)
+    A = J32.T @ J32
+    g = J32.T @ r32
+    lam32 = np.float32(lam)
+    Al = A + lam32 * np.diag(np.maximum(np.diag(A), np.float32(o["damping_floor"])))
+    d, ok = _chol32_solve(Al.astype(np.float32), g, o["pivot_rel"])
+    if not ok:
+        A64 = J32.astype(np.float64).T @ J32.astype(np.float64)
+        g64 = J32.astype(np.float64).T @ r32.astype(np.float64)
+        Al64 = A64 + lam * np.diag(np.maximum(np.diag(A64), o["damping_floor"]))
+        try:
+            d = np.linalg.solve(Al64, -g64)
+        except np.linalg.LinAlgError:
+            return not bool(ora["trace_acc"][t - 1])    # FP64 also fails: a reject
+    qt = (q.astype(np.float32) + d.astype(np.float32)).astype(np.float64)
+    c, ct = oracle.cost(tree, tg, w, q), oracle.cost(tree, tg, w, qt)
+    noise = 2 * (np.sqrt(c) + np.sqrt(max(ct, 0.0))) * FP32_RES_ERR + 4 * (c + ct) * 2.0 ** -24
+    acc32 = bool(ct < c)
+    return acc32 != bool(ora["trace_acc"][t - 1]) or abs(ct - c) <= noise
 
 
 def first_divergence(acc_gpu, acc_ora):
@@ -105,30 +150,49 @@ def at_limit(tree, q, eps=1e-6):
 
 
 def compare_outcome(ctx, rid, tree, tg, seed, w, o, status, iters, ora, variant=0):
-    """'same' when the GPU's success flag (and, if both converged, iteration
-    count) equals the oracle's; 'excused' when the difference traces back to
-    something FP32 cannot settle (a near-tie, a final or crossing error within
-    5% of a tolerance, or a first differing decision that is FP32-fragile or
-    taken from an iterate on a joint limit's kink); else 'bad'.  ora:
-    oracle.lm_solve result with a full trace."""
+    """(verdict, reason).  verdict 'same' when the GPU's success flag (and, if
+    both converged, iteration count) equals the oracle's; 'excused' when the
+    difference traces back to something FP32 cannot settle, named by reason:
+    'near-tie' (an oracle decision with |c' - c| <= 1e-5 c), 'borderline' (a
+    final or crossing error within 5% of a tolerance), 'fp32-replay' (the
+    first differing decision flips when replayed in FP32, fp32_replay_flips)
+    or 'limit-kink' (taken from an iterate on a joint limit); else 'bad'.
+    ora: oracle.lm_solve result with a full trace."""
     cg, co = (status & 0xff) == 0, (ora["status"] & 0xff) == 0
     if cg == co and (not cg or iters == ora["iters"]):
-        return "same"
-    if ora["trace_tie"].any() or borderline({"pos_err": [ora["pos_err"]], "rot_err": [ora["rot_err"]]}, 0):
-        return "excused"
+        return "same", ""
+    if ora["trace_tie"].any():
+        return "excused", "near-tie"
+    if borderline({"pos_err": [ora["pos_err"]], "rot_err": [ora["rot_err"]]}, 0):
+        return "excused", "borderline"
     if cg and co and borderline_at(tree, tg, w, ora["trace_q"], int(min(iters, ora["iters"]))):
-        return "excused"
+        return "excused", "borderline"
     kw = {"variant": variant} if variant else {}
     res = solve_gpu(ctx, rid, tree, tg[None], np.asarray(seed)[None], 1, w, o,
                     trace_iters=o["max_iters"], **kw)
     t = first_divergence(res["trace_accept"][0], ora["trace_acc"])
     if t == 0:
-        return "bad"
-    if fp32_fragile(tree, tg, w, o, seed, ora, t):
-        return "excused"
+        return "bad", "no differing decision"
+    if fp32_replay_flips(tree, tg, w, o, seed, ora, t):
+        return "excused", "fp32-replay"
     qg = np.asarray(seed) if t == 1 else res["trace_q"][0][t - 2]
     qo = np.asarray(seed) if t == 1 else ora["trace_q"][t - 2]
-    return "excused" if at_limit(tree, qg) or at_limit(tree, qo) else "bad"
+    if at_limit(tree, qg) or at_limit(tree, qo):
+        return "excused", "limit-kink"
+    return "bad", f"decision {t} differs"
+
+
+def max_excused(n, frac=0.02):
+    """Excuses a parity test tolerates over n compared problems: 2%, and at
+    least one where n >= 20."""
+    return max(int(frac * n), 1 if n >= 20 else 0)
+
+
+def check_excused(label, excused, n, frac=0.02):
+    """Prints the excused problems (index, reason) and asserts their count
+    is within max_excused(n, frac)."""
+    print(f"{label}: {len(excused)} of {n} excused {excused}")
+    assert len(excused) <= max_excused(n, frac), (label, len(excused), n, excused)
 
 
 def borderline(ora_res, p, tol_pos=1e-3, tol_rot=1e-2, frac=0.05):

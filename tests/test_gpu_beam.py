@@ -20,7 +20,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import compare_outcome, soa, targets_dev
+from tests.gpu_util import check_excused, compare_outcome, soa, targets_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -83,7 +83,7 @@ def _stage_agreement(ctx, rid, tree, tg, starts, Kst, status, q, w, o, iters, sa
     as in the LM tests: near-tie, borderline error, or a first differing
     accept decision that FP32 cannot settle)."""
     oo = dict(o, max_iters=iters)
-    bad, excused, close = [], 0, 0
+    bad, excused, close = [], [], 0
     for p in sample:
         ora = oracle.lm_solve(tree, tg[p // Kst], w, oo, starts[p], n_trace=max(iters, 1))
         cg, co = (status[p] & 0xFF) == 0, (ora["status"] & 0xFF) == 0
@@ -91,14 +91,14 @@ def _stage_agreement(ctx, rid, tree, tg, starts, Kst, status, q, w, o, iters, sa
             close += 1
         if cg == co:
             continue
-        v = compare_outcome(ctx, rid, tree, tg[p // Kst], starts[p], w, oo, status[p],
-                            ora["iters"], ora)
+        v, why = compare_outcome(ctx, rid, tree, tg[p // Kst], starts[p], w, oo, status[p],
+                                 ora["iters"], ora)
         if v == "bad":
             bad.append(int(p))
             print(f"problem {p}: gpu status {status[p]}, oracle {ora['status']} "
-                  f"pos {ora['pos_err']} rot {ora['rot_err']}")
-        else:
-            excused += 1
+                  f"pos {ora['pos_err']} rot {ora['rot_err']} ({why})")
+        elif v == "excused":
+            excused.append((int(p), why))
     return bad, excused, close
 
 
@@ -124,10 +124,12 @@ def test_beam_small_batch_full_parity(ctx, rid, variant):
                                   res["stage0_joints"].T, w, o, 6, range(N0))
     b1, e1, c1 = _stage_agreement(ctx, rid, tree, tg, seeds1, 4, res["stage1_status"],
                                   res["stage1_joints"].T, w, o, 10, range(N1))
-    print(f"beam T={T} variant={variant}: stage 0 {len(b0)} unexplained, {e0} excused, "
-          f"{c0}/{N0} within 1e-3 rad; stage 1 {len(b1)} unexplained, {e1} excused, "
+    print(f"beam T={T} variant={variant}: stage 0 {len(b0)} unexplained, {len(e0)} excused, "
+          f"{c0}/{N0} within 1e-3 rad; stage 1 {len(b1)} unexplained, {len(e1)} excused, "
           f"{c1}/{N1} within 1e-3 rad; success {res['target_success'].mean():.2f}")
     assert not b0 and not b1
+    check_excused(f"beam stage 0 (variant {variant})", e0, N0)
+    check_excused(f"beam stage 1 (variant {variant})", e1, N1)
     assert c0 >= 0.9 * N0
     _check_errors(res, tree, tg, T)
 
@@ -147,9 +149,11 @@ def test_beam_full_size_batch2000_sampled(ctx, rid):
                                  res["stage0_joints"].T, w, o, 6, s0)
     b1, e1, _ = _stage_agreement(ctx, rid, tree, tg, seeds1, 4, res["stage1_status"],
                                  res["stage1_joints"].T, w, o, 10, s1)
-    print(f"beam T=2000: stage 0 {len(b0)} unexplained / {e0} excused of {len(s0)}, stage 1 "
-          f"{len(b1)} / {e1} of {len(s1)}; success {res['target_success'].mean():.4f}")
+    print(f"beam T=2000: stage 0 {len(b0)} unexplained / {len(e0)} excused of {len(s0)}, stage 1 "
+          f"{len(b1)} / {len(e1)} of {len(s1)}; success {res['target_success'].mean():.4f}")
     assert not b0 and not b1
+    check_excused("beam T=2000 stage 0", e0, len(s0))
+    check_excused("beam T=2000 stage 1", e1, len(s1))
     _check_errors(res, tree, tg, 16)
 
 

@@ -14,7 +14,8 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import compare_outcome, quat_to_R, rot_angle, soa, solve_gpu, targets_dev
+from tests.gpu_util import (check_excused, compare_outcome, quat_to_R, rot_angle, soa, solve_gpu,
+                            targets_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -119,17 +120,19 @@ def test_lm_success_agreement(ctx, rids, name, variant):
          "damping_floor": 1e-6, "pivot_rel": 1e-6}
     kw = {"variant": variant} if variant else {}
     res = solve_gpu(ctx, rids[name], tree, tg, seeds, K, w, o, **kw)
-    bad, excused = [], 0
+    bad, excused = [], []
     for p in range(T * K):
         ora = oracle.lm_solve(tree, tg[p // K], w, o, seeds[p], n_trace=30)
-        v = compare_outcome(ctx, rids[name], tree, tg[p // K], seeds[p], w, o, res["status"][p],
-                            res["iters"][p], ora, variant=variant)
+        v, why = compare_outcome(ctx, rids[name], tree, tg[p // K], seeds[p], w, o, res["status"][p],
+                                 res["iters"][p], ora, variant=variant)
         if v == "bad":
-            bad.append(p)
-        excused += v == "excused"
+            bad.append((p, why))
+        elif v == "excused":
+            excused.append((p, why))
     conv = ((res["status"] & 0xFF) == 0).mean()
-    print(f"{name} variant {variant}: success {conv:.3f}, {excused} excused, unexplained {bad}")
+    print(f"{name} variant {variant}: success {conv:.3f}, {len(excused)} excused, unexplained {bad}")
     assert not bad
+    check_excused(f"{name} variant {variant}", excused, T * K)
 
 
 def test_mimic_hand_lm_from_nearby_seeds(ctx, rids):
@@ -151,20 +154,22 @@ def test_mimic_hand_lm_from_nearby_seeds(ctx, rids):
          "lambda_max": 1e10, "early_exit": False, "tol_pos": 1e-3, "tol_rot": 1e-2,
          "damping_floor": 1e-6, "pivot_rel": 1e-6}
     res = solve_gpu(ctx, rids["hand16_mimic"], tree, tg, seeds, 1, w, o)
-    bad, excused = [], 0
+    bad, excused = [], []
     for p in range(T):
         ora = oracle.lm_solve(tree, tg[p], w, o, seeds[p], n_trace=30)
-        v = compare_outcome(ctx, rids["hand16_mimic"], tree, tg[p], seeds[p], w, o,
-                            res["status"][p], res["iters"][p], ora)
+        v, why = compare_outcome(ctx, rids["hand16_mimic"], tree, tg[p], seeds[p], w, o,
+                                 res["status"][p], res["iters"][p], ora)
         if v == "bad":
-            bad.append(p)
-        excused += v == "excused"
+            bad.append((p, why))
+        elif v == "excused":
+            excused.append((p, why))
     conv = (res["status"] & 0xFF) == 0
     for p in np.nonzero(conv)[0]:
         _, pe, _ = oracle.residual(tree, tg[p], w, res["q"][p].astype(np.float64))
         assert np.all(pe <= 1e-3 + 1e-5)
-    print(f"hand16_mimic near seeds: success {conv.mean():.3f}, {excused} excused, unexplained {bad}")
+    print(f"hand16_mimic near seeds: success {conv.mean():.3f}, {len(excused)} excused, unexplained {bad}")
     assert not bad
+    check_excused("hand16_mimic near seeds", excused, T)
     assert conv.mean() >= 0.8
 
 
@@ -235,18 +240,14 @@ def test_upload_errors_and_lane_variant(ctx, rids):
 
 def test_mobile_base_workload(ctx, rids):
     """Sec. V-B: arm poses reachable from the base at the origin, moved
-    horizontally by up to 1 m, solved with the SE(2) base pose as variables.
-
-    The robot is redundant (10 variables for a 6-D pose) and has no rest
-    term here, so the damped normal matrix is conditioned by 1 / lambda along
-    the pose's null space: once lambda falls below ~1e-6 the FP32 Jacobian's
-    rounding (~1e-7 relative) moves the null-space part of the step by O(1),
-    and the FP32 and FP64 runs reach different points of the solution set.
-    What is unique is compared instead: every success the GPU reports is a
-    valid solution by the oracle's FK (errors within the tolerance plus
-    1e-5), and the success rates per problem and per target agree within 4
-    points.  Best-of-K succeeds on more targets than the same solve with the
-    base fixed at the origin (the arm alone)."""
+    horizontally by up to 1 m, solved with the SE(2) base pose as variables
+    (pose + limit + rest 0.01, early exit at 5 mm / 0.05 rad).  The rest term
+    bounds the damped system's condition along the pose's 4-dimensional null
+    space, so the FP32 and FP64 runs follow the same iterates and the success
+    flags agree per problem (a disagreement only where FP32 cannot settle it,
+    counted).  Every success the GPU reports is a valid solution by the
+    oracle's FK, and best-of-K succeeds on more targets than the same solve
+    with the base fixed at the origin (the arm alone)."""
     wl = synth.workload("mobile", targets=128)
     g = wl["groups"][0]
     mob, K = g["tree"], g["K"]
@@ -254,20 +255,29 @@ def test_mobile_base_workload(ctx, rids):
     tg = oracle.targets_from(mob, g["q_star"])
     w, o = wl["weights"], wl["options"]
     res = solve_gpu(ctx, rids["mobile_arm7"], mob, tg, g["seeds"], K, w, o, best=True)
-    ora = oracle.lm_solve_batch(mob, tg, g["seeds"], K, w, o)
     conv_g = (res["status"] & 0xFF) == 0
-    conv_o = (ora["status"] & 0xFF) == 0
     for p in np.nonzero(conv_g)[0]:
         _, pe, re = oracle.residual(mob, tg[p // K], w, res["q"][p].astype(np.float64))
         assert pe[0] <= o["tol_pos"] + 1e-5 and re[0] <= o["tol_rot"] + 1e-5, (p, pe, re)
-    _, succ_o = oracle.best_of_k(ora["status"], ora["cost"], ora["pose_cost"], K)
+    bad, excused, conv_o = [], [], []
+    for p in range(T * K):
+        ora = oracle.lm_solve(mob, tg[p // K], w, o, g["seeds"][p], n_trace=o["max_iters"])
+        conv_o.append((ora["status"] & 0xFF) == 0)
+        v, why = compare_outcome(ctx, rids["mobile_arm7"], mob, tg[p // K], g["seeds"][p], w, o,
+                                 res["status"][p], res["iters"][p], ora)
+        if v == "bad":
+            bad.append((p, why))
+        elif v == "excused":
+            excused.append((p, why))
+    conv_o = np.array(conv_o)
     sm = res["target_success"].mean()
+    so = conv_o.reshape(T, K).any(1).mean()
     arm = synth.arm7(0)
     rid_arm = ctx.upload(arm)
     fixed = solve_gpu(ctx, rid_arm, arm, tg, wl["fixed_base"]["seeds"], K, w, o, best=True)
     sf = fixed["target_success"].mean()
     print(f"mobile base: per problem {conv_g.mean():.3f} (oracle {conv_o.mean():.3f}), per target "
-          f"{sm:.3f} (oracle {succ_o.mean():.3f}); fixed base {sf:.3f}")
-    assert abs(conv_g.mean() - conv_o.mean()) <= 0.04
-    assert abs(sm - succ_o.mean()) <= 0.04
+          f"{sm:.3f} (oracle {so:.3f}); fixed base {sf:.3f}; unexplained {bad}")
+    assert not bad
+    check_excused("mobile base", excused, T * K)
     assert sm > sf

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import compare_outcome, soa, targets_dev
+from tests.gpu_util import check_excused, compare_outcome, soa, targets_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -115,22 +115,25 @@ def test_autotune_and_oracle_sample(ctx, batch):
     torch.cuda.synchronize()
     got = _host(gs)
     rng = np.random.default_rng(3)
-    bad = excused = 0
+    bad, excused, n = [], [], 0
     for g, out in zip(groups, got):
         N = g["seeds_np"].shape[0]
         for p in rng.choice(N, min(N, 40), replace=False):
             o = oracle.lm_solve(g["tree"], g["tg"][p // g["K"]], g["wd"], wl["options"],
                                 g["seeds_np"][p], n_trace=wl["options"]["max_iters"])
-            v = compare_outcome(ctx, g["rid"], g["tree"], g["tg"][p], g["seeds_np"][p], g["wd"],
-                                wl["options"], out["status"][p], out["iters"][p], o)
+            v, why = compare_outcome(ctx, g["rid"], g["tree"], g["tg"][p], g["seeds_np"][p], g["wd"],
+                                     wl["options"], out["status"][p], out["iters"][p], o)
+            n += 1
             if v == "bad":
                 print(f"{g['tree'].name} problem {p}: gpu iters {out['iters'][p]} status {out['status'][p]}, "
-                      f"oracle {o['iters']} status {o['status']}")
-            bad += v == "bad"
-            excused += v == "excused"
+                      f"oracle {o['iters']} status {o['status']} ({why})")
+                bad.append((g["tree"].name, int(p)))
+            elif v == "excused":
+                excused.append((g["tree"].name, int(p), why))
         print(f"{g['tree'].name}: success {np.mean((out['status'] & 0xff) == 0):.3f}")
-    print(f"oracle sample: {bad} unexplained, {excused} excused")
-    assert bad == 0
+    print(f"oracle sample: {bad} unexplained, {len(excused)} excused of {n}")
+    assert not bad
+    check_excused("scheduler oracle sample", excused, n)
 
 
 def test_full_size_mixed84k_sampled(ctx):
@@ -155,19 +158,23 @@ def test_full_size_mixed84k_sampled(ctx):
     torch.cuda.synchronize()
     got = _host(gs)
     rng = np.random.default_rng(17)
-    bad = excused = 0
+    bad, excused, n = [], [], 0
     for g, out in zip(groups, got):
         st = out["status"] & 0xff
         assert np.all(np.isin(st, [0, 1, 2]))
         # early exit: converged problems stop at their first point within tolerance
         np.testing.assert_array_equal(out["iters_to_tol"][st == 0], out["iters"][st == 0])
-        for p in rng.choice(g["tg"].shape[0], 12, replace=False):
+        for p in rng.choice(g["tg"].shape[0], 20, replace=False):
             o = oracle.lm_solve(g["tree"], g["tg"][p], g["wd"], wl["options"], g["seeds_np"][p],
                                 n_trace=wl["options"]["max_iters"])
-            v = compare_outcome(ctx, g["rid"], g["tree"], g["tg"][p], g["seeds_np"][p], g["wd"],
-                                wl["options"], out["status"][p], out["iters"][p], o)
-            bad += v == "bad"
-            excused += v == "excused"
+            v, why = compare_outcome(ctx, g["rid"], g["tree"], g["tg"][p], g["seeds_np"][p], g["wd"],
+                                     wl["options"], out["status"][p], out["iters"][p], o)
+            n += 1
+            if v == "bad":
+                bad.append((g["tree"].name, int(p), why))
+            elif v == "excused":
+                excused.append((g["tree"].name, int(p), why))
         print(f"{g['tree'].name}: {st.size} problems, success {np.mean(st == 0):.4f}")
-    print(f"mixed84k sample: {bad} unexplained, {excused} excused of 36")
-    assert bad == 0
+    print(f"mixed84k sample: {bad} unexplained, {len(excused)} excused of {n}")
+    assert not bad
+    check_excused("mixed84k sample", excused, n)

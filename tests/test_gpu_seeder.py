@@ -1,15 +1,17 @@
 """GPU parity of the learned seeder's MFMA kernels against the FP64 MLP
-oracle in BF16-emulation mode (forward within 1e-3 relative, gradients
-within 2e-2 relative, Frobenius per tensor), Adam's update against its
-closed form on the GPU's own gradients, and the training/inference/
-checkpoint paths."""
+oracle in BF16-emulation mode: forward within 1e-3 relative (Frobenius per
+tensor) and every element within 1e-2 of the tensor's RMS; gradients within
+2e-2 relative and every element within 5e-2 of the tensor's RMS; Adam over
+several steps (parameters and both moments, element by element) against the
+oracle's Adam fed the GPU's own gradients; the training/inference/checkpoint
+paths; and the seeded pipeline with the seeder trained at full size."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
 from oracle import mlp
-from tests.gpu_util import borderline
+from tests.gpu_util import borderline, check_excused
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +49,15 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-30))
 
 
+def _max_over_rms(a, b):
+    """Largest element-wise difference over the reference tensor's RMS: a
+    wrong row or column stands out here even where the Frobenius norm of the
+    whole tensor hides it."""
+    b = np.asarray(b, dtype=np.float64)
+    rms = max(float(np.sqrt(np.mean(b * b))), 1e-30)
+    return float(np.abs(np.asarray(a, dtype=np.float64) - b).max() / rms)
+
+
 @pytest.mark.parametrize("hidden,depth,B", [(128, 2, 200), (512, 3, 300)])
 def test_forward_matches_bf16_oracle(ctx, arm, hidden, depth, B):
     import paper_2505_03728_amd as pk
@@ -58,8 +69,9 @@ def test_forward_matches_bf16_oracle(ctx, arm, hidden, depth, B):
     torch.cuda.synchronize()
     yo, _ = mlp.forward(init, x, emulate_bf16=True)
     rel = _rel(y.cpu().numpy(), yo)
-    print(f"forward h={hidden} d={depth}: rel err {rel:.2e}")
-    assert rel <= 1e-3
+    el = _max_over_rms(y.cpu().numpy(), yo)
+    print(f"forward h={hidden} d={depth}: rel err {rel:.2e}, max element err / RMS {el:.2e}")
+    assert rel <= 1e-3 and el <= 1e-2
     # parameters round-trip through the padded device layout
     got = sd.get(0)
     for (W, b), (Wg, bg) in zip(init, got):
@@ -117,8 +129,10 @@ def test_gradients_match_bf16_oracle(ctx, arm, hidden, depth, B):
     assert abs(loss.item() - lo) <= 1e-3 * lo
     for li, ((gW, gb), (oW, ob)) in enumerate(zip(g, go)):
         rw, rb = _rel(gW, oW), _rel(gb, ob)
-        print(f"layer {li}: dW rel {rw:.2e}, db rel {rb:.2e}")
+        ew, eb = _max_over_rms(gW, oW), _max_over_rms(gb, ob)
+        print(f"layer {li}: dW rel {rw:.2e} (max element / RMS {ew:.2e}), db rel {rb:.2e} ({eb:.2e})")
         assert rw <= 2e-2 and rb <= 2e-2
+        assert ew <= 5e-2 and eb <= 5e-2
 
 
 def test_adam_step_closed_form_and_training(ctx, arm):
@@ -151,6 +165,49 @@ def test_adam_step_closed_form_and_training(ctx, arm):
     L = log.cpu().numpy()
     print("loss", L[0], L[len(L) // 2], L[-1])
     assert np.all(np.isfinite(L)) and L[-8:].mean() < 0.8 * L[:8].mean()
+
+
+def test_adam_several_steps_elementwise(ctx, arm):
+    """Four training steps on one fixed batch (index order, the batch is the
+    whole set): after each, the GPU's parameters and both Adam moments equal,
+    element by element, the oracle's Adam fed the gradients the GPU reports
+    for that step, from the same initial parameters.  The oracle takes the
+    hyperparameters as the library receives them (FP32-rounded lr, betas and
+    eps, promoted).  Tolerances: v to 1e-6 relative (a sum of squares); m to
+    1e-6 of the same recursion run on |g| (m may cancel to near zero while its
+    terms do not); parameters to 2e-7 + 1e-6 |p| (the bias corrections
+    1 - beta^t lose digits in FP32 at small t, about 1e-5 of a step of lr)."""
+    import paper_2505_03728_amd as pk
+    import torch
+    f32 = lambda v: float(np.float32(v))
+    init = synth.mlp_init([7, 128, 128, 56], 41)
+    sd = pk.Seeder(ctx, arm, K=8, hidden=128, depth=2, init=init)
+    q = synth.uniform_configs(synth.arm7(0), 1024, 42)
+    qdev = _dev(q.T)
+    cur = [(W.astype(np.float64), b.astype(np.float64)) for W, b in init]
+    opt = mlp.Adam(cur, lr=f32(1e-3), b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8))
+    scale = [[np.zeros(np.shape(W)), np.zeros(np.shape(b))] for W, b in cur]
+    worst = {"p": 0.0, "m": 0.0, "v": 0.0}
+    for step in range(4):
+        sd.train(qdev, batch=1024, epochs=1, lr=1e-3)
+        torch.cuda.synchronize()
+        g = [(W.astype(np.float64), b.astype(np.float64)) for W, b in sd.get(1)]
+        cur = opt.step(cur, g)
+        gp, gm, gv = sd.get(0), sd.get(2), sd.get(3)
+        for li in range(len(cur)):
+            for j in range(2):
+                scale[li][j] = opt.b1 * scale[li][j] + (1 - opt.b1) * np.abs(g[li][j])
+                dp = np.abs(gp[li][j] - cur[li][j])
+                assert np.all(dp <= 2e-7 + 1e-6 * np.abs(cur[li][j])), (step, li, j, dp.max())
+                dm = np.abs(gm[li][j] - opt.m[li][j])
+                assert np.all(dm <= 1e-6 * scale[li][j] + 1e-30), (step, li, j, dm.max())
+                dv = np.abs(gv[li][j] - opt.v[li][j])
+                assert np.all(dv <= 1e-6 * np.abs(opt.v[li][j]) + 1e-30), (step, li, j, dv.max())
+                worst["p"] = max(worst["p"], float(dp.max()))
+                worst["m"] = max(worst["m"], float((dm / (scale[li][j] + 1e-30)).max()))
+                worst["v"] = max(worst["v"], float((dv / (np.abs(opt.v[li][j]) + 1e-30)).max()))
+    print(f"Adam over 4 steps: max |dp| {worst['p']:.2e}, max dm / scale {worst['m']:.2e}, "
+          f"max rel dv {worst['v']:.2e}")
 
 
 def test_infer_seeds_within_limits_and_checkpoint(ctx, arm, tmp_path):
@@ -188,19 +245,43 @@ def test_infer_seeds_within_limits_and_checkpoint(ctx, arm, tmp_path):
 
 @pytest.fixture(scope="module")
 def trained(ctx, arm):
-    """A seeder (hidden 256, depth 3) trained briefly on (FK(q), q) pairs."""
+    """The seeder at the learned-seed workload's full size: MLP
+    7-512-512-512-56 (K = 8), trained on its 2M (FK(q), q) pairs for 20
+    epochs, batch 8192, Adam lr 1e-3, its seeded initial weights and epoch
+    orders."""
     import paper_2505_03728_amd as pk
     import torch
-    tree = synth.arm7(0)
-    init = synth.mlp_init([7, 256, 256, 256, 56], 31)
-    sd = pk.Seeder(ctx, arm, K=8, hidden=256, depth=3, init=init)
-    S, E = 262144, 6
-    q = synth.uniform_configs(tree, S, 32)
-    perm = np.stack([synth.epoch_permutation(S, 33, e) for e in range(E)])
-    log = torch.zeros(E * (S // 8192), device=DEV)
-    sd.train(_dev(q.T), batch=8192, epochs=E, lr=1e-3, perm=torch.from_numpy(perm).to(DEV),
-             loss_log=log)
+    wl = synth.workload("seeder")
+    mc = wl["mlp"]
+    init = synth.mlp_init([7] + [mc["hidden"]] * mc["depth"] + [7 * wl["K"]], mc["init_seed"])
+    sd = pk.Seeder(ctx, arm, K=wl["K"], hidden=mc["hidden"], depth=mc["depth"], init=init)
+    S, E = wl["train_q"].shape[0], mc["epochs"]
+    perm = np.stack([synth.epoch_permutation(S, mc["shuffle_seed"], e) for e in range(E)])
+    log = torch.zeros(E * (S // mc["batch"]), device=DEV)
+    sd.train(_dev(wl["train_q"].T), batch=mc["batch"], epochs=E, lr=mc["lr"],
+             perm=torch.from_numpy(perm).to(DEV), loss_log=log)
+    torch.cuda.synchronize()
     return sd, log
+
+
+def test_trained_full_size_net_matches_oracle(ctx, arm, trained):
+    """The trained full-size network (its parameters read back) against the
+    oracle's BF16-emulated forward on a sample of fresh targets, element by
+    element, through both the fused inference kernel and the layer path."""
+    import torch
+    sd, log = trained
+    L = log.cpu().numpy()
+    assert np.all(np.isfinite(L)) and L[-50:].mean() < 0.5 * L[:50].mean()
+    x, _ = _inputs(512, 61)
+    xd = _dev(x)
+    yf, yl = sd.forward(xd), sd.forward(xd, layers=True)
+    torch.cuda.synchronize()
+    assert torch.equal(yf, yl)
+    yo, _ = mlp.forward(sd.get(0), x, emulate_bf16=True)
+    rel, el = _rel(yf.cpu().numpy(), yo), _max_over_rms(yf.cpu().numpy(), yo)
+    print(f"trained 512x3 net: loss {L[0]:.3f} -> {L[-50:].mean():.3f}; forward rel {rel:.2e}, "
+          f"max element / RMS {el:.2e}")
+    assert rel <= 1e-3 and el <= 1e-2
 
 
 def test_seeded_pipeline_and_gain_over_random_seeds(ctx, arm, trained):
@@ -286,14 +367,15 @@ def test_seeded_pipeline_full_size_sampled(ctx, arm, trained):
     assert int(res["n_fallback"].item()) == int((src != 0).sum())
     o = dict(wl["options"], max_iters=10, early_exit=True)
     rng = np.random.default_rng(23)
-    bad = excused = 0
-    for t in np.sort(rng.choice(T, 48, replace=False)):
+    bad, excused = 0, []
+    sample = np.sort(rng.choice(T, 64, replace=False))
+    for t in sample:
         outs = [oracle.lm_solve(tree, tg[t], wl["weights"], o, sn[t * 8 + k], n_trace=10) for k in range(8)]
         so = any((r["status"] & 0xff) == 0 for r in outs)
         if so != (src[t] == 0):
             if any(r["trace_tie"].any() or borderline({"pos_err": [r["pos_err"]], "rot_err": [r["rot_err"]]}, 0)
                    for r in outs):
-                excused += 1
+                excused.append((int(t), "near-tie or borderline"))
             else:
                 bad += 1
     bj = res["best_joints"].cpu().numpy().T.astype(np.float64)
@@ -301,5 +383,6 @@ def test_seeded_pipeline_full_size_sampled(ctx, arm, trained):
         _, pe, re = oracle.residual(tree, tg[t], wl["weights"], bj[t])
         assert pe[0] <= 1e-3 * 1.05 and re[0] <= 1e-2 * 1.05
     print(f"seeded 131072: success {succ.mean():.4f}, learned {np.mean(src == 0):.4f}; "
-          f"sample {bad} unexplained, {excused} excused of 48")
+          f"sample {bad} unexplained, {len(excused)} excused of {len(sample)}")
     assert bad == 0
+    check_excused("seeded 131072 sample", excused, len(sample))

@@ -4,12 +4,13 @@ FP64 oracle, through the C ABI.
 Per trajectory: the success flag (both endpoint poses within tolerance)
 agrees with the oracle's unless the oracle's endpoint error is within 5% of
 a tolerance; the final cost agrees within 1e-3 relative and the trajectory
-within 1e-3 rad for at least 90% of the trajectories (the rest are FP32
-accept decisions taken differently on a near-flat cost, counted and printed).
-Chains of 4, 6, 7 and 10 variables cover every instantiation of the kernel;
-the 10-variable mobile base is compared element-wise over two iterations and
-on its success flags over the full run (its trajectories are not unique to
-FP32 precision, see that test).
+within 1e-3 rad.  A trajectory outside that is excused only when the
+oracle's own run took a near-tie decision (|c' - c| <= 1e-5 c), which FP32
+kinematics cannot reproduce; at most one per test, listed.  Chains of 4, 6, 7
+and 10 variables cover every instantiation of the kernel; the 10-variable
+mobile base is compared element-wise over two iterations and on its success
+flags over the full run (its trajectories are not unique to FP32 precision,
+see that test).
 """
 import numpy as np
 import pytest
@@ -52,7 +53,7 @@ def _compare(tree, res, st, gl, init, costs, o, label):
     if c.get("vmax") is None:
         c["vmax"] = [0.0] * tree.dof
         c["w_vel"] = 0.0
-    close, bad = 0, []
+    close, bad, far, excused = 0, [], [], []
     for b in range(B):
         ora = traj.lm_solve(tree, st[b], gl[b], c, o, init[b].astype(np.float64))
         cg, co = (res["status"][b] & 0xFF) == 0, ora["status"] == oracle.CONVERGED
@@ -60,13 +61,20 @@ def _compare(tree, res, st, gl, init, costs, o, label):
                   np.any(np.abs(ora["rot_err"] - o["tol_rot"]) <= 0.05 * o["tol_rot"]))
         if cg != co and not border:
             bad.append(b)
-        if (abs(res["cost"][b] - ora["cost"]) <= 1e-3 * ora["cost"] and
-                np.abs(res["traj"][b] - ora["Q"]).max() <= 1e-3):
+        dc = abs(res["cost"][b] - ora["cost"]) / ora["cost"]
+        dq = np.abs(res["traj"][b] - ora["Q"]).max()
+        if dc <= 1e-3 and dq <= 1e-3:
             close += 1
+        elif ora["trace_tie"].any():
+            excused.append((b, f"near-tie at iteration {int(np.argmax(ora['trace_tie'])) + 1}",
+                            float(dc), float(dq)))
+        else:
+            far.append((b, float(dc), float(dq)))
     conv = ((res["status"] & 0xFF) == 0).mean()
-    print(f"{label}: {close}/{B} within 1e-3, success {conv:.3f}, status disagreements {bad}")
-    assert not bad
-    assert close >= 0.9 * B
+    print(f"{label}: {close}/{B} within 1e-3, success {conv:.3f}, status disagreements {bad}, "
+          f"excused {excused}, unexplained {far}")
+    assert not bad and not far
+    assert len(excused) <= 1
     return conv
 
 
@@ -129,6 +137,31 @@ def test_traj_argument_errors(ctx):
                          torch.zeros((0, 8, 7), device=DEV), wl["costs"],
                          pk.Options.from_dict(wl["options"]))
     assert out["traj"].shape == (0, 8, 7)
+    # the binding refuses buffers whose sizes differ from the robot's and the
+    # call's, before any launch: a wrong DoF in init, start / goal / vmax of
+    # the wrong shape, a non-float32 or non-contiguous init
+    o = pk.Options.from_dict(wl["options"])
+    good = torch.zeros((2, 8, 7), device=DEV)
+    vmax = torch.full((7,), 2.0, device=DEV)
+    bad_cases = [(z, z, torch.zeros((2, 8, 6), device=DEV), vmax),
+                 (torch.zeros((7, 3), device=DEV), z, good, vmax),
+                 (z, torch.zeros((3, 2), device=DEV), good, vmax),
+                 (z, z, good, torch.zeros(6, device=DEV)),
+                 (z, z, good.double(), vmax),
+                 (z, z, torch.zeros((2, 7, 8), device=DEV).transpose(1, 2), vmax)]
+    for st, gl, ini, vm in bad_cases:
+        with pytest.raises(pk.PkError) as e:
+            ctx.traj_solve(rid, st, gl, ini, wl["costs"], o, vmax=vm)
+        assert e.value.code == -1
+    # a velocity weight without velocity limits is refused by the library
+    with pytest.raises(pk.PkError) as e:
+        ctx.traj_solve(rid, z, z, good, dict(wl["costs"], w_vel=1.0), o, vmax=None)
+    assert e.value.code == -1 and "vmax" in str(e.value)
+    pose = torch.zeros((7, 2), device=DEV)
+    pose[3] = 1.0                                   # identity orientation at the origin
+    out = ctx.traj_solve(rid, pose, pose, good, dict(wl["costs"], w_vel=0.0), o, vmax=None)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out["traj"]).all()
 
 
 def _chain_case(robot, T):
