@@ -249,117 +249,6 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, const __
     epilogue<WM, WN>(epi, acc, cv, m0 + wm * 16 * WM, n0 + wn * 16 * WN, lane, (int)blockIdx.z);
 }
 
-// Both operands K-contiguous (A[m][k], B[n][k]), 128 x 128 output tiles.
-// The K tiles (BK wide) are copied global -> LDS by the load unit itself
-// (global_load_lds_dwordx4, 1 KB per wave instruction) into a ring of NS
-// stages, NS - 1 steps ahead of the MFMAs, with one barrier per step.  A
-// block walks several output tiles when the grid is smaller than the tile
-// count, and the ring runs on across tile boundaries, so the next tile's
-// first copies overlap this tile's epilogue.  The 16-byte chunk c of LDS
-// row r holds global chunk c ^ swz(r), so the 16-row fragment reads hit
-// distinct banks.
-template <int SW, int CH>
-PK_DEV int lds_swz(int r) { return (SW == 0 ? r : SW == 1 ? r >> 1 : r >> 2) & (CH - 1); }
-
-// The grid's blocks are handed to the 8 XCDs in turn (linear id mod 8); tile
-// `it` of block b is chosen so that the blocks of one XCD work on a
-// contiguous run of tiles (the N tiles of an A row block share its L2).
-PK_DEV int tile_of(int b, int it, int G) { return it * G + (b % 8) * (G / 8) + b / 8; }
-
-template <int BK, int NS, int SW, class Epi>
-__global__ __launch_bounds__(256) void gemm_dma_kernel(int M, int N, int K, const __bf16 *__restrict__ A,
-                                                       int lda, const __bf16 *__restrict__ B, int ldb, Epi epi)
-{
-    constexpr int BM = 128, BN = 128, STAGE = (BM + BN) * BK;
-    constexpr int CH = BK / 8, RP = 64 / CH;            // 16-byte chunks per row, rows per 1 KB piece
-    constexpr int PA = BM / RP, PW = (BM + BN) / RP / 4;  // A pieces per stage, pieces per wave
-    static_assert(NS >= 2 && PW * (NS - 2) <= 63, "vmcnt counts the copies of NS - 2 steps");
-    __shared__ __attribute__((aligned(1024))) __bf16 lds[NS * STAGE];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int G = (int)gridDim.x, bid = (int)blockIdx.x;
-    const int nx = N / BN, ntile = nx * (M / BM), nk = K / BK;
-    const int off = tile_of(bid, 0, G);
-    const int nit = off < ntile ? (ntile - off + G - 1) / G : 0;
-    const int S = nit * nk;                               // steps of this block
-
-    // Piece g = PW * wave + i of a stage: g < PA copies A rows, else B rows.
-    int poff[PW];
-    bool pa[PW];
-#pragma unroll
-    for (int i = 0; i < PW; ++i) {
-        const int g = wave * PW + i;
-        const int r = (g % PA) * RP + lane / CH;
-        const int c = (lane % CH) ^ lds_swz<SW, CH>(r);
-        pa[i] = g < PA;
-        poff[i] = r * (pa[i] ? lda : ldb) + 8 * c;
-    }
-    auto issue = [&](int st) {
-        const int t = tile_of(bid, st / nk, G), kt = st % nk;
-        const __bf16 *a0 = A + (size_t)(t / nx) * BM * lda + kt * BK;
-        const __bf16 *b0 = B + (size_t)(t % nx) * BN * ldb + kt * BK;
-        __bf16 *dst = lds + (st % NS) * STAGE + wave * PW * 512;
-#pragma unroll
-        for (int i = 0; i < PW; ++i)
-            __builtin_amdgcn_global_load_lds((const void *)((pa[i] ? a0 : b0) + poff[i]),
-                                             (__attribute__((address_space(3))) void *)(dst + i * 512), 16, 0, 0);
-    };
-
-    f32x4 acc[4][4], cv[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const int r16 = lane & 15, kg = lane >> 4, xr = lds_swz<SW, CH>(r16);
-#pragma unroll
-    for (int t = 0; t < NS - 1; ++t)
-        if (t < S) issue(t);
-    bool stored = false;
-    for (int st = 0; st < S; ++st) {
-        // This wave's copies of step st have landed once at most the later
-        // steps' copies are outstanding (loads retire in order; after the
-        // epilogue's stores only a full drain is safe); the barrier then
-        // publishes all waves' copies and retires the reads of the ring
-        // slot refilled next.
-        if (st + NS - 2 < S && !stored)
-            asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(PW * (NS - 2)) : "memory");
-        else
-            asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-        stored = false;
-        if (st + NS - 1 < S) issue(st + NS - 1);
-        const int kt = st % nk, t = tile_of(bid, st / nk, G);
-        const int m0 = (t / nx) * BM, n0 = (t % nx) * BN;
-        if (kt == 0) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) cv[j] = epi.col(n0 + wn * 64 + 16 * j + 4 * kg);
-        }
-        const __bf16 *sA = lds + (st % NS) * STAGE, *sB = sA + BM * BK;
-#pragma unroll
-        for (int ks = 0; ks < BK / 32; ++ks) {
-            const int co = 8 * ((4 * ks + kg) ^ xr);
-            bf16x8 af[4], bfr[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) af[i] = *(const bf16x8 *)&sA[(wm * 64 + 16 * i + r16) * BK + co];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bfr[j] = *(const bf16x8 *)&sB[(wn * 64 + 16 * j + r16) * BK + co];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
-        }
-        if (kt == nk - 1) {
-            epilogue<4, 4>(epi, acc, cv, m0 + wm * 64, n0 + wn * 64, lane, 0);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-            stored = true;
-        }
-    }
-}
-
 template <int AL, int BL, int WM, int WN, class Epi>
 hipError_t gemm_tile(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb, Epi epi,
                      hipStream_t s, int splits)
