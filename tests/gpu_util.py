@@ -88,6 +88,21 @@ def _chol32_solve(A, g, pivot_rel):
 FP32_RES_ERR = 2.0 ** -20
 
 
+def lambda_at(o, acc, t):
+    """Damping used at iteration t (1-based) after the accept sequence acc."""
+    lam = o["lambda0"]
+    for i in range(t - 1):
+        lam = max(lam / o["nu_down"], o["lambda_min"]) if acc[i] else \
+            min(lam * o["nu_up"], o["lambda_max"])
+    return lam
+
+
+# Largest distance (rad or m, any joint) between the GPU's and the oracle's
+# iterates before their first differing decision that the state-drift excuse
+# accepts.
+DRIFT_MAX = 1e-3
+
+
 def fp32_replay_flips(tree, tg, w, o, seed, ora, t):
     """Whether the oracle's accept decision at iteration t (1-based) is one
     that FP32 arithmetic does not reproduce.  The step is replayed on the host
@@ -101,10 +116,7 @@ def fp32_replay_flips(tree, tg, w, o, seed, ora, t):
     scale): 2 (sqrt c + sqrt c') FP32_RES_ERR + 4 (c + c') 2^-24."""
     import oracle
     q = np.asarray(seed, dtype=np.float64) if t == 1 else ora["trace_q"][t - 2]
-    lam = o["lambda0"]
-    for i in range(t - 1):
-        lam = max(lam / o["nu_down"], o["lambda_min"]) if ora["trace_acc"][i] else \
-            min(lam * o["nu_up"], o["lambda_max"])
+    lam = lambda_at(o, ora["trace_acc"], t)
     r, _, _ = oracle.residual(tree, tg, w, q)
     J = oracle.jacobian(tree, tg, w, q)
     J32, r32 = J.astype(np.float32), r.astype(np.float32)
@@ -128,15 +140,6 @@ def fp32_replay_flips(tree, tg, w, o, seed, ora, t):
     return acc32 != bool(ora["trace_acc"][t - 1]) or abs(ct - c) <= noise
 
 
-def first_divergence(acc_gpu, acc_ora):
-    """First iteration (1-based) at which two accept sequences differ, or 0."""
-    n = min(len(acc_gpu), len(acc_ora))
-    for i in range(n):
-        if int(acc_gpu[i]) != int(acc_ora[i]):
-            return i + 1
-    return 0
-
-
 def at_limit(tree, q, eps=1e-6):
     """Some joint within eps (relative to 1 + |limit|) of a limit: the limit
     residual's kink, where whether its Jacobian row is active (the strict
@@ -149,37 +152,128 @@ def at_limit(tree, q, eps=1e-6):
                 np.any(np.abs(q - hi) <= eps * (1 + np.abs(hi))))
 
 
-def compare_outcome(ctx, rid, tree, tg, seed, w, o, status, iters, ora, variant=0):
-    """(verdict, reason).  verdict 'same' when the GPU's success flag (and, if
-    both converged, iteration count) equals the oracle's; 'excused' when the
-    difference traces back to something FP32 cannot settle, named by reason:
-    'near-tie' (an oracle decision with |c' - c| <= 1e-5 c), 'borderline' (a
-    final or crossing error within 5% of a tolerance), 'fp32-replay' (the
-    first differing decision flips when replayed in FP32, fp32_replay_flips)
-    or 'limit-kink' (taken from an iterate on a joint limit); else 'bad'.
+def first_departure(res, ora, seed):
+    """First iteration (1-based) at which the GPU's traced run leaves the
+    oracle's: ('decision', t) where the accept decisions differ, ('state', t)
+    where both decided alike but the iterates after t are more than DRIFT_MAX
+    apart; (None, 0) if neither happens in the traced iterations."""
+    acc_g, acc_o = res["trace_accept"][0], ora["trace_acc"]
+    q_g, q_o = res["trace_q"][0], ora["trace_q"]
+    for i in range(min(len(acc_g), len(acc_o))):
+        if int(acc_g[i]) != int(acc_o[i]):
+            return "decision", i + 1
+        if np.abs(q_g[i].astype(np.float64) - q_o[i]).max() > DRIFT_MAX:
+            return "state", i + 1
+    return None, 0
+
+
+# Unit roundoff of FP32.
+U32 = 2.0 ** -24
+
+
+def step_error_bound(tree, tg, w, o, q, lam):
+    """(step, bound): the exact LM step from q at damping lam and the
+    first-order forward error estimate of solving for it in FP32,
+    |d delta| <= n kappa u |delta| (kappa the condition number of the damped
+    normal matrix, n its order; Higham, Accuracy and Stability of Numerical
+    Algorithms, 2002, Sec. 10.1).  step is None when the solve fails."""
+    q = np.asarray(q, dtype=np.float64)
+    J = oracle.jacobian(tree, tg, w, q)
+    A = J.T @ J
+    Al = A + lam * np.diag(np.maximum(np.diag(A), o["damping_floor"]))
+    d, ok, _ = oracle.lm_step(tree, tg, w, o, q, lam)
+    if not ok:
+        return None, 0.0
+    return d, A.shape[0] * np.linalg.cond(Al) * U32 * np.linalg.norm(d)
+
+
+def ill_conditioned(tree, tg, w, o, q, lam):
+    """Whether the accept decision of the exact LM iteration from q at damping
+    lam is within what the forward error of an FP32 solve can move: a step
+    error within step_error_bound moves the trial cost by at most
+    |grad c(q + delta)| |d delta|; the decision is ill conditioned when
+    |c(q + delta) - c(q)| is within that."""
+    q = np.asarray(q, dtype=np.float64)
+    d, bound = step_error_bound(tree, tg, w, o, q, lam)
+    if d is None:
+        return False
+    c, ct = oracle.cost(tree, tg, w, q), oracle.cost(tree, tg, w, q + d)
+    r1, _, _ = oracle.residual(tree, tg, w, q + d)
+    grad = 2.0 * oracle.jacobian(tree, tg, w, q + d).T @ r1
+    return abs(ct - c) <= np.linalg.norm(grad) * bound
+
+
+def exact_action(tree, tg, w, o, q, lam):
+    """The exact (FP64) LM iteration from q at damping lam: (accepted, step)."""
+    q = np.asarray(q, dtype=np.float64)
+    d, ok, _ = oracle.lm_step(tree, tg, w, o, q, lam)
+    acc = bool(ok) and oracle.cost(tree, tg, w, q + d) < oracle.cost(tree, tg, w, q)
+    return acc, d
+
+
+def compare_outcome(ctx, rid, tree, tg, seed, w, o, status, itt, ora, variant=0):
+    """(verdict, reason).  verdict 'same' when the GPU's success flag equals
+    the oracle's and, if both converged, so does the first iteration at which
+    the tolerance held (itt, the GPU's iters_to_tol; with early exit that is
+    the iteration count itself, without it the iterations that follow
+    convergence are steps at the rounding floor of the cost, whose count is
+    not an outcome).  Otherwise 'excused' when the difference traces back to
+    something FP32 cannot settle, else 'bad'.  The reasons: 'borderline' (a
+    final or crossing error within 5% of a tolerance), or, at the first
+    iteration where the GPU's traced run leaves the oracle's (first_departure:
+    a differing decision or iterates moving apart):
+      'near-tie'      the oracle's |c' - c| <= 1e-5 c at a differing decision;
+      'fp32-replay'   the differing decision flips when replayed in FP32 from
+                      the oracle's state (fp32_replay_flips);
+      'conditioning'  the exact decision there is ill conditioned
+                      (ill_conditioned), or, where the iterates move apart,
+                      the two steps differ by no more than the forward error
+                      of an FP32 solve (step_error_bound);
+      'limit-kink'    taken from an iterate on a joint limit, where rounding
+                      decides whether the limit row is active;
+      'state-drift'   the GPU's iterate before it is within DRIFT_MAX of the
+                      oracle's, and exact arithmetic from the GPU's iterate
+                      takes the GPU's decision and step: the method turns on a
+                      difference of state that accumulated rounding made.
     ora: oracle.lm_solve result with a full trace."""
     cg, co = (status & 0xff) == 0, (ora["status"] & 0xff) == 0
-    if cg == co and (not cg or iters == ora["iters"]):
+    if cg == co and (not cg or itt == ora["iters_to_tol"]):
         return "same", ""
-    if ora["trace_tie"].any():
-        return "excused", "near-tie"
     if borderline({"pos_err": [ora["pos_err"]], "rot_err": [ora["rot_err"]]}, 0):
         return "excused", "borderline"
-    if cg and co and borderline_at(tree, tg, w, ora["trace_q"], int(min(iters, ora["iters"]))):
+    if cg and co and borderline_at(tree, tg, w, ora["trace_q"], int(min(itt, ora["iters_to_tol"]))):
         return "excused", "borderline"
     kw = {"variant": variant} if variant else {}
     res = solve_gpu(ctx, rid, tree, tg[None], np.asarray(seed)[None], 1, w, o,
                     trace_iters=o["max_iters"], **kw)
-    t = first_divergence(res["trace_accept"][0], ora["trace_acc"])
+    kind, t = first_departure(res, ora, seed)
     if t == 0:
-        return "bad", "no differing decision"
-    if fp32_replay_flips(tree, tg, w, o, seed, ora, t):
+        return "bad", "traced runs do not part"
+    if kind == "decision" and ora["trace_tie"][t - 1]:
+        return "excused", "near-tie"
+    if kind == "decision" and fp32_replay_flips(tree, tg, w, o, seed, ora, t):
         return "excused", "fp32-replay"
-    qg = np.asarray(seed) if t == 1 else res["trace_q"][0][t - 2]
-    qo = np.asarray(seed) if t == 1 else ora["trace_q"][t - 2]
+    qg = np.asarray(seed, dtype=np.float64) if t == 1 else res["trace_q"][0][t - 2].astype(np.float64)
+    qo = np.asarray(seed, dtype=np.float64) if t == 1 else ora["trace_q"][t - 2]
+    lam = lambda_at(o, ora["trace_acc"], t)
+    if kind == "decision" and ill_conditioned(tree, tg, w, o, qo, lam):
+        return "excused", "conditioning"
+    if kind == "state" and t > 0:
+        d, bound = step_error_bound(tree, tg, w, o, qo, lam)
+        step_g = res["trace_q"][0][t - 1].astype(np.float64) - qg
+        step_o = ora["trace_q"][t - 1] - qo
+        if d is not None and np.linalg.norm(step_g - step_o) <= bound:
+            return "excused", "conditioning"
     if at_limit(tree, qg) or at_limit(tree, qo):
         return "excused", "limit-kink"
-    return "bad", f"decision {t} differs"
+    drift = float(np.abs(qg - qo).max())
+    if drift <= DRIFT_MAX:
+        acc, d = exact_action(tree, tg, w, o, qg, lam)
+        step_g = res["trace_q"][0][t - 1].astype(np.float64) - qg
+        if acc == bool(res["trace_accept"][0][t - 1]) and \
+                (not acc or np.abs(d - step_g).max() <= DRIFT_MAX):
+            return "excused", f"state-drift {drift:.1e}"
+    return "bad", f"{kind} {t} differs"
 
 
 def max_excused(n, frac=0.02):

@@ -92,7 +92,7 @@ def _stage_agreement(ctx, rid, tree, tg, starts, Kst, status, q, w, o, iters, sa
         if cg == co:
             continue
         v, why = compare_outcome(ctx, rid, tree, tg[p // Kst], starts[p], w, oo, status[p],
-                                 ora["iters"], ora)
+                                 ora["iters_to_tol"], ora)
         if v == "bad":
             bad.append(int(p))
             print(f"problem {p}: gpu status {status[p]}, oracle {ora['status']} "

@@ -103,18 +103,15 @@ def test_residual_jacobian_parity(ctx, rids, name):
 @pytest.mark.parametrize("name,variant", [("arm7_tool", 1), ("arm7_tool", 2), ("scara4", 0),
                                           ("mobile_arm7", 0), ("hand16_mimic", 0)])
 def test_lm_success_agreement(ctx, rids, name, variant):
-    """Pose + limit + rest (0.01); the mobile arm without the rest term: its
-    10 variables leave a 4-dimensional null space of the pose, along which a
-    rest term makes the last iterations a creep of relative cost decreases
-    near 1e-3 on a damped system of condition ~1e5, accept decisions FP32
-    cannot reproduce (the case that showed it: problem 13 parts at iteration
-    20 with its pose still converged on the GPU)."""
+    """Pose + limit + rest (0.01) on every robot: the rest term also gives the
+    mobile arm's 4-dimensional null space of the pose a unique optimum, so
+    that success flags (and the iteration at which the tolerance is first
+    met) are outcomes the two precisions can agree on."""
     tree = ROBOTS[name]
     T, K = 48, 2
     tg = oracle.targets_from(tree, synth.uniform_configs(tree, T, 303))
     seeds = synth.uniform_configs(tree, T * K, 304)
-    w = {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 10.0,
-         "w_rest": 0.0 if name == "mobile_arm7" else 0.01}
+    w = {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 10.0, "w_rest": 0.01}
     o = {"max_iters": 30, "lambda0": 1e-3, "nu_up": 10.0, "nu_down": 10.0, "lambda_min": 1e-10,
          "lambda_max": 1e10, "early_exit": False, "tol_pos": 1e-3, "tol_rot": 1e-2,
          "damping_floor": 1e-6, "pivot_rel": 1e-6}
@@ -124,7 +121,7 @@ def test_lm_success_agreement(ctx, rids, name, variant):
     for p in range(T * K):
         ora = oracle.lm_solve(tree, tg[p // K], w, o, seeds[p], n_trace=30)
         v, why = compare_outcome(ctx, rids[name], tree, tg[p // K], seeds[p], w, o, res["status"][p],
-                                 res["iters"][p], ora, variant=variant)
+                                 res["iters_to_tol"][p], ora, variant=variant)
         if v == "bad":
             bad.append((p, why))
         elif v == "excused":
@@ -158,7 +155,7 @@ def test_mimic_hand_lm_from_nearby_seeds(ctx, rids):
     for p in range(T):
         ora = oracle.lm_solve(tree, tg[p], w, o, seeds[p], n_trace=30)
         v, why = compare_outcome(ctx, rids["hand16_mimic"], tree, tg[p], seeds[p], w, o,
-                                 res["status"][p], res["iters"][p], ora)
+                                 res["status"][p], res["iters_to_tol"][p], ora)
         if v == "bad":
             bad.append((p, why))
         elif v == "excused":
@@ -264,7 +261,7 @@ def test_mobile_base_workload(ctx, rids):
         ora = oracle.lm_solve(mob, tg[p // K], w, o, g["seeds"][p], n_trace=o["max_iters"])
         conv_o.append((ora["status"] & 0xFF) == 0)
         v, why = compare_outcome(ctx, rids["mobile_arm7"], mob, tg[p // K], g["seeds"][p], w, o,
-                                 res["status"][p], res["iters"][p], ora)
+                                 res["status"][p], res["iters_to_tol"][p], ora)
         if v == "bad":
             bad.append((p, why))
         elif v == "excused":

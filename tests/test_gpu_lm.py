@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import (borderline, check_excused, compare_outcome, quat_to_R, rot_angle, soa,
+from tests.gpu_util import (check_excused, compare_outcome, quat_to_R, rot_angle, soa,
                             solve_gpu, targets_dev)
 
 pytestmark = pytest.mark.gpu
@@ -133,20 +133,6 @@ def test_lm_first_iterates_and_success_arm16(ctx, rids):
     np.testing.assert_array_equal(conv_g, conv_o)
 
 
-def _agreement(res, ora, K=1):
-    conv_g = (res["status"] & 0xff) == 0
-    bad, excused = [], []
-    for p, o in enumerate(ora):
-        cg, co = bool(conv_g[p]), (o["status"] & 0xff) == 0
-        if cg == co:
-            continue
-        if o["trace_tie"].any() or borderline({"pos_err": [o["pos_err"]], "rot_err": [o["rot_err"]]}, 0):
-            excused.append((p, "near-tie or borderline"))
-        else:
-            bad.append(p)
-    return bad, excused
-
-
 @pytest.mark.parametrize("name,wl_name,T", [("arm7", "arm131k", 64), ("hand16", "mixed84k", 96)])
 def test_lm_success_agreement(ctx, rids, name, wl_name, T):
     wl = synth.workload(wl_name, targets=T)
@@ -157,7 +143,14 @@ def test_lm_success_agreement(ctx, rids, name, wl_name, T):
     w = g.get("weights", wl["weights"])
     res = solve_gpu(ctx, rids[name], tree, tg, g["seeds"], K, w, o)
     ora = _oracle_traces(tree, tg, g["seeds"], K, w, o, o["max_iters"])
-    bad, excused = _agreement(res, ora, K)
+    bad, excused = [], []
+    for p, x in enumerate(ora):
+        v, why = compare_outcome(ctx, rids[name], tree, tg[p // K], g["seeds"][p], w, o,
+                                 res["status"][p], res["iters_to_tol"][p], x)
+        if v == "bad":
+            bad.append((p, why))
+        elif v == "excused":
+            excused.append((p, why))
     agree = 1 - (len(bad) + len(excused)) / len(ora)
     print(f"{name}/{wl_name}: agreement {agree:.4f}, excused {len(excused)}, unexplained {bad}")
     assert not bad
@@ -193,7 +186,7 @@ def test_full_size_arm131k_sampled(ctx, rids):
     for p in sample:
         ora = oracle.lm_solve(tree, tg[p // K], wl["weights"], o, g["seeds"][p], n_trace=30)
         v, why = compare_outcome(ctx, rids["arm7"], tree, tg[p // K], g["seeds"][p], wl["weights"], o,
-                                 res["status"][p], res["iters"][p], ora)
+                                 res["status"][p], res["iters_to_tol"][p], ora)
         if v == "bad":
             bad.append((int(p), why))
         elif v == "excused":

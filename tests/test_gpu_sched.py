@@ -122,7 +122,7 @@ def test_autotune_and_oracle_sample(ctx, batch):
             o = oracle.lm_solve(g["tree"], g["tg"][p // g["K"]], g["wd"], wl["options"],
                                 g["seeds_np"][p], n_trace=wl["options"]["max_iters"])
             v, why = compare_outcome(ctx, g["rid"], g["tree"], g["tg"][p], g["seeds_np"][p], g["wd"],
-                                     wl["options"], out["status"][p], out["iters"][p], o)
+                                     wl["options"], out["status"][p], out["iters_to_tol"][p], o)
             n += 1
             if v == "bad":
                 print(f"{g['tree'].name} problem {p}: gpu iters {out['iters'][p]} status {out['status'][p]}, "
@@ -168,7 +168,7 @@ def test_full_size_mixed84k_sampled(ctx):
             o = oracle.lm_solve(g["tree"], g["tg"][p], g["wd"], wl["options"], g["seeds_np"][p],
                                 n_trace=wl["options"]["max_iters"])
             v, why = compare_outcome(ctx, g["rid"], g["tree"], g["tg"][p], g["seeds_np"][p], g["wd"],
-                                     wl["options"], out["status"][p], out["iters"][p], o)
+                                     wl["options"], out["status"][p], out["iters_to_tol"][p], o)
             n += 1
             if v == "bad":
                 bad.append((g["tree"].name, int(p), why))
