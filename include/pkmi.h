@@ -56,6 +56,8 @@ typedef struct pk_ctx pk_ctx;
 #define PK_MAX_JOINTS 64          /* variables (non-fixed joints) per robot      */
 #define PK_MAX_TREE_JOINTS 128    /* joints of a description, fixed ones included */
 #define PK_MAX_EES 8
+#define PK_MAX_DEVICES 64         /* devices the allocation-free entry point serves */
+#define PK_NOALLOC_MAX_PROBLEMS (1 << 20)  /* problems per pk_ik_solve_noalloc call  */
 
 /* Kernel variants for pk_lm_options.variant. */
 #define PK_VARIANT_AUTO 0     /* pick by robot shape and the autotune table  */
@@ -216,6 +218,22 @@ int pk_residual_jacobian(pk_ctx *ctx, int32_t robot_id, int64_t N, int32_t K,
 int pk_ik_solve(pk_ctx *ctx, int32_t robot_id, const pk_ik_problem *problem,
                 const pk_cost_weights *w, const pk_lm_options *opt,
                 const pk_ik_outputs *out, void *stream);
+
+/* pk_ik_solve without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and errors as pk_ik_solve; the
+ * scratch that best-of-K needs when the caller passes no cost, pose_cost or
+ * status buffer (12 bytes per problem) comes from a 12 MiB device array that
+ * the library holds on each GPU until the process ends, instead of the
+ * context's grow-only workspace.  The caller still owns every input and
+ * output.  Limit: T*K <= PK_NOALLOC_MAX_PROBLEMS, else PK_EUNSUPPORTED before
+ * anything is launched.  All calls on one GPU (every context on it) share the
+ * array, which keeps the last call's contents: calls that overlap in time on
+ * one GPU (different streams, or different threads) race, so the caller
+ * serialises them (one stream, or events).  Asynchronous on `stream`. */
+int pk_ik_solve_noalloc(pk_ctx *ctx, int32_t robot_id, const pk_ik_problem *problem,
+                        const pk_cost_weights *w, const pk_lm_options *opt,
+                        const pk_ik_outputs *out, void *stream);
 
 /* ------------------------------------------------------- mixed batches
  * Several groups of problems (different robots, shapes, weights) solved

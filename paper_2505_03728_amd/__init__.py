@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libpkmi.so")
 CONVERGED, MAX_ITERS, STALLED, NONFINITE = 0, 1, 2, 3
 JOINT_REVOLUTE, JOINT_PRISMATIC, JOINT_FIXED = 0, 1, 2
 FLAG_FP64 = 0x100
+NOALLOC_MAX_PROBLEMS = 1 << 20      # problems per pk_ik_solve_noalloc call (include/pkmi.h)
 EE_POSE, EE_POSITION = 0, 1
 VARIANT_AUTO, VARIANT_LANE, VARIANT_WAVE = 0, 1, 2
 
@@ -155,6 +156,7 @@ def lib():
                                            vp, vp]
         L.pk_ik_solve.argtypes = [vp, i32, C.POINTER(_Problem), C.POINTER(_Weights),
                                   C.POINTER(_Options), C.POINTER(_Outputs), vp]
+        L.pk_ik_solve_noalloc.argtypes = L.pk_ik_solve.argtypes
         fp = C.POINTER(C.c_float)
         L.pk_seeder_create.argtypes = [vp, i32, i32, i32, i32, fp, i64, C.POINTER(i32)]
         L.pk_seeder_param_count.argtypes = [vp, i32, C.POINTER(i64)]
@@ -567,6 +569,22 @@ class Context:
         w, op = weights._c(), options._c()
         self._call(lib().pk_ik_solve(self._h, rid, C.byref(pr), C.byref(w), C.byref(op),
                                      C.byref(o), self.stream()))
+        return out
+
+    def ik_solve_noalloc(self, rid, targets, seeds, K, weights: Weights, options: Options, out):
+        """As ik_solve, through the allocation-free entry point (T*K at most
+        NOALLOC_MAX_PROBLEMS; calls on one GPU share its scratch and must not
+        overlap in time)."""
+        info = self.robot_info(rid)
+        if targets.dim() != 2:
+            raise PkError(-1, f"targets: shape {tuple(targets.shape)}, expected (floats, T)")
+        T = targets.shape[1]
+        self._check_ik(info, targets, seeds, T, K, out)
+        pr = _Problem(T, K, _ptr(targets), _ptr(seeds))
+        o = self._outputs_c(out)
+        w, op = weights._c(), options._c()
+        self._call(lib().pk_ik_solve_noalloc(self._h, rid, C.byref(pr), C.byref(w), C.byref(op),
+                                             C.byref(o), self.stream()))
         return out
 
 

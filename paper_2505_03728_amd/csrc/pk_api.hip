@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -169,6 +170,38 @@ hipError_t pk::launch_lm(const RobotEntry &rb, const SolveParams &P, int variant
                                       : launch_lm_wave(rb.dev, rb.host, P, s, persist_blocks);
 }
 
+// Scratch of the allocation-free solve: pose-only cost, total cost and status
+// of up to PK_NOALLOC_MAX_PROBLEMS problems when best-of-K needs them and the
+// caller did not ask for them.  One copy per GPU, held until the process
+// ends; its device address is looked up once per device (scratch_ptr).
+static __device__ __align__(256) float scratch[3 * (size_t)PK_NOALLOC_MAX_PROBLEMS];
+
+namespace {
+std::mutex g_scratch_mu;
+float *g_scratch_dev[PK_MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of `scratch` on `device` (current), looked up on the first
+// call for that device.  The host-side name of the array is not a device
+// address and is never passed to a kernel or a copy.
+static int scratch_ptr(pk_ctx *ctx, int device, float **ptr)
+{
+    if (device < 0 || device >= PK_MAX_DEVICES)
+        return fail(ctx, PK_EUNSUPPORTED, "device %d beyond the %d devices the scratch table holds",
+                    device, PK_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(ctx, PK_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                        hipGetErrorString(e));
+        g_scratch_dev[device] = (float *)p;
+    }
+    *ptr = g_scratch_dev[device];
+    return PK_OK;
+}
+
 // ------------------------------------------------------------------- API
 
 extern "C" {
@@ -186,6 +219,13 @@ int pk_create(pk_ctx **out, int device_ordinal)
         return fail(nullptr, PK_EHIP, "pk_create: hipSetDevice(%d) failed", device_ordinal);
     pk_ctx *c = new pk_ctx;
     c->device = device_ordinal;
+    float *scr = nullptr;
+    int rc = scratch_ptr(c, device_ordinal, &scr);      // once per device, device current
+    if (rc) {
+        g_err_noctx = c->err;
+        delete c;
+        return rc;
+    }
     *out = c;
     return PK_OK;
 }
@@ -517,21 +557,25 @@ static int ensure_ws(pk_ctx *ctx, size_t bytes)
     return PK_OK;
 }
 
-int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_weights *w,
-                const pk_lm_options *o, const pk_ik_outputs *out, void *stream)
+// Shared body of pk_ik_solve and pk_ik_solve_noalloc.  noalloc: the
+// best-of-K scratch comes from `scratch` (problem count bounded) instead of
+// the context's grow-only workspace.
+static int ik_solve_impl(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_weights *w,
+                         const pk_lm_options *o, const pk_ik_outputs *out, void *stream, bool noalloc)
 {
-    if (!ctx) return fail(nullptr, PK_EINVAL, "pk_ik_solve: ctx is NULL");
+    const char *fn = noalloc ? "pk_ik_solve_noalloc" : "pk_ik_solve";
+    if (!ctx) return fail(nullptr, PK_EINVAL, "%s: ctx is NULL", fn);
     RobotEntry *rb = robot_of(ctx, id);
-    if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_ik_solve: unknown robot %d", id);
-    if (!pr || !w || !o || !out) return fail(ctx, PK_EINVAL, "pk_ik_solve: NULL argument");
-    if (pr->n_targets < 0 || pr->K < 1) return fail(ctx, PK_EINVAL, "pk_ik_solve: bad T=%lld K=%d", (long long)pr->n_targets, pr->K);
+    if (!rb) return fail(ctx, PK_ENOTFOUND, "%s: unknown robot %d", fn, id);
+    if (!pr || !w || !o || !out) return fail(ctx, PK_EINVAL, "%s: NULL argument", fn);
+    if (pr->n_targets < 0 || pr->K < 1) return fail(ctx, PK_EINVAL, "%s: bad T=%lld K=%d", fn, (long long)pr->n_targets, pr->K);
     const int64_t N = pr->n_targets * pr->K;
     if (N == 0) return PK_OK;
-    if (N >= (int64_t)1 << 31) return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve: %lld problems, limit 2^31 - 1", (long long)N);
-    if (!pr->targets || !pr->seeds || !out->joints) return fail(ctx, PK_EINVAL, "pk_ik_solve: NULL targets/seeds/joints");
+    if (N >= (int64_t)1 << 31) return fail(ctx, PK_EUNSUPPORTED, "%s: %lld problems, limit 2^31 - 1", fn, (long long)N);
+    if (!pr->targets || !pr->seeds || !out->joints) return fail(ctx, PK_EINVAL, "%s: NULL targets/seeds/joints", fn);
     if (out->trace_iters < 0 || out->trace_iters > 64 ||
         (out->trace_iters > 0 && (!out->trace_q || !out->trace_accept)))
-        return fail(ctx, PK_EINVAL, "pk_ik_solve: bad trace request");
+        return fail(ctx, PK_EINVAL, "%s: bad trace request", fn);
 
     SolveParams P;
     int variant = 0;
@@ -545,9 +589,14 @@ int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_
     // them and the caller did not ask for them.
     float *ws_f = nullptr;
     if (want_best && !(out->pose_cost && out->cost && out->status)) {
-        int rc = ensure_ws(ctx, (size_t)N * 4 * 3);
-        if (rc) return rc;
-        ws_f = (float *)ctx->ws;
+        if (noalloc) {
+            int rc = scratch_ptr(ctx, ctx->device, &ws_f);
+            if (rc) return rc;
+        } else {
+            int rc = ensure_ws(ctx, (size_t)N * 4 * 3);
+            if (rc) return rc;
+            ws_f = (float *)ctx->ws;
+        }
     }
 
     P.K = pr->K; P.N = N; P.T = pr->n_targets;
@@ -564,6 +613,22 @@ int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_
     if (want_best)
         PK_HIP(ctx, launch_best_of_k(P, H.nv, out->best_index, out->best_joints, out->target_success, s));
     return PK_OK;
+}
+
+int pk_ik_solve(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_weights *w,
+                const pk_lm_options *o, const pk_ik_outputs *out, void *stream)
+{
+    return ik_solve_impl(ctx, id, pr, w, o, out, stream, false);
+}
+
+int pk_ik_solve_noalloc(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const pk_cost_weights *w,
+                        const pk_lm_options *o, const pk_ik_outputs *out, void *stream)
+{
+    if (pr && pr->n_targets > 0 && pr->K > 0 &&
+        pr->n_targets * (int64_t)pr->K > (int64_t)PK_NOALLOC_MAX_PROBLEMS)
+        return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve_noalloc: %lld problems, limit %d",
+                    (long long)(pr->n_targets * (int64_t)pr->K), PK_NOALLOC_MAX_PROBLEMS);
+    return ik_solve_impl(ctx, id, pr, w, o, out, stream, true);
 }
 
 }  // extern "C"
