@@ -1,15 +1,23 @@
 """Benchmark: batched LM IK solves/s on one MI355X.
 
-Workload (one step): 16384 reachable targets x 8 random in-limit seeds on
-the seeded 7-DoF arm (131072 LM problems), FP32, 30 LM iterations, pose +
-joint-limit + rest (0.01) residuals, best-of-8 per target.  Inputs are
-resident in HBM before timing (targets are FK of seeded configurations,
-computed on the GPU).  value = successful targets (1 mm / 0.01 rad) per
-second of the timed region.
+Headline workload (one step): 16384 reachable targets x 8 random in-limit
+seeds on the seeded 7-DoF arm (131072 LM problems), FP32, at most 30 LM
+iterations with early exit at 1 mm / 0.01 rad, pose + joint-limit + rest
+(0.01) residuals, best-of-8 per target.  Inputs are resident in HBM before
+timing (targets are FK of seeded configurations, computed on the GPU).  The
+step (LM launch + best-of-K launch) is captured once into a HIP graph; the
+step time is the median over the timed replays, each bracketed by HIP events.
+value = successful targets (1 mm / 0.01 rad) per second of that time.
+
+The same line carries the learned-seed comparison: the seeder MLP
+(7-512-512-512-56, BF16 matrix cores) trained here on 2M (FK(q), q) pairs,
+then learned seeds + <= 10 LM iterations + random-seed fallback against plain
+LM from 8 random seeds, on 131072 fresh targets (success, solves/s,
+iterations to tolerance, FP32 roofline fraction of each form).
 
 Prints one JSON line.  The roofline entry is for the LM kernel, timed alone
 with HIP events on its stream; the CPU baseline is the FP64 oracle on a
-bounded sample of the same workload on the host's cores.
+bounded sample of the headline workload on the host's cores (and on one).
 """
 import argparse
 import json
@@ -21,33 +29,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VALU_PEAK = 157.3      # TFLOP/s, MI355X FP32 vector (datasheet; packed FP32)
+FP32_VALU_UNPACKED = 78.6   # TFLOP/s, 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
+BF16_MFMA_PEAK = 2500.0     # TFLOP/s, MI355X dense BF16 matrix cores (datasheet)
 
 # HBM traffic per launch of the arm LM kernel: rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for
 # a 256 MiB device-to-device copy (--copy-probe).  Valid only while the kernel
-# sources hash to `sha256`; otherwise the bench reports traffic as null.
+# sources hash to `sha256` and the run is the profiled workload; otherwise the
+# bench reports traffic as null.
 LANE_KERNEL_SOURCES = ["paper_2505_03728_amd/csrc/lm_lane.hip", "paper_2505_03728_amd/csrc/pk_device.hpp",
                        "paper_2505_03728_amd/csrc/pk_internal.hpp", "include/pkmi.h"]
-ARM_TRAFFIC = {"sha256": "654297e882ee13f6", "fetch_kib": 2828.1, "write_kib": 7680.0, "fetch_scale": 2.0,
-               "write_scale": 1.0}
+ARM_TRAFFIC = {"sha256": None, "fetch_kib": None, "write_kib": None, "fetch_scale": 2.0,
+               "write_scale": 1.0,
+               "workload": {"targets": 16384, "K": 8, "max_iters": 30, "early_exit": True},
+               "profile": "profiles/lm_lane_arm131k_hbm_counters.md"}
 
 
 def sources_hash(files):
     import hashlib
     h = hashlib.sha256()
-    root = os.path.dirname(os.path.abspath(__file__))
     for f in files:
-        with open(os.path.join(root, f), "rb") as fh:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def arm_traffic_bytes():
+def arm_traffic_bytes(workload):
+    """HBM bytes per launch from the stored counter readings, or None when the
+    kernel sources or the workload differ from the profiled ones."""
     t = ARM_TRAFFIC
-    if t["sha256"] is None or t["sha256"] != sources_hash(LANE_KERNEL_SOURCES):
+    if t["sha256"] is None or t["sha256"] != sources_hash(LANE_KERNEL_SOURCES) or \
+            workload != t["workload"]:
         return None
     return round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
-FP32_VALU_UNPACKED = 78.6   # TFLOP/s, 256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz
 
 
 def parse():
@@ -57,8 +71,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="headline only (skip the learned-seed comparison)")
     ap.add_argument("--targets", type=int, default=16384)
     ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--fixed-budget", action="store_true",
+                    help="early exit off (every problem runs all its iterations)")
     ap.add_argument("--workload", default="arm131k",
                     choices=["arm131k", "tree4k", "mixed84k", "seeder", "beam", "mobile", "traj"])
     ap.add_argument("--epochs", type=int, default=20)
@@ -67,46 +85,110 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(tree, wl, T_full, K, budget_s):
-    """FP64 oracle on the host: whole chunks of targets until the budget is spent."""
-    import numpy as np
+def host_cpu():
+    """CPU model, logical CPUs of the host and CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    return {"cpu_model": model, "host_logical_cpus": os.cpu_count(), "affinity_cpus": aff}
 
+
+# A GPU's share of its host is 16 CPUs: the oracle's thread pool is sized to
+# the CPUs this process may run on, at most that share.
+CPU_SHARE = 16
+
+
+def oracle_threads():
+    return max(1, min(CPU_SHARE, host_cpu()["affinity_cpus"]))
+
+
+def cpu_baseline(tree, wl, T_full, K, budget_s):
+    """FP64 oracle on the host: whole chunks of targets until the budget is
+    spent, on the pool's threads; then a shorter sample on one thread."""
     import oracle
     import synth
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = oracle_threads()
     g = synth.workload("arm131k", targets=T_full)["groups"][0]
-    chunk = 512
-    done_t = succ = 0
-    t0 = time.perf_counter()
-    elapsed = 0.0
-    while done_t < T_full and elapsed < budget_s:
-        a, b = done_t, min(T_full, done_t + chunk)
-        tg = oracle.targets_from(tree, g["q_star"][a:b])
-        s0 = time.perf_counter()
-        r = oracle.lm_solve_batch(tree, tg, g["seeds"][a * K:b * K], K, wl["weights"],
-                                  wl["options"], threads=threads)
-        _, ok = oracle.best_of_k(r["status"], r["cost"], r["pose_cost"], K)
-        elapsed += time.perf_counter() - s0
-        succ += int(ok.sum())
-        done_t = b
-    rate = succ / elapsed if elapsed > 0 else 0.0
-    return {"value": rate, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {done_t} of {T_full} targets x {K} seeds, FP64, "
-                      f"{wl['options']['max_iters']} iterations, {elapsed:.1f} s (FK of targets "
-                      f"not timed)",
-            "success_rate": succ / max(done_t, 1)}
+
+    def run(nthreads, budget, chunk):
+        done_t = succ = 0
+        elapsed = 0.0
+        while done_t < T_full and elapsed < budget:
+            a, b = done_t, min(T_full, done_t + chunk)
+            tg = oracle.targets_from(tree, g["q_star"][a:b])
+            s0 = time.perf_counter()
+            r = oracle.lm_solve_batch(tree, tg, g["seeds"][a * K:b * K], K, wl["weights"],
+                                      wl["options"], threads=nthreads)
+            _, ok = oracle.best_of_k(r["status"], r["cost"], r["pose_cost"], K)
+            elapsed += time.perf_counter() - s0
+            succ += int(ok.sum())
+            done_t = b
+        return succ, done_t, elapsed
+
+    succ, done_t, elapsed = run(threads, budget_s, 512)
+    s1, d1, e1 = run(1, budget_s / 3, 32)
+    cpu = host_cpu()
+    return {"value": succ / elapsed if elapsed > 0 else 0.0, "unit": "solves/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {done_t} of {T_full} targets x {K} seeds, FP64, at most "
+                      f"{wl['options']['max_iters']} iterations (early exit "
+                      f"{'on' if wl['options']['early_exit'] else 'off'}), {elapsed:.1f} s on "
+                      f"{threads} threads (FK of targets not timed); one thread: first {d1} "
+                      f"targets, {e1:.1f} s",
+            "success_rate": succ / max(done_t, 1),
+            "value_1thread": s1 / e1 if e1 > 0 else 0.0,
+            **cpu}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
-                                   f"--gpus {args.gpus} is not supported"}))
-        sys.exit(2)
-    if args.workload != "arm131k":
-        {"tree4k": run_tree, "mixed84k": run_mixed, "seeder": run_seeder,
-         "beam": run_beam, "mobile": run_mobile, "traj": run_traj}[args.workload](args)
-        return
+def _replay_times(fn, steps, warmup):
+    """Per-step times (ms) of fn, each bracketed by HIP events on the current
+    stream, after warmup untimed calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record(st)
+        fn()
+        e1.record(st)
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) for e0, e1 in ev]
+
+
+def _stats(ts):
+    import numpy as np
+    a = np.asarray(ts)
+    return {"median": float(np.median(a)), "p10": float(np.percentile(a, 10)),
+            "p90": float(np.percentile(a, 90)), "mean": float(a.mean()), "reps": int(a.size)}
+
+
+def _itt_per_target(itt, T, K):
+    """Iterations to tolerance per target: the fewest over its seeds (solved
+    targets only), mean and median."""
+    import numpy as np
+    itt = itt.reshape(T, K)
+    best = np.where(itt >= 0, itt, 10 ** 6).min(1)
+    ok = best < 10 ** 6
+    return (float(best[ok].mean()) if ok.any() else None,
+            float(np.median(best[ok])) if ok.any() else None)
+
+
+def headline(args, ctx):
+    """The benchmark's step, graph-captured; the LM kernel timed alone for the
+    roofline."""
     import numpy as np
     import torch
 
@@ -116,11 +198,11 @@ def main():
 
     dev = "cuda:0"
     wl = synth.workload("arm131k", targets=args.targets)
+    wl["options"]["early_exit"] = not args.fixed_budget
     g = wl["groups"][0]
     tree, K = g["tree"], g["K"]
     T = g["q_star"].shape[0]
     N = T * K
-    ctx = pk.Context(0)
     rid = ctx.upload(tree)
     info = ctx.robot_info(rid)
 
@@ -135,35 +217,30 @@ def main():
     out["status"] = torch.empty(N, dtype=torch.int32, device=dev)
     out["cost"] = torch.empty(N, dtype=torch.float32, device=dev)
 
-    for _ in range(args.warmup):
+    # warm up eagerly (the library sizes its workspace here), then capture
+    for _ in range(max(1, args.warmup)):
         ctx.ik_solve(rid, targets, seeds, K, w, o, out)
     torch.cuda.synchronize()
-    print(f"# warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        with torch.cuda.graph(graph, stream=cap):
+            ctx.ik_solve(rid, targets, seeds, K, w, o, out)
+    torch.cuda.current_stream().wait_stream(cap)
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.ik_solve(rid, targets, seeds, K, w, o, out)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = e0.elapsed_time(e1) / args.steps
+    print(f"# graph captured; warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    ts = _replay_times(graph.replay, args.steps, args.warmup)
+    st = _stats(ts)
+    ms_step = st["median"]
     success = int(out["target_success"].sum().item())
     value = success / (ms_step / 1e3)
-    print(f"# timed {args.steps} steps: {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
+    print(f"# timed {args.steps} graph replays: median {ms_step:.4f} ms/step", file=sys.stderr, flush=True)
 
     # LM kernel alone (no best-of-K launch), HIP events on the same stream.
     out2 = ctx.alloc_outputs(rid, T, K, best=False, full=True)
-    ctx.ik_solve(rid, targets, seeds, K, w, o, out2)
-    torch.cuda.synchronize()
-    ks = max(5, args.steps)
-    e0.record(stream)
-    for _ in range(ks):
-        ctx.ik_solve(rid, targets, seeds, K, w, o, out2)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / ks
+    kts = _replay_times(lambda: ctx.ik_solve(rid, targets, seeds, K, w, o, out2), max(5, args.steps), 1)
+    k_ms = float(np.mean(kts))
     iters = int(out2["iters"].sum().item())
     accepts = int(out2["accepts"].sum().item())
     blocks = [info["chain_len"]] * info["chains"] if (info["chains"] and args.variant != 2) else None
@@ -171,10 +248,10 @@ def main():
     achieved = flops / (k_ms / 1e3) / 1e12
     conv = ((out2["status"] & 0xFF) == pk.CONVERGED).float().mean().item()
     fp64 = ((out2["status"] & pk.FLAG_FP64) != 0).float().mean().item()
-    itt = out2["iters_to_tol"].cpu().numpy().reshape(T, K)
-    itt_t = np.where(itt >= 0, itt, 10 ** 6).min(1)
-    solved = itt_t < 10 ** 6
+    itt_mean, itt_med = _itt_per_target(out2["iters_to_tol"].cpu().numpy(), T, K)
     hbm = lm_bytes(info["n"], info["m"], info["target_floats"], N, T)
+    wkey = {"targets": T, "K": K, "max_iters": wl["options"]["max_iters"],
+            "early_exit": bool(wl["options"]["early_exit"])}
 
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev)
@@ -197,17 +274,23 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"7-DoF arm LM IK: {T} targets x {K} random seeds = {N} problems, "
-                               f"{wl['options']['max_iters']} iterations, pose(1.0/0.5) + limit(10) "
-                               f"+ rest(0.01), best-of-{K}", "targets": T, "seeds_per_target": K,
-                   "problems": N, "lm_iters": wl["options"]["max_iters"],
+                               f"at most {wl['options']['max_iters']} iterations (early exit "
+                               f"{'on' if wl['options']['early_exit'] else 'off'}), pose(1.0/0.5) + "
+                               f"limit(10) + rest(0.01), best-of-{K}", "targets": T,
+                   "seeds_per_target": K, "problems": N, "lm_iters": wl["options"]["max_iters"],
+                   "early_exit": bool(wl["options"]["early_exit"]),
                    "variant": ["auto", "lane", "wave"][args.variant]},
+        "timing": {"method": "HIP graph of the step (LM + best-of-K launches), replayed; "
+                             "each replay bracketed by HIP events; ms_per_step = median",
+                   **{k: (round(v, 5) if isinstance(v, float) else v) for k, v in st.items()}},
         "success_rate": success / T,
         "problem_convergence": round(conv, 5),
         "fp64_fallback_fraction": round(fp64, 5),
-        "iters_to_tol_mean_per_target": float(itt_t[solved].mean()) if solved.any() else None,
+        "iters_to_tol_per_target": {"mean": itt_mean, "median": itt_med},
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": FP32_VALU_PEAK,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VALU_PEAK, 5),
-                     "traffic": arm_traffic_bytes() if args.variant != 2 else None,
+                     "traffic": arm_traffic_bytes(wkey) if args.variant != 2 else None,
+                     "traffic_source": ARM_TRAFFIC["profile"],
                      "kernel": "lm_lane_kernel<1,7,pose>" if args.variant != 2
                      else "lm_wave_kernel", "kernel_ms": round(k_ms, 5),
                      "algorithmic_flops": flops, "algorithmic_hbm_bytes": hbm,
@@ -215,6 +298,128 @@ def main():
                      "frac_of_unpacked": round(achieved / FP32_VALU_UNPACKED, 5),
                      "lm_problem_iterations": iters, "accepted": accepts},
     }
+    return res, tree, wl, T, K
+
+
+def learned_vs_random(args, ctx, epochs=None):
+    """The learned-seed form against plain random-seed LM on the seeder
+    workload: 131072 fresh targets of the 7-DoF arm, K = 8."""
+    import numpy as np
+    import torch
+
+    import paper_2505_03728_amd as pk
+    from paper_2505_03728_amd.flops import lm_flops
+    import synth
+    wl = synth.workload("seeder")
+    tree, K = wl["tree"], wl["K"]
+    mc = wl["mlp"]
+    rid = ctx.upload(tree)
+    init = synth.mlp_init([7] + [mc["hidden"]] * mc["depth"] + [7 * K], mc["init_seed"])
+    sd = pk.Seeder(ctx, rid, K=K, hidden=mc["hidden"], depth=mc["depth"], init=init)
+    S = wl["train_q"].shape[0]
+    E = epochs or mc["epochs"]
+    qtr = torch.from_numpy(np.ascontiguousarray(wl["train_q"].T.astype(np.float32))).cuda()
+    perm = torch.from_numpy(np.stack([synth.epoch_permutation(S, mc["shuffle_seed"], e)
+                                      for e in range(E)])).cuda()
+    steps_tr = E * (S // mc["batch"])
+    log = torch.zeros(steps_tr, device="cuda")
+    t0 = time.perf_counter()
+    sd.train(qtr, batch=mc["batch"], epochs=E, lr=mc["lr"], perm=perm, loss_log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del perm, qtr
+    print(f"# trained {steps_tr} steps in {train_s:.2f} s, loss {log[0].item():.4f} -> "
+          f"{log[-1].item():.4f}", file=sys.stderr, flush=True)
+    T = wl["eval_q_star"].shape[0]
+    targets = _dev_targets(ctx, rid, tree, wl["eval_q_star"])
+    rseeds = torch.from_numpy(np.ascontiguousarray(wl["plain_seeds"].T.astype(np.float32))).cuda()
+    w = pk.Weights.from_dict(wl["weights"])
+    plain_o = pk.Options.from_dict(wl["options"], early_exit=True)          # <= 30 iterations
+    ref_o = pk.Options.from_dict(wl["options"], max_iters=10, early_exit=True)
+    plain = ctx.alloc_outputs(rid, T, K, best=True)
+    ts_plain = _replay_times(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, plain_o, plain),
+                             args.steps, args.warmup)
+    plain10 = ctx.alloc_outputs(rid, T, K, best=True)
+    ts_plain10 = _replay_times(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, ref_o, plain10),
+                               args.steps, args.warmup)
+    res_l = {}
+
+    def learned():
+        res_l["o"] = ctx.ik_solve_seeded(rid, targets, sd, w, ref_o, fallback=plain_o,
+                                         fallback_seeds=rseeds, fallback_K=K, counters=True)
+    ts_learn = _replay_times(learned, args.steps, args.warmup)
+    seeds_buf = torch.empty((7, T * K), device="cuda")
+    ts_infer = _replay_times(lambda: sd.infer(targets, seeds_buf), args.steps, args.warmup)
+    torch.cuda.synchronize()
+    ms_learn, ms_plain = _stats(ts_learn)["median"], _stats(ts_plain)["median"]
+    ms_plain10, ms_infer = _stats(ts_plain10)["median"], _stats(ts_infer)["median"]
+    lo = res_l["o"]
+    s_plain = int(plain["target_success"].sum())
+    s_plain10 = int(plain10["target_success"].sum())
+    s_learn = int(lo["target_success"].sum())
+    src = lo["source"].cpu().numpy()
+    itt_l = lo["iters_to_tol"].cpu().numpy()
+    itt_p_mean, itt_p_med = _itt_per_target(plain["iters_to_tol"].cpu().numpy(), T, K)
+    blocks = [7]
+    fl_plain = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(plain["iters"].sum()),
+                        int(plain["accepts"].sum()), T * K)
+    n_fb = int(lo["n_fallback"].item())
+    fl_lm = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["refine_iters"].sum()),
+                     int(lo["refine_accepts"].sum()), T * K)
+    fl_lm += lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["fallback_iters"].sum()),
+                      int(lo["fallback_accepts"].sum()), n_fb * K)
+    dims = [7] + [mc["hidden"]] * mc["depth"] + [7 * K]
+    fl_mlp = 2.0 * T * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+    v_learn = s_learn / (ms_learn / 1e3)
+    v_plain = s_plain / (ms_plain / 1e3)
+    ok_l = itt_l >= 0
+    tfl = lambda f, ms: f / (ms / 1e3) / 1e12
+    return {
+        "targets": T, "seeds_per_target": K,
+        "timing": "median of per-call HIP-event times (eager launches)",
+        "learned": {"solves_per_s": round(v_learn, 1), "success_rate": s_learn / T,
+                    "ms": round(ms_learn, 5),
+                    "success_from_learned_seeds": float(np.mean(src == 0)),
+                    "fallback_targets": n_fb,
+                    "iters_to_tol_mean": float(itt_l[ok_l].mean()) if ok_l.any() else None,
+                    "iters_to_tol_median": float(np.median(itt_l[ok_l])) if ok_l.any() else None,
+                    "lm_tflops": round(tfl(fl_lm, ms_learn), 4),
+                    "frac_fp32": round(tfl(fl_lm, ms_learn) / FP32_VALU_PEAK, 6),
+                    "inference_ms": round(ms_infer, 5),
+                    "inference_frac_bf16": round(tfl(fl_mlp, ms_infer) / BF16_MFMA_PEAK, 5),
+                    "schedule": f"seeder -> <= 10 LM iterations (early exit) -> {K} random seeds "
+                                f"x <= 30 iterations on the unsolved targets"},
+        "plain_random": {"solves_per_s": round(v_plain, 1), "success_rate": s_plain / T,
+                         "ms": round(ms_plain, 5),
+                         "iters_to_tol_mean": itt_p_mean, "iters_to_tol_median": itt_p_med,
+                         "tflops": round(tfl(fl_plain, ms_plain), 4),
+                         "frac_fp32": round(tfl(fl_plain, ms_plain) / FP32_VALU_PEAK, 6),
+                         "success_rate_10_iters": s_plain10 / T,
+                         "solves_per_s_10_iters": round(s_plain10 / (ms_plain10 / 1e3), 1)},
+        "speedup_learned_vs_plain": round(v_learn / v_plain, 3),
+        "seeder_training": {"samples": S, "epochs": E, "batch": mc["batch"], "steps": steps_tr,
+                            "seconds": round(train_s, 3), "loss_first": float(log[0]),
+                            "loss_last": float(log[-1])},
+        "mlp_flops": fl_mlp,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                                   f"--gpus {args.gpus} is not supported"}))
+        sys.exit(2)
+    if args.workload != "arm131k":
+        {"tree4k": run_tree, "mixed84k": run_mixed, "seeder": run_seeder,
+         "beam": run_beam, "mobile": run_mobile, "traj": run_traj}[args.workload](args)
+        return
+    import paper_2505_03728_amd as pk
+    ctx = pk.Context(0)
+    res, tree, wl, T, K = headline(args, ctx)
+    if not args.no_learned:
+        print("# learned seeds vs random seeds ...", file=sys.stderr, flush=True)
+        res["learned_vs_random"] = learned_vs_random(args, ctx, args.epochs)
     if not args.no_cpu:
         print("# cpu baseline (FP64 oracle) ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(tree, wl, T, K, args.cpu_seconds)
@@ -259,7 +464,7 @@ def _dev_targets(ctx, rid, tree, q_star):
 def _oracle_rate(groups, weights, options, budget_s):
     """FP64 oracle over the groups' problems (round robin chunks) within the budget."""
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = oracle_threads()
     done = succ = 0
     elapsed = 0.0
     off = [0] * len(groups)
@@ -387,119 +592,33 @@ def run_mixed(args):
 def run_seeder(args):
     """Learned seeder (trained here) + <= 10 LM iterations with fallback, against
     8 random seeds x 30 iterations, on 131072 fresh targets of the 7-DoF arm."""
-    import numpy as np
-    import torch
-
     import paper_2505_03728_amd as pk
-    from paper_2505_03728_amd.flops import lm_flops
     import synth
-    wl = synth.workload("seeder")
-    tree, K = wl["tree"], wl["K"]
-    mc = wl["mlp"]
     ctx = pk.Context(0)
-    rid = ctx.upload(tree)
-    init = synth.mlp_init([7] + [mc["hidden"]] * mc["depth"] + [7 * K], mc["init_seed"])
-    sd = pk.Seeder(ctx, rid, K=K, hidden=mc["hidden"], depth=mc["depth"], init=init)
-    S = wl["train_q"].shape[0]
-    E = args.epochs
-    qtr = torch.from_numpy(np.ascontiguousarray(wl["train_q"].T.astype(np.float32))).cuda()
-    perm = torch.from_numpy(np.stack([synth.epoch_permutation(S, mc["shuffle_seed"], e)
-                                      for e in range(E)])).cuda()
-    steps_tr = E * (S // mc["batch"])
-    log = torch.zeros(steps_tr, device="cuda")
-    t0 = time.perf_counter()
-    sd.train(qtr, batch=mc["batch"], epochs=E, lr=mc["lr"], perm=perm, loss_log=log)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
-    del perm, qtr
-    print(f"# trained {steps_tr} steps in {train_s:.2f} s, loss {log[0].item():.4f} -> "
-          f"{log[-1].item():.4f}", file=sys.stderr, flush=True)
-    T = wl["eval_q_star"].shape[0]
-    targets = _dev_targets(ctx, rid, tree, wl["eval_q_star"])
-    rseeds = torch.from_numpy(np.ascontiguousarray(wl["plain_seeds"].T.astype(np.float32))).cuda()
-    w = pk.Weights.from_dict(wl["weights"])
-    plain_o = pk.Options.from_dict(wl["options"])                          # 30 iterations
-    ref_o = pk.Options.from_dict(wl["options"], max_iters=10, early_exit=True)
-    plain = ctx.alloc_outputs(rid, T, K, best=True)
-    ms_plain = _time(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, plain_o, plain), args.steps,
-                     args.warmup)
-    plain10 = ctx.alloc_outputs(rid, T, K, best=True)
-    ms_plain10 = _time(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, ref_o, plain10), args.steps,
-                       args.warmup)
-    res_l = {}
-    sched = {"k": 0}
-
-    def learned():
-        res_l["o"] = ctx.ik_solve_seeded(rid, targets, sd, w, ref_o, fallback=plain_o,
-                                         fallback_seeds=rseeds, fallback_K=K, counters=True,
-                                         refine_iters_per_launch=sched["k"], refine_blocks_per_cu=4)
-    # refinement schedule: one launch, or k iterations per launch with compaction
-    tune = {}
-    for k in (0, 2, 3, 5):
-        sched["k"] = k
-        tune[k] = _time(learned, 3, 1)
-    sched["k"] = min(tune, key=tune.get)
-    print(f"# refinement schedule: {tune} -> k={sched['k']}", file=sys.stderr, flush=True)
-    ms_learn = _time(learned, args.steps, args.warmup)
-    seeds_buf = torch.empty((7, T * K), device="cuda")
-    ms_infer = _time(lambda: sd.infer(targets, seeds_buf), args.steps, args.warmup)
-    torch.cuda.synchronize()
-    lo = res_l["o"]
-    s_plain = int(plain["target_success"].sum())
-    s_plain10 = int(plain10["target_success"].sum())
-    s_learn = int(lo["target_success"].sum())
-    src = lo["source"].cpu().numpy()
-    itt_l = lo["iters_to_tol"].cpu().numpy()
-    itt_p = plain["iters_to_tol"].cpu().numpy().reshape(T, K)
-    itt_p = np.where(itt_p >= 0, itt_p, 10 ** 6).min(1)
-    blocks = [7]
-    fl_plain = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(plain["iters"].sum()),
-                        int(plain["accepts"].sum()), T * K)
-    n_fb = int(lo["n_fallback"].item())
-    fl_lm = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["refine_iters"].sum()),
-                     int(lo["refine_accepts"].sum()), T * K)
-    fl_lm += lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["fallback_iters"].sum()),
-                      int(lo["fallback_accepts"].sum()), n_fb * K)
-    dims = [7] + [mc["hidden"]] * mc["depth"] + [7 * K]
-    fl_mlp = 2.0 * T * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
-    v_learn = s_learn / (ms_learn / 1e3)
-    v_plain = s_plain / (ms_plain / 1e3)
-    res = _line("IK solves/sec at 1mm/0.01rad success", v_learn, "solves/s", args, ms_learn,
-                {"workload": f"7-DoF arm, {T} fresh targets: learned seeder (MLP 7-512-512-512-56, "
-                             f"K={K}, BF16 MFMA) + <=10 LM iterations (early exit) + fallback to "
-                             f"{K} random seeds x 30 iterations, vs plain {K} random seeds x 30 "
-                             f"iterations", "targets": T, "seeds_per_target": K,
-                 "train_samples": S, "epochs": E, "batch": mc["batch"],
-                 "refine_iters_per_launch": sched["k"]},
-                success_rate=s_learn / T,
-                learned={"solves_per_s": round(v_learn, 1), "success_rate": s_learn / T,
-                         "success_from_learned_seeds": float(np.mean(src == 0)),
-                         "fallback_targets": n_fb, "ms": round(ms_learn, 5),
-                         "iters_to_tol_mean": float(itt_l[itt_l >= 0].mean()),
-                         "lm_tflops": round(fl_lm / ((ms_learn - ms_infer) / 1e3) / 1e12, 4),
-                         "lm_frac_fp32": round(fl_lm / ((ms_learn - ms_infer) / 1e3) / 1e12 / FP32_VALU_PEAK, 6)},
-                plain_random={"solves_per_s": round(v_plain, 1), "success_rate": s_plain / T,
-                              "ms": round(ms_plain, 5),
-                              "iters_to_tol_mean": float(itt_p[itt_p < 10 ** 6].mean()),
-                              "tflops": round(fl_plain / (ms_plain / 1e3) / 1e12, 4),
-                              "frac_fp32": round(fl_plain / (ms_plain / 1e3) / 1e12 / FP32_VALU_PEAK, 6),
-                              "success_rate_10_iters": s_plain10 / T,
-                              "solves_per_s_10_iters": round(s_plain10 / (ms_plain10 / 1e3), 1)},
-                speedup_vs_plain=round(v_learn / v_plain, 3),
-                seeder_training={"steps": steps_tr, "seconds": round(train_s, 3),
-                                 "loss_first": float(log[0]), "loss_last": float(log[-1])},
-                roofline={"bound": "mfma", "achieved": round(fl_mlp / (ms_infer / 1e3) / 1e12, 3),
-                          "peak": 2500.0, "unit": "TFLOP/s",
-                          "frac": round(fl_mlp / (ms_infer / 1e3) / 1e12 / 2500.0, 5), "traffic": None,
+    lv = learned_vs_random(args, ctx, args.epochs)
+    wl = synth.workload("seeder")
+    L, P = lv["learned"], lv["plain_random"]
+    res = _line("IK solves/sec at 1mm/0.01rad success", L["solves_per_s"], "solves/s", args, L["ms"],
+                {"workload": f"7-DoF arm, {lv['targets']} fresh targets: learned seeder (MLP "
+                             f"7-512-512-512-56, K={lv['seeds_per_target']}, BF16 MFMA) + <=10 LM "
+                             f"iterations (early exit) + fallback to random seeds, vs plain random "
+                             f"seeds", "targets": lv["targets"], "seeds_per_target": lv["seeds_per_target"],
+                 "epochs": lv["seeder_training"]["epochs"]},
+                success_rate=L["success_rate"], learned_vs_random=lv,
+                roofline={"bound": "mfma", "achieved": round(lv["mlp_flops"] / (L["inference_ms"] / 1e3) / 1e12, 3),
+                          "peak": BF16_MFMA_PEAK, "unit": "TFLOP/s", "frac": L["inference_frac_bf16"],
+                          "traffic": None,
                           "kernel": "seeder inference (fused BF16 MFMA MLP kernel + encode + seeds)",
-                          "kernel_ms": round(ms_infer, 5), "algorithmic_flops": fl_mlp})
+                          "kernel_ms": L["inference_ms"], "algorithmic_flops": lv["mlp_flops"]})
     if not args.no_cpu:
-        g = {"tree": tree, "q_star": wl["eval_q_star"], "seeds": wl["plain_seeds"], "K": K}
-        rate, th, done, el = _oracle_rate([g], wl["weights"], wl["options"], args.cpu_seconds)
+        g = {"tree": wl["tree"], "q_star": wl["eval_q_star"], "seeds": wl["plain_seeds"], "K": wl["K"]}
+        rate, th, done, el = _oracle_rate([g], wl["weights"], dict(wl["options"], early_exit=True),
+                                          args.cpu_seconds)
         res["cpu_baseline"] = {"value": rate, "unit": "solves/s", "cores": th, "kind": "oracle",
-                               "sample": f"plain form: first {done} of {T} targets x {K} seeds, {el:.1f} s"}
+                               "sample": f"plain form: first {done} of {lv['targets']} targets x "
+                                         f"{wl['K']} seeds, {el:.1f} s", **host_cpu()}
     print(json.dumps(res), flush=True)
-
+    ctx.close()
 
 
 # IK-Beam GPU times of the paper's Table II (analytic Jacobians, RTX 4090,
@@ -561,7 +680,7 @@ def run_beam(args):
                           "kernel_ms": round(k_ms, 5), "algorithmic_flops": flops})
     if not args.no_cpu:
         import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = oracle_threads()
         done = succ = 0
         el = 0.0
         while done < B and el < args.cpu_seconds:

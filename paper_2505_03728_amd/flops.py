@@ -81,7 +81,8 @@ def lm_flops(parent, ee_joint, ee_kind, blocks, iters, accepts, problems):
 
 
 # Algorithmic HBM bytes per problem of a solve: seeds in and joints out
-# (4 n each), per-EE errors (8 m), cost, iterations, accepts, status,
-# iterations-to-tolerance (16); targets (4 * target floats) once per target.
-def lm_bytes(n, m, target_floats, problems, targets):
-    return problems * (8 * n + 8 * m + 16) + targets * 4 * target_floats
+# (4 n each), per-EE errors (8 m), and 4 bytes per per-problem scalar output
+# (by default all six: cost, pose-only cost, iterations, accepts, status,
+# iterations-to-tolerance); targets (4 * target floats) once per target.
+def lm_bytes(n, m, target_floats, problems, targets, scalars=6):
+    return problems * (8 * n + 8 * m + 4 * scalars) + targets * 4 * target_floats
