@@ -547,11 +547,18 @@ def run_mixed(args):
                        "weights": pk.Weights.from_dict(g["weights"]), "wd": g["weights"],
                        "out": ctx.alloc_outputs(rid, T, 1)})
     o = pk.Options.from_dict(wl["options"])
-    k, bpc, tune_ms, variants = ctx.autotune_mixed(groups, o)
+    tuned = ctx.autotune_mixed(groups, o)
+    k, wpc, wg, variants = tuned["k"], tuned["waves_per_cu"], tuned["workgroup_size"], tuned["variants"]
+    mode = "single persistent launch" if tuned["mode"] == pk.SCHED_SINGLE else "per-group launches"
     vnames = ["lane" if v == pk.VARIANT_LANE else "wave" for v in variants]
-    print(f"# autotuned k={k} blocks/CU={bpc} variants={vnames} ({tune_ms:.3f} ms)", file=sys.stderr,
-          flush=True)
+    print(f"# autotuned {mode} k={k} waves/CU={wpc} workgroup={wg} variants={vnames} ({tuned['ms']:.3f} ms)",
+          file=sys.stderr, flush=True)
     ms = _time(lambda: ctx.ik_solve_mixed(groups, o), args.steps, args.warmup)
+    # the best of the other mode on the same groups, for comparison
+    other = pk.SCHED_PER_GROUP if tuned["mode"] == pk.SCHED_SINGLE else pk.SCHED_SINGLE
+    ms_other = min(_time(lambda: ctx.ik_solve_mixed(groups, o, iters_per_launch=kk, waves_per_cu=ww,
+                                                    variants=variants, mode=other), args.steps, args.warmup)
+                   for kk in (0, 25) for ww in (4, 8))
     # the same groups launched one by one without the scheduler
     ms_sep = _time(lambda: [ctx.ik_solve(g["rid"], g["targets"], g["seeds"], 1, g["weights"], o, g["out"])
                             for g in groups], args.steps, args.warmup)
@@ -573,13 +580,19 @@ def run_mixed(args):
     res = _line("IK solves/sec at 1mm/0.01rad success", conv / (ms / 1e3), "solves/s", args, ms,
                 {"workload": "mixed batch in one graph launch: 60000 7-DoF arm + 20000 16-DoF hand "
                              "(4 fingertip positions) + 4096 34-DoF tree problems, early exit, <= 50 "
-                             "iterations", "problems": N, "iters_per_launch": k, "blocks_per_cu": bpc,
+                             "iterations", "problems": N, "schedule": mode, "iters_per_launch": k,
+                 "waves_per_cu": wpc, "workgroup_size": wg,
                  "lanes_per_problem": {g["tree"].name: (1 if v == pk.VARIANT_LANE else 64)
                                        for g, v in zip(groups, variants)}},
                 success_rate=conv / N, groups=per, ms_separate_launches=round(ms_sep, 5),
+                ms_other_schedule={"schedule": "per-group launches" if other == pk.SCHED_PER_GROUP
+                                   else "single persistent launch", "ms": round(ms_other, 5)},
                 roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
                           "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
-                          "kernel": "persistent LM kernels (3 groups)", "algorithmic_flops": flops})
+                          "kernel": "lm_mixed_kernel (one persistent launch over all groups)"
+                          if tuned["mode"] == pk.SCHED_SINGLE else
+                          "persistent lm_lane / lm_wave kernels (one per group, concurrent)",
+                          "algorithmic_flops": flops})
     if not args.no_cpu:
         rate, th, done, el = _oracle_rate(
             [{"tree": g["tree"], "q_star": g["q_star"], "seeds": g["seeds_np"], "K": 1, "w": g["wd"]}

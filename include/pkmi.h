@@ -253,28 +253,56 @@ typedef struct {
 } pk_ik_group;
 
 #define PK_MAX_GROUPS 16
+#define PK_SCHED_SINGLE 0
+#define PK_SCHED_PER_GROUP 1
 
 typedef struct {
     int32_t iters_per_launch;    /* k; 0 = all iterations in one launch        */
-    int32_t blocks_per_cu;       /* persistent grid = blocks_per_cu x CUs       */
+    int32_t waves_per_cu;        /* persistent grid = waves_per_cu x CUs wavefronts */
     int32_t use_graph;           /* 1 = capture / replay a hipGraph             */
+    int32_t workgroup_size;      /* threads per workgroup: 64, 128 or 256 (each
+                                    wavefront pops its own work items); 0 = 64  */
+    int32_t mode;                /* PK_SCHED_SINGLE: every group in ONE persistent
+                                    launch per round, its wavefronts popping
+                                    (group, problem range) items from one device
+                                    queue (at most 8 groups; robots with at most 16
+                                    tree levels and 4 EEs); PK_SCHED_PER_GROUP: each
+                                    group's persistent launches on a stream of its
+                                    own, the groups running concurrently         */
     int32_t variant[PK_MAX_GROUPS];  /* per group: lanes per problem, PK_VARIANT_LANE (1)
                                         or PK_VARIANT_WAVE (64); PK_VARIANT_AUTO = the
                                         options' choice                          */
-} pk_sched_options;              /* k and blocks_per_cu zero = the autotuned entry if any */
+} pk_sched_options;              /* k and waves_per_cu zero = the autotuned entry if any */
 
 /* Asynchronous on `stream`.  sched may be NULL (graph on, autotuned or
- * default schedule). */
+ * default schedule).  All groups share the options (one iteration budget). */
 int pk_ik_solve_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
                       const pk_lm_options *opt, const pk_sched_options *sched, void *stream);
-/* Times every candidate schedule (k in {5, 10, 25, all} x blocks per CU in
- * {2, 4, 8} x, for each group whose robot the per-lane kernel supports, one or
- * 64 lanes per problem; graph on) on these groups, stores the fastest for
- * batches of this signature and returns it.  Runs the solve several times
- * (the outputs hold the last run).  Synchronous. */
+/* Times every candidate schedule (both modes x k in {1, 2, 5, 10, 25, all} x
+ * wavefronts per CU in {2, 4, 8} x, in single mode, workgroup sizes {64, 128,
+ * 256} that fit the LDS x, for each group whose robot the per-lane kernel
+ * supports, one or 64 lanes per problem; graph on) on these groups, stores the fastest in the
+ * context's table under the batch's key (the groups' robot classes: variables
+ * n, EEs m, EE kind; the iteration budget, early exit and variant options;
+ * the GPU architecture, e.g. gfx950) and returns it.  When the environment
+ * variable PK_AUTOTUNE_TABLE names a file, the table is written there as JSON
+ * (pk_create reads that file into every new context).  Runs the solve several
+ * times (the outputs hold the last run).  Synchronous. */
 int pk_autotune_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
                       const pk_lm_options *opt, pk_sched_options *best, float *best_ms,
                       void *stream);
+/* The context's autotune table as JSON: {"format": "pkmi-autotune-1",
+ * "entries": [{"key", "k", "waves_per_cu", "workgroup_size", "variants",
+ * "ms"}, ...]}, one entry per line.  Synchronous host file I/O. */
+int pk_autotune_save(pk_ctx *ctx, const char *path);
+/* Adds (or replaces) the entries of a file written by pk_autotune_save;
+ * *entries (optional) = entries read.  PK_ENOTFOUND if the file cannot be
+ * read. */
+int pk_autotune_load(pk_ctx *ctx, const char *path, int32_t *entries);
+/* The table's entry for this batch's key (what pk_ik_solve_mixed uses when k
+ * and waves_per_cu are zero); PK_ENOTFOUND if there is none. */
+int pk_autotune_lookup(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
+                       const pk_lm_options *opt, pk_sched_options *found, float *ms);
 
 /* ---------------------------------------------------------------- seeder
  * Learned seeder: an MLP (BF16 matrix-core GEMMs, FP32 accumulation) from an
@@ -336,7 +364,7 @@ typedef struct {
                                         k iterations per launch with the unfinished
                                         problems compacted in between (persistent
                                         kernel, hipGraph), as pk_ik_solve_mixed   */
-    int32_t refine_blocks_per_cu;    /* persistent grid for k > 0 (0 = 4)        */
+    int32_t refine_blocks_per_cu;    /* persistent grid for k > 0: wavefronts per CU (0 = 4) */
 } pk_seeded_options;
 
 typedef struct {

@@ -26,6 +26,7 @@ FLAG_FP64 = 0x100
 NOALLOC_MAX_PROBLEMS = 1 << 20      # problems per pk_ik_solve_noalloc call (include/pkmi.h)
 EE_POSE, EE_POSITION = 0, 1
 VARIANT_AUTO, VARIANT_LANE, VARIANT_WAVE = 0, 1, 2
+SCHED_SINGLE, SCHED_PER_GROUP = 0, 1
 
 
 class LibraryMissing(RuntimeError):
@@ -130,8 +131,9 @@ MAX_GROUPS = 16
 
 
 class _Sched(C.Structure):
-    _fields_ = [("iters_per_launch", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("use_graph", C.c_int32), ("variant", C.c_int32 * MAX_GROUPS)]
+    _fields_ = [("iters_per_launch", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("use_graph", C.c_int32), ("workgroup_size", C.c_int32), ("mode", C.c_int32),
+                ("variant", C.c_int32 * MAX_GROUPS)]
 
 
 _lib = None
@@ -174,6 +176,10 @@ def lib():
                                         C.POINTER(_Sched), vp]
         L.pk_autotune_mixed.argtypes = [vp, i32, C.POINTER(_Group), C.POINTER(_Options),
                                         C.POINTER(_Sched), C.POINTER(C.c_float), vp]
+        L.pk_autotune_save.argtypes = [vp, C.c_char_p]
+        L.pk_autotune_load.argtypes = [vp, C.c_char_p, C.POINTER(i32)]
+        L.pk_autotune_lookup.argtypes = [vp, i32, C.POINTER(_Group), C.POINTER(_Options),
+                                         C.POINTER(_Sched), C.POINTER(C.c_float)]
         L.pk_ik_beam.argtypes = [vp, i32, i64, vp, vp, C.POINTER(_Weights), C.POINTER(_Options),
                                  C.POINTER(_BeamSchedule), C.POINTER(_BeamOutputs), vp]
         L.pk_traj_solve.argtypes = [vp, i32, C.POINTER(_TrajProblem), C.POINTER(_TrajCosts),
@@ -184,7 +190,8 @@ def lib():
                   "pk_seeder_forward_layers", "pk_seeder_grad", "pk_seeder_train",
                   "pk_seeder_infer", "pk_seeder_save",
                   "pk_seeder_load", "pk_ik_solve_seeded", "pk_ik_solve_mixed",
-                  "pk_autotune_mixed", "pk_ik_beam", "pk_traj_solve"]:
+                  "pk_autotune_mixed", "pk_autotune_save", "pk_autotune_load",
+                  "pk_autotune_lookup", "pk_ik_solve_noalloc", "pk_ik_beam", "pk_traj_solve"]:
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -197,7 +204,8 @@ def exported_symbols():
             "pk_seeder_param_count", "pk_seeder_get", "pk_seeder_forward",
             "pk_seeder_forward_layers", "pk_seeder_grad",
             "pk_seeder_train", "pk_seeder_infer", "pk_seeder_save", "pk_seeder_load",
-            "pk_ik_solve_seeded", "pk_ik_solve_mixed", "pk_autotune_mixed", "pk_ik_beam",
+            "pk_ik_solve_seeded", "pk_ik_solve_mixed", "pk_autotune_mixed", "pk_autotune_save",
+            "pk_autotune_load", "pk_autotune_lookup", "pk_ik_solve_noalloc", "pk_ik_beam",
             "pk_traj_solve"]
 
 
@@ -457,29 +465,58 @@ class Context:
                             g["weights"]._c(), self._outputs_c(g["out"]))
         return arr
 
-    def ik_solve_mixed(self, groups, options: Options, iters_per_launch=0, blocks_per_cu=0,
-                       use_graph=True, variants=None):
+    def ik_solve_mixed(self, groups, options: Options, iters_per_launch=0, waves_per_cu=0,
+                       use_graph=True, variants=None, workgroup_size=0, mode=None):
         """groups: list of dicts rid, targets [tf, T], seeds [n, T*K], K, weights, out
         (from alloc_outputs).  variants: per group VARIANT_LANE / VARIANT_WAVE (None =
-        the options' choice).  Zero k and blocks_per_cu pick the autotuned entry."""
+        the options' choice).  mode: SCHED_SINGLE (one persistent launch per round over
+        every group, the default) or SCHED_PER_GROUP.  Zero k and waves_per_cu pick the
+        autotuned entry."""
         arr = self._groups_c(groups)
         v = (C.c_int32 * MAX_GROUPS)(*(list(variants or []) + [0] * MAX_GROUPS)[:MAX_GROUPS])
-        sch = _Sched(iters_per_launch, blocks_per_cu, 1 if use_graph else 0, v)
+        sch = _Sched(iters_per_launch, waves_per_cu, 1 if use_graph else 0, workgroup_size,
+                     SCHED_SINGLE if mode is None else mode, v)
         o = options._c()
         self._call(lib().pk_ik_solve_mixed(self._h, len(groups), arr, C.byref(o), C.byref(sch),
                                            self.stream()))
         return groups
 
+    @staticmethod
+    def _sched_dict(sch, n, ms):
+        return {"mode": sch.mode, "k": sch.iters_per_launch, "waves_per_cu": sch.waves_per_cu,
+                "workgroup_size": sch.workgroup_size, "variants": list(sch.variant)[:n], "ms": ms}
+
     def autotune_mixed(self, groups, options: Options):
-        """Times the candidate schedules on these groups; returns (k, blocks_per_cu, ms,
-        per-group variants)."""
+        """Times the candidate schedules on these groups; returns the fastest as a
+        dict: k, waves_per_cu, workgroup_size, variants (per group), ms."""
         arr = self._groups_c(groups)
         sch = _Sched()
         ms = C.c_float()
         o = options._c()
         self._call(lib().pk_autotune_mixed(self._h, len(groups), arr, C.byref(o), C.byref(sch),
                                            C.byref(ms), self.stream()))
-        return sch.iters_per_launch, sch.blocks_per_cu, ms.value, list(sch.variant)[:len(groups)]
+        return self._sched_dict(sch, len(groups), ms.value)
+
+    def autotune_lookup(self, groups, options: Options):
+        """The autotune table's entry for this batch (dict as autotune_mixed), or None."""
+        arr = self._groups_c(groups)
+        sch = _Sched()
+        ms = C.c_float()
+        o = options._c()
+        rc = lib().pk_autotune_lookup(self._h, len(groups), arr, C.byref(o), C.byref(sch), C.byref(ms))
+        if rc == -5:
+            return None
+        self._call(rc)
+        return self._sched_dict(sch, len(groups), ms.value)
+
+    def autotune_save(self, path):
+        self._call(lib().pk_autotune_save(self._h, os.fsencode(path)))
+
+    def autotune_load(self, path):
+        """Reads a table written by autotune_save; returns the number of entries."""
+        n = C.c_int32()
+        self._call(lib().pk_autotune_load(self._h, os.fsencode(path), C.byref(n)))
+        return n.value
 
     def alloc_beam_outputs(self, rid, T, n_seeds=64, keep=4, stages=False, device=None):
         """Device tensors for ik_beam: best_joints [n, T], best_index,

@@ -11,13 +11,17 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpkmi.so")
 SOURCES = ["pk_api.hip", "pk_debug.hip", "lm_lane.hip", "lm_wave.hip", "lm_wave_d8.hip",
            "lm_wave_d16.hip", "lm_wave_d32.hip", "lm_wave_d64.hip", "seeder.hip",
-           "pipeline.hip", "sched.hip", "beam.hip", "traj.hip"]
+           "pipeline.hip", "sched.hip", "lm_mixed.hip", "beam.hip", "traj.hip"]
 ARCH = "gfx950"
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # packed FP32 VALU ops are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one source expression: the same device
+    # function then rounds the same way in every kernel it is inlined into
+    # (the mixed-batch kernel and the per-robot kernels give identical results)
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]

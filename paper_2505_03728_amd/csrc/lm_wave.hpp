@@ -464,7 +464,7 @@ template <int DMAX, int MMAX>
 PK_DEV void wave_problem(const RobotC *__restrict__ rb, const SolveParams &P, float *lds, int64_t wi)
 {
     using L = Lds<DMAX, MMAX>;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;     // wavefronts of a multi-wave block each run their own problem
     const int64_t p = P.active ? (int64_t)P.active[wi] : wi;
     const int64_t N = P.N, T = P.T, t = p / P.K;
     const int n = rb->n, m = rb->m, max_depth = rb->max_depth;

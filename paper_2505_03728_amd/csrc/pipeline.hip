@@ -170,7 +170,8 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
         pk_sched_options so;
         memset(&so, 0, sizeof so);
         so.iters_per_launch = o->refine_iters_per_launch;
-        so.blocks_per_cu = o->refine_blocks_per_cu > 0 ? o->refine_blocks_per_cu : 4;
+        so.waves_per_cu = o->refine_blocks_per_cu > 0 ? o->refine_blocks_per_cu : 4;
+        so.workgroup_size = 64;
         so.use_graph = 1;
         rc = sched_run(ctx, 1, &g, &o->refine, so, s);
         if (rc) return rc;

@@ -226,6 +226,7 @@ int pk_create(pk_ctx **out, int device_ordinal)
         delete c;
         return rc;
     }
+    sched_load_env(c);
     *out = c;
     return PK_OK;
 }

@@ -44,6 +44,8 @@ int prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *w,
 hipError_t launch_lm(const RobotEntry &rb, const SolveParams &P, int variant, hipStream_t s,
                      int persist_blocks = 0);
 void sched_free(pk_ctx *ctx);
+// Reads the autotune table named by PK_AUTOTUNE_TABLE, if any, into ctx.
+void sched_load_env(pk_ctx *ctx);
 // The mixed scheduler on these groups (no argument checks beyond the
 // per-group ones); used by the seeded pipeline's refinement.
 int sched_run(pk_ctx *ctx, int n_groups, const pk_ik_group *groups, const pk_lm_options *opt,

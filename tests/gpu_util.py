@@ -156,10 +156,12 @@ def first_departure(res, ora, seed):
     """First iteration (1-based) at which the GPU's traced run leaves the
     oracle's: ('decision', t) where the accept decisions differ, ('state', t)
     where both decided alike but the iterates after t are more than DRIFT_MAX
-    apart; (None, 0) if neither happens in the traced iterations."""
+    apart; (None, 0) if neither happens in the iterations both runs took."""
     acc_g, acc_o = res["trace_accept"][0], ora["trace_acc"]
     q_g, q_o = res["trace_q"][0], ora["trace_q"]
-    for i in range(min(len(acc_g), len(acc_o))):
+    # iterations both runs took (a run that stopped early pads its trace)
+    common = min(len(acc_g), len(acc_o), int(res["iters"][0]), int(ora["iters"]))
+    for i in range(common):
         if int(acc_g[i]) != int(acc_o[i]):
             return "decision", i + 1
         if np.abs(q_g[i].astype(np.float64) - q_o[i]).max() > DRIFT_MAX:
@@ -239,9 +241,10 @@ def compare_outcome(ctx, rid, tree, tg, seed, w, o, status, itt, ora, variant=0)
     cg, co = (status & 0xff) == 0, (ora["status"] & 0xff) == 0
     if cg == co and (not cg or itt == ora["iters_to_tol"]):
         return "same", ""
-    if borderline({"pos_err": [ora["pos_err"]], "rot_err": [ora["rot_err"]]}, 0):
+    tol = {"tol_pos": o["tol_pos"], "tol_rot": o["tol_rot"]}
+    if borderline({"pos_err": [ora["pos_err"]], "rot_err": [ora["rot_err"]]}, 0, **tol):
         return "excused", "borderline"
-    if cg and co and borderline_at(tree, tg, w, ora["trace_q"], int(min(itt, ora["iters_to_tol"]))):
+    if cg and co and borderline_at(tree, tg, w, ora["trace_q"], int(min(itt, ora["iters_to_tol"])), **tol):
         return "excused", "borderline"
     kw = {"variant": variant} if variant else {}
     res = solve_gpu(ctx, rid, tree, tg[None], np.asarray(seed)[None], 1, w, o,

@@ -59,17 +59,22 @@ def test_mixed_equals_separate_launches(ctx, batch):
         ctx.ik_solve(g["rid"], g["targets"], g["seeds"], g["K"], g["weights"], opt, g["out"])
     torch.cuda.synchronize()
     ref = _host(sep)
-    for k, bpc, graph in [(5, 2, True), (10, 4, True), (0, 1, False), (3, 8, False)]:
+    S, PG = pk.SCHED_SINGLE, pk.SCHED_PER_GROUP
+    for mode, k, wpc, wg, graph in [(S, 5, 2, 64, True), (S, 10, 4, 128, True), (S, 0, 1, 64, False),
+                                    (S, 3, 8, 256, False), (S, 1, 4, 64, True), (PG, 5, 2, 64, True),
+                                    (PG, 0, 4, 64, False)]:
         gs = _fresh(ctx, [dict(g) for g in groups])
-        ctx.ik_solve_mixed(gs, opt, iters_per_launch=k, blocks_per_cu=bpc, use_graph=graph)
+        ctx.ik_solve_mixed(gs, opt, iters_per_launch=k, waves_per_cu=wpc, workgroup_size=wg,
+                           use_graph=graph, mode=mode)
         if graph:       # replay the cached graph once more on the same buffers
-            ctx.ik_solve_mixed(gs, opt, iters_per_launch=k, blocks_per_cu=bpc, use_graph=graph)
+            ctx.ik_solve_mixed(gs, opt, iters_per_launch=k, waves_per_cu=wpc, workgroup_size=wg,
+                               use_graph=graph, mode=mode)
         torch.cuda.synchronize()
         got = _host(gs)
         for gi, (a, b) in enumerate(zip(ref, got)):
             for key in KEYS:
-                np.testing.assert_array_equal(a[key], b[key], err_msg=f"k={k} group {gi} {key}")
-        print(f"k={k} blocks/CU={bpc} graph={graph}: identical to separate launches")
+                np.testing.assert_array_equal(a[key], b[key], err_msg=f"mode={mode} k={k} group {gi} {key}")
+        print(f"mode={mode} k={k} waves/CU={wpc} workgroup={wg} graph={graph}: identical to separate launches")
 
 
 def test_mixed_per_group_variants_equal_separate_launches(ctx, batch):
@@ -86,7 +91,7 @@ def test_mixed_per_group_variants_equal_separate_launches(ctx, batch):
     ref = _host(sep)
     opt = pk.Options.from_dict(wl["options"])
     gs = _fresh(ctx, [dict(g) for g in groups])
-    ctx.ik_solve_mixed(gs, opt, iters_per_launch=10, blocks_per_cu=4, use_graph=True,
+    ctx.ik_solve_mixed(gs, opt, iters_per_launch=10, waves_per_cu=4, use_graph=True,
                        variants=[pk.VARIANT_WAVE] * len(groups))
     torch.cuda.synchronize()
     got = _host(gs)
@@ -96,7 +101,7 @@ def test_mixed_per_group_variants_equal_separate_launches(ctx, batch):
     # a lane mapping requested for the tree robot is refused
     with pytest.raises(pk.PkError):
         ctx.ik_solve_mixed(_fresh(ctx, [dict(g) for g in groups]), opt, iters_per_launch=10,
-                           blocks_per_cu=4, variants=[0, 0, pk.VARIANT_LANE])
+                           waves_per_cu=4, variants=[0, 0, pk.VARIANT_LANE])
 
 
 def test_autotune_and_oracle_sample(ctx, batch):
@@ -105,9 +110,13 @@ def test_autotune_and_oracle_sample(ctx, batch):
     wl, groups = batch
     opt = pk.Options.from_dict(wl["options"])
     gs = _fresh(ctx, [dict(g) for g in groups], best=True)
-    k, bpc, ms, variants = ctx.autotune_mixed(gs, opt)
-    print(f"autotuned: k={k}, blocks/CU={bpc}, variants={variants}, {ms:.3f} ms")
-    assert k in (5, 10, 25, 0) and bpc in (2, 4, 8) and ms > 0
+    tuned = ctx.autotune_mixed(gs, opt)
+    print(f"autotuned: {tuned}")
+    k, variants = tuned["k"], tuned["variants"]
+    assert k in (1, 2, 5, 10, 25, 0) and tuned["waves_per_cu"] in (2, 4, 8) and tuned["ms"] > 0
+    assert tuned["mode"] in (pk.SCHED_SINGLE, pk.SCHED_PER_GROUP)
+    assert tuned["workgroup_size"] in (64, 128, 256)
+    assert ctx.autotune_lookup(gs, opt) == tuned
     # the tree robot has only the wave mapping; the others may take either
     assert variants[2] == pk.VARIANT_WAVE and all(v in (pk.VARIANT_LANE, pk.VARIANT_WAVE) for v in variants)
     gs = _fresh(ctx, [dict(g) for g in groups], best=True)
@@ -153,7 +162,7 @@ def test_full_size_mixed84k_sampled(ctx):
                        "K": 1, "weights": pk.Weights.from_dict(g["weights"]), "wd": g["weights"]})
     opt = pk.Options.from_dict(wl["options"])
     gs = _fresh(ctx, groups)
-    ctx.ik_solve_mixed(gs, opt, iters_per_launch=25, blocks_per_cu=8, use_graph=True,
+    ctx.ik_solve_mixed(gs, opt, iters_per_launch=25, waves_per_cu=8, use_graph=True,
                        variants=[pk.VARIANT_LANE, pk.VARIANT_LANE, pk.VARIANT_WAVE])
     torch.cuda.synchronize()
     got = _host(gs)
@@ -178,3 +187,39 @@ def test_full_size_mixed84k_sampled(ctx):
     print(f"mixed84k sample: {bad} unexplained, {len(excused)} excused of {n}")
     assert not bad
     check_excused("mixed84k sample", excused, n)
+
+
+def test_autotune_table_json_round_trip(ctx, batch, tmp_path, monkeypatch):
+    """The tuned schedule is stored as JSON keyed by the batch's robot classes
+    (n, m, EE kind), options and architecture; a new context reads it from the
+    file named by PK_AUTOTUNE_TABLE (and through autotune_load) and finds the
+    same entry for the same robot classes (under its own robot ids)."""
+    import json
+
+    import paper_2505_03728_amd as pk
+    wl, groups = batch
+    opt = pk.Options.from_dict(wl["options"])
+    gs = _fresh(ctx, [dict(g) for g in groups])
+    tuned = ctx.autotune_lookup(gs, opt) or ctx.autotune_mixed(gs, opt)
+    path = tmp_path / "autotune.json"
+    ctx.autotune_save(str(path))
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "pkmi-autotune-1"
+    keys = [e["key"] for e in doc["entries"]]
+    print(keys)
+    assert any(k.startswith("n7_m1_pose+n16_m4_position+n34_m4_pose|") and "|gfx" in k for k in keys)
+    monkeypatch.setenv("PK_AUTOTUNE_TABLE", str(path))
+    c2 = pk.Context(0)
+    try:
+        g2 = []
+        for g in groups:
+            d = dict(g)
+            d["rid"] = c2.upload(g["tree"])
+            g2.append(d)
+        g2 = _fresh(c2, g2)
+        got = c2.autotune_lookup(g2, opt)
+        fields = ("mode", "k", "waves_per_cu", "workgroup_size", "variants")
+        assert got is not None and {k: got[k] for k in fields} == {k: tuned[k] for k in fields}
+        assert c2.autotune_load(str(path)) == len(keys)
+    finally:
+        c2.close()
