@@ -301,6 +301,12 @@ def headline(args, ctx):
     return res, tree, wl, T, K
 
 
+# Learned form's later passes: restart budget, and random seeds per target for
+# the fallback (also the plain form's seed count for its >= 99% comparison).
+RESTART_ITERS = 20
+FALLBACK_K = 128
+
+
 def learned_vs_random(args, ctx, epochs=None):
     """The learned-seed form against plain random-seed LM on the seeder
     workload: 131072 fresh targets of the 7-DoF arm, K = 8."""
@@ -332,7 +338,12 @@ def learned_vs_random(args, ctx, epochs=None):
           f"{log[-1].item():.4f}", file=sys.stderr, flush=True)
     T = wl["eval_q_star"].shape[0]
     targets = _dev_targets(ctx, rid, tree, wl["eval_q_star"])
-    rseeds = torch.from_numpy(np.ascontiguousarray(wl["plain_seeds"].T.astype(np.float32))).cuda()
+    # random in-limit seeds: the first 8 per target are the plain form's, all
+    # FALLBACK_K of them serve the learned form's fallback and the plain form at
+    # FALLBACK_K seeds
+    rseeds_all = torch.from_numpy(np.ascontiguousarray(
+        synth.uniform_configs(tree, T * FALLBACK_K, 17).T.astype(np.float32))).cuda()
+    rseeds = rseeds_all[:, :T * K].contiguous()
     w = pk.Weights.from_dict(wl["weights"])
     plain_o = pk.Options.from_dict(wl["options"], early_exit=True)          # <= 30 iterations
     ref_o = pk.Options.from_dict(wl["options"], max_iters=10, early_exit=True)
@@ -342,11 +353,15 @@ def learned_vs_random(args, ctx, epochs=None):
     plain10 = ctx.alloc_outputs(rid, T, K, best=True)
     ts_plain10 = _replay_times(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, ref_o, plain10),
                                args.steps, args.warmup)
+    plain_big = ctx.alloc_outputs(rid, T, FALLBACK_K, best=True)
+    ts_plain_big = _replay_times(lambda: ctx.ik_solve(rid, targets, rseeds_all, FALLBACK_K, w, plain_o,
+                                                      plain_big), max(5, args.steps // 4), 1)
     res_l = {}
 
     def learned():
         res_l["o"] = ctx.ik_solve_seeded(rid, targets, sd, w, ref_o, fallback=plain_o,
-                                         fallback_seeds=rseeds, fallback_K=K, counters=True)
+                                         fallback_seeds=rseeds_all, fallback_K=FALLBACK_K, counters=True,
+                                         restart_iters=RESTART_ITERS)
     ts_learn = _replay_times(learned, args.steps, args.warmup)
     seeds_buf = torch.empty((7, T * K), device="cuda")
     ts_infer = _replay_times(lambda: sd.infer(targets, seeds_buf), args.steps, args.warmup)
@@ -364,10 +379,18 @@ def learned_vs_random(args, ctx, epochs=None):
     fl_plain = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(plain["iters"].sum()),
                         int(plain["accepts"].sum()), T * K)
     n_fb = int(lo["n_fallback"].item())
+    n_rs = int(lo["n_restart"].item())
     fl_lm = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["refine_iters"].sum()),
                      int(lo["refine_accepts"].sum()), T * K)
+    fl_lm += lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["restart_iters"].sum()),
+                      int(lo["restart_accepts"].sum()), n_rs * K)
     fl_lm += lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(lo["fallback_iters"].sum()),
-                      int(lo["fallback_accepts"].sum()), n_fb * K)
+                      int(lo["fallback_accepts"].sum()), n_fb * FALLBACK_K)
+    ms_big = _stats(ts_plain_big)["median"]
+    s_big = int(plain_big["target_success"].sum())
+    fl_big = lm_flops(tree.parent, tree.ee_joint, tree.ee_kind, blocks, int(plain_big["iters"].sum()),
+                      int(plain_big["accepts"].sum()), T * FALLBACK_K)
+    itt_b_mean, itt_b_med = _itt_per_target(plain_big["iters_to_tol"].cpu().numpy(), T, FALLBACK_K)
     dims = [7] + [mc["hidden"]] * mc["depth"] + [7 * K]
     fl_mlp = 2.0 * T * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
     v_learn = s_learn / (ms_learn / 1e3)
@@ -380,15 +403,19 @@ def learned_vs_random(args, ctx, epochs=None):
         "learned": {"solves_per_s": round(v_learn, 1), "success_rate": s_learn / T,
                     "ms": round(ms_learn, 5),
                     "success_from_learned_seeds": float(np.mean(src == 0)),
-                    "fallback_targets": n_fb,
+                    "success_from_restart": float(np.mean(src == 2)),
+                    "success_from_fallback": float(np.mean(src == 1)),
+                    "restarted_targets": n_rs, "fallback_targets": n_fb,
                     "iters_to_tol_mean": float(itt_l[ok_l].mean()) if ok_l.any() else None,
                     "iters_to_tol_median": float(np.median(itt_l[ok_l])) if ok_l.any() else None,
                     "lm_tflops": round(tfl(fl_lm, ms_learn), 4),
                     "frac_fp32": round(tfl(fl_lm, ms_learn) / FP32_VALU_PEAK, 6),
                     "inference_ms": round(ms_infer, 5),
                     "inference_frac_bf16": round(tfl(fl_mlp, ms_infer) / BF16_MFMA_PEAK, 5),
-                    "schedule": f"seeder -> <= 10 LM iterations (early exit) -> {K} random seeds "
-                                f"x <= 30 iterations on the unsolved targets"},
+                    "schedule": f"seeder ({K} seeds) -> <= 10 LM iterations (early exit) -> unsolved "
+                                f"targets: LM restarted from the refined joints, <= {RESTART_ITERS} "
+                                f"iterations -> still unsolved: {FALLBACK_K} random seeds x <= 30 "
+                                f"iterations"},
         "plain_random": {"solves_per_s": round(v_plain, 1), "success_rate": s_plain / T,
                          "ms": round(ms_plain, 5),
                          "iters_to_tol_mean": itt_p_mean, "iters_to_tol_median": itt_p_med,
@@ -396,7 +423,13 @@ def learned_vs_random(args, ctx, epochs=None):
                          "frac_fp32": round(tfl(fl_plain, ms_plain) / FP32_VALU_PEAK, 6),
                          "success_rate_10_iters": s_plain10 / T,
                          "solves_per_s_10_iters": round(s_plain10 / (ms_plain10 / 1e3), 1)},
+        "plain_random_many_seeds": {"seeds_per_target": FALLBACK_K,
+                                    "solves_per_s": round(s_big / (ms_big / 1e3), 1),
+                                    "success_rate": s_big / T, "ms": round(ms_big, 5),
+                                    "iters_to_tol_mean": itt_b_mean, "iters_to_tol_median": itt_b_med,
+                                    "frac_fp32": round(tfl(fl_big, ms_big) / FP32_VALU_PEAK, 6)},
         "speedup_learned_vs_plain": round(v_learn / v_plain, 3),
+        "speedup_learned_vs_plain_many_seeds": round(v_learn / (s_big / (ms_big / 1e3)), 3),
         "seeder_training": {"samples": S, "epochs": E, "batch": mc["batch"], "steps": steps_tr,
                             "seconds": round(train_s, 3), "loss_first": float(log[0]),
                             "loss_last": float(log[-1])},

@@ -350,10 +350,16 @@ int pk_seeder_infer(pk_ctx *ctx, int32_t seeder_id, const float *targets, int64_
 /* Learned seeds + LM refinement, with random-seed LM as the fallback:
  *   1. the seeder gives K seeds per target (pk_seeder_infer);
  *   2. LM with `refine` on the T*K problems, best-of-K per target;
- *   3. targets that no learned seed solved are listed on the device and
- *      solved again from fallback_seeds [n][T*fallback_K] with `fallback`;
- *   4. per target the result of the pass that solved it.
- * Asynchronous on `stream`; no host synchronisation inside. */
+ *   3. (restart_iters > 0) the K problems of each target that step 2 did not
+ *      solve are listed on the device and LM is started again from their
+ *      final joints (lambda back at lambda0, early exit as `refine`) for
+ *      restart_iters iterations, best-of-K again;
+ *   4. targets still unsolved are listed on the device and solved again from
+ *      fallback_seeds [n][T*fallback_K] with `fallback`;
+ *   5. per target the result of the pass that solved it.
+ * Steps 3 and 4 run persistent launches over their lists (wavefronts pop
+ * items from a device queue), so their cost follows the listed problems, not
+ * T.  Asynchronous on `stream`; no host synchronisation inside. */
 typedef struct {
     int32_t seeder_id;
     int32_t fallback_K;              /* 0 = no fallback                          */
@@ -365,19 +371,27 @@ typedef struct {
                                         problems compacted in between (persistent
                                         kernel, hipGraph), as pk_ik_solve_mixed   */
     int32_t refine_blocks_per_cu;    /* persistent grid for k > 0: wavefronts per CU (0 = 4) */
+    int32_t restart_iters;           /* step 3's iteration budget; 0 = no step 3    */
+    int32_t persist_waves_per_cu;    /* grid of steps 3 and 4: wavefronts per CU (0 = 8) */
 } pk_seeded_options;
 
 typedef struct {
     float *best_joints;              /* [n][T] required                          */
     int32_t *target_success;         /* [T]                                      */
-    int32_t *source;                 /* [T] 0 learned seeds, 1 fallback, -1 none  */
+    int32_t *source;                 /* [T] 0 learned seeds, 2 learned seeds after the
+                                        restart, 1 fallback, -1 none               */
     int32_t *iters_to_tol;           /* [T] fewest LM iterations to tolerance over
-                                        the succeeding pass's seeds, -1 if none   */
+                                        the succeeding pass's seeds (after a restart:
+                                        refine.max_iters + the restart's), -1 if none */
     int32_t *refine_iters;           /* [T*K] optional counters of pass 2         */
     int32_t *refine_accepts;         /* [T*K]                                    */
     int32_t *fallback_iters;         /* [T*fallback_K] optional, 0 if not re-solved */
     int32_t *fallback_accepts;       /* [T*fallback_K]                           */
     int32_t *n_fallback;             /* device scalar: targets re-solved          */
+    int32_t *restart_iters;          /* [T*K] optional counters of step 3, 0 if not
+                                        restarted                                 */
+    int32_t *restart_accepts;        /* [T*K]                                    */
+    int32_t *n_restart;              /* device scalar: targets restarted          */
 } pk_seeded_outputs;
 
 int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t n_targets, const float *targets,

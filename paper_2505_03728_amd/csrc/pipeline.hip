@@ -1,8 +1,12 @@
-// Learned seeds + LM refinement with a random-seed LM fallback on the
-// targets the learned seeds did not solve.  Everything stays on the device:
-// the failed targets are compacted into an active list that the fallback LM
-// launch (sized for the worst case) reads, so the host never synchronises.
+// Learned seeds + LM refinement, a restart of the unsolved targets' problems
+// from their refined joints, and a random-seed LM fallback on the targets
+// still unsolved.  Everything stays on the device: each later pass's
+// problems are compacted into an active list that a persistent LM launch
+// (wavefronts popping items from a device queue) reads, so the host never
+// synchronises and a pass costs what its listed problems cost.
 #include <string.h>
+
+#include <algorithm>
 
 #include "pk_ctx.hpp"
 #include "pk_device.hpp"
@@ -16,8 +20,8 @@ __global__ void fill_i32_kernel(int64_t count, int32_t v, int32_t *p)
     if (i < count) p[i] = v;
 }
 
-// Targets with no successful learned seed -> active problem list of the
-// fallback (fallback_K problems per target).
+// Targets not solved (success[t] == 0) -> active problem list of a later
+// pass (Kf problems per target, problem t * Kf + k).
 __global__ void fallback_list_kernel(int64_t T, int Kf, const int32_t *__restrict__ success,
                                      int32_t *count_t, int32_t *count_p, int32_t *active)
 {
@@ -30,8 +34,8 @@ __global__ void fallback_list_kernel(int64_t T, int Kf, const int32_t *__restric
 
 struct MergeArgs {
     int64_t T;
-    int K, Kf, n;
-    const int32_t *best_a, *succ_a, *itt_a;
+    int K, Kf, n, refine_its;
+    const int32_t *best_a, *succ_a, *succ_r, *itt_a;
     const float *joints_a;
     const int32_t *status_b, *itt_b;
     const float *cost_b, *pcost_b, *joints_b;
@@ -45,14 +49,18 @@ __global__ void merge_kernel(MergeArgs a)
     if (t >= a.T) return;
     const int64_t NA = a.T * a.K, NB = a.T * a.Kf;
     int src = -1, it = -1;
-    if (a.succ_a[t]) {
-        src = 0;
+    // pass A (learned seeds), or its restart: best_a / itt_a then hold the
+    // restart's values for the targets that were restarted
+    const bool restarted = a.succ_r && !a.succ_a[t];
+    if (a.succ_a[t] || (restarted && a.succ_r[t])) {
+        src = restarted ? 2 : 0;
         const int b = a.best_a[t];
         for (int j = 0; j < a.n; ++j) a.best_joints[(int64_t)j * a.T + t] = a.joints_a[(int64_t)j * NA + t * a.K + b];
         for (int k = 0; k < a.K; ++k) {
             const int v = a.itt_a[t * a.K + k];
             if (v >= 0 && (it < 0 || v < it)) it = v;
         }
+        if (restarted) it += a.refine_its;
     } else if (a.Kf > 0) {
         bool any;
         const int b = best_of_k_pick(a.status_b, a.cost_b, a.pcost_b, t * a.Kf, a.Kf, any);
@@ -113,8 +121,15 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
     const int64_t NA = T * K, NB = T * Kf;
     if (NA >= (int64_t)1 << 31 || NB >= (int64_t)1 << 31)
         return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve_seeded: too many problems");
+    const int R = o->restart_iters;
+    if (R < 0) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: restart_iters < 0");
+    const int wpc = o->persist_waves_per_cu > 0 ? o->persist_waves_per_cu : 8;
+    hipDeviceProp_t prop;
+    PK_HIP(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    const int persist = wpc * prop.multiProcessorCount;
+    const int64_t NS = std::max(NA, NB);   // resumable-state words of the persistent passes
     // Workspace layout (4-byte words).
-    const size_t words = (size_t)NA * (2 * n + 5) + 2 * T + 8 + (size_t)NB * (n + 6);
+    const size_t words = (size_t)NA * (2 * n + 6) + 3 * T + 16 + (size_t)NB * (n + 6) + 2 * (size_t)NS;
     if (words * 4 > ctx->ws2_bytes) {
         if (ctx->ws2) (void)hipFree(ctx->ws2);
         ctx->ws2 = nullptr;
@@ -133,7 +148,11 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
     int32_t *spare_a = (int32_t *)f;    f += NA;
     int32_t *best_a = (int32_t *)f;     f += T;
     int32_t *succ_a = (int32_t *)f;     f += T;
-    int32_t *counters = (int32_t *)f;   f += 8;
+    int32_t *succ_r = (int32_t *)f;     f += T;
+    int32_t *list_r = (int32_t *)f;     f += NA;
+    int32_t *counters = (int32_t *)f;   f += 16;   // [0..1] fallback list, [2..3] restart list, [4] queue head
+    float *st_lambda = f;               f += NS;
+    int32_t *st_state = (int32_t *)f;   f += NS;
     float *joints_b = f;                f += (size_t)NB * n;
     float *cost_b = f;                  f += NB;
     float *pcost_b = f;                 f += NB;
@@ -179,26 +198,53 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
         PK_HIP(ctx, launch_lm(*rb, PA, va, s));
         PK_HIP(ctx, launch_best_of_k(PA, n, best_a, nullptr, succ_a, s));
     }
-    // Pass B: random seeds on the failed targets only.
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, (int64_t)8, 0, counters);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, (int64_t)16, 0, counters);
+    // Pass A': the K problems of each unsolved target again from their
+    // refined joints (lambda back at lambda0), in place, then best-of-K again.
+    const int32_t *succ_now = succ_a;
+    if (R > 0) {
+        if (out->restart_iters)
+            hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(NA, 256)), dim3(256), 0, s, NA, 0, out->restart_iters);
+        if (out->restart_accepts)
+            hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(NA, 256)), dim3(256), 0, s, NA, 0, out->restart_accepts);
+        hipLaunchKernelGGL(fallback_list_kernel, dim3(nblk(T, 256)), dim3(256), 0, s, T, K, succ_a,
+                           counters + 2, counters + 3, list_r);
+        SolveParams PR = PA;
+        PR.max_iters = R;
+        PR.seeds = joints_a;            // each problem reads its joints before writing them
+        PR.iters = out->restart_iters; PR.accepts = out->restart_accepts;
+        PR.active = list_r; PR.n_active = counters + 3;
+        PR.st_lambda = st_lambda; PR.st_state = st_state;
+        PR.resume = 0; PR.iter_budget = R;
+        PR.queue_head = counters + 4;
+        PK_HIP(ctx, launch_lm(*rb, PR, va, s, persist));
+        PK_HIP(ctx, launch_best_of_k(PA, n, best_a, nullptr, succ_r, s));
+        succ_now = succ_r;
+    }
+    // Pass B: random seeds on the targets still unsolved.
     if (Kf > 0) {
         if (out->fallback_iters)
             hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(NB, 256)), dim3(256), 0, s, NB, 0, out->fallback_iters);
         if (out->fallback_accepts)
             hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(NB, 256)), dim3(256), 0, s, NB, 0, out->fallback_accepts);
-        hipLaunchKernelGGL(fallback_list_kernel, dim3(nblk(T, 256)), dim3(256), 0, s, T, Kf, succ_a,
+        hipLaunchKernelGGL(fallback_list_kernel, dim3(nblk(T, 256)), dim3(256), 0, s, T, Kf, succ_now,
                            counters, counters + 1, active);
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, (int64_t)1, 0, counters + 4);
         PK_HIP(ctx, hipGetLastError());
         PB.K = Kf; PB.N = NB; PB.T = T;
         PB.targets = targets; PB.seeds = o->fallback_seeds;
         PB.joints = joints_b; PB.cost = cost_b; PB.pose_cost = pcost_b; PB.status = status_b;
         PB.iters = out->fallback_iters; PB.accepts = out->fallback_accepts; PB.iters_to_tol = itt_b;
         PB.active = active; PB.n_active = counters + 1;
-        PK_HIP(ctx, launch_lm(*rb, PB, vb, s));
+        PB.st_lambda = st_lambda; PB.st_state = st_state;
+        PB.resume = 0; PB.iter_budget = PB.max_iters;
+        PB.queue_head = counters + 4;
+        PK_HIP(ctx, launch_lm(*rb, PB, vb, s, persist));
     }
     MergeArgs m;
-    m.T = T; m.K = K; m.Kf = Kf; m.n = n;
-    m.best_a = best_a; m.succ_a = succ_a; m.itt_a = itt_a; m.joints_a = joints_a;
+    m.T = T; m.K = K; m.Kf = Kf; m.n = n; m.refine_its = o->refine.max_iters;
+    m.best_a = best_a; m.succ_a = succ_a; m.succ_r = R > 0 ? succ_r : nullptr; m.itt_a = itt_a;
+    m.joints_a = joints_a;
     m.status_b = status_b; m.itt_b = itt_b; m.cost_b = cost_b; m.pcost_b = pcost_b; m.joints_b = joints_b;
     m.best_joints = out->best_joints; m.success = out->target_success; m.source = out->source;
     m.itt = out->iters_to_tol;
@@ -206,5 +252,7 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
     PK_HIP(ctx, hipGetLastError());
     if (out->n_fallback)
         PK_HIP(ctx, hipMemcpyAsync(out->n_fallback, counters, 4, hipMemcpyDeviceToDevice, s));
+    if (out->n_restart)
+        PK_HIP(ctx, hipMemcpyAsync(out->n_restart, counters + 2, 4, hipMemcpyDeviceToDevice, s));
     return PK_OK;
 }
