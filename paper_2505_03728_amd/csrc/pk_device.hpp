@@ -234,37 +234,49 @@ PK_DEV void jr_inv_blocks(const PoseLog &L, const float *Re, float *M, float *N)
         a2 = (t2 - 4.f * L.sh * L.sh) * (0.5f * it2 * it2);   // 2 cos - 2 = -4 sin^2(th/2)
         a3 = (2.f * th - 3.f * st + th * ct) * (0.5f * it3 * it2);
     }
-    float Ph[9], Rh[9], PP[9];
-    hat(L.phi, Ph);
-    hat(L.rho, Rh);
-    mm3(Ph, Ph, PP);
-    float P[9];
+    // With f = phi, r = rho, d = f.r, c = f x r, t2 = |f|^2 and the identity
+    // hat(a) hat(b) = b a^T - (a.b) I, the products of hats in P and Q reduce
+    // to outer products:
+    //   Ph Ph = f f^T - t2 I,
+    //   Ph Rh + Rh Ph - Ph Rh Ph = r f^T + f r^T - 2 d I + d Ph,
+    //   3 Ph Rh Ph - Ph Ph Rh - Rh Ph Ph = f c^T - c f^T - d Ph,
+    //   Ph Rh Ph Ph + Ph Ph Rh Ph = -2 d (f f^T - t2 I),
+    // so P = I + Ph/2 + k (f f^T - t2 I) and
+    //   Q(-rho,-phi) = hat((a1 - a2) d f - r/2) + a1 (r f^T + f r^T)
+    //                + a2 (f c^T - c f^T) - 2 a3 d f f^T + 2 d (a3 t2 - a1) I.
+    const float *f = L.phi, *r = L.rho;
+    const float d = f[0] * r[0] + f[1] * r[1] + f[2] * r[2];
+    const float ff2 = f[0] * f[0] + f[1] * f[1] + f[2] * f[2];   // t2 of the identities
+    float c[3];
+    cross(f, r, c);
+    float P[9], Q[9];
+    const float pd = 1.f - k * ff2;                       // diagonal of P
+    const float qd = 2.f * d * (a3 * ff2 - a1);           // diagonal of Q
+    const float qf = -2.f * a3 * d;                       // f f^T coefficient of Q
+    float sk[3];                                          // skew part of Q
 #pragma unroll
-    for (int i = 0; i < 9; ++i) P[i] = 0.5f * Ph[i] + k * PP[i];
-    P[0] += 1.f; P[4] += 1.f; P[8] += 1.f;
-    // Q(-rho,-phi) = -Rh/2 + a1 (Ph Rh + Rh Ph - Ph Rh Ph)
-    //               + a2 (-Ph Ph Rh - Rh Ph Ph + 3 Ph Rh Ph) + a3 (Ph Rh Ph Ph + Ph Ph Rh Ph)
-    float X[9], Y[9], Z[9], PPR[9], RPP[9], ZP[9], PZ[9];
-    mm3(Ph, Rh, X);
-    mm3(Rh, Ph, Y);
-    mm3(X, Ph, Z);
-    mm3(Ph, X, PPR);
-    mm3(Y, Ph, RPP);
-    mm3(Z, Ph, ZP);
-    mm3(Ph, Z, PZ);
-    float Q[9];
+    for (int i = 0; i < 3; ++i) sk[i] = (a1 - a2) * d * f[i] - 0.5f * r[i];
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-        Q[i] = -0.5f * Rh[i] + a1 * (X[i] + Y[i] - Z[i]) + a2 * (3.f * Z[i] - PPR[i] - RPP[i]) +
-               a3 * (ZP[i] + PZ[i]);
-    float T1[9], B[9];
-    mm3(P, Q, T1);
-    mm3(T1, P, B);
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float ff = f[i] * f[j];
+            P[3 * i + j] = k * ff + (i == j ? pd : 0.f);
+            Q[3 * i + j] = a1 * (r[i] * f[j] + f[i] * r[j]) + a2 * (f[i] * c[j] - c[i] * f[j]) + qf * ff +
+                           (i == j ? qd : 0.f);
+        }
+    // + hat(f)/2 on P, + hat(sk) on Q
+    P[1] -= 0.5f * f[2]; P[2] += 0.5f * f[1]; P[5] -= 0.5f * f[0];
+    P[3] += 0.5f * f[2]; P[6] -= 0.5f * f[1]; P[7] += 0.5f * f[0];
+    Q[1] -= sk[2]; Q[2] += sk[1]; Q[5] -= sk[0];
+    Q[3] += sk[2]; Q[6] -= sk[1]; Q[7] += sk[0];
+    // M = P Re^T;  N = B Re^T = -P Q P Re^T = -P (Q M)
     mmT3(P, Re, M);
-    float NB[9];
-    mmT3(B, Re, NB);
+    float QM[9], PQM[9];
+    mm3(Q, M, QM);
+    mm3(P, QM, PQM);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) N[i] = -NB[i];
+    for (int i = 0; i < 9; ++i) N[i] = -PQM[i];
 }
 
 // Best of K problems base .. base+K-1: the lowest total cost among those
