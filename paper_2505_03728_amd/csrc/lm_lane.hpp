@@ -52,12 +52,12 @@ struct Slots {
     static constexpr int RES = COL + C * L * ROWS;
     static constexpr int DG = RES + C * ROWS;
     static constexpr int GX = DG + C * L;
-    static constexpr int TOTAL = GX + C * L;
-    // Single chains keep the FP32 normal equations of the current point
-    // instead: packed J^T J (+ diagonal terms) then J^T r, over the columns'
-    // slots, formed once per taken point and reused by rejected steps.
+    // Single chains keep only the FP32 normal equations of the current point:
+    // packed J^T J (+ diagonal terms) then J^T r after the targets, formed
+    // once per taken point and reused by rejected steps (their rare FP64
+    // re-solve rebuilds the Jacobian in registers, so no column slots).
     static constexpr int AG = COL;
-    static_assert(C > 1 || Star<C, L, KIND>::NA + L <= TOTAL - COL, "normal equations fit");
+    static constexpr int TOTAL = C == 1 ? AG + Star<C, L, KIND>::NA + L : GX + C * L;
 };
 
 // FK along chain c at q; optionally keeps each joint's world axis and origin.
@@ -226,32 +226,6 @@ PK_DEV void joint_terms(const RobotC *__restrict__ rb, const SolveParams &P, con
     gx = dl * rl + P.w_rest * rr;
 }
 
-// Single chain: Jacobian columns, EE residual rows and the limit/rest
-// diagonal terms at q into LDS, from the chain's kept FK (joint axes and
-// origins), the EE frame and its pose log.
-template <int L, int KIND>
-PK_DEV void jacobian1(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
-                      const LaneLds &S, const float *q, const float (*om)[3], const float (*pj)[3],
-                      const float *Re, const float *pe, const float *r, const PoseLog &lg)
-{
-    using SL = Slots<1, L, KIND>;
-    constexpr int ROWS = SL::ROWS;
-    float M[9], Nb[9];
-    if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
-#pragma unroll
-    for (int u = 0; u < ROWS; ++u) S[SL::RES + u] = r[u];
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-        float col[ROWS], dg, gx;
-        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, col);
-#pragma unroll
-        for (int u = 0; u < ROWS; ++u) S[SL::COL + i * ROWS + u] = col[u];
-        joint_terms(rb, P, qr, q, i, dg, gx);
-        S[SL::DG + i] = dg;
-        S[SL::GX + i] = gx;
-    }
-}
-
 // Single chain: FP32 J^T J (+ diagonal terms) and J^T r at q straight from
 // the columns as they are formed (the sums of form_normal, in its order;
 // the columns never go through LDS), into the cached normal equations (AG).
@@ -287,21 +261,6 @@ PK_DEV void normal1(const RobotC *__restrict__ rb, const SolveParams &P, const f
 
 template <int C, int L, int KIND, typename T>
 PK_DEV void form_normal(const LaneLds &S, int c, T *A, T *g);
-
-// Single chain: FP32 J^T J and J^T r from the columns in LDS, written over
-// them (AG) for the steps that follow.
-template <int L, int KIND>
-PK_DEV void cache_normal1(const LaneLds &S)
-{
-    using SL = Slots<1, L, KIND>;
-    constexpr int NA = Star<1, L, KIND>::NA;
-    float A[NA], g[L];
-    form_normal<1, L, KIND, float>(S, 0, A, g);
-#pragma unroll
-    for (int i = 0; i < NA; ++i) S[SL::AG + i] = A[i];
-#pragma unroll
-    for (int i = 0; i < L; ++i) S[SL::AG + NA + i] = g[i];
-}
 
 // Single-chain robots: cost and errors at q and, when the point is taken
 // (the start point, or a trial with cost below `cur`), its Jacobian and
@@ -363,35 +322,6 @@ PK_DEV void form_normal(const LaneLds &S, int c, T *A, T *g)
 #pragma unroll
         for (int u = 0; u < ROWS; ++u) s += (T)col[i][u] * (T)r[u];
         g[i] = s;
-    }
-}
-
-// The same block in FP64 with one column held at a time: the other column of
-// each product is read from LDS again (the compiler may not keep it across
-// rows), which keeps the register use of this rarely taken path low.
-template <int C, int L, int KIND>
-PK_DEV void form_normal64(const LaneLds &S, int c, double *A, double *g)
-{
-    using SL = Slots<C, L, KIND>;
-    constexpr int ROWS = SL::ROWS;
-#pragma unroll
-    for (int i = 0; i < L; ++i) {
-        double ci[ROWS];
-#pragma unroll
-        for (int u = 0; u < ROWS; ++u) ci[u] = (double)S[SL::COL + (c * L + i) * ROWS + u];
-#pragma unroll
-        for (int k = 0; k <= i; ++k) {
-            double s = 0;
-#pragma unroll
-            for (int u = 0; u < ROWS; ++u) s += ci[u] * (double)S[SL::COL + (c * L + k) * ROWS + u];
-            if (k == i) s += (double)S[SL::DG + c * L + i];
-            A[tri(i, k)] = s;
-        }
-        double s = (double)S[SL::GX + c * L + i];
-#pragma unroll
-        for (int u = 0; u < ROWS; ++u) s += ci[u] * (double)S[SL::RES + c * ROWS + u];
-        g[i] = s;
-        __asm__ volatile("" ::: "memory");
     }
 }
 
@@ -471,28 +401,47 @@ PK_DEV bool step_fp64(const SolveParams &P, const LaneLds &S, float lam, float *
     return ok;
 }
 
-// Single chain, FP64 re-solve: the columns at q are formed again (the same
-// FP32 values the cached normal equations came from), J^T J and J^T r in
-// FP64, then the FP32 cache is restored.
+// Single chain, FP64 re-solve: the Jacobian at q is formed again in
+// registers (the same FP32 columns the cached normal equations came from),
+// J^T J and J^T r accumulated in FP64 with each product's columns recomputed
+// (a rare path: register use, not work, is what it must keep low), damped
+// and factored in FP64.  The FP32 cache in LDS is left as it was.
 template <int L, int KIND>
 PK_DEV bool step_fp64_1(const RobotC *__restrict__ rb, const SolveParams &P, const float *__restrict__ qr,
                         const LaneLds &S, const float *q, float lam, float *delta)
 {
     using SL = Slots<1, L, KIND>;
     constexpr int ROWS = SL::ROWS;
-    float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS], pe_err, re_err;
+    float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS], pe_err, re_err, M[9], Nb[9];
     PoseLog lg;
     chain_fk<1, L, true>(rb, 0, q, om, pj, Re, pe);
     ee_residual<KIND>(P, S, SL::TG, Re, pe, r, pe_err, re_err, &lg);
-    jacobian1<L, KIND>(rb, P, qr, S, q, om, pj, Re, pe, r, lg);
-    __asm__ volatile("" ::: "memory");   // the FK values die before the FP64 system is formed
+    if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
     double A[Star<1, L, KIND>::NA], g[L], x[L];
-    form_normal64<1, L, KIND>(S, 0, A, g);
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        float ci[ROWS], dg, gx;
+        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, ci);
+        joint_terms(rb, P, qr, q, i, dg, gx);
+#pragma unroll
+        for (int k = 0; k <= i; ++k) {
+            float ck[ROWS];
+            jac_column<KIND>(P, M, Nb, om[k], pj[k], pe, ck);
+            double a = 0;
+#pragma unroll
+            for (int u = 0; u < ROWS; ++u) a += (double)ci[u] * (double)ck[u];
+            if (k == i) a += (double)dg;
+            A[tri(i, k)] = a;
+        }
+        double b = (double)gx;
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) b += (double)ci[u] * (double)r[u];
+        g[i] = b;
+    }
     const bool ok = chol_damped<L, double>(A, (double)lam, (double)P.damping_floor, 0.0, A);
     chol_solve_neg<L, double>(A, g, x);
 #pragma unroll
     for (int i = 0; i < L; ++i) delta[i] = (float)x[i];
-    cache_normal1<L, KIND>(S);
     return ok;
 }
 
