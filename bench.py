@@ -749,9 +749,9 @@ def run_beam(args):
 
 def run_mobile(args):
     """IK with a mobile base (Sec. V-B): 4096 translated targets x 4 seeds on the
-    arm with its SE(2) base pose as variables (prismatic x, y + revolute yaw, on
-    the per-wavefront kernel); the same targets with the base fixed at the
-    origin (arm alone) are solved once for the success comparison."""
+    arm with its SE(2) base pose as variables (prismatic x, y + revolute yaw: a
+    10-joint chain on the per-lane kernel); the same targets with the base
+    fixed at the origin (arm alone) are solved once for the success comparison."""
     import numpy as np
     import torch
 
@@ -798,8 +798,9 @@ def run_mobile(args):
                 fp64_fallback_fraction=float(((st & 0x100) != 0).mean()),
                 roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
                           "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
-                          "kernel": "lm_wave_kernel<16,4>", "kernel_ms": round(ms, 5),
-                          "algorithmic_flops": flops})
+                          "kernel": (f"lm_lane_kernel<1,{ctx.robot_info(rid)['chain_len']},pose+prismatic>"
+                                     if ctx.robot_info(rid)["chains"] == 1 else "lm_wave_kernel<16,4>"),
+                          "kernel_ms": round(ms, 5), "algorithmic_flops": flops})
     if not args.no_cpu:
         rate, th, done, el = _oracle_rate([{"tree": mob, "q_star": g["q_star"], "seeds": g["seeds"],
                                             "K": K}], wl["weights"], wl["options"], args.cpu_seconds)

@@ -186,9 +186,11 @@ const char *pk_last_error(pk_ctx *ctx);
 
 /* Copies the tree to the device (FP32) and returns its id.  Validates shape,
  * parent order, unit axes (within 1e-3; renormalised), limits, joint kinds
- * and EE references; folds fixed joints.  Robots with prismatic or mimic
- * joints run on the per-wavefront kernel (PK_VARIANT_LANE is unsupported for
- * them).
+ * and EE references; folds fixed joints.  The per-lane kernel
+ * (PK_VARIANT_LANE) serves single chains of 2 to 10 joints (revolute or
+ * prismatic) ending in one EE and the star of 4 chains x 4 revolute joints
+ * with 4 position EEs; other robots, and robots with mimic joints, run on
+ * the per-wavefront kernel (PK_VARIANT_LANE is unsupported for them).
  * Synchronous. */
 int pk_robot_upload(pk_ctx *ctx, const pk_tree *tree, int32_t *robot_id);
 /* n variables (joints neither fixed nor mimic), m EEs, target floats per target (sum of EE widths), residual rows

@@ -1,92 +1,29 @@
-// Launches of the per-lane LM kernel (device code in lm_lane.hpp): one
-// 64-problem block per launch item, or persistent blocks popping items from
-// a device queue.
-#include "lm_lane.hpp"
+// Per-lane LM path: the 7-joint arm and the 4 x 4 hand star instantiated
+// here, other single chains (2 to 10 joints, pose or position EE, revolute
+// or prismatic joints) in lm_lane_chain*.hip; dispatch by robot shape.
+#include "lm_lane_kernels.hpp"
 
 namespace pk {
-namespace lane {
-
-// Next work item of this block: the block index for a plain grid, else an
-// atomic pop from the device queue (block = one wavefront).
-PK_DEV int64_t pop_item(int32_t *head)
-{
-    int v = 0;
-    if (threadIdx.x == 0) v = atomicAdd(head, 1);
-    return (int64_t)__shfl(v, 0, 64);
-}
-
-// One 64-problem item per block; no state kept between launches.
-template <int C, int L, int KIND>
-__global__ __launch_bounds__(BLOCK) void lm_lane_kernel(const RobotC *__restrict__ rb,
-                                                        const float *__restrict__ qr, SolveParams P)
-{
-    using SL = Slots<C, L, KIND>;
-    __shared__ float smem[SL::TOTAL * BLOCK];
-    const LaneLds S{smem + threadIdx.x};
-    const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
-    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i < nact) lane_problem<C, L, KIND, false>(rb, qr, P, S, i);
-}
-
-// Persistent variant: blocks pop 64-problem items from P.queue_head until
-// the active list is exhausted; problem state is resumable.
-template <int C, int L, int KIND>
-PK_DEV void persist_loop(const RobotC *__restrict__ rb, const float *__restrict__ qr,
-                         const SolveParams &P, float *smem)
-{
-    const LaneLds S{smem + threadIdx.x};
-    const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
-    const int64_t nitems = (nact + BLOCK - 1) / BLOCK;
-    int64_t item = pop_item(P.queue_head);
-    while (item < nitems) {
-        const int64_t i = item * BLOCK + threadIdx.x;
-        if (i < nact) lane_problem<C, L, KIND, true>(rb, qr, P, S, i);
-        item = pop_item(P.queue_head);
-    }
-}
-
-template <int C, int L, int KIND>
-__global__ __launch_bounds__(BLOCK) void lm_lane_persist_kernel(const RobotC *__restrict__ rb,
-                                                                const float *__restrict__ qr,
-                                                                SolveParams P)
-{
-    __shared__ float smem[Slots<C, L, KIND>::TOTAL * BLOCK];
-    persist_loop<C, L, KIND>(rb, qr, P, smem);
-}
-
-template <int C, int L, int KIND>
-hipError_t launch_star(const RobotC *rb, const SolveParams &P, int persist_blocks, hipStream_t s)
-{
-    const int block = BLOCK;
-    int64_t grid = (P.N + block - 1) / block;
-    const bool persist = P.queue_head != nullptr;
-    if (persist && persist_blocks > 0 && persist_blocks < grid) grid = persist_blocks;
-    // rest pose: caller's array, else the robot's mid-range table
-    const float *qr = P.q_rest ? P.q_rest : rb->mid;
-    if (persist)
-        hipLaunchKernelGGL((lm_lane_persist_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb,
-                           qr, P);
-    else
-        hipLaunchKernelGGL((lm_lane_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb, qr, P);
-    return hipGetLastError();
-}
-
-}  // namespace lane
 
 bool lane_variant_available(int chains, int chain_len, int kind)
 {
-    return (chains == 1 && chain_len == 7 && kind == PK_EE_POSE) ||
+    return (chains == 1 && chain_len >= 2 && chain_len <= PK_LANE_MAX_CHAIN) ||
            (chains == 4 && chain_len == 4 && kind == PK_EE_POSITION);
 }
 
 hipError_t launch_lm_lane(const RobotC *dev_robot, const RobotC &h, const SolveParams &P,
                           hipStream_t s, int persist_blocks)
 {
-    const int kind = h.e[0].kind;
-    if (h.chains == 1 && h.chain_len == 7 && kind == PK_EE_POSE)
+    const int kind = h.e[0].kind | (h.prismatic ? lane::LANE_PRISMATIC : 0), L = h.chain_len;
+    if (h.chains == 1 && L == 7 && kind == PK_EE_POSE)
         return lane::launch_star<1, 7, PK_EE_POSE>(dev_robot, P, persist_blocks, s);
-    if (h.chains == 4 && h.chain_len == 4 && kind == PK_EE_POSITION)
+    if (h.chains == 4 && L == 4 && kind == PK_EE_POSITION)
         return lane::launch_star<4, 4, PK_EE_POSITION>(dev_robot, P, persist_blocks, s);
+    if (h.chains == 1) {
+        if (L <= 4) return launch_lane_chain_a(L, kind, dev_robot, P, persist_blocks, s);
+        if (L <= 7) return launch_lane_chain_b(L, kind, dev_robot, P, persist_blocks, s);
+        return launch_lane_chain_c(L, kind, dev_robot, P, persist_blocks, s);
+    }
     return hipErrorInvalidValue;
 }
 

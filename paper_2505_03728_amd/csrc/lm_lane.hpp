@@ -1,8 +1,9 @@
 // Per-lane Levenberg-Marquardt IK kernel: one problem per lane, the whole LM
 // state (q, lambda, J^T J, J^T r, the Cholesky factor) in registers.
 //
-// Robot shape: a "star" of C serial chains of L revolute joints hanging off
-// the base, one EE at each chain tip (a serial arm is C = 1).  Because a
+// Robot shape: a "star" of C serial chains of L joints (revolute, or
+// prismatic on a single chain) hanging off the base, one EE at each chain tip
+// (a serial arm is C = 1).  Because a
 // chain's joints only move its own EE, J^T J is block diagonal with C dense
 // L x L blocks; each block is factored on its own.  Robot constants are
 // uniform across the launch and are read with scalar loads.
@@ -19,12 +20,19 @@
 namespace pk {
 namespace lane {
 
+// The kernels' KIND template argument: the EE kind (PK_EE_POSE or
+// PK_EE_POSITION) plus LANE_PRISMATIC when the robot has prismatic joints
+// (robots without them compile the revolute-only code).
+constexpr int LANE_PRISMATIC = 4;
+constexpr int ee_of(int kind) { return kind & 3; }
+constexpr bool pris_of(int kind) { return (kind & LANE_PRISMATIC) != 0; }
+
 
 template <int C, int L, int KIND>
 struct Star {
     static constexpr int N = C * L;
     static constexpr int NA = L * (L + 1) / 2;   // packed lower triangle of one block
-    static constexpr int ROWS = KIND == PK_EE_POSE ? 6 : 3;
+    static constexpr int ROWS = ee_of(KIND) == PK_EE_POSE ? 6 : 3;
 };
 
 PK_DEV constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
@@ -46,7 +54,7 @@ struct LaneLds {
 template <int C, int L, int KIND>
 struct Slots {
     static constexpr int ROWS = Star<C, L, KIND>::ROWS;
-    static constexpr int TGW = KIND == PK_EE_POSE ? 12 : 3;
+    static constexpr int TGW = ee_of(KIND) == PK_EE_POSE ? 12 : 3;
     static constexpr int TG = 0;
     static constexpr int COL = C * TGW;
     static constexpr int RES = COL + C * L * ROWS;
@@ -61,7 +69,9 @@ struct Slots {
 };
 
 // FK along chain c at q; optionally keeps each joint's world axis and origin.
-template <int C, int L, bool KEEP>
+// A prismatic joint (a robot constant, so the branch is uniform) does not
+// rotate its frame and slides its origin by q along its axis.
+template <int C, int L, bool KEEP, int KIND = PK_EE_POSE>
 PK_DEV void chain_fk(const RobotC *__restrict__ rb, int c, const float *q, float (*om)[3],
                      float (*pj)[3], float *Re, float *pe)
 {
@@ -70,9 +80,11 @@ PK_DEV void chain_fk(const RobotC *__restrict__ rb, int c, const float *q, float
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         const int j = c * L + i;
-        float s, co, On[9], pn[3];
-        joint_sincos(q[j], s, co);
+        float s = 0.f, co = 1.f, On[9], pn[3];
+        const bool pris = pris_of(KIND) && rb->j[j].type == PK_JOINT_PRISMATIC;
+        if (!pris) joint_sincos(q[j], s, co);
         joint_step(O, p, rb->j[j].G, rb->j[j].t, s, co, On, pn);
+        if (pris) joint_slide(On, q[j], pn);
 #pragma unroll
         for (int u = 0; u < 9; ++u) O[u] = On[u];
 #pragma unroll
@@ -97,7 +109,7 @@ PK_DEV void ee_residual(const SolveParams &P, const LaneLds &S, int tg_slot, con
 #pragma unroll
     for (int u = 0; u < 3; ++u) d[u] = pe[u] - S[tg_slot + u];
     perr = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    if constexpr (KIND == PK_EE_POSE) {
+    if constexpr (ee_of(KIND) == PK_EE_POSE) {
         float Rt[9];
 #pragma unroll
         for (int u = 0; u < 9; ++u) Rt[u] = S[tg_slot + 3 + u];
@@ -128,7 +140,7 @@ PK_DEV void eval_cost(const RobotC *__restrict__ rb, const SolveParams &P,
     for (int c = 0; c < C; ++c) {
         float Re[9], pe[3], r[ROWS];
         PoseLog lg;
-        chain_fk<C, L, false>(rb, c, q, nullptr, nullptr, Re, pe);
+        chain_fk<C, L, false, KIND>(rb, c, q, nullptr, nullptr, Re, pe);
         ee_residual<KIND>(P, S, SL::TG + c * SL::TGW, Re, pe, r, perr[c], rerr[c], &lg);
 #pragma unroll
         for (int u = 0; u < ROWS; ++u) cp += r[u] * r[u];
@@ -144,6 +156,31 @@ PK_DEV void eval_cost(const RobotC *__restrict__ rb, const SolveParams &P,
     cost = cp + cj;
 }
 
+// Weighted Jacobian column of a joint with world axis w and origin pj, for
+// the single EE at pe (M, Nb: the EE's right-Jacobian-inverse blocks, pose
+// EEs only): a revolute joint moves the EE with twist (w x (pe - pj), w), a
+// prismatic one with (w, 0).
+template <int KIND>
+PK_DEV void jac_column(const SolveParams &P, const float *M, const float *Nb, const float *w,
+                       const float *pj, const float *pe, bool pris, float *col)
+{
+    float v[3], wv[3];
+    joint_twist(pris_of(KIND) && pris, w, pj, pe, v, wv);
+    if constexpr (ee_of(KIND) == PK_EE_POSE) {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
+            float nw = Nb[3 * u] * wv[0] + Nb[3 * u + 1] * wv[1] + Nb[3 * u + 2] * wv[2];
+            float mw = M[3 * u] * wv[0] + M[3 * u + 1] * wv[1] + M[3 * u + 2] * wv[2];
+            col[u] = P.w_pos * (mv + nw);
+            col[3 + u] = P.w_rot * mw;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 3; ++u) col[u] = P.w_pos * v[u];
+    }
+}
+
 // Normal equations at q: for each chain, the packed J_c^T J_c (+ limit and
 // rest diagonal) and J^T r, handed to sink.a(c, idx, v) / sink.g(j, v).
 // Jacobian of chain c at q (weighted EE rows and the limit/rest diagonal
@@ -156,60 +193,25 @@ PK_DEV void eval_jacobian_chain(const RobotC *__restrict__ rb, const SolveParams
     constexpr int ROWS = SL::ROWS;
     float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS], pe_err, re_err, M[9], Nb[9];
     PoseLog lg;
-    chain_fk<C, L, true>(rb, c, q, om, pj, Re, pe);
+    chain_fk<C, L, true, KIND>(rb, c, q, om, pj, Re, pe);
     ee_residual<KIND>(P, S, SL::TG + c * SL::TGW, Re, pe, r, pe_err, re_err, &lg);
-    if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
+    if constexpr (ee_of(KIND) == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
 #pragma unroll
     for (int u = 0; u < ROWS; ++u) S[SL::RES + c * ROWS + u] = r[u];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
-        float lev[3] = {pe[0] - pj[i][0], pe[1] - pj[i][1], pe[2] - pj[i][2]}, v[3];
-        cross(om[i], lev, v);
-        const int base = SL::COL + (c * L + i) * ROWS;
-        if constexpr (KIND == PK_EE_POSE) {
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
-                float nw = Nb[3 * u] * om[i][0] + Nb[3 * u + 1] * om[i][1] + Nb[3 * u + 2] * om[i][2];
-                float mw = M[3 * u] * om[i][0] + M[3 * u + 1] * om[i][1] + M[3 * u + 2] * om[i][2];
-                S[base + u] = P.w_pos * (mv + nw);
-                S[base + 3 + u] = P.w_rot * mw;
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < 3; ++u) S[base + u] = P.w_pos * v[u];
-        }
         const int j = c * L + i;
+        const int base = SL::COL + (c * L + i) * ROWS;
+        float col[ROWS];
+        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, rb->j[j].type == PK_JOINT_PRISMATIC, col);
+#pragma unroll
+        for (int u = 0; u < ROWS; ++u) S[base + u] = col[u];
         const float over = q[j] - rb->j[j].hi, under = rb->j[j].lo - q[j];
         const float rl = P.w_limit * (fmaxf(over, 0.f) + fmaxf(under, 0.f));
         const float rr = P.w_rest * (q[j] - qr[j]);
         const float dl = over > 0.f ? P.w_limit : (under > 0.f ? -P.w_limit : 0.f);
         S[SL::DG + j] = dl * dl + P.w_rest * P.w_rest;
         S[SL::GX + j] = dl * rl + P.w_rest * rr;
-    }
-}
-
-// Weighted Jacobian column of a joint with world axis w and origin pj, for
-// the single EE at pe (M, Nb: the EE's right-Jacobian-inverse blocks, pose
-// EEs only).
-template <int KIND>
-PK_DEV void jac_column(const SolveParams &P, const float *M, const float *Nb, const float *w,
-                       const float *pj, const float *pe, float *col)
-{
-    float lev[3] = {pe[0] - pj[0], pe[1] - pj[1], pe[2] - pj[2]}, v[3];
-    cross(w, lev, v);
-    if constexpr (KIND == PK_EE_POSE) {
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            float mv = M[3 * u] * v[0] + M[3 * u + 1] * v[1] + M[3 * u + 2] * v[2];
-            float nw = Nb[3 * u] * w[0] + Nb[3 * u + 1] * w[1] + Nb[3 * u + 2] * w[2];
-            float mw = M[3 * u] * w[0] + M[3 * u + 1] * w[1] + M[3 * u + 2] * w[2];
-            col[u] = P.w_pos * (mv + nw);
-            col[3 + u] = P.w_rot * mw;
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < 3; ++u) col[u] = P.w_pos * v[u];
     }
 }
 
@@ -237,12 +239,12 @@ PK_DEV void normal1(const RobotC *__restrict__ rb, const SolveParams &P, const f
     using SL = Slots<1, L, KIND>;
     constexpr int ROWS = SL::ROWS, NA = Star<1, L, KIND>::NA;
     float M[9], Nb[9];
-    if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
+    if constexpr (ee_of(KIND) == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
     float col[L][ROWS];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         float dg, gx;
-        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, col[i]);
+        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, rb->j[i].type == PK_JOINT_PRISMATIC, col[i]);
         joint_terms(rb, P, qr, q, i, dg, gx);
 #pragma unroll
         for (int k = 0; k <= i; ++k) {
@@ -275,7 +277,7 @@ PK_DEV bool eval_point1(const RobotC *__restrict__ rb, const SolveParams &P, con
     constexpr int ROWS = SL::ROWS;
     float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS];
     PoseLog lg;
-    chain_fk<1, L, true>(rb, 0, q, om, pj, Re, pe);
+    chain_fk<1, L, true, KIND>(rb, 0, q, om, pj, Re, pe);
     ee_residual<KIND>(P, S, SL::TG, Re, pe, r, perr[0], rerr[0], &lg);
     float cp = 0.f, cj = 0.f;
 #pragma unroll
@@ -414,19 +416,19 @@ PK_DEV bool step_fp64_1(const RobotC *__restrict__ rb, const SolveParams &P, con
     constexpr int ROWS = SL::ROWS;
     float om[L][3], pj[L][3], Re[9], pe[3], r[ROWS], pe_err, re_err, M[9], Nb[9];
     PoseLog lg;
-    chain_fk<1, L, true>(rb, 0, q, om, pj, Re, pe);
+    chain_fk<1, L, true, KIND>(rb, 0, q, om, pj, Re, pe);
     ee_residual<KIND>(P, S, SL::TG, Re, pe, r, pe_err, re_err, &lg);
-    if constexpr (KIND == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
+    if constexpr (ee_of(KIND) == PK_EE_POSE) jr_inv_blocks(lg, Re, M, Nb);
     double A[Star<1, L, KIND>::NA], g[L], x[L];
 #pragma unroll
     for (int i = 0; i < L; ++i) {
         float ci[ROWS], dg, gx;
-        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, ci);
+        jac_column<KIND>(P, M, Nb, om[i], pj[i], pe, rb->j[i].type == PK_JOINT_PRISMATIC, ci);
         joint_terms(rb, P, qr, q, i, dg, gx);
 #pragma unroll
         for (int k = 0; k <= i; ++k) {
             float ck[ROWS];
-            jac_column<KIND>(P, M, Nb, om[k], pj[k], pe, ck);
+            jac_column<KIND>(P, M, Nb, om[k], pj[k], pe, rb->j[k].type == PK_JOINT_PRISMATIC, ck);
             double a = 0;
 #pragma unroll
             for (int u = 0; u < ROWS; ++u) a += (double)ci[u] * (double)ck[u];
@@ -452,7 +454,7 @@ PK_DEV bool meets_tol(const SolveParams &P, const float *perr, const float *rerr
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         ok &= perr[c] <= P.tol_pos;
-        if (KIND == PK_EE_POSE) ok &= rerr[c] <= P.tol_rot;
+        if (ee_of(KIND) == PK_EE_POSE) ok &= rerr[c] <= P.tol_rot;
     }
     return ok;
 }
@@ -482,7 +484,7 @@ PK_DEV bool load_problem(const SolveParams &P, const LaneLds &S, const float *qs
         q[j] = qsrc[j * N + p];
         finite &= isfinite(q[j]);
     }
-    const int W = KIND == PK_EE_POSE ? 7 : 3;
+    const int W = ee_of(KIND) == PK_EE_POSE ? 7 : 3;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         float v[W];
@@ -494,7 +496,7 @@ PK_DEV bool load_problem(const SolveParams &P, const LaneLds &S, const float *qs
         const int base = SL::TG + c * SL::TGW;
 #pragma unroll
         for (int u = 0; u < 3; ++u) S[base + u] = v[u];
-        if constexpr (KIND == PK_EE_POSE) {
+        if constexpr (ee_of(KIND) == PK_EE_POSE) {
             float R[9];
             quat_to_rot(v[3], v[4], v[5], v[6], R);
 #pragma unroll

@@ -142,8 +142,8 @@ int pk::prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *
     if (!finite_w(w)) return fail(ctx, PK_EINVAL, "cost weights: non-finite value");
     const RobotC &H = rb.host;
     variant = o->variant;
-    // the per-lane kernel has revolute joints only, none of them mimic
-    const bool lane_ok = H.chains > 0 && H.prismatic == 0 && H.n_mimic == 0 &&
+    // the per-lane kernel: no mimic joints; prismatic joints on single chains
+    const bool lane_ok = H.chains > 0 && H.n_mimic == 0 && (H.prismatic == 0 || H.chains == 1) &&
                          lane_variant_available(H.chains, H.chain_len, H.e[0].kind);
     const bool wave_ok = wave_variant_available(H.n);
     if (variant == PK_VARIANT_AUTO) variant = lane_ok ? PK_VARIANT_LANE : PK_VARIANT_WAVE;

@@ -40,6 +40,7 @@ struct EEC {
 };
 
 constexpr int PK_STEP_PIVOTS = 16;   // pivots per elimination step (LDS slots)
+constexpr int PK_LANE_MAX_CHAIN = 10; // longest single chain the per-lane kernel serves
 
 struct RobotC {
     int32_t n, m, tgt_floats, pose_rows;   // pose_rows = sum of EE row counts

@@ -137,8 +137,11 @@ std::string tune_key(pk_ctx *ctx, int n_groups, const pk_ik_group *g, const pk_l
 // then runs in per-group mode).
 int path_of(const RobotC &H, int variant)
 {
-    if (variant == PK_VARIANT_LANE)
-        return H.chains == 1 ? MIX_LANE_ARM : MIX_LANE_HAND;
+    if (variant == PK_VARIANT_LANE) {
+        if (H.chains == 1 && H.chain_len == 7 && H.e[0].kind == PK_EE_POSE) return MIX_LANE_ARM;
+        if (H.chains == 4 && H.chain_len == 4 && H.e[0].kind == PK_EE_POSITION) return MIX_LANE_HAND;
+        return MIX_WAVE_64_8;
+    }
     return (H.max_depth + 1 <= 16 && H.m <= 4) ? MIX_WAVE_16_4 : MIX_WAVE_64_8;
 }
 
@@ -658,7 +661,7 @@ int pk_autotune_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
         const RobotEntry *rb = robot_of(ctx, groups[g].robot_id);
         if (!rb) return fail(ctx, PK_ENOTFOUND, "pk_autotune_mixed: group %d: unknown robot", g);
         const RobotC &H = rb->host;
-        if (H.chains > 0 && H.prismatic == 0 && H.n_mimic == 0 &&
+        if (H.chains > 0 && H.n_mimic == 0 && (H.prismatic == 0 || H.chains == 1) &&
             lane_variant_available(H.chains, H.chain_len, H.e[0].kind))
             flex.push_back(g);
     }

@@ -252,6 +252,13 @@ def compare_outcome(ctx, rid, tree, tg, seed, w, o, status, itt, ora, variant=0)
     kind, t = first_departure(res, ora, seed)
     if t == 0:
         return "bad", "traced runs do not part"
+    return departure_excuse(tree, tg, w, o, seed, ora, res, kind, t)
+
+
+def departure_excuse(tree, tg, w, o, seed, ora, res, kind, t):
+    """(verdict, reason) for a traced GPU run (res, one problem) that leaves
+    the oracle's at iteration t (first_departure): the rules of
+    compare_outcome."""
     if kind == "decision" and ora["trace_tie"][t - 1]:
         return "excused", "near-tie"
     if kind == "decision" and fp32_replay_flips(tree, tg, w, o, seed, ora, t):

@@ -100,8 +100,9 @@ def test_residual_jacobian_parity(ctx, rids, name):
     assert worst_r <= 2e-5 and worst_j <= 1e-4
 
 
-@pytest.mark.parametrize("name,variant", [("arm7_tool", 1), ("arm7_tool", 2), ("scara4", 0),
-                                          ("mobile_arm7", 0), ("hand16_mimic", 0)])
+@pytest.mark.parametrize("name,variant", [("arm7_tool", 1), ("arm7_tool", 2), ("scara4", 1),
+                                          ("scara4", 2), ("mobile_arm7", 1), ("mobile_arm7", 2),
+                                          ("hand16_mimic", 0)])
 def test_lm_success_agreement(ctx, rids, name, variant):
     """Pose + limit + rest (0.01) on every robot: the rest term also gives the
     mobile arm's 4-dimensional null space of the pose a unique optimum, so
@@ -223,11 +224,11 @@ def test_upload_errors_and_lane_variant(ctx, rids):
     with pytest.raises(pk.PkError) as e:
         ctx.upload(t4)
     assert e.value.code == -2
-    # prismatic robots have no per-lane kernel
-    tree = ROBOTS["scara4"]
+    # mimic robots have no per-lane kernel
+    tree = ROBOTS["hand16_mimic"]
     tg = oracle.targets_from(tree, synth.uniform_configs(tree, 4, 1))
     with pytest.raises(pk.PkError) as e:
-        solve_gpu(ctx, rids["scara4"], tree, tg, synth.uniform_configs(tree, 4, 2), 1,
+        solve_gpu(ctx, rids["hand16_mimic"], tree, tg, synth.uniform_configs(tree, 4, 2), 1,
                   {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 10.0, "w_rest": 0.0},
                   {"max_iters": 5, "lambda0": 1e-3, "nu_up": 10.0, "nu_down": 10.0,
                    "lambda_min": 1e-10, "lambda_max": 1e10, "early_exit": False, "tol_pos": 1e-3,
