@@ -62,7 +62,11 @@ typedef struct pk_ctx pk_ctx;
 /* Kernel variants for pk_lm_options.variant. */
 #define PK_VARIANT_AUTO 0     /* pick by robot shape and the autotune table  */
 #define PK_VARIANT_LANE 1     /* one problem per lane; star-of-chains robots  */
-#define PK_VARIANT_WAVE 2     /* one problem per 64-lane wavefront; any tree  */
+#define PK_VARIANT_WAVE 2     /* one problem per 64-lane wavefront; any tree:
+                                 the path-pair layout where it applies, else
+                                 the lane-per-joint layout                    */
+#define PK_VARIANT_WAVE_JOINT 3  /* one problem per wavefront, lane-per-joint
+                                    layout forced (any tree)                 */
 
 /* Joint kinds (Sec. III-B: fixed, revolute and prismatic joints). */
 #define PK_JOINT_REVOLUTE 0   /* rotation by q about the axis                 */
@@ -190,7 +194,11 @@ const char *pk_last_error(pk_ctx *ctx);
  * (PK_VARIANT_LANE) serves single chains of 2 to 10 joints (revolute or
  * prismatic) ending in one EE and the star of 4 chains x 4 revolute joints
  * with 4 position EEs; other robots, and robots with mimic joints, run on
- * the per-wavefront kernel (PK_VARIANT_LANE is unsupported for them).
+ * the per-wavefront kernel (PK_VARIANT_LANE is unsupported for them).  The
+ * per-wavefront kernel gives each (joint, EE path) pair a lane -- a joint
+ * shared by several root-to-EE paths gets one lane per path -- when the
+ * robot has no mimic joints, at most 16 levels and at most 64 such pairs
+ * (the path-pair layout); otherwise each joint gets one lane.
  * Synchronous. */
 int pk_robot_upload(pk_ctx *ctx, const pk_tree *tree, int32_t *robot_id);
 /* n variables (joints neither fixed nor mimic), m EEs, target floats per target (sum of EE widths), residual rows

@@ -14,7 +14,7 @@ import numpy as np
 
 __all__ = ["Context", "Seeder", "Weights", "Options", "lib", "LibraryMissing", "PkError",
            "CONVERGED", "MAX_ITERS", "STALLED", "NONFINITE", "FLAG_FP64",
-           "EE_POSE", "EE_POSITION", "VARIANT_AUTO", "VARIANT_LANE", "VARIANT_WAVE",
+           "EE_POSE", "EE_POSITION", "VARIANT_AUTO", "VARIANT_LANE", "VARIANT_WAVE", "VARIANT_WAVE_JOINT",
            "pack_targets", "target_floats"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +25,7 @@ JOINT_REVOLUTE, JOINT_PRISMATIC, JOINT_FIXED = 0, 1, 2
 FLAG_FP64 = 0x100
 NOALLOC_MAX_PROBLEMS = 1 << 20      # problems per pk_ik_solve_noalloc call (include/pkmi.h)
 EE_POSE, EE_POSITION = 0, 1
-VARIANT_AUTO, VARIANT_LANE, VARIANT_WAVE = 0, 1, 2
+VARIANT_AUTO, VARIANT_LANE, VARIANT_WAVE, VARIANT_WAVE_JOINT = 0, 1, 2, 3
 SCHED_SINGLE, SCHED_PER_GROUP = 0, 1
 
 

@@ -9,6 +9,7 @@
 // Method: Sec. III-A (LM over the sum of squared weighted residuals) for each
 // problem, as in the per-lane and per-wavefront kernels it instantiates.
 #include "lm_lane.hpp"
+#include "lm_path.hpp"
 #include "lm_wave.hpp"
 #include "sched_table.hpp"
 
@@ -84,6 +85,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void lm
         case MIX_LANE_HAND:
             run_lane<4, 4, PK_EE_POSITION>(G, ws, first, lane);
             break;
+        case MIX_PATH_16_4:
+            path::path_problem<16, 4>(G.rb, G.P, ws, first);
+            break;
         default:
             wave::wave_problem<16, 4>(G.rb, G.P, ws, first);
             break;
@@ -103,6 +107,7 @@ int mixed_lds_floats(int path)
     case MIX_LANE_ARM: return align4(lane::Slots<1, 7, PK_EE_POSE>::TOTAL * lane::BLOCK);
     case MIX_LANE_HAND: return align4(lane::Slots<4, 4, PK_EE_POSITION>::TOTAL * lane::BLOCK);
     case MIX_WAVE_16_4: return align4(wave::Lds<16, 4>::FLOATS);
+    case MIX_PATH_16_4: return align4(path::Lds<16, 4>::FLOATS);
     default: return 0;
     }
 }

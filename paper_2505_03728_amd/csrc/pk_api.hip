@@ -149,9 +149,9 @@ int pk::prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *
     if (variant == PK_VARIANT_AUTO) variant = lane_ok ? PK_VARIANT_LANE : PK_VARIANT_WAVE;
     if (variant == PK_VARIANT_LANE && !lane_ok)
         return fail(ctx, PK_EUNSUPPORTED, "no per-lane kernel for this robot shape");
-    if (variant == PK_VARIANT_WAVE && !wave_ok)
+    if ((variant == PK_VARIANT_WAVE || variant == PK_VARIANT_WAVE_JOINT) && !wave_ok)
         return fail(ctx, PK_EUNSUPPORTED, "no wave kernel for n=%d", H.n);
-    if (variant != PK_VARIANT_LANE && variant != PK_VARIANT_WAVE)
+    if (variant != PK_VARIANT_LANE && variant != PK_VARIANT_WAVE && variant != PK_VARIANT_WAVE_JOINT)
         return fail(ctx, PK_EINVAL, "unknown variant %d", variant);
     memset(&P, 0, sizeof P);
     weights_into(w, P);
@@ -166,8 +166,10 @@ int pk::prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *
 hipError_t pk::launch_lm(const RobotEntry &rb, const SolveParams &P, int variant, hipStream_t s,
                          int persist_blocks)
 {
-    return variant == PK_VARIANT_LANE ? launch_lm_lane(rb.dev, rb.host, P, s, persist_blocks)
-                                      : launch_lm_wave(rb.dev, rb.host, P, s, persist_blocks);
+    if (variant == PK_VARIANT_LANE) return launch_lm_lane(rb.dev, rb.host, P, s, persist_blocks);
+    if (variant == PK_VARIANT_WAVE && path_variant_available(rb.host))
+        return launch_lm_path(rb.dev, rb.host, P, s, persist_blocks);
+    return launch_lm_wave(rb.dev, rb.host, P, s, persist_blocks);
 }
 
 // Scratch of the allocation-free solve: pose-only cost, total cost and status
@@ -249,6 +251,91 @@ int pk_destroy(pk_ctx *ctx)
 const char *pk_last_error(pk_ctx *ctx)
 {
     return ctx ? ctx->err.c_str() : g_err_noctx.c_str();
+}
+
+// Path-pair layout (PathC) of the wavefront kernel that gives each (joint,
+// EE path) pair a lane.  Leaves R.path.ok = 0 when the robot does not fit it
+// (mimic joints, more than PK_PATH_MAX_DEPTH levels, more than 64 pairs).
+// Needs R's joints, EEs, ancestor sets and elimination schedule.
+static void build_path_layout(RobotC &R)
+{
+    PathC &Pc = R.path;
+    memset(&Pc, 0, sizeof Pc);
+    const int n = R.n, m = R.m;
+    if (R.n_mimic > 0 || R.max_depth + 1 > PK_PATH_MAX_DEPTH) return;
+    int lane_of[PK_MAX_JOINTS][PK_MAX_EES], own_lane[PK_MAX_JOINTS], og[PK_MAX_JOINTS];
+    for (int j = 0; j < n; ++j) {
+        own_lane[j] = og[j] = -1;
+        for (int k = 0; k < PK_MAX_EES; ++k) lane_of[j][k] = -1;
+    }
+    int lanes = 0;
+    for (int k = 0; k < m; ++k) {
+        const int e = R.e[k].joint;
+        for (int d = 0; d <= R.j[e].depth; ++d) {
+            if (lanes >= 64) return;
+            const int j = R.anc_at[e][d];
+            lane_of[j][k] = lanes;
+            Pc.joint[lanes] = (uint8_t)j;
+            Pc.group[lanes] = (int8_t)k;
+            ++lanes;
+        }
+    }
+    for (int j = 0; j < n; ++j) {
+        for (int k = 0; k < m && og[j] < 0; ++k)
+            if (lane_of[j][k] >= 0) og[j] = k;
+        if (og[j] >= 0) {
+            own_lane[j] = lane_of[j][og[j]];
+            continue;
+        }
+        if (lanes >= 64) return;   // a joint on no EE path: one lane of its own
+        own_lane[j] = lanes;
+        Pc.joint[lanes] = (uint8_t)j;
+        Pc.group[lanes] = -1;
+        ++lanes;
+    }
+    Pc.lanes = lanes;
+    memset(Pc.merge_step, PK_PATH_NONE, sizeof Pc.merge_step);
+    memset(Pc.copies, PK_PATH_NONE, sizeof Pc.copies);
+    for (int l = 0; l < 64; ++l) {
+        Pc.lane_ee[l] = -1;
+        for (int d = 0; d < PK_PATH_MAX_DEPTH; ++d) Pc.anc[l][d] = (uint8_t)l;
+    }
+    for (int k = 0; k < m; ++k) Pc.lane_ee[lane_of[R.e[k].joint][k]] = (int8_t)k;
+    uint32_t pdep[PK_MAX_JOINTS] = {0}, mdep[PK_MAX_JOINTS] = {0};
+    for (int l = 0; l < lanes; ++l) {
+        const int j = Pc.joint[l], k = Pc.group[l], dep = R.j[j].depth;
+        Pc.owner[l] = (uint8_t)own_lane[j];
+        if (k < 0) continue;
+        for (int d = 0; d <= dep; ++d) Pc.anc[l][d] = (uint8_t)lane_of[R.anc_at[j][d]][k];
+        for (int b = 0; b < 4; ++b) {
+            const int d = dep - (1 << b);
+            Pc.jump[l] |= (uint32_t)(d >= 0 ? lane_of[R.anc_at[j][d]][k] : l) << (8 * b);
+        }
+        // updates: the pivots owned by path k below joint j
+        for (int i = 0; i < n; ++i)
+            if (og[i] == k && ((R.janc[i] >> j) & 1ull)) Pc.upd[l] |= 1ull << R.step_of[i];
+    }
+    for (int i = 0; i < n; ++i)
+        if (og[i] >= 0 && pdep[R.step_of[i]] < (uint32_t)R.j[i].depth) pdep[R.step_of[i]] = R.j[i].depth;
+    int ncopy = 0;
+    for (int j = 0; j < n; ++j) {
+        if (og[j] < 0) continue;
+        int c = 0;
+        for (int k = og[j] + 1; k < m; ++k)
+            if (lane_of[j][k] >= 0) Pc.copies[own_lane[j]][c++] = (uint8_t)lane_of[j][k];
+        if (c == 0) continue;
+        ncopy = c > ncopy ? c : ncopy;
+        // The other copies take updates only from pivots of their own paths
+        // below j; the merge follows the last of them.
+        int ms = 0;
+        for (int i = 0; i < n; ++i)
+            if (((R.janc[i] >> j) & 1ull) && og[i] != og[j] && R.step_of[i] + 1 > ms) ms = R.step_of[i] + 1;
+        Pc.merge_step[own_lane[j]] = (uint8_t)ms;
+        if (mdep[ms] < (uint32_t)R.j[j].depth + 1) mdep[ms] = R.j[j].depth + 1;
+    }
+    Pc.ncopy = ncopy;
+    for (int s = 0; s < R.nstep; ++s) Pc.step_info[s] = pdep[s] | (mdep[s] << 8);
+    Pc.ok = 1;
 }
 
 int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
@@ -486,6 +573,7 @@ int pk_robot_upload(pk_ctx *ctx, const pk_tree *t, int32_t *robot_id)
         R.chains = star ? roots : 0;
         R.chain_len = star ? L : 0;
     }
+    build_path_layout(R);
 
     RobotEntry ent;
     ent.host = R;

@@ -41,6 +41,35 @@ struct EEC {
 
 constexpr int PK_STEP_PIVOTS = 16;   // pivots per elimination step (LDS slots)
 constexpr int PK_LANE_MAX_CHAIN = 10; // longest single chain the per-lane kernel serves
+constexpr int PK_PATH_MAX_DEPTH = 16; // tree levels the path-pair wavefront kernel serves
+constexpr uint8_t PK_PATH_NONE = 0xff;
+
+// Path-pair layout of one problem on a 64-lane wavefront.  Lane l holds the
+// pair (joint[l], path group[l]): every joint on the path from the root to EE
+// k has a lane in group k, so a joint shared by several EE paths has one copy
+// per path; a joint on no EE path has one lane with group -1.  Each copy holds
+// the part of its joint's row of J^T J that its path's EE rows give; the
+// owner copy (the one in the lowest-numbered path) also holds the limit and
+// rest rows and, once the other copies are merged into it, the whole row.
+struct PathC {
+    int32_t ok;                    // the layout applies to this robot
+    int32_t lanes;                 // lanes in use
+    int32_t ncopy;                 // most copies of one joint, minus one
+    int32_t pad;
+    uint8_t joint[64];             // lane -> joint
+    int8_t group[64];              // lane -> EE path (-1: the joint is on no EE path)
+    uint8_t owner[64];             // lane -> lane of its joint's owner copy
+    uint8_t merge_step[64];        // owner lanes of shared joints: the step whose merge phase
+                                   // adds the other copies' rows (PK_PATH_NONE: no merge)
+    int8_t lane_ee[64];            // lane -> the EE whose joint it holds in that EE's path (-1)
+    uint8_t anc[64][PK_PATH_MAX_DEPTH];   // [l][d]: lane of l's ancestor at depth d in l's path
+                                          // (l itself at its depth and beyond, and for group -1)
+    uint8_t copies[64][8];         // owner lanes: the other copies' lanes (PK_PATH_NONE-padded)
+    uint32_t jump[64];             // byte k: lane of l's path ancestor 2^k levels up (l if none)
+    uint64_t upd[64];              // bit s: at step s the pivot owned by l's path lies below l's joint
+    uint32_t step_info[64];        // [s] bits 0-7: deepest pivot depth of step s; bits 8-15:
+                                   // 1 + deepest depth merged at step s (0: no merge phase)
+};
 
 struct RobotC {
     int32_t n, m, tgt_floats, pose_rows;   // pose_rows = sum of EE row counts
@@ -65,6 +94,7 @@ struct RobotC {
     uint8_t step_joint[PK_MAX_JOINTS];
     uint8_t step_of[PK_MAX_JOINTS];
     uint8_t step_pos[PK_MAX_JOINTS];
+    PathC path;
 };
 
 // Uniform per-call data for the LM kernels (passed by value).
@@ -109,6 +139,9 @@ hipError_t launch_lm_lane(const RobotC *dev_robot, const RobotC &host_robot,
                           const SolveParams &P, hipStream_t s, int persist_blocks = 0);
 bool wave_variant_available(int n);
 hipError_t launch_lm_wave(const RobotC *dev_robot, const RobotC &host_robot,
+                          const SolveParams &P, hipStream_t s, int persist_blocks = 0);
+bool path_variant_available(const RobotC &host_robot);
+hipError_t launch_lm_path(const RobotC *dev_robot, const RobotC &host_robot,
                           const SolveParams &P, hipStream_t s, int persist_blocks = 0);
 hipError_t launch_best_of_k(const SolveParams &P, int n, int32_t *best_index,
                             float *best_joints, int32_t *success, hipStream_t s);

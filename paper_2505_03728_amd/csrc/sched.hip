@@ -142,7 +142,9 @@ int path_of(const RobotC &H, int variant)
         if (H.chains == 4 && H.chain_len == 4 && H.e[0].kind == PK_EE_POSITION) return MIX_LANE_HAND;
         return MIX_WAVE_64_8;
     }
-    return (H.max_depth + 1 <= 16 && H.m <= 4) ? MIX_WAVE_16_4 : MIX_WAVE_64_8;
+    if (H.max_depth + 1 > 16 || H.m > 4) return MIX_WAVE_64_8;
+    if (variant == PK_VARIANT_WAVE && path_variant_available(H)) return MIX_PATH_16_4;
+    return MIX_WAVE_16_4;
 }
 
 void drop_graphs(SchedCache &C)
@@ -273,7 +275,7 @@ int table_for(pk_ctx *ctx, SchedCache &C, const std::string &key, const std::vec
         int slot = 0;
         for (int pass = 0; pass < 2; ++pass)
             for (const GroupPlan &pl : plans) {
-                const bool wave = pl.path == MIX_WAVE_16_4;
+                const bool wave = pl.path == MIX_WAVE_16_4 || pl.path == MIX_PATH_16_4;
                 if (wave != (pass == 0)) continue;
                 MixedGroup &G = te.base.g[slot++];
                 G.rb = pl.rb->dev;

@@ -20,9 +20,11 @@ namespace pk {
 enum MixedPath : int32_t {
     MIX_LANE_ARM = 0,     // one problem per lane, serial 7-joint arm, one pose EE
     MIX_LANE_HAND = 1,    // one problem per lane, 4 chains of 4 joints, 4 position EEs
-    MIX_WAVE_16_4 = 2,    // one problem per wavefront, depth <= 16 levels, <= 4 EEs
-    MIX_WAVE_64_8 = 3,    // one problem per wavefront, any tree (<= 64 joints, 8 EEs)
-    MIX_PATHS = 4
+    MIX_WAVE_16_4 = 2,    // one problem per wavefront, lane per joint, depth <= 16 levels, <= 4 EEs
+    MIX_PATH_16_4 = 3,    // one problem per wavefront, lane per (joint, EE path) pair,
+                          // depth <= 16 levels, <= 4 EEs
+    MIX_WAVE_64_8 = 4,    // one problem per wavefront, any tree (<= 64 joints, 8 EEs)
+    MIX_PATHS = 5
 };
 
 // Groups one persistent launch serves (its description travels by value as
@@ -37,7 +39,7 @@ struct MixedGroup {
     int32_t *list[2];         // active lists of alternate rounds
     int32_t *count;           // [2] active-list sizes
     int32_t path;             // MixedPath
-    int32_t per_item;         // problems per work item: 64 (lane paths) or 1 (wave paths)
+    int32_t per_item;         // problems per work item: 64 (lane paths) or 1 (wavefront paths)
 };
 
 struct MixedArgs {

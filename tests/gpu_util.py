@@ -189,6 +189,20 @@ def step_error_bound(tree, tg, w, o, q, lam):
     return d, A.shape[0] * np.linalg.cond(Al) * U32 * np.linalg.norm(d)
 
 
+def iterate_allowance(tree, tg, w, o, seed, n, floor=1e-4):
+    """Per iteration 1..n: max(floor, the FP32 forward-error bound
+    (step_error_bound) accumulated over the oracle's accepted steps so far):
+    how far an FP32 iterate may sit from the exact one."""
+    ora = oracle.lm_solve(tree, tg, w, o, seed, n_trace=n)
+    out, bound, q_prev = [], 0.0, np.asarray(seed, np.float64)
+    for i in range(min(n, len(ora["trace_acc"]))):
+        if ora["trace_acc"][i]:
+            bound += step_error_bound(tree, tg, w, o, q_prev, lambda_at(o, ora["trace_acc"], i + 1))[1]
+        q_prev = ora["trace_q"][i]
+        out.append(max(floor, bound))
+    return np.asarray(out)
+
+
 def ill_conditioned(tree, tg, w, o, q, lam):
     """Whether the accept decision of the exact LM iteration from q at damping
     lam is within what the forward error of an FP32 solve can move: a step
