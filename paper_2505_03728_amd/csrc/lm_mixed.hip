@@ -60,6 +60,7 @@ PK_DEV void run_lane(const MixedGroup &G, float *ws, int64_t first, int lane)
     if (i < nact) lane::lane_problem<C, L, KIND, true>(G.rb, G.qr, P, lane::LaneLds{ws + lane}, i);
 }
 
+// MixedArgs is the first kernel argument (offset 0 of the argument segment).
 template <int WG>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void lm_mixed_kernel(
     const MixedArgs a, const int32_t *__restrict__ item_end, int32_t *head, int lds_floats)
@@ -76,6 +77,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void lm
         if (item >= total) break;
         int g = 0;
         while (g < ng - 1 && item >= item_end[g]) ++g;
+        g = __builtin_amdgcn_readfirstlane(g);   // uniform: item is
         const MixedGroup &G = a.g[g];
         const int64_t first = item - (g > 0 ? item_end[g - 1] : 0);
         switch (G.path) {
@@ -86,7 +88,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void lm
             run_lane<4, 4, PK_EE_POSITION>(G, ws, first, lane);
             break;
         case MIX_PATH_16_4:
-            path::path_problem<16, 4>(G.rb, G.P, ws, first);
+            path::path_problem<16, 4>(
+                G.rb, path::kernel_params_at(offsetof(MixedArgs, g) + g * sizeof(MixedGroup) + offsetof(MixedGroup, P)),
+                ws, first);
             break;
         default:
             wave::wave_problem<16, 4>(G.rb, G.P, ws, first);

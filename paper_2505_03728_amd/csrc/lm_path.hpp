@@ -38,21 +38,66 @@ using wave::wave_max;
 using wave::wave_sum;
 using wave::wave_sync;
 
+// The call's parameters in the kernel-argument segment (constant memory).
+// path_problem reads them through this pointer, so that in its long LM loop
+// a field is fetched with a scalar load where it is used instead of every
+// field being held in SGPRs (and spilled) across the loop.
+using KParams = const __attribute__((address_space(4))) SolveParams;
+
+// The kernel argument at byte `offset` of the argument segment.
+PK_DEV KParams *kernel_params_at(size_t offset)
+{
+    return (KParams *)((const __attribute__((address_space(4))) char *)__builtin_amdgcn_kernarg_segment_ptr() +
+                       offset);
+}
+
+// A wave-uniform value taken as a new one (in an SGPR) by the compiler: what
+// it derives from the value is formed after this point, where it is used,
+// rather than hoisted and held from an earlier one.
+PK_DEV int fresh_uniform(int v)
+{
+    v = __builtin_amdgcn_readfirstlane(v);
+    __asm__ volatile("" : "+s"(v));
+    return v;
+}
+
+PK_DEV KParams *fresh_uniform(KParams *p)
+{
+    const uint64_t a = (uint64_t)p;
+    const int lo = fresh_uniform((int)(uint32_t)a), hi = fresh_uniform((int)(uint32_t)(a >> 32));
+    return (KParams *)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // LDS layout of one wavefront's problem (float offsets).
 template <int DMAX, int MMAX>
 struct Lds {
     static constexpr int ES = 60;                   // floats per EE record (slots as wave::E_*)
     static constexpr int SS = DMAX + 4;             // pivot slot stride, in values of the solve's type
-    static constexpr int XF = 0;                    // [64][12] transform exchange of the FK rounds
-    static constexpr int JA = XF + 64 * 12;         // [64][8]  joint axis and origin (last evaluated point)
-    static constexpr int JC = JA + 64 * 8;          // [64][8]  Jacobian block of the lane's pair
+    // One region serves three uses in turn within an LM pass: the transform
+    // exchange of the FK rounds; then, per lane, the joint axis and origin of
+    // the evaluated point (read by the Jacobian); then the pivot rows of the
+    // solve (the axes and origins are dead by then).
+    static constexpr int XF = 0;                    // [64][12] FK exchange; [64][12] axis, origin
+    static constexpr int JA = XF;
+    static constexpr int PV = XF;                   // [MMAX][SS] pivot rows by path, FP64-sized
+    static constexpr int JC = XF + 64 * 12;         // [64][8]  Jacobian block of the lane's pair
     static constexpr int CS = JC + 64 * 8;          // [64][12] joint constants G (row-major), t
     static constexpr int EC = CS + 64 * 12;         // [MMAX][12] EE constants G, t
     static constexpr int TG = EC + MMAX * 12;       // [MMAX][12] EE targets p, R
     static constexpr int EX = TG + MMAX * 12;       // [MMAX][ES] EE records (last evaluated point)
     static constexpr int RS = EX + MMAX * ES;       // [MMAX][8] EE residual rows (current point)
-    static constexpr int PV = RS + MMAX * 8;        // [MMAX][SS] pivot rows by path, FP64-sized
-    static constexpr int FLOATS = PV + 2 * MMAX * SS;
+    static constexpr int FLOATS = RS + MMAX * 8;
+    static_assert(2 * MMAX * SS <= 64 * 12, "pivot rows fit the FK exchange region");
+};
+
+// A lane's row of the tree-structured normal matrix, by ancestor depth, in
+// groups of four (register tuples the LDS stores can take directly).
+template <typename T, int DMAX>
+struct Row {
+    typedef T V4 __attribute__((ext_vector_type(4)));
+    V4 v[DMAX / 4];
+    PK_DEV T get(int d) const { return v[d >> 2][d & 3]; }
+    PK_DEV void set(int d, T x) { v[d >> 2][d & 3] = x; }
 };
 
 // What a lane holds (registers), from PathC and the joint table.
@@ -66,8 +111,8 @@ struct LaneInfo {
     int step;       // elimination step of j
     int mstep;      // owner lanes of shared joints: step of the merge phase
     int gkind;      // kind of the path's EE
-    bool own;       // owner copy of a joint
-    bool pris;      // prismatic joint
+    int own;        // owner copy of a joint (0/1)
+    int pris;       // prismatic joint (0/1)
     float lo, hi, qr;
     uint32_t ancp[DMAX / 4];   // lane of the path ancestor at depth d (byte d)
     uint64_t upd;   // bit s: this lane's row takes an update at step s
@@ -153,7 +198,8 @@ PK_DEV void point(const SolveParams &P, const LaneInfo<DMAX> &I, int lane, int m
         wave_sync();
     }
     {
-        float *ja = lds + L::JA + lane * 8;
+        // (the last round's reads are done: the lane's slot takes its axis and origin)
+        float *ja = lds + L::JA + lane * 12;
         ja[0] = R[2];
         ja[1] = R[5];
         ja[2] = R[8];
@@ -259,7 +305,7 @@ PK_DEV void jacobian(const SolveParams &P, const LaneInfo<DMAX> &I, int lane, fl
     float col[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (I.grp >= 0) {
         const float *e = lds + L::EX + I.grp * L::ES;
-        const float *ja = lds + L::JA + lane * 8;
+        const float *ja = lds + L::JA + lane * 12;
         const float om[3] = {ja[0], ja[1], ja[2]}, pj[3] = {ja[3], ja[4], ja[5]};
         float v[3], wv[3];
         joint_twist(I.pris, om, pj, e + wave::E_PE, v, wv);
@@ -288,9 +334,13 @@ PK_DEV void jacobian(const SolveParams &P, const LaneInfo<DMAX> &I, int lane, fl
 // blocks in LDS, and g = EE k's term of (J^T r)_j; returns EE k's term of A_jj.
 template <int DMAX, int MMAX, typename T>
 PK_DEV T jtj_rows(const float *lds, const LaneInfo<DMAX> &I, int lane, int max_depth,
-                  T (&r)[DMAX], T &g)
+                  Row<T, DMAX> &r, T &g)
 {
     using L = Lds<DMAX, MMAX>;
+    // new values (as in path_solve): the per-depth conditions are formed here
+    int dep = I.dep;
+    __asm__ volatile("" : "+v"(dep));
+    max_depth = fresh_uniform(max_depth);
     const float *own = lds + L::JC + lane * 8;
     float cj[6];
 #pragma unroll
@@ -310,8 +360,8 @@ PK_DEV T jtj_rows(const float *lds, const LaneInfo<DMAX> &I, int lane, int max_d
 #pragma unroll
             for (int u = 0; u < 6; ++u) s += (T)cj[u] * (T)ca[u];
         }
-        r[d] = d < I.dep ? s : (T)0;
-        diag = d == I.dep ? s : diag;
+        r.set(d, d < dep ? s : (T)0);
+        diag = d == dep ? s : diag;
         __asm__ volatile("" ::: "memory");   // one ancestor block in flight at a time
     }
     return diag;
@@ -324,14 +374,20 @@ PK_DEV T jtj_rows(const float *lds, const LaneInfo<DMAX> &I, int lane, int max_d
 // not positive and finite.  sinfo: lane s holds step s's PathC::step_info.
 // slots: LDS, one pivot row (SS values of T) per path.
 template <int DMAX, typename T>
-PK_DEV bool path_solve(T (&r)[DMAX], T dgu, T dfull, T g, float lam, float dfloor, float thresh_rel,
+PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float dfloor, float thresh_rel,
                        const LaneInfo<DMAX> &I, int lane, int nstep, uint32_t sinfo, int ncopy,
-                       int max_depth, T *slots, float &delta)
+                       uint32_t copy_depths, int max_depth, T *slots, float &delta)
 {
     constexpr int SS = DMAX + 4;
-    const T damp = I.own ? (T)lam * (dfull > (T)dfloor ? dfull : (T)dfloor) : (T)0;
+    // the lane's depth and ownership and the tree depth as new values:
+    // conditions on them are formed here, not shared with (and kept live
+    // from) the row forming
+    int dep = I.dep, own = I.own;
+    __asm__ volatile("" : "+v"(dep), "+v"(own));
+    max_depth = fresh_uniform(max_depth);
+    const T damp = own ? (T)lam * (dfull > (T)dfloor ? dfull : (T)dfloor) : (T)0;
     T dg = dgu + damp;
-    const float dmax = wave_max(I.own ? (float)(dfull + damp) : 0.f);
+    const float dmax = wave_max(own ? (float)(dfull + damp) : 0.f);
     T thresh = 0;
     if (thresh_rel > 0.f) thresh = (T)thresh_rel * (T)dmax;
     T b = I.j >= 0 ? -g : (T)0;
@@ -347,12 +403,14 @@ PK_DEV bool path_solve(T (&r)[DMAX], T dgu, T dfull, T g, float lam, float dfloo
                 const int cl = copy_lane(I, c);
                 const int src = cl == PK_PATH_NONE ? lane : cl;
                 const bool use = mg && cl != PK_PATH_NONE;
+                // (uniform conditions without early exits: an unrolled loop
+                // with breaks makes the compiler copy the whole row per exit)
 #pragma unroll
                 for (int d = 0; d < DMAX; ++d) {
-                    if (d + 1 >= mdep) break;
-                    const T o = __shfl(r[d], src, 64);
-                    if (use) r[d] += o;
-                    if ((d & 3) == 3) __asm__ volatile("" ::: "memory");   // four values in flight
+                    if (d + 1 < mdep) {
+                        const T o = __shfl(r.get(d), src, 64);
+                        if (use) r.set(d, r.get(d) + o);
+                    }
                 }
                 const T od = __shfl(dg, src, 64), ob = __shfl(b, src, 64);
                 if (use) {
@@ -362,12 +420,14 @@ PK_DEV bool path_solve(T (&r)[DMAX], T dgu, T dfull, T g, float lam, float dfloo
             }
         }
         wave_sync();   // the previous step's slot reads are done
-        if (I.own && I.step == st) {
+        if (own && I.step == st) {
             bad = bad || !(dg > thresh) || !(dg < (T)INFINITY);
             if (I.grp >= 0) {
+                // Entries at and past the pivot's depth are not part of its
+                // row; readers use only those below their own, shallower depth.
                 T *sl = slots + I.grp * SS;
 #pragma unroll
-                for (int d = 0; d < DMAX; ++d) sl[d] = d < I.dep ? r[d] : (T)0;
+                for (int i = 0; i < DMAX / 4; ++i) *(typename Row<T, DMAX>::V4 *)(sl + 4 * i) = r.v[i];
                 sl[DMAX] = dg;
                 sl[DMAX + 1] = b;
             }
@@ -376,13 +436,15 @@ PK_DEV bool path_solve(T (&r)[DMAX], T dgu, T dfull, T g, float lam, float dfloo
         if ((I.upd >> st) & 1ull) {
             const T *sk = slots + I.grp * SS;
             const T piv = sk[DMAX], bk = sk[DMAX + 1];
-            const T sel = sk[I.dep];
+            const T sel = sk[dep];
             const T c = sel * recip(piv);
+            // by groups of four up to the step's deepest pivot: the lanes
+            // updated lie above their pivots, so their rows end before it;
+            // entries of a group past the lane's own depth take values no
+            // reader uses
 #pragma unroll
-            for (int d = 0; d < DMAX; ++d) {
-                if ((d & 3) == 0 && d >= pdep) break;
-                r[d] -= c * sk[d];
-            }
+            for (int i = 0; i < DMAX / 4; ++i)
+                if (4 * i < pdep) r.v[i] -= c * *(const typename Row<T, DMAX>::V4 *)(sk + 4 * i);
             dg -= c * sel;
             b -= c * bk;
         }
@@ -390,16 +452,18 @@ PK_DEV bool path_solve(T (&r)[DMAX], T dgu, T dfull, T g, float lam, float dfloo
     if (__any(bad)) return false;
     // Back substitution, root first: x_j = (b_j - sum_d r_j[d] x_anc(d)) /
     // pivot_j on the owner, then copied to the joint's other copies.
-    const T ipj = I.own ? recip(dg) : (T)0;
+    const T ipj = own ? recip(dg) : (T)0;
     T s = 0, x = 0;
 #pragma unroll
     for (int D = 0; D < DMAX; ++D) {
         if (D <= max_depth) {
-            if (I.own && I.dep == D) x = (b - s) * ipj;
-            const T xo = __shfl(x, I.owner, 64);
-            if (I.dep == D) x = xo;
+            if (own && dep == D) x = (b - s) * ipj;
+            if ((copy_depths >> D) & 1) {   // uniform: some joint at depth D has copies
+                const T xo = __shfl(x, I.owner, 64);
+                if (dep == D) x = xo;
+            }
             const T xa = __shfl(x, wave::anc_lane<DMAX>(I.ancp, D), 64);
-            if (I.dep > D) s += r[D] * xa;
+            if (dep > D) s += r.get(D) * xa;
         }
     }
     delta = I.j >= 0 ? (float)x : 0.f;
@@ -409,14 +473,16 @@ PK_DEV bool path_solve(T (&r)[DMAX], T dgu, T dfull, T g, float lam, float dfloo
 // One LM problem (active index wi) on this wavefront; resumable (state in
 // HBM, at most P.iter_budget iterations per launch when P.st_state is set).
 template <int DMAX, int MMAX>
-PK_DEV void path_problem(const RobotC *__restrict__ rb, const SolveParams &P, float *lds, int64_t wi)
+PK_DEV void path_problem(const RobotC *__restrict__ rb, KParams *Pk, float *lds, int64_t wi)
 {
+    const SolveParams &P = *(const SolveParams *)Pk;
     using L = Lds<DMAX, MMAX>;
     const int lane = threadIdx.x & 63;     // wavefronts of a multi-wave block each run their own problem
     const int64_t p = P.active ? (int64_t)P.active[wi] : wi;
     const int64_t N = P.N, T = P.T, t = p / P.K;
     const PathC &Pc = rb->path;
-    const int n = rb->n, m = rb->m, max_depth = rb->max_depth, nstep = rb->nstep, ncopy = Pc.ncopy;
+    const int n = rb->n, m = rb->m, nstep0 = rb->nstep, max_depth0 = rb->max_depth, ncopy0 = Pc.ncopy;
+    const uint32_t copy_depths = Pc.copy_depths;
     const bool resumable = P.st_state != nullptr, resume = resumable && P.resume;
 
     LaneInfo<DMAX> I;
@@ -446,7 +512,7 @@ PK_DEV void path_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
     }
     I.upd = inl ? Pc.upd[l] : 0ull;
     I.jump = inl ? Pc.jump[l] : (uint32_t)lane * 0x01010101u;
-    const uint32_t sinfo = lane < nstep ? Pc.step_info[lane] : 0u;
+    const uint32_t sinfo = lane < nstep0 ? Pc.step_info[lane] : 0u;
     {
         float *cs = lds + L::CS + lane * 12;
 #pragma unroll
@@ -532,14 +598,24 @@ PK_DEV void path_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
     float qt = q;
     bool first = true, evaluate = true;
     for (;;) {
+        // The call's parameters are re-read (scalar loads) in each pass
+        // rather than held in SGPRs across the loop, which spills them.
+        const SolveParams &Q = *(const SolveParams *)fresh_uniform(Pk);
+        // likewise the robot's sizes: the per-depth conditions of the unrolled
+        // loops are formed at their uses
+        const int max_depth = fresh_uniform(max_depth0), nstep = fresh_uniform(nstep0),
+                  ncopy = fresh_uniform(ncopy0);
         bool acc = false;
-        // The lane tables are re-read each pass rather than values derived
-        // from them kept live across the whole loop.
+        // The lane tables are taken as new values in each pass, so that what
+        // the compiler derives from them (addresses, per-depth lane masks) is
+        // formed where it is used instead of held across the whole loop.
 #pragma unroll
         for (int i = 0; i < DMAX / 4; ++i) __asm__ volatile("" : "+v"(I.ancp[i]));
         __asm__ volatile("" : "+v"(I.jump), "+v"(I.cp0), "+v"(I.cp1));
+        __asm__ volatile("" : "+v"(I.dep), "+v"(I.own), "+v"(I.grp), "+v"(I.ee), "+v"(I.owner));
+        __asm__ volatile("" : "+v"(I.j), "+v"(I.step), "+v"(I.mstep));
         if (evaluate) {
-            point<DMAX, MMAX>(P, I, lane, max_depth, qt, lds, X);
+            point<DMAX, MMAX>(Q, I, lane, max_depth, qt, lds, X);
             acc = first || X.cost < cost;
         }
         if (!first) ++iters;
@@ -556,30 +632,30 @@ PK_DEV void path_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
             if (first) {
                 if (!resume) {
                     itt = meets ? 0 : -1;
-                    done = P.early_exit && itt == 0;
+                    done = Q.early_exit && itt == 0;
                 }
             } else {
-                lam = fmaxf(lam / P.nu_down, P.lambda_min);
+                lam = fmaxf(lam / Q.nu_down, Q.lambda_min);
                 ++accepts;
                 if (meets) {
                     if (itt < 0) itt = iters;
-                    if (P.early_exit) done = true;
+                    if (Q.early_exit) done = true;
                 }
             }
             if (!done && iters < iter_end) {
                 wave_sync();
-                jacobian<DMAX, MMAX>(P, I, lane, lds);
+                jacobian<DMAX, MMAX>(Q, I, lane, lds);
             }
         } else if (!first) {
-            if (lam >= P.lambda_max) {
+            if (lam >= Q.lambda_max) {
                 stalled = true;
                 done = true;
             }
-            lam = fminf(lam * P.nu_up, P.lambda_max);
+            lam = fminf(lam * Q.nu_up, Q.lambda_max);
         }
-        if (!first && iters - 1 < P.trace_iters) {
-            if (I.own) P.trace_q[((int64_t)(iters - 1) * n + I.j) * N + p] = q;
-            if (lane == 0) P.trace_acc[(int64_t)(iters - 1) * N + p] = acc ? 1 : 0;
+        if (!first && iters - 1 < Q.trace_iters) {
+            if (I.own) Q.trace_q[((int64_t)(iters - 1) * n + I.j) * N + p] = q;
+            if (lane == 0) Q.trace_acc[(int64_t)(iters - 1) * N + p] = acc ? 1 : 0;
         }
         first = false;
         if (done || iters >= iter_end) break;
@@ -590,25 +666,29 @@ PK_DEV void path_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
         bool ok;
         {
             wave_sync();   // the blocks are visible
-            float r[DMAX], ge;
+            Row<float, DMAX> r;
+            float ge;
             const float dgu = jtj_rows<DMAX, MMAX, float>(lds, I, lane, max_depth, r, ge) +
-                              (I.own ? dl * dl + P.w_rest * P.w_rest : 0.f);
-            const float g = ge + (I.own ? dl * rl + P.w_rest * rr : 0.f);
+                              (I.own ? dl * dl + Q.w_rest * Q.w_rest : 0.f);
+            const float g = ge + (I.own ? dl * rl + Q.w_rest * rr : 0.f);
             const float dfull = add_copies<DMAX, float>(dgu, I, lane, ncopy);
-            ok = path_solve<DMAX, float>(r, dgu, dfull, g, lam, P.damping_floor, P.pivot_rel, I, lane,
-                                         nstep, sinfo, ncopy, max_depth, (float *)(lds + L::PV), delta);
+            ok = path_solve<DMAX, float>(r, dgu, dfull, g, lam, Q.damping_floor, Q.pivot_rel, I, lane,
+                                         nstep, sinfo, ncopy, copy_depths, max_depth, (float *)(lds + L::PV),
+                                         delta);
         }
         if (!ok) {
             // Re-form the damped system and gradient in FP64 from the FP32
             // Jacobian blocks and residuals, and solve again.
             flags |= PK_FLAG_FP64;
-            double r[DMAX], gd;
+            Row<double, DMAX> r;
+            double gd;
             const double dgd = jtj_rows<DMAX, MMAX, double>(lds, I, lane, max_depth, r, gd) +
-                               (I.own ? (double)dl * dl + (double)P.w_rest * P.w_rest : 0.0);
-            if (I.own) gd += (double)dl * rl + (double)P.w_rest * rr;
+                               (I.own ? (double)dl * dl + (double)Q.w_rest * Q.w_rest : 0.0);
+            if (I.own) gd += (double)dl * rl + (double)Q.w_rest * rr;
             const double dfd = add_copies<DMAX, double>(dgd, I, lane, ncopy);
-            ok = path_solve<DMAX, double>(r, dgd, dfd, gd, lam, P.damping_floor, 0.f, I, lane, nstep,
-                                          sinfo, ncopy, max_depth, (double *)(lds + L::PV), delta);
+            ok = path_solve<DMAX, double>(r, dgd, dfd, gd, lam, Q.damping_floor, 0.f, I, lane, nstep,
+                                          sinfo, ncopy, copy_depths, max_depth, (double *)(lds + L::PV),
+                                          delta);
         }
         qt = q + delta;
         evaluate = ok;   // a failed solve counts as a rejected step
@@ -639,15 +719,26 @@ PK_DEV void path_problem(const RobotC *__restrict__ rb, const SolveParams &P, fl
     }
 }
 
+struct PathKernelArgs {     // the argument list of lm_path_kernel, for the offset of P
+    const RobotC *rb;
+    SolveParams P;
+};
+
+// Four wavefronts per SIMD where the LDS allows it (<= 4 EEs: 9.4 KiB per
+// wavefront), so that a batch of 4 x 256 x 4 problems is resident at once;
+// the compiler then keeps the kernel within 128 VGPRs (its spills land in
+// the per-problem set-up and in the FP64 re-solve, not in the LM loop).
 template <int DMAX, int MMAX>
-__global__ __launch_bounds__(64) void lm_path_kernel(const RobotC *__restrict__ rb, SolveParams P)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MMAX <= 4 ? 4 : 3))) void lm_path_kernel(
+    const RobotC *__restrict__ rb, SolveParams P)
 {
+    KParams *Pk = kernel_params_at(offsetof(PathKernelArgs, P));
     using L = Lds<DMAX, MMAX>;
     __shared__ __attribute__((aligned(16))) float lds[L::FLOATS];
     const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
     int64_t wi = P.queue_head ? wave::pop_item_wave(P.queue_head) : (int64_t)blockIdx.x;
     while (wi < nact) {
-        path_problem<DMAX, MMAX>(rb, P, lds, wi);
+        path_problem<DMAX, MMAX>(rb, Pk, lds, wi);
         if (!P.queue_head) break;
         __syncthreads();
         wi = wave::pop_item_wave(P.queue_head);

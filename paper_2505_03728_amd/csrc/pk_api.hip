@@ -325,6 +325,7 @@ static void build_path_layout(RobotC &R)
             if (lane_of[j][k] >= 0) Pc.copies[own_lane[j]][c++] = (uint8_t)lane_of[j][k];
         if (c == 0) continue;
         ncopy = c > ncopy ? c : ncopy;
+        Pc.copy_depths |= 1u << R.j[j].depth;
         // The other copies take updates only from pivots of their own paths
         // below j; the merge follows the last of them.
         int ms = 0;

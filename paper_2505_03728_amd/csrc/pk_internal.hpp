@@ -55,7 +55,7 @@ struct PathC {
     int32_t ok;                    // the layout applies to this robot
     int32_t lanes;                 // lanes in use
     int32_t ncopy;                 // most copies of one joint, minus one
-    int32_t pad;
+    uint32_t copy_depths;          // bit d: some joint at depth d has more than one copy
     uint8_t joint[64];             // lane -> joint
     int8_t group[64];              // lane -> EE path (-1: the joint is on no EE path)
     uint8_t owner[64];             // lane -> lane of its joint's owner copy
