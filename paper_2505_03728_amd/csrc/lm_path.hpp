@@ -34,9 +34,35 @@ namespace path {
 using wave::bcast_i;
 using wave::PointVal;
 using wave::recip;
-using wave::wave_max;
-using wave::wave_sum;
 using wave::wave_sync;
+
+// Wave-wide reductions on DPP lane moves (no LDS traffic): an inclusive scan
+// within each row of 16 lanes (row shifts by 1, 2, 4, 8), then the row totals
+// carried across rows (row broadcasts of lanes 15 and 31); lane 63 ends with
+// the total, which readlane makes uniform.  Lanes a move does not reach add
+// the identity.
+template <typename Op>
+PK_DEV float dpp_reduce(float v, int identity, Op op)
+{
+    v = op(v, __int_as_float(__builtin_amdgcn_update_dpp(identity, __float_as_int(v), 0x111, 0xf, 0xf, false)));
+    v = op(v, __int_as_float(__builtin_amdgcn_update_dpp(identity, __float_as_int(v), 0x112, 0xf, 0xf, false)));
+    v = op(v, __int_as_float(__builtin_amdgcn_update_dpp(identity, __float_as_int(v), 0x114, 0xf, 0xf, false)));
+    v = op(v, __int_as_float(__builtin_amdgcn_update_dpp(identity, __float_as_int(v), 0x118, 0xf, 0xf, false)));
+    v = op(v, __int_as_float(__builtin_amdgcn_update_dpp(identity, __float_as_int(v), 0x142, 0xa, 0xf, false)));
+    v = op(v, __int_as_float(__builtin_amdgcn_update_dpp(identity, __float_as_int(v), 0x143, 0xc, 0xf, false)));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+PK_DEV float wave_sum(float v)
+{
+    return dpp_reduce(v, 0, [](float a, float b) { return a + b; });
+}
+
+// (of non-negative values)
+PK_DEV float wave_max_nonneg(float v)
+{
+    return dpp_reduce(v, 0, [](float a, float b) { return fmaxf(a, b); });
+}
 
 // The call's parameters in the kernel-argument segment (constant memory).
 // path_problem reads them through this pointer, so that in its long LM loop
@@ -330,7 +356,7 @@ PK_DEV void jacobian(const SolveParams &P, const LaneInfo<DMAX> &I, int lane, fl
 }
 
 // The lane's part of row j of J^T J by ancestor depth, r[d] = EE k's term of
-// A(j, ancestor at depth d) for d < depth j, in precision T from the FP32
+// A(j, ancestor at depth d) for d < depth j (later entries: don't-care), in precision T from the FP32
 // blocks in LDS, and g = EE k's term of (J^T r)_j; returns EE k's term of A_jj.
 template <int DMAX, int MMAX, typename T>
 PK_DEV T jtj_rows(const float *lds, const LaneInfo<DMAX> &I, int lane, int max_depth,
@@ -360,7 +386,8 @@ PK_DEV T jtj_rows(const float *lds, const LaneInfo<DMAX> &I, int lane, int max_d
 #pragma unroll
             for (int u = 0; u < 6; ++u) s += (T)cj[u] * (T)ca[u];
         }
-        r.set(d, d < dep ? s : (T)0);
+        // entries at and past the lane's depth take values no reader uses
+        r.set(d, s);
         diag = d == dep ? s : diag;
         __asm__ volatile("" ::: "memory");   // one ancestor block in flight at a time
     }
@@ -387,7 +414,7 @@ PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float df
     max_depth = fresh_uniform(max_depth);
     const T damp = own ? (T)lam * (dfull > (T)dfloor ? dfull : (T)dfloor) : (T)0;
     T dg = dgu + damp;
-    const float dmax = wave_max(own ? (float)(dfull + damp) : 0.f);
+    const float dmax = wave_max_nonneg(own ? (float)(dfull + damp) : 0.f);
     T thresh = 0;
     if (thresh_rel > 0.f) thresh = (T)thresh_rel * (T)dmax;
     T b = I.j >= 0 ? -g : (T)0;
