@@ -293,7 +293,7 @@ def headline(args, ctx):
                      "traffic": arm_traffic_bytes(wkey) if args.variant != 2 else None,
                      "traffic_source": ARM_TRAFFIC["profile"],
                      "kernel": "lm_lane_kernel<1,7,pose>" if args.variant != 2
-                     else "lm_wave_kernel", "kernel_ms": round(k_ms, 5),
+                     else "lm_path_kernel<8,4>", "kernel_ms": round(k_ms, 5),
                      "algorithmic_flops": flops, "algorithmic_hbm_bytes": hbm,
                      "peak_unpacked_fp32": FP32_VALU_UNPACKED,
                      "frac_of_unpacked": round(achieved / FP32_VALU_UNPACKED, 5),
@@ -521,7 +521,8 @@ def _oracle_rate(groups, weights, options, budget_s):
 
 
 def run_tree(args):
-    """34-DoF tree, 4 pose EEs, 4096 problems, 40 iterations (wave-per-problem kernel)."""
+    """34-DoF tree, 4 pose EEs, 4096 problems, 40 iterations (one problem per wavefront,
+    path-pair layout)."""
     import numpy as np
     import torch
 
@@ -550,7 +551,7 @@ def run_tree(args):
                 fp64_fallback_fraction=float(((out["status"] & 0x100) != 0).float().mean()),
                 roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
                           "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
-                          "kernel": "lm_wave_kernel<16,4>", "kernel_ms": round(ms, 5),
+                          "kernel": "lm_path_kernel<16,4>", "kernel_ms": round(ms, 5),
                           "algorithmic_flops": flops})
     if not args.no_cpu:
         rate, th, done, el = _oracle_rate([{"tree": tree, "q_star": g["q_star"], "seeds": g["seeds"],
@@ -625,7 +626,7 @@ def run_mixed(args):
                           "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
                           "kernel": "lm_mixed_kernel (one persistent launch over all groups)"
                           if tuned["mode"] == pk.SCHED_SINGLE else
-                          "persistent lm_lane / lm_wave kernels (one per group, concurrent)",
+                          "persistent lm_lane / lm_path kernels (one per group, concurrent)",
                           "algorithmic_flops": flops})
     if not args.no_cpu:
         rate, th, done, el = _oracle_rate(
@@ -799,7 +800,7 @@ def run_mobile(args):
                 roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
                           "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
                           "kernel": (f"lm_lane_kernel<1,{ctx.robot_info(rid)['chain_len']},pose+prismatic>"
-                                     if ctx.robot_info(rid)["chains"] == 1 else "lm_wave_kernel<16,4>"),
+                                     if ctx.robot_info(rid)["chains"] == 1 else "lm_path_kernel<16,4>"),
                           "kernel_ms": round(ms, 5), "algorithmic_flops": flops})
     if not args.no_cpu:
         rate, th, done, el = _oracle_rate([{"tree": mob, "q_star": g["q_star"], "seeds": g["seeds"],

@@ -289,7 +289,7 @@ typedef struct {
 int pk_ik_solve_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
                       const pk_lm_options *opt, const pk_sched_options *sched, void *stream);
 /* Times every candidate schedule (both modes x k in {1, 2, 5, 10, 25, all} x
- * wavefronts per CU in {2, 4, 8} x, in single mode, workgroup sizes {64, 128,
+ * wavefronts per CU in {2, 4, 8, 16} x, in single mode, workgroup sizes {64, 128,
  * 256} that fit the LDS x, for each group whose robot the per-lane kernel
  * supports, one or 64 lanes per problem; graph on) on these groups, stores the fastest in the
  * context's table under the batch's key (the groups' robot classes: variables

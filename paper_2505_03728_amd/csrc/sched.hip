@@ -653,7 +653,7 @@ int pk_autotune_mixed(pk_ctx *ctx, int32_t n_groups, const pk_ik_group *groups,
     PK_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
     const int ks[] = {1, 2, 5, 10, 25, 0};
-    const int ws[] = {2, 4, 8};
+    const int ws[] = {2, 4, 8, 16};   // 16: four wavefronts per SIMD (the path-pair tree kernel)
     const int wgs[] = {64, 128, 256};
     // Lanes per problem: both mappings for groups the per-lane kernel
     // supports (all combinations up to 4 such groups, else each one flipped
