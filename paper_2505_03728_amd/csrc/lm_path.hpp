@@ -421,7 +421,7 @@ PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float df
     bool bad = false;
     for (int st = 0; st < nstep; ++st) {
         const unsigned si = (unsigned)bcast_i((int)sinfo, st);
-        const int pdep = (int)(si & 0xffu), mdep = (int)((si >> 8) & 0xffu);
+        const int mdep = (int)((si >> 8) & 0xffu);
         if (mdep > 0) {
             // Merge phase: the owners of the joints merged at this step add
             // their other copies' rows, diagonals and right-hand sides.
@@ -461,17 +461,20 @@ PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float df
         }
         wave_sync();   // the step's pivot rows are visible
         if ((I.upd >> st) & 1ull) {
+            // The whole slot is read at once (one LDS round trip; loads
+            // issued under per-group conditions waited one after another) and
+            // applied to the whole row: entries past the lane's own depth take
+            // values no reader uses.
+            typedef typename Row<T, DMAX>::V4 V4;
             const T *sk = slots + I.grp * SS;
+            V4 sv[DMAX / 4];
+#pragma unroll
+            for (int i = 0; i < DMAX / 4; ++i) sv[i] = *(const V4 *)(sk + 4 * i);
             const T piv = sk[DMAX], bk = sk[DMAX + 1];
             const T sel = sk[dep];
             const T c = sel * recip(piv);
-            // by groups of four up to the step's deepest pivot: the lanes
-            // updated lie above their pivots, so their rows end before it;
-            // entries of a group past the lane's own depth take values no
-            // reader uses
 #pragma unroll
-            for (int i = 0; i < DMAX / 4; ++i)
-                if (4 * i < pdep) r.v[i] -= c * *(const typename Row<T, DMAX>::V4 *)(sk + 4 * i);
+            for (int i = 0; i < DMAX / 4; ++i) r.v[i] -= c * sv[i];
             dg -= c * sel;
             b -= c * bk;
         }
