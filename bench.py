@@ -551,7 +551,7 @@ def run_tree(args):
                 fp64_fallback_fraction=float(((out["status"] & 0x100) != 0).float().mean()),
                 roofline={"bound": "alu", "achieved": round(ach, 4), "peak": FP32_VALU_PEAK,
                           "unit": "TFLOP/s", "frac": round(ach / FP32_VALU_PEAK, 6), "traffic": None,
-                          "kernel": "lm_path_kernel<16,4>", "kernel_ms": round(ms, 5),
+                          "kernel": "lm_path_kernel<16,4,12>", "kernel_ms": round(ms, 5),
                           "algorithmic_flops": flops})
     if not args.no_cpu:
         rate, th, done, el = _oracle_rate([{"tree": tree, "q_star": g["q_star"], "seeds": g["seeds"],

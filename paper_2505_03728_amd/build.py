@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpkmi.so")
 SOURCES = ["pk_api.hip", "pk_debug.hip", "lm_lane.hip", "lm_lane_chain_a.hip", "lm_lane_chain_b.hip",
            "lm_lane_chain_c.hip", "lm_wave.hip", "lm_wave_d8.hip",
-           "lm_wave_d16.hip", "lm_wave_d32.hip", "lm_wave_d64.hip", "lm_path.hip", "seeder.hip",
+           "lm_wave_d16.hip", "lm_wave_d32.hip", "lm_wave_d64.hip", "lm_path.hip", "lm_path_d16.hip", "seeder.hip",
            "pipeline.hip", "sched.hip", "lm_mixed.hip", "beam.hip", "traj.hip"]
 ARCH = "gfx950"
 

@@ -117,11 +117,13 @@ struct Lds {
 };
 
 // A lane's row of the tree-structured normal matrix, by ancestor depth, in
-// groups of four (register tuples the LDS stores can take directly).
-template <typename T, int DMAX>
+// groups of four (register tuples the LDS stores can take directly).  N
+// entries serve trees of up to N + 1 levels (a joint's row has one entry per
+// proper ancestor).
+template <typename T, int N>
 struct Row {
     typedef T V4 __attribute__((ext_vector_type(4)));
-    V4 v[DMAX / 4];
+    V4 v[N / 4];
     PK_DEV T get(int d) const { return v[d >> 2][d & 3]; }
     PK_DEV void set(int d, T x) { v[d >> 2][d & 3] = x; }
 };
@@ -358,9 +360,9 @@ PK_DEV void jacobian(const SolveParams &P, const LaneInfo<DMAX> &I, int lane, fl
 // The lane's part of row j of J^T J by ancestor depth, r[d] = EE k's term of
 // A(j, ancestor at depth d) for d < depth j (later entries: don't-care), in precision T from the FP32
 // blocks in LDS, and g = EE k's term of (J^T r)_j; returns EE k's term of A_jj.
-template <int DMAX, int MMAX, typename T>
+template <int DMAX, int MMAX, typename T, int RW>
 PK_DEV T jtj_rows(const float *lds, const LaneInfo<DMAX> &I, int lane, int max_depth,
-                  Row<T, DMAX> &r, T &g)
+                  Row<T, RW> &r, T &g)
 {
     using L = Lds<DMAX, MMAX>;
     // new values (as in path_solve): the per-depth conditions are formed here
@@ -387,7 +389,7 @@ PK_DEV T jtj_rows(const float *lds, const LaneInfo<DMAX> &I, int lane, int max_d
             for (int u = 0; u < 6; ++u) s += (T)cj[u] * (T)ca[u];
         }
         // entries at and past the lane's depth take values no reader uses
-        r.set(d, s);
+        if (d < RW) r.set(d < RW ? d : 0, s);
         diag = d == dep ? s : diag;
         __asm__ volatile("" ::: "memory");   // one ancestor block in flight at a time
     }
@@ -400,8 +402,8 @@ PK_DEV T jtj_rows(const float *lds, const LaneInfo<DMAX> &I, int lane, int max_d
 // a pivot is not above thresh_rel * max damped diagonal (thresh_rel > 0) or
 // not positive and finite.  sinfo: lane s holds step s's PathC::step_info.
 // slots: LDS, one pivot row (SS values of T) per path.
-template <int DMAX, typename T>
-PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float dfloor, float thresh_rel,
+template <int DMAX, typename T, int RW>
+PK_DEV bool path_solve(Row<T, RW> &r, T dgu, T dfull, T g, float lam, float dfloor, float thresh_rel,
                        const LaneInfo<DMAX> &I, int lane, int nstep, uint32_t sinfo, int ncopy,
                        uint32_t copy_depths, int max_depth, T *slots, float &delta)
 {
@@ -433,7 +435,7 @@ PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float df
                 // (uniform conditions without early exits: an unrolled loop
                 // with breaks makes the compiler copy the whole row per exit)
 #pragma unroll
-                for (int d = 0; d < DMAX; ++d) {
+                for (int d = 0; d < RW; ++d) {
                     if (d + 1 < mdep) {
                         const T o = __shfl(r.get(d), src, 64);
                         if (use) r.set(d, r.get(d) + o);
@@ -454,7 +456,7 @@ PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float df
                 // row; readers use only those below their own, shallower depth.
                 T *sl = slots + I.grp * SS;
 #pragma unroll
-                for (int i = 0; i < DMAX / 4; ++i) *(typename Row<T, DMAX>::V4 *)(sl + 4 * i) = r.v[i];
+                for (int i = 0; i < RW / 4; ++i) *(typename Row<T, RW>::V4 *)(sl + 4 * i) = r.v[i];
                 sl[DMAX] = dg;
                 sl[DMAX + 1] = b;
             }
@@ -465,16 +467,16 @@ PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float df
             // issued under per-group conditions waited one after another) and
             // applied to the whole row: entries past the lane's own depth take
             // values no reader uses.
-            typedef typename Row<T, DMAX>::V4 V4;
+            typedef typename Row<T, RW>::V4 V4;
             const T *sk = slots + I.grp * SS;
-            V4 sv[DMAX / 4];
+            V4 sv[RW / 4];
 #pragma unroll
-            for (int i = 0; i < DMAX / 4; ++i) sv[i] = *(const V4 *)(sk + 4 * i);
+            for (int i = 0; i < RW / 4; ++i) sv[i] = *(const V4 *)(sk + 4 * i);
             const T piv = sk[DMAX], bk = sk[DMAX + 1];
             const T sel = sk[dep];
             const T c = sel * recip(piv);
 #pragma unroll
-            for (int i = 0; i < DMAX / 4; ++i) r.v[i] -= c * sv[i];
+            for (int i = 0; i < RW / 4; ++i) r.v[i] -= c * sv[i];
             dg -= c * sel;
             b -= c * bk;
         }
@@ -493,7 +495,7 @@ PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float df
                 if (dep == D) x = xo;
             }
             const T xa = __shfl(x, wave::anc_lane<DMAX>(I.ancp, D), 64);
-            if (dep > D) s += r.get(D) * xa;
+            if (D < RW && dep > D) s += r.get(D < RW ? D : 0) * xa;
         }
     }
     delta = I.j >= 0 ? (float)x : 0.f;
@@ -502,7 +504,7 @@ PK_DEV bool path_solve(Row<T, DMAX> &r, T dgu, T dfull, T g, float lam, float df
 
 // One LM problem (active index wi) on this wavefront; resumable (state in
 // HBM, at most P.iter_budget iterations per launch when P.st_state is set).
-template <int DMAX, int MMAX>
+template <int DMAX, int MMAX, int RW = DMAX>
 PK_DEV void path_problem(const RobotC *__restrict__ rb, KParams *Pk, float *lds, int64_t wi)
 {
     const SolveParams &P = *(const SolveParams *)Pk;
@@ -696,13 +698,13 @@ PK_DEV void path_problem(const RobotC *__restrict__ rb, KParams *Pk, float *lds,
         bool ok;
         {
             wave_sync();   // the blocks are visible
-            Row<float, DMAX> r;
+            Row<float, RW> r;
             float ge;
-            const float dgu = jtj_rows<DMAX, MMAX, float>(lds, I, lane, max_depth, r, ge) +
+            const float dgu = jtj_rows<DMAX, MMAX, float, RW>(lds, I, lane, max_depth, r, ge) +
                               (I.own ? dl * dl + Q.w_rest * Q.w_rest : 0.f);
             const float g = ge + (I.own ? dl * rl + Q.w_rest * rr : 0.f);
             const float dfull = add_copies<DMAX, float>(dgu, I, lane, ncopy);
-            ok = path_solve<DMAX, float>(r, dgu, dfull, g, lam, Q.damping_floor, Q.pivot_rel, I, lane,
+            ok = path_solve<DMAX, float, RW>(r, dgu, dfull, g, lam, Q.damping_floor, Q.pivot_rel, I, lane,
                                          nstep, sinfo, ncopy, copy_depths, max_depth, (float *)(lds + L::PV),
                                          delta);
         }
@@ -710,13 +712,13 @@ PK_DEV void path_problem(const RobotC *__restrict__ rb, KParams *Pk, float *lds,
             // Re-form the damped system and gradient in FP64 from the FP32
             // Jacobian blocks and residuals, and solve again.
             flags |= PK_FLAG_FP64;
-            Row<double, DMAX> r;
+            Row<double, RW> r;
             double gd;
-            const double dgd = jtj_rows<DMAX, MMAX, double>(lds, I, lane, max_depth, r, gd) +
+            const double dgd = jtj_rows<DMAX, MMAX, double, RW>(lds, I, lane, max_depth, r, gd) +
                                (I.own ? (double)dl * dl + (double)Q.w_rest * Q.w_rest : 0.0);
             if (I.own) gd += (double)dl * rl + (double)Q.w_rest * rr;
             const double dfd = add_copies<DMAX, double>(dgd, I, lane, ncopy);
-            ok = path_solve<DMAX, double>(r, dgd, dfd, gd, lam, Q.damping_floor, 0.f, I, lane, nstep,
+            ok = path_solve<DMAX, double, RW>(r, dgd, dfd, gd, lam, Q.damping_floor, 0.f, I, lane, nstep,
                                           sinfo, ncopy, copy_depths, max_depth, (double *)(lds + L::PV),
                                           delta);
         }
@@ -758,7 +760,7 @@ struct PathKernelArgs {     // the argument list of lm_path_kernel, for the offs
 // wavefront), so that a batch of 4 x 256 x 4 problems is resident at once;
 // the compiler then keeps the kernel within 128 VGPRs (its spills land in
 // the per-problem set-up and in the FP64 re-solve, not in the LM loop).
-template <int DMAX, int MMAX>
+template <int DMAX, int MMAX, int RW>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MMAX <= 4 ? 4 : 3))) void lm_path_kernel(
     const RobotC *__restrict__ rb, SolveParams P)
 {
@@ -768,19 +770,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MMAX <= 4 ? 
     const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
     int64_t wi = P.queue_head ? wave::pop_item_wave(P.queue_head) : (int64_t)blockIdx.x;
     while (wi < nact) {
-        path_problem<DMAX, MMAX>(rb, Pk, lds, wi);
+        path_problem<DMAX, MMAX, RW>(rb, Pk, lds, wi);
         if (!P.queue_head) break;
         __syncthreads();
         wi = wave::pop_item_wave(P.queue_head);
     }
 }
 
-template <int DMAX, int MMAX>
+template <int DMAX, int MMAX, int RW>
 hipError_t launch_path(const RobotC *rb, const SolveParams &P, int persist_blocks, hipStream_t s)
 {
     int64_t grid = P.N;
     if (P.queue_head && persist_blocks > 0 && persist_blocks < grid) grid = persist_blocks;
-    hipLaunchKernelGGL((lm_path_kernel<DMAX, MMAX>), dim3((unsigned)grid), dim3(64), 0, s, rb, P);
+    hipLaunchKernelGGL((lm_path_kernel<DMAX, MMAX, RW>), dim3((unsigned)grid), dim3(64), 0, s, rb, P);
     return hipGetLastError();
 }
 

@@ -160,14 +160,19 @@ def test_hand_early_exit_wave_vs_oracle(ctx):
     check_excused("hand16 early exit", excused, tg.shape[0])
 
 
-def _first_iterates_agree(a, b, tree, tg, seeds, K, w, o, min_same=0.97):
+def _first_iterates_agree(a, b, tree, tg, seeds, K, w, o, min_same=0.97, decidable=None):
     """Two FP32 kernels on the same problems: the accept patterns of the
-    traced iterations agree on at least min_same of the problems, and where
-    they agree the iterates differ by at most twice the FP32 allowance of
-    each (iterate_allowance: 1e-4, or the accumulated forward-error bound
-    where it is larger)."""
+    traced iterations agree on at least min_same of the problems (of those
+    marked in `decidable`, if given: problems whose exact trace has no
+    near-tie, where FP32 rounding cannot flip a decision), and where they
+    agree the iterates differ by at most twice the FP32 allowance of each
+    (iterate_allowance: 1e-4, or the accumulated forward-error bound where it
+    is larger)."""
     same_acc = np.all(a["trace_accept"] == b["trace_accept"], axis=1)
-    assert same_acc.mean() >= min_same, same_acc.mean()
+    sel = np.ones(len(same_acc), bool) if decidable is None else np.asarray(decidable, bool)
+    print(f"  accept patterns differ on problems {np.nonzero(~same_acc)[0].tolist()} "
+          f"(near-tie problems excluded from the count: {np.nonzero(~sel)[0].tolist()})")
+    assert same_acc[sel].mean() >= min_same, same_acc[sel].mean()
     dqi = np.abs(a["trace_q"].astype(np.float64) - b["trace_q"]).max(axis=2)   # [N, iters]
     over = np.nonzero(same_acc & (dqi.max(axis=1) > 1e-4))[0]
     n = dqi.shape[1]
@@ -234,12 +239,15 @@ def test_path_layout_shared_and_orphan_joints(ctx):
     o = dict(synth.workload("tree4k")["options"], max_iters=30)
     a = solve_gpu(ctx, rid, tree, tg, seeds, 1, w, o, trace_iters=5, variant=pk.VARIANT_WAVE)
     b = solve_gpu(ctx, rid, tree, tg, seeds, 1, w, o, trace_iters=5, variant=pk.VARIANT_WAVE_JOINT)
-    _first_iterates_agree(a, b, tree, tg, seeds, 1, w, o)
+    oras = [oracle.lm_solve(tree, tg[p], w, o, seeds[p], n_trace=o["max_iters"]) for p in range(T)]
+    # (near-ties in the exact trace are excluded, as in the oracle comparison below)
+    _first_iterates_agree(a, b, tree, tg, seeds, 1, w, o, min_same=1.0,
+                          decidable=[not ora["trace_tie"][:5].any() for ora in oras])
     assert not np.array_equal(a["trace_q"], b["trace_q"])
     excluded = 0
     bad, excused = [], []
     for p in range(T):
-        ora = oracle.lm_solve(tree, tg[p], w, o, seeds[p], n_trace=o["max_iters"])
+        ora = oras[p]
         if ora["trace_tie"][:5].any():
             excluded += 1
         else:
