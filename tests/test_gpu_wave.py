@@ -265,3 +265,64 @@ def test_path_layout_shared_and_orphan_joints(ctx):
           f"unexplained {bad}")
     assert not bad
     check_excused("branchy8", excused, T)
+
+
+def _hand5():
+    """A palm of two joints carrying five fingers of three joints, a position
+    EE at each fingertip (5 EEs: the path-pair kernel's 8-EE instantiation,
+    with the palm shared by five paths)."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    parent, axes = [-1, 0], ["z", "y"]
+    ee = []
+    for c in range(5):
+        for i in range(3):
+            j = len(parent)
+            parent.append(1 if i == 0 else j - 1)
+            axes.append("zyz"[i])
+        ee.append(len(parent) - 1)
+    n = len(parent)
+    offs = synth._xz_offsets(rng, n, 0.02, 0.06)
+    eeo = synth._xz_offsets(rng, 5, 0.01, 0.03)
+    return synth._finish("hand5", parent, np.tile([1.0, 0, 0, 0], (n, 1)), offs,
+                         [synth._AX[a] for a in axes], np.full(n, 2.0), ee, eeo,
+                         np.tile([1.0, 0, 0, 0], (5, 1)), [synth.EE_POSITION] * 5)
+
+
+def test_path_layout_five_ees(ctx):
+    """Five position EEs (the 8-EE instantiation, three wavefronts per SIMD)
+    against the oracle and against the lane-per-joint layout."""
+    import paper_2505_03728_amd as pk
+    tree = _hand5()
+    rid = ctx.upload(tree)
+    T = 64
+    tg = oracle.targets_from(tree, synth.uniform_configs(tree, T, 5))
+    seeds = synth.uniform_configs(tree, T, 6)
+    # light limit and rest weights: with the usual 10 / 0.01 the oracle solves none of these
+    # (17 joints for 15 position rows, limits of +-2 rad)
+    w = {"w_pos": 1.0, "w_rot": 0.5, "w_limit": 0.1, "w_rest": 0.001, "q_rest": None}
+    o = dict(synth.workload("tree4k")["options"], max_iters=50)
+    a = solve_gpu(ctx, rid, tree, tg, seeds, 1, w, o, trace_iters=5, variant=pk.VARIANT_WAVE)
+    b = solve_gpu(ctx, rid, tree, tg, seeds, 1, w, o, trace_iters=5, variant=pk.VARIANT_WAVE_JOINT)
+    oras = [oracle.lm_solve(tree, tg[p], w, o, seeds[p], n_trace=o["max_iters"]) for p in range(T)]
+    _first_iterates_agree(a, b, tree, tg, seeds, 1, w, o, min_same=1.0,
+                          decidable=[not ora["trace_tie"][:5].any() for ora in oras])
+    bad, excused, excluded = [], [], 0
+    for p in range(T):
+        ora = oras[p]
+        if ora["trace_tie"][:5].any():
+            excluded += 1
+        else:
+            np.testing.assert_array_equal(a["trace_accept"][p], ora["trace_acc"][:5])
+            dq = np.abs(a["trace_q"][p] - ora["trace_q"][:5]).max()
+            assert dq <= 1e-4, (p, dq)
+        v, why = compare_outcome(ctx, rid, tree, tg[p], seeds[p], w, o, a["status"][p],
+                                 a["iters_to_tol"][p], ora, variant=pk.VARIANT_WAVE)
+        if v == "bad":
+            bad.append((p, why))
+        elif v == "excused":
+            excused.append((p, why))
+    conv = ((a["status"] & 0xff) == 0).mean()
+    print(f"hand5: {excluded} excluded (near-ties), success {conv:.3f}, excused {len(excused)}, "
+          f"unexplained {bad}")
+    assert not bad
+    check_excused("hand5", excused, T)
