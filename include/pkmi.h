@@ -365,7 +365,13 @@ int pk_seeder_infer(pk_ctx *ctx, int32_t seeder_id, const float *targets, int64_
  *      final joints (lambda back at lambda0, early exit as `refine`) for
  *      restart_iters iterations, best-of-K again;
  *   4. targets still unsolved are listed on the device and solved again from
- *      fallback_seeds [n][T*fallback_K] with `fallback`;
+ *      fallback_seeds [n][T*fallback_K] with `fallback`: all fallback_K seeds
+ *      at once, or (fallback_chunk = c, 0 < c < fallback_K) in stages of c
+ *      seeds, seeds k*c .. k*c+c-1 of a target run in stage k only if none of
+ *      its earlier stages' problems converged.  Every fallback problem's LM is
+ *      independent of the others, so the stages solve exactly the targets that
+ *      one pass over all fallback_K seeds solves, and each run problem gives
+ *      the same result; a target's pick is the best of the seeds it ran;
  *   5. per target the result of the pass that solved it.
  * Steps 3 and 4 run persistent launches over their lists (wavefronts pop
  * items from a device queue), so their cost follows the listed problems, not
@@ -383,6 +389,8 @@ typedef struct {
     int32_t refine_blocks_per_cu;    /* persistent grid for k > 0: wavefronts per CU (0 = 4) */
     int32_t restart_iters;           /* step 3's iteration budget; 0 = no step 3    */
     int32_t persist_waves_per_cu;    /* grid of steps 3 and 4: wavefronts per CU (0 = 8) */
+    int32_t fallback_chunk;          /* seeds per target per fallback stage (0 or
+                                        >= fallback_K: one stage)                 */
 } pk_seeded_options;
 
 typedef struct {
@@ -395,13 +403,14 @@ typedef struct {
                                         refine.max_iters + the restart's), -1 if none */
     int32_t *refine_iters;           /* [T*K] optional counters of pass 2         */
     int32_t *refine_accepts;         /* [T*K]                                    */
-    int32_t *fallback_iters;         /* [T*fallback_K] optional, 0 if not re-solved */
+    int32_t *fallback_iters;         /* [T*fallback_K] optional, 0 if not run      */
     int32_t *fallback_accepts;       /* [T*fallback_K]                           */
     int32_t *n_fallback;             /* device scalar: targets re-solved          */
     int32_t *restart_iters;          /* [T*K] optional counters of step 3, 0 if not
                                         restarted                                 */
     int32_t *restart_accepts;        /* [T*K]                                    */
     int32_t *n_restart;              /* device scalar: targets restarted          */
+    int32_t *n_fallback_problems;    /* device scalar: fallback problems run      */
 } pk_seeded_outputs;
 
 int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t n_targets, const float *targets,

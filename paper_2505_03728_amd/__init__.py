@@ -81,7 +81,7 @@ class _SeededOptions(C.Structure):
     _fields_ = [("seeder_id", C.c_int32), ("fallback_K", C.c_int32), ("fallback_seeds", C.c_void_p),
                 ("refine", _Options), ("fallback", _Options), ("refine_iters_per_launch", C.c_int32),
                 ("refine_blocks_per_cu", C.c_int32), ("restart_iters", C.c_int32),
-                ("persist_waves_per_cu", C.c_int32)]
+                ("persist_waves_per_cu", C.c_int32), ("fallback_chunk", C.c_int32)]
 
 
 class _SeededOutputs(C.Structure):
@@ -90,7 +90,8 @@ class _SeededOutputs(C.Structure):
                 ("refine_iters", C.c_void_p), ("refine_accepts", C.c_void_p),
                 ("fallback_iters", C.c_void_p), ("fallback_accepts", C.c_void_p),
                 ("n_fallback", C.c_void_p), ("restart_iters", C.c_void_p),
-                ("restart_accepts", C.c_void_p), ("n_restart", C.c_void_p)]
+                ("restart_accepts", C.c_void_p), ("n_restart", C.c_void_p),
+                ("n_fallback_problems", C.c_void_p)]
 
 
 class _BeamSchedule(C.Structure):
@@ -396,12 +397,14 @@ class Context:
     def ik_solve_seeded(self, rid, targets, seeder, weights: Weights, refine: Options,
                         fallback: Options = None, fallback_seeds=None, fallback_K=0,
                         counters=False, refine_iters_per_launch=0, refine_blocks_per_cu=0,
-                        restart_iters=0, persist_waves_per_cu=0):
+                        restart_iters=0, persist_waves_per_cu=0, fallback_chunk=0):
         """Learned seeds + LM, an optional restart of the unsolved targets' problems
-        from their refined joints, fallback to random-seed LM (see include/pkmi.h).
+        from their refined joints, fallback to random-seed LM, all at once or in
+        stages of fallback_chunk seeds (see include/pkmi.h).
 
         Returns a dict of device tensors: best_joints [n, T], target_success,
-        source, iters_to_tol [T], n_fallback, n_restart [1] (and the LM counters)."""
+        source, iters_to_tol [T], n_fallback, n_restart, n_fallback_problems [1]
+        (and the LM counters)."""
         torch = self._torch
         T = targets.shape[1]
         info = self.robot_info(rid)
@@ -413,7 +416,7 @@ class Context:
         i = lambda *s: torch.empty(s, dtype=torch.int32, device=dev)
         out = {"best_joints": torch.empty((info["n"], T), dtype=torch.float32, device=dev),
                "target_success": i(T), "source": i(T), "iters_to_tol": i(T), "n_fallback": i(1),
-               "n_restart": i(1)}
+               "n_restart": i(1), "n_fallback_problems": i(1)}
         if counters:
             out.update(refine_iters=i(T * K), refine_accepts=i(T * K),
                        fallback_iters=i(max(T * fallback_K, 1)),
@@ -422,13 +425,13 @@ class Context:
         fb = fallback or refine
         so = _SeededOptions(seeder.id, int(fallback_K), _ptr(fallback_seeds), refine._c(), fb._c(),
                             int(refine_iters_per_launch), int(refine_blocks_per_cu), int(restart_iters),
-                            int(persist_waves_per_cu))
+                            int(persist_waves_per_cu), int(fallback_chunk))
         oo = _SeededOutputs(*[_ptr(out.get(k)) for k in ["best_joints", "target_success", "source",
                                                           "iters_to_tol", "refine_iters",
                                                           "refine_accepts", "fallback_iters",
                                                           "fallback_accepts", "n_fallback",
                                                           "restart_iters", "restart_accepts",
-                                                          "n_restart"]])
+                                                          "n_restart", "n_fallback_problems"]])
         w = weights._c()
         self._call(lib().pk_ik_solve_seeded(self._h, rid, T, _ptr(targets), C.byref(w), C.byref(so),
                                             C.byref(oo), self.stream()))

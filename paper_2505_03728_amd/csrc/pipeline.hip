@@ -32,12 +32,42 @@ __global__ void fallback_list_kernel(int64_t T, int Kf, const int32_t *__restric
     for (int k = 0; k < Kf; ++k) active[(int64_t)pos * Kf + k] = (int32_t)(t * Kf + k);
 }
 
+// Fallback stage [c0, c1) of every target's Kf random seeds.  Stage 0 lists
+// the targets the earlier passes left unsolved; a later stage lists those
+// that ran the previous stage [cp, c0) and got no converged problem from it.
+// done[t] counts the target's fallback seeds run so far.
+__global__ void fallback_stage_kernel(int64_t T, int Kf, int cp, int c0, int c1,
+                                      const int32_t *__restrict__ success,
+                                      const int32_t *__restrict__ status, int32_t *done,
+                                      int32_t *count_t, int32_t *count_p, int32_t *count_stage,
+                                      int32_t *active)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    if (c0 == 0) {
+        if (success[t]) {
+            done[t] = 0;
+            return;
+        }
+    } else {
+        if (done[t] != c0) return;
+        for (int k = cp; k < c0; ++k)
+            if ((status[t * Kf + k] & 0xff) == PK_CONVERGED) return;
+    }
+    done[t] = c1;
+    const int w = c1 - c0;
+    const int pos = atomicAdd(count_stage, w);
+    if (count_t) atomicAdd(count_t, 1);
+    atomicAdd(count_p, w);
+    for (int k = 0; k < w; ++k) active[pos + k] = (int32_t)(t * Kf + c0 + k);
+}
+
 struct MergeArgs {
     int64_t T;
     int K, Kf, n, refine_its;
     const int32_t *best_a, *succ_a, *succ_r, *itt_a;
     const float *joints_a;
-    const int32_t *status_b, *itt_b;
+    const int32_t *status_b, *itt_b, *done_b;
     const float *cost_b, *pcost_b, *joints_b;
     float *best_joints;
     int32_t *success, *source, *itt;
@@ -62,12 +92,15 @@ __global__ void merge_kernel(MergeArgs a)
         }
         if (restarted) it += a.refine_its;
     } else if (a.Kf > 0) {
+        // the fallback seeds this target ran (every stage up to its first
+        // converged problem)
+        const int kr = a.done_b[t];
         bool any;
-        const int b = best_of_k_pick(a.status_b, a.cost_b, a.pcost_b, t * a.Kf, a.Kf, any);
+        const int b = best_of_k_pick(a.status_b, a.cost_b, a.pcost_b, t * a.Kf, kr, any);
         for (int j = 0; j < a.n; ++j) a.best_joints[(int64_t)j * a.T + t] = a.joints_b[(int64_t)j * NB + t * a.Kf + b];
         if (any) {
             src = 1;
-            for (int k = 0; k < a.Kf; ++k) {
+            for (int k = 0; k < kr; ++k) {
                 const int v = a.itt_b[t * a.Kf + k];
                 if (v >= 0 && (it < 0 || v < it)) it = v;
             }
@@ -101,6 +134,7 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
     if (!targets || !out->best_joints) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: NULL targets/best_joints");
     if (o->fallback_K < 0 || (o->fallback_K > 0 && !o->fallback_seeds))
         return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: fallback seeds missing");
+    if (o->fallback_chunk < 0) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: fallback_chunk < 0");
     hipStream_t s = (hipStream_t)stream;
     PK_HIP(ctx, hipSetDevice(ctx->device));
     SolveParams PA, PB;
@@ -118,6 +152,7 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
     }
     if (srobot != robot_id) return fail(ctx, PK_EINVAL, "pk_ik_solve_seeded: seeder belongs to robot %d", srobot);
     const int n = rb->host.nv, Kf = o->fallback_K;
+    const int Kc = o->fallback_chunk > 0 && o->fallback_chunk < Kf ? o->fallback_chunk : Kf;
     const int64_t NA = T * K, NB = T * Kf;
     if (NA >= (int64_t)1 << 31 || NB >= (int64_t)1 << 31)
         return fail(ctx, PK_EUNSUPPORTED, "pk_ik_solve_seeded: too many problems");
@@ -129,7 +164,7 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
     const int persist = wpc * prop.multiProcessorCount;
     const int64_t NS = std::max(NA, NB);   // resumable-state words of the persistent passes
     // Workspace layout (4-byte words).
-    const size_t words = (size_t)NA * (2 * n + 6) + 3 * T + 16 + (size_t)NB * (n + 6) + 2 * (size_t)NS;
+    const size_t words = (size_t)NA * (2 * n + 6) + 4 * T + 16 + (size_t)NB * (n + 6) + 2 * (size_t)NS;
     if (words * 4 > ctx->ws2_bytes) {
         if (ctx->ws2) (void)hipFree(ctx->ws2);
         ctx->ws2 = nullptr;
@@ -150,7 +185,10 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
     int32_t *succ_a = (int32_t *)f;     f += T;
     int32_t *succ_r = (int32_t *)f;     f += T;
     int32_t *list_r = (int32_t *)f;     f += NA;
-    int32_t *counters = (int32_t *)f;   f += 16;   // [0..1] fallback list, [2..3] restart list, [4] queue head
+    int32_t *done_b = (int32_t *)f;     f += T;
+    // [0..1] fallback targets and problems, [2..3] restart list, [4] queue
+    // head, [5] problems of the current fallback stage
+    int32_t *counters = (int32_t *)f;   f += 16;
     float *st_lambda = f;               f += NS;
     int32_t *st_state = (int32_t *)f;   f += NS;
     float *joints_b = f;                f += (size_t)NB * n;
@@ -227,25 +265,29 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
             hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(NB, 256)), dim3(256), 0, s, NB, 0, out->fallback_iters);
         if (out->fallback_accepts)
             hipLaunchKernelGGL(fill_i32_kernel, dim3(nblk(NB, 256)), dim3(256), 0, s, NB, 0, out->fallback_accepts);
-        hipLaunchKernelGGL(fallback_list_kernel, dim3(nblk(T, 256)), dim3(256), 0, s, T, Kf, succ_now,
-                           counters, counters + 1, active);
-        hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, (int64_t)1, 0, counters + 4);
-        PK_HIP(ctx, hipGetLastError());
         PB.K = Kf; PB.N = NB; PB.T = T;
         PB.targets = targets; PB.seeds = o->fallback_seeds;
         PB.joints = joints_b; PB.cost = cost_b; PB.pose_cost = pcost_b; PB.status = status_b;
         PB.iters = out->fallback_iters; PB.accepts = out->fallback_accepts; PB.iters_to_tol = itt_b;
-        PB.active = active; PB.n_active = counters + 1;
+        PB.active = active; PB.n_active = counters + 5;
         PB.st_lambda = st_lambda; PB.st_state = st_state;
         PB.resume = 0; PB.iter_budget = PB.max_iters;
         PB.queue_head = counters + 4;
-        PK_HIP(ctx, launch_lm(*rb, PB, vb, s, persist));
+        for (int cp = 0, c0 = 0; c0 < Kf; cp = c0, c0 += Kc) {
+            const int c1 = std::min(Kf, c0 + Kc);
+            hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, (int64_t)2, 0, counters + 4);
+            hipLaunchKernelGGL(fallback_stage_kernel, dim3(nblk(T, 256)), dim3(256), 0, s, T, Kf, cp, c0,
+                               c1, succ_now, status_b, done_b, c0 == 0 ? counters : nullptr, counters + 1,
+                               counters + 5, active);
+            PK_HIP(ctx, hipGetLastError());
+            PK_HIP(ctx, launch_lm(*rb, PB, vb, s, persist));
+        }
     }
     MergeArgs m;
     m.T = T; m.K = K; m.Kf = Kf; m.n = n; m.refine_its = o->refine.max_iters;
     m.best_a = best_a; m.succ_a = succ_a; m.succ_r = R > 0 ? succ_r : nullptr; m.itt_a = itt_a;
     m.joints_a = joints_a;
-    m.status_b = status_b; m.itt_b = itt_b; m.cost_b = cost_b; m.pcost_b = pcost_b; m.joints_b = joints_b;
+    m.status_b = status_b; m.itt_b = itt_b; m.done_b = done_b; m.cost_b = cost_b; m.pcost_b = pcost_b; m.joints_b = joints_b;
     m.best_joints = out->best_joints; m.success = out->target_success; m.source = out->source;
     m.itt = out->iters_to_tol;
     hipLaunchKernelGGL(merge_kernel, dim3(nblk(T, 256)), dim3(256), 0, s, m);
@@ -254,5 +296,7 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
         PK_HIP(ctx, hipMemcpyAsync(out->n_fallback, counters, 4, hipMemcpyDeviceToDevice, s));
     if (out->n_restart)
         PK_HIP(ctx, hipMemcpyAsync(out->n_restart, counters + 2, 4, hipMemcpyDeviceToDevice, s));
+    if (out->n_fallback_problems)
+        PK_HIP(ctx, hipMemcpyAsync(out->n_fallback_problems, counters + 1, 4, hipMemcpyDeviceToDevice, s));
     return PK_OK;
 }

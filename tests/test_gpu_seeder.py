@@ -326,6 +326,39 @@ def test_seeded_pipeline_and_gain_over_random_seeds(ctx, arm, trained):
     for t in np.nonzero(s_both)[0][:200]:
         _, pe, re = oracle.residual(tree, tg[t], wl["weights"], bj[t])
         assert pe[0] <= 1e-3 * 1.05 and re[0] <= 1e-2 * 1.05
+    # the fallback in stages of c seeds: the same targets solved, every run
+    # problem's counters as in the single stage, a stage prefix of each
+    # fallback target's seeds run, and a target stops short of all 8 seeds
+    # only once a stage has solved it
+    fi_all = fi
+    nfp = int(both["n_fallback_problems"].item())
+    assert nfp == 8 * nfb
+    for c in (2, 3):
+        st = ctx.ik_solve_seeded(arm, targets, sd, w, ref, fallback=fb, fallback_seeds=rseeds,
+                                 fallback_K=8, counters=True, fallback_chunk=c)
+        torch.cuda.synchronize()
+        for key in ["target_success", "source", "n_fallback", "refine_iters"]:
+            np.testing.assert_array_equal(st[key].cpu().numpy(), both[key].cpu().numpy(),
+                                          err_msg=f"chunk {c} {key}")
+        fi_c = st["fallback_iters"].cpu().numpy().reshape(T, 8)
+        kr = (fi_c > 0).sum(axis=1)
+        ends = set(range(c, 8, c)) | {8}
+        s_c = st["target_success"].cpu().numpy().astype(bool)
+        for t in np.nonzero(~s_learn)[0]:
+            assert kr[t] in ends, (c, t, kr[t])
+            np.testing.assert_array_equal(fi_c[t, :kr[t]], fi_all[t, :kr[t]])
+            assert kr[t] == 8 or s_c[t], (c, t)
+        assert np.all(kr[s_learn] == 0)
+        assert int(st["n_fallback_problems"].item()) == int(kr.sum())
+        itt_c = st["iters_to_tol"].cpu().numpy()
+        itt_b = both["iters_to_tol"].cpu().numpy()
+        fb_ok = src == 1
+        assert np.all(itt_c[fb_ok] >= itt_b[fb_ok])
+        bj_c = st["best_joints"].cpu().numpy().T.astype(np.float64)
+        for t in np.nonzero(fb_ok)[0][:100]:
+            _, pe, re = oracle.residual(tree, tg[t], wl["weights"], bj_c[t])
+            assert pe[0] <= 1e-3 * 1.05 and re[0] <= 1e-2 * 1.05
+        print(f"fallback in stages of {c}: {int(kr.sum())} of {nfp} fallback problems run")
     # a restart pass between the refinement and the fallback: only targets the
     # refinement did not solve are restarted (their K problems, from the
     # refined joints), a restart success keeps the fallback off that target,
