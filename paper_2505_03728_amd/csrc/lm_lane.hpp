@@ -165,7 +165,21 @@ PK_DEV void jac_column(const SolveParams &P, const float *M, const float *Nb, co
                        const float *pj, const float *pe, bool pris, float *col)
 {
     float v[3], wv[3];
-    joint_twist(pris_of(KIND) && pris, w, pj, pe, v, wv);
+    if constexpr (pris_of(KIND)) {
+        // the joint type as a 0/1 factor (a uniform condition per column
+        // used in selects had doubled the kernel's register allocation)
+        const float rv = pris ? 0.f : 1.f, pv = 1.f - rv;
+        const float lev[3] = {pe[0] - pj[0], pe[1] - pj[1], pe[2] - pj[2]};
+        float vr[3];
+        cross(w, lev, vr);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            v[u] = rv * vr[u] + pv * w[u];
+            wv[u] = rv * w[u];
+        }
+    } else {
+        joint_twist(false, w, pj, pe, v, wv);
+    }
     if constexpr (ee_of(KIND) == PK_EE_POSE) {
 #pragma unroll
         for (int u = 0; u < 3; ++u) {

@@ -427,22 +427,22 @@ PK_DEV bool path_solve(Row<T, RW> &r, T dgu, T dfull, T g, float lam, float dflo
         if (mdep > 0) {
             // Merge phase: the owners of the joints merged at this step add
             // their other copies' rows, diagonals and right-hand sides.
+            // Every entry of a copy's row is exchanged, those at and past
+            // the owner's depth too (they stay don't-care), so that all of a
+            // copy's exchanges are in flight together rather than one per
+            // merged depth.
             const bool mg = I.mstep == st;
             for (int c = 0; c < ncopy; ++c) {
                 const int cl = copy_lane(I, c);
                 const int src = cl == PK_PATH_NONE ? lane : cl;
                 const bool use = mg && cl != PK_PATH_NONE;
-                // (uniform conditions without early exits: an unrolled loop
-                // with breaks makes the compiler copy the whole row per exit)
+                Row<T, RW> o;
 #pragma unroll
-                for (int d = 0; d < RW; ++d) {
-                    if (d + 1 < mdep) {
-                        const T o = __shfl(r.get(d), src, 64);
-                        if (use) r.set(d, r.get(d) + o);
-                    }
-                }
+                for (int d = 0; d < RW; ++d) o.set(d, __shfl(r.get(d), src, 64));
                 const T od = __shfl(dg, src, 64), ob = __shfl(b, src, 64);
                 if (use) {
+#pragma unroll
+                    for (int i = 0; i < RW / 4; ++i) r.v[i] += o.v[i];
                     dg += od;
                     b += ob;
                 }
@@ -483,21 +483,23 @@ PK_DEV bool path_solve(Row<T, RW> &r, T dgu, T dfull, T g, float lam, float dflo
     }
     if (__any(bad)) return false;
     // Back substitution, root first: x_j = (b_j - sum_d r_j[d] x_anc(d)) /
-    // pivot_j on the owner, then copied to the joint's other copies.
+    // pivot_j on the owner.  At depths with shared joints a lane reads its
+    // ancestor's x from that joint's owner (whose lane it looks up off the
+    // dependent chain); the copies take their owner's x at the end.
     const T ipj = own ? recip(dg) : (T)0;
     T s = 0, x = 0;
 #pragma unroll
     for (int D = 0; D < DMAX; ++D) {
         if (D <= max_depth) {
             if (own && dep == D) x = (b - s) * ipj;
-            if ((copy_depths >> D) & 1) {   // uniform: some joint at depth D has copies
-                const T xo = __shfl(x, I.owner, 64);
-                if (dep == D) x = xo;
-            }
-            const T xa = __shfl(x, wave::anc_lane<DMAX>(I.ancp, D), 64);
+            int al = wave::anc_lane<DMAX>(I.ancp, D);
+            if ((copy_depths >> D) & 1)   // uniform: some joint at depth D has copies
+                al = __shfl(I.owner, al, 64);
+            const T xa = __shfl(x, al, 64);
             if (D < RW && dep > D) s += r.get(D < RW ? D : 0) * xa;
         }
     }
+    if (copy_depths) x = __shfl(x, I.owner, 64);
     delta = I.j >= 0 ? (float)x : 0.f;
     return true;
 }
