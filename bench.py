@@ -364,6 +364,21 @@ def learned_vs_random(args, ctx, epochs=None):
                                          fallback_seeds=rseeds_all, fallback_K=FALLBACK_K, counters=True,
                                          restart_iters=RESTART_ITERS)
     ts_learn = _replay_times(learned, args.steps, args.warmup)
+    # both forms again with target_exit: a problem also ends once another
+    # problem of its target in its run of lanes met the tolerance (per-target
+    # success and first iteration at the tolerance unchanged)
+    plain_te_o = pk.Options.from_dict(wl["options"], early_exit=True, target_exit=True)
+    ref_te_o = pk.Options.from_dict(wl["options"], max_iters=10, early_exit=True, target_exit=True)
+    plain_te = ctx.alloc_outputs(rid, T, K, best=True)
+    ts_plain_te = _replay_times(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, plain_te_o, plain_te),
+                                args.steps, args.warmup)
+    res_t = {}
+
+    def learned_te():
+        res_t["o"] = ctx.ik_solve_seeded(rid, targets, sd, w, ref_te_o, fallback=plain_te_o,
+                                         fallback_seeds=rseeds_all, fallback_K=FALLBACK_K, counters=True,
+                                         restart_iters=RESTART_ITERS)
+    ts_learn_te = _replay_times(learned_te, args.steps, args.warmup)
     seeds_buf = torch.empty((7, T * K), device="cuda")
     ts_infer = _replay_times(lambda: sd.infer(targets, seeds_buf), args.steps, args.warmup)
     torch.cuda.synchronize()
@@ -396,6 +411,14 @@ def learned_vs_random(args, ctx, epochs=None):
     fl_mlp = 2.0 * T * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
     v_learn = s_learn / (ms_learn / 1e3)
     v_plain = s_plain / (ms_plain / 1e3)
+    ms_learn_te, ms_plain_te = _stats(ts_learn_te)["median"], _stats(ts_plain_te)["median"]
+    lt = res_t["o"]
+    s_learn_te = int(lt["target_success"].sum())
+    s_plain_te = int(plain_te["target_success"].sum())
+    v_learn_te = s_learn_te / (ms_learn_te / 1e3)
+    v_plain_te = s_plain_te / (ms_plain_te / 1e3)
+    its_te = int(lt["refine_iters"].sum() + lt["restart_iters"].sum() + lt["fallback_iters"].sum())
+    its_pp = int(lo["refine_iters"].sum() + lo["restart_iters"].sum() + lo["fallback_iters"].sum())
     ok_l = itt_l >= 0
     tfl = lambda f, ms: f / (ms / 1e3) / 1e12
     return {
@@ -430,6 +453,16 @@ def learned_vs_random(args, ctx, epochs=None):
                                     "iters_to_tol_mean": itt_b_mean, "iters_to_tol_median": itt_b_med,
                                     "frac_fp32": round(tfl(fl_big, ms_big) / FP32_VALU_PEAK, 6)},
         "speedup_learned_vs_plain": round(v_learn / v_plain, 3),
+        "target_exit": {"rule": "both forms with target_exit: a problem also ends in the pass in which "
+                                "another problem of its target in its run of lanes met the tolerance",
+                        "learned": {"solves_per_s": round(v_learn_te, 1), "success_rate": s_learn_te / T,
+                                    "ms": round(ms_learn_te, 5), "lm_iterations": its_te,
+                                    "lm_iterations_without": its_pp},
+                        "plain_random": {"solves_per_s": round(v_plain_te, 1), "success_rate": s_plain_te / T,
+                                         "ms": round(ms_plain_te, 5),
+                                         "lm_iterations": int(plain_te["iters"].sum()),
+                                         "lm_iterations_without": int(plain["iters"].sum())}},
+        "speedup_learned_vs_plain_target_exit": round(v_learn_te / v_plain_te, 3),
         "speedup_learned_vs_plain_many_seeds": round(v_learn / (s_big / (ms_big / 1e3)), 3),
         "seeder_training": {"samples": S, "epochs": E, "batch": mc["batch"], "steps": steps_tr,
                             "seconds": round(train_s, 3), "loss_first": float(log[0]),

@@ -46,6 +46,8 @@ typedef struct pk_ctx pk_ctx;
 #define PK_MAX_ITERS 1        /* iteration budget spent, not within tolerance */
 #define PK_STALLED 2          /* a step was rejected with lambda at lambda_max */
 #define PK_NONFINITE 3        /* NaN/Inf in the seed or target: left untouched */
+#define PK_TARGET_SOLVED 4    /* ended by target_exit: another problem of its
+                                 target met the tolerance in the same pass    */
 #define PK_FLAG_FP64 0x100    /* some Cholesky pivot fell below pivot_rel times
                                  the largest diagonal and the step was re-solved
                                  in FP64                                      */
@@ -131,7 +133,18 @@ typedef struct {
  * at lambda_max ends the problem as PK_STALLED).  Every trial counts as one
  * iteration.  With early_exit, a problem stops as soon as every EE is within
  * tol_pos (metres) and, for pose EEs, tol_rot (radians); the test is
- * inclusive and runs at the seed and after every accepted step. */
+ * inclusive and runs at the seed and after every accepted step.
+ * target_exit (with early_exit): a problem also ends, as PK_TARGET_SOLVED, in
+ * the pass in which another problem of its target meets the tolerance, when
+ * the two run side by side: in one run of consecutive lanes of the per-lane
+ * kernel's wavefront (K consecutive problems of a target share a wavefront
+ * when K divides 64, and each 64-problem block of a target when 64 divides
+ * K).  A target's success and first iteration at tolerance are those of the
+ * run without it; its best-of-K pick is among the problems that met the
+ * tolerance by then.  Honoured by pk_ik_solve (and its allocation-free form)
+ * and by pk_ik_solve_seeded's single-launch passes; the per-wavefront kernels
+ * (one problem per wavefront), resumed problems, pk_ik_solve_mixed and
+ * pk_ik_beam ignore it. */
 typedef struct {
     int32_t max_iters;
     float lambda0, nu_up, nu_down, lambda_min, lambda_max;
@@ -140,6 +153,7 @@ typedef struct {
     float damping_floor;         /* e.g. 1e-6                                 */
     float pivot_rel;             /* FP64 re-solve below this pivot ratio (1e-6) */
     int32_t variant;             /* PK_VARIANT_*                              */
+    int32_t target_exit;         /* 0/1, see above                            */
 } pk_lm_options;
 
 /* A batch: T targets, K seeds each, N = T*K problems; problem p uses target

@@ -20,7 +20,7 @@ __all__ = ["Context", "Seeder", "Weights", "Options", "lib", "LibraryMissing", "
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpkmi.so")
 
-CONVERGED, MAX_ITERS, STALLED, NONFINITE = 0, 1, 2, 3
+CONVERGED, MAX_ITERS, STALLED, NONFINITE, TARGET_SOLVED = 0, 1, 2, 3, 4
 JOINT_REVOLUTE, JOINT_PRISMATIC, JOINT_FIXED = 0, 1, 2
 FLAG_FP64 = 0x100
 NOALLOC_MAX_PROBLEMS = 1 << 20      # problems per pk_ik_solve_noalloc call (include/pkmi.h)
@@ -60,7 +60,8 @@ class _Options(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("lambda0", C.c_float), ("nu_up", C.c_float),
                 ("nu_down", C.c_float), ("lambda_min", C.c_float), ("lambda_max", C.c_float),
                 ("early_exit", C.c_int32), ("tol_pos", C.c_float), ("tol_rot", C.c_float),
-                ("damping_floor", C.c_float), ("pivot_rel", C.c_float), ("variant", C.c_int32)]
+                ("damping_floor", C.c_float), ("pivot_rel", C.c_float), ("variant", C.c_int32),
+                ("target_exit", C.c_int32)]
 
 
 class _Problem(C.Structure):
@@ -230,7 +231,7 @@ class Weights:
 class Options:
     def __init__(self, max_iters=30, lambda0=1e-3, nu_up=10.0, nu_down=10.0, lambda_min=1e-10,
                  lambda_max=1e10, early_exit=False, tol_pos=1e-3, tol_rot=1e-2,
-                 damping_floor=1e-6, pivot_rel=1e-6, variant=VARIANT_AUTO):
+                 damping_floor=1e-6, pivot_rel=1e-6, variant=VARIANT_AUTO, target_exit=False):
         self.__dict__.update(locals())
         del self.__dict__["self"]
 
@@ -246,7 +247,7 @@ class Options:
         return _Options(int(self.max_iters), self.lambda0, self.nu_up, self.nu_down,
                         self.lambda_min, self.lambda_max, int(bool(self.early_exit)),
                         self.tol_pos, self.tol_rot, self.damping_floor, self.pivot_rel,
-                        int(self.variant))
+                        int(self.variant), int(bool(self.target_exit)))
 
 
 def target_floats(ee_kind) -> int:

@@ -134,6 +134,7 @@ extern "C" int pk_ik_beam(pk_ctx *ctx, int32_t robot_id, int64_t T, const float 
     pk_lm_options o0 = *opt, o1 = *opt;
     o0.max_iters = sch->iters0;
     o1.max_iters = sch->iters1;
+    o0.target_exit = o1.target_exit = 0;   // the beam ranks every seed's cost
     SolveParams P0, P1;
     int v0 = 0, v1 = 0;
     int rc = prepare_solve(ctx, *rb, w, &o0, P0, v0);

@@ -461,6 +461,24 @@ PK_DEV bool step_fp64_1(const RobotC *__restrict__ rb, const SolveParams &P, con
     return ok;
 }
 
+// Lanes of this wavefront that hold problems of target t in one run of
+// consecutive lanes with this one (bit mask).  Called by every lane that
+// holds a problem.
+PK_DEV uint64_t target_run_mask(int64_t t)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t act = __ballot(1);
+    const int64_t tp = __shfl(t, (lane + 63) & 63, 64);
+    const bool start = lane == 0 || !((act >> (lane - 1)) & 1) || tp != t;
+    const uint64_t R = __ballot(start);
+    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1);   // bits 0..lane
+    const int s = 63 - __builtin_clzll(R & upto);                      // this run's first lane
+    const uint64_t after = R & ~upto;
+    const uint64_t from_s = ~0ull << s;
+    const uint64_t mask = after ? from_s & ((1ull << __builtin_ctzll(after)) - 1) : from_s;
+    return mask & act;
+}
+
 template <int C, int L, int KIND>
 PK_DEV bool meets_tol(const SolveParams &P, const float *perr, const float *rerr)
 {
@@ -596,7 +614,7 @@ PK_DEV bool lane_step(const RobotC *__restrict__ rb, const SolveParams &P, const
 template <int C, int L, int KIND>
 PK_DEV void write_result(const SolveParams &P, int64_t p, const float *q, float cost, float pcost,
                          const float *perr, const float *rerr, int iters, int accepts, int itt,
-                         int flags, bool stalled, bool finished)
+                         int flags, bool stalled, bool finished, bool tsolved = false)
 {
     using St = Star<C, L, KIND>;
     const int64_t N = P.N;
@@ -615,7 +633,8 @@ PK_DEV void write_result(const SolveParams &P, int64_t p, const float *q, float 
     if (P.iters) P.iters[p] = iters;
     if (P.accepts) P.accepts[p] = accepts;
     if (P.status)
-        P.status[p] = (conv ? PK_CONVERGED : (stalled ? PK_STALLED : PK_MAX_ITERS)) | flags;
+        P.status[p] = (conv ? PK_CONVERGED
+                            : tsolved ? PK_TARGET_SOLVED : (stalled ? PK_STALLED : PK_MAX_ITERS)) | flags;
     if (P.iters_to_tol) P.iters_to_tol[p] = itt;
 }
 
@@ -639,8 +658,13 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
         return;
     }
     int iters = 0, accepts = 0, itt = -1, flags = 0;
-    bool done = false, stalled = false;
+    bool done = false, stalled = false, tsolved = false;
     float lam = P.lambda0;
+    // target_exit: the problem also ends in the pass in which a problem of
+    // its target in the same run of lanes meets the tolerance (problems
+    // started from their seeds in this launch only)
+    const bool texit = P.target_exit && !resume;
+    const uint64_t trun = texit ? target_run_mask(p / P.K) : 0;
     if (resume) {
         const int st = P.st_state[p];
         iters = P.iters[p];
@@ -680,6 +704,7 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
 #pragma unroll
             for (int j = 0; j < St::N; ++j) qt[j] = q[j] + delta[j];
         }
+        bool met = false;   // the point taken in this pass meets the tolerance
         float ct = INFINITY, pct = 0.f, pe_t[C], re_t[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) pe_t[c] = re_t[c] = 0.f;
@@ -701,6 +726,7 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
                 itt = meets_tol<C, L, KIND>(P, perr, rerr) ? 0 : -1;
                 done = P.early_exit && itt == 0;
             }
+            met = itt == 0;
             first = false;
         } else {
             ++iters;
@@ -721,6 +747,7 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
                 if (meets_tol<C, L, KIND>(P, perr, rerr)) {
                     if (itt < 0) itt = iters;
                     if (P.early_exit) done = true;
+                    met = true;
                 }
             } else {
                 if (lam >= P.lambda_max) {
@@ -731,10 +758,18 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
             }
             write_trace<C, L, KIND>(P, iters - 1, p, q, acc);
         }
+        if (texit) {   // uniform: every lane of the pass takes part
+            const uint64_t others = __ballot(met) & trun & ~(1ull << (threadIdx.x & 63));
+            if (!done && others) {
+                done = true;
+                tsolved = true;
+            }
+        }
         if (done || iters >= iter_end) break;
     }
     const bool finished = done || iters >= P.max_iters;
-    write_result<C, L, KIND>(P, p, q, cost, pcost, perr, rerr, iters, accepts, itt, flags, stalled, finished);
+    write_result<C, L, KIND>(P, p, q, cost, pcost, perr, rerr, iters, accepts, itt, flags, stalled, finished,
+                             tsolved);
     if (resumable) {
         P.st_lambda[p] = lam;
         P.st_state[p] = flags | (stalled ? PK_ST_STALLED : 0) | (finished ? PK_ST_DONE : 0);

@@ -161,6 +161,7 @@ int pk::prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *
     P.tol_pos = o->tol_pos; P.tol_rot = o->tol_rot;
     P.damping_floor = o->damping_floor; P.pivot_rel = o->pivot_rel;
     P.max_iters = o->max_iters; P.early_exit = o->early_exit ? 1 : 0;
+    P.target_exit = o->early_exit && o->target_exit ? 1 : 0;
     return PK_OK;
 }
 

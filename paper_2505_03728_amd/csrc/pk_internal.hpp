@@ -122,6 +122,9 @@ struct SolveParams {
     int32_t *st_state;
     int32_t resume;
     int32_t iter_budget;
+    // Per-lane kernel: a problem started from its seed also ends once a
+    // problem of its target in its run of consecutive lanes met the tolerance.
+    int32_t target_exit;
     // Persistent launch: blocks pop work items (64 problems for the per-lane
     // kernel, 1 for the wave kernel) from *queue_head until none are left.
     int32_t *queue_head;

@@ -199,6 +199,7 @@ int build_plans(pk_ctx *ctx, SchedCache &C, int n_groups, const pk_ik_group *gro
         pl.rb = rb;
         pl.out = gr.out;
         pk_lm_options og = *opt;
+        og.target_exit = 0;   // resumed, compacted problems: not honoured here
         if (sch.variant[g] != PK_VARIANT_AUTO) og.variant = sch.variant[g];
         int rc = prepare_solve(ctx, *rb, &gr.weights, &og, pl.P, pl.variant);
         if (rc) return rc;
