@@ -11,7 +11,7 @@ value = successful targets (1 mm / 0.01 rad) per second of that time.
 
 The same line carries the learned-seed comparison: the seeder MLP
 (7-512-512-512-56, BF16 matrix cores) trained here on 2M (FK(q), q) pairs,
-then learned seeds + <= 10 LM iterations + random-seed fallback against plain
+then learned seeds + <= 6 LM iterations + restart + random-seed fallback against plain
 LM from 8 random seeds, on 131072 fresh targets (success, solves/s,
 iterations to tolerance, FP32 roofline fraction of each form).
 
@@ -302,8 +302,11 @@ def headline(args, ctx):
     return res, tree, wl, T, K
 
 
-# Learned form's later passes: restart budget, and random seeds per target for
-# the fallback (also the plain form's seed count for its >= 99% comparison).
+# Learned form's passes: LM iterations from the learned seeds, the restart
+# budget, and random seeds per target for the fallback (also the plain form's
+# seed count for its >= 99% comparison).  Six refinement iterations leave more
+# targets to the restart than ten but cost less overall (same success).
+REFINE_ITERS = 6
 RESTART_ITERS = 20
 FALLBACK_K = 128
 
@@ -347,7 +350,7 @@ def learned_vs_random(args, ctx, epochs=None):
     rseeds = rseeds_all[:, :T * K].contiguous()
     w = pk.Weights.from_dict(wl["weights"])
     plain_o = pk.Options.from_dict(wl["options"], early_exit=True)          # <= 30 iterations
-    ref_o = pk.Options.from_dict(wl["options"], max_iters=10, early_exit=True)
+    ref_o = pk.Options.from_dict(wl["options"], max_iters=REFINE_ITERS, early_exit=True)
     plain = ctx.alloc_outputs(rid, T, K, best=True)
     ts_plain = _replay_times(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, plain_o, plain),
                              args.steps, args.warmup)
@@ -368,7 +371,8 @@ def learned_vs_random(args, ctx, epochs=None):
     # problem of its target in its run of lanes met the tolerance (per-target
     # success and first iteration at the tolerance unchanged)
     plain_te_o = pk.Options.from_dict(wl["options"], early_exit=True, target_exit=True)
-    ref_te_o = pk.Options.from_dict(wl["options"], max_iters=10, early_exit=True, target_exit=True)
+    ref_te_o = pk.Options.from_dict(wl["options"], max_iters=REFINE_ITERS, early_exit=True,
+                                    target_exit=True)
     plain_te = ctx.alloc_outputs(rid, T, K, best=True)
     ts_plain_te = _replay_times(lambda: ctx.ik_solve(rid, targets, rseeds, K, w, plain_te_o, plain_te),
                                 args.steps, args.warmup)
@@ -436,7 +440,7 @@ def learned_vs_random(args, ctx, epochs=None):
                     "frac_fp32": round(tfl(fl_lm, ms_learn) / FP32_VALU_PEAK, 6),
                     "inference_ms": round(ms_infer, 5),
                     "inference_frac_bf16": round(tfl(fl_mlp, ms_infer) / BF16_MFMA_PEAK, 5),
-                    "schedule": f"seeder ({K} seeds) -> <= 10 LM iterations (early exit) -> unsolved "
+                    "schedule": f"seeder ({K} seeds) -> <= {REFINE_ITERS} LM iterations (early exit) -> unsolved "
                                 f"targets: LM restarted from the refined joints, <= {RESTART_ITERS} "
                                 f"iterations -> still unsolved: {FALLBACK_K} random seeds x <= 30 "
                                 f"iterations"},
@@ -671,7 +675,7 @@ def run_mixed(args):
 
 
 def run_seeder(args):
-    """Learned seeder (trained here) + <= 10 LM iterations with fallback, against
+    """Learned seeder (trained here) + <= 6 LM iterations, restart and fallback, against
     8 random seeds x 30 iterations, on 131072 fresh targets of the 7-DoF arm."""
     import paper_2505_03728_amd as pk
     import synth
@@ -681,9 +685,9 @@ def run_seeder(args):
     L, P = lv["learned"], lv["plain_random"]
     res = _line("IK solves/sec at 1mm/0.01rad success", L["solves_per_s"], "solves/s", args, L["ms"],
                 {"workload": f"7-DoF arm, {lv['targets']} fresh targets: learned seeder (MLP "
-                             f"7-512-512-512-56, K={lv['seeds_per_target']}, BF16 MFMA) + <=10 LM "
-                             f"iterations (early exit) + fallback to random seeds, vs plain random "
-                             f"seeds", "targets": lv["targets"], "seeds_per_target": lv["seeds_per_target"],
+                             f"7-512-512-512-56, K={lv['seeds_per_target']}, BF16 MFMA) + <={REFINE_ITERS} LM "
+                             f"iterations (early exit) + restart + fallback to random seeds, vs plain "
+                             f"random seeds", "targets": lv["targets"], "seeds_per_target": lv["seeds_per_target"],
                  "epochs": lv["seeder_training"]["epochs"]},
                 success_rate=L["success_rate"], learned_vs_random=lv,
                 roofline={"bound": "mfma", "achieved": round(lv["mlp_flops"] / (L["inference_ms"] / 1e3) / 1e12, 3),

@@ -643,7 +643,7 @@ PK_DEV void write_result(const SolveParams &P, int64_t p, const float *q, float 
 // stops after P.iter_budget iterations.  Each pass of the loop evaluates one
 // point (first the starting point, then each trial), so the cost evaluation
 // has a single call site.
-template <int C, int L, int KIND, bool RESUMABLE>
+template <int C, int L, int KIND, bool RESUMABLE, bool TEXIT = false>
 PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict__ qr,
                          const SolveParams &P, const LaneLds &S, int64_t i)
 {
@@ -663,7 +663,7 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
     // target_exit: the problem also ends in the pass in which a problem of
     // its target in the same run of lanes meets the tolerance (problems
     // started from their seeds in this launch only)
-    const bool texit = P.target_exit && !resume;
+    const bool texit = TEXIT && !resume;
     const uint64_t trun = texit ? target_run_mask(p / P.K) : 0;
     if (resume) {
         const int st = P.st_state[p];

@@ -19,7 +19,9 @@ PK_DEV int64_t pop_item(int32_t *head)
 }
 
 // One 64-problem item per block; no state kept between launches.
-template <int C, int L, int KIND>
+// TEXIT: the instantiation for target_exit (separate kernels, so that the
+// others' loops carry no trace of it).
+template <int C, int L, int KIND, bool TEXIT>
 __global__ __launch_bounds__(BLOCK) void lm_lane_kernel(const RobotC *__restrict__ rb,
                                                         const float *__restrict__ qr, SolveParams P)
 {
@@ -28,12 +30,12 @@ __global__ __launch_bounds__(BLOCK) void lm_lane_kernel(const RobotC *__restrict
     const LaneLds S{smem + threadIdx.x};
     const int64_t nact = P.n_active ? (int64_t)*P.n_active : P.N;
     const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (i < nact) lane_problem<C, L, KIND, false>(rb, qr, P, S, i);
+    if (i < nact) lane_problem<C, L, KIND, false, TEXIT>(rb, qr, P, S, i);
 }
 
 // Persistent variant: blocks pop 64-problem items from P.queue_head until
 // the active list is exhausted; problem state is resumable.
-template <int C, int L, int KIND>
+template <int C, int L, int KIND, bool TEXIT>
 PK_DEV void persist_loop(const RobotC *__restrict__ rb, const float *__restrict__ qr,
                          const SolveParams &P, float *smem)
 {
@@ -43,18 +45,18 @@ PK_DEV void persist_loop(const RobotC *__restrict__ rb, const float *__restrict_
     int64_t item = pop_item(P.queue_head);
     while (item < nitems) {
         const int64_t i = item * BLOCK + threadIdx.x;
-        if (i < nact) lane_problem<C, L, KIND, true>(rb, qr, P, S, i);
+        if (i < nact) lane_problem<C, L, KIND, true, TEXIT>(rb, qr, P, S, i);
         item = pop_item(P.queue_head);
     }
 }
 
-template <int C, int L, int KIND>
+template <int C, int L, int KIND, bool TEXIT>
 __global__ __launch_bounds__(BLOCK) void lm_lane_persist_kernel(const RobotC *__restrict__ rb,
                                                                 const float *__restrict__ qr,
                                                                 SolveParams P)
 {
     __shared__ float smem[Slots<C, L, KIND>::TOTAL * BLOCK];
-    persist_loop<C, L, KIND>(rb, qr, P, smem);
+    persist_loop<C, L, KIND, TEXIT>(rb, qr, P, smem);
 }
 
 template <int C, int L, int KIND>
@@ -66,11 +68,15 @@ hipError_t launch_star(const RobotC *rb, const SolveParams &P, int persist_block
     if (persist && persist_blocks > 0 && persist_blocks < grid) grid = persist_blocks;
     // rest pose: caller's array, else the robot's mid-range table
     const float *qr = P.q_rest ? P.q_rest : rb->mid;
-    if (persist)
-        hipLaunchKernelGGL((lm_lane_persist_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb,
-                           qr, P);
+    const dim3 g((unsigned)grid), b(block);
+    if (persist && P.target_exit)
+        hipLaunchKernelGGL((lm_lane_persist_kernel<C, L, KIND, true>), g, b, 0, s, rb, qr, P);
+    else if (persist)
+        hipLaunchKernelGGL((lm_lane_persist_kernel<C, L, KIND, false>), g, b, 0, s, rb, qr, P);
+    else if (P.target_exit)
+        hipLaunchKernelGGL((lm_lane_kernel<C, L, KIND, true>), g, b, 0, s, rb, qr, P);
     else
-        hipLaunchKernelGGL((lm_lane_kernel<C, L, KIND>), dim3((unsigned)grid), dim3(block), 0, s, rb, qr, P);
+        hipLaunchKernelGGL((lm_lane_kernel<C, L, KIND, false>), g, b, 0, s, rb, qr, P);
     return hipGetLastError();
 }
 
