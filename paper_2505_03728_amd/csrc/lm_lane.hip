@@ -12,17 +12,17 @@ bool lane_variant_available(int chains, int chain_len, int kind)
 }
 
 hipError_t launch_lm_lane(const RobotC *dev_robot, const RobotC &h, const SolveParams &P,
-                          hipStream_t s, int persist_blocks)
+                          hipStream_t s, int persist_blocks, const BestOut *best)
 {
     const int kind = h.e[0].kind | (h.prismatic ? lane::LANE_PRISMATIC : 0), L = h.chain_len;
     if (h.chains == 1 && L == 7 && kind == PK_EE_POSE)
-        return lane::launch_star<1, 7, PK_EE_POSE>(dev_robot, P, persist_blocks, s);
+        return lane::launch_star<1, 7, PK_EE_POSE>(dev_robot, P, persist_blocks, s, best);
     if (h.chains == 4 && L == 4 && kind == PK_EE_POSITION)
-        return lane::launch_star<4, 4, PK_EE_POSITION>(dev_robot, P, persist_blocks, s);
+        return lane::launch_star<4, 4, PK_EE_POSITION>(dev_robot, P, persist_blocks, s, best);
     if (h.chains == 1) {
-        if (L <= 4) return launch_lane_chain_a(L, kind, dev_robot, P, persist_blocks, s);
-        if (L <= 7) return launch_lane_chain_b(L, kind, dev_robot, P, persist_blocks, s);
-        return launch_lane_chain_c(L, kind, dev_robot, P, persist_blocks, s);
+        if (L <= 4) return launch_lane_chain_a(L, kind, dev_robot, P, persist_blocks, s, best);
+        if (L <= 7) return launch_lane_chain_b(L, kind, dev_robot, P, persist_blocks, s, best);
+        return launch_lane_chain_c(L, kind, dev_robot, P, persist_blocks, s, best);
     }
     return hipErrorInvalidValue;
 }

@@ -638,6 +638,15 @@ PK_DEV void write_result(const SolveParams &P, int64_t p, const float *q, float 
     if (P.iters_to_tol) P.iters_to_tol[p] = itt;
 }
 
+// A problem's final joints, costs and convergence, for a best-of-K taken in
+// the launch that solved it.
+template <int N>
+struct LaneFinal {
+    float q[N];
+    float cost, pcost;
+    bool conv;
+};
+
 // One LM problem (active index i) on this lane.  With P.st_state the run is
 // resumable: it continues from the state a previous launch left in HBM and
 // stops after P.iter_budget iterations.  Each pass of the loop evaluates one
@@ -645,7 +654,8 @@ PK_DEV void write_result(const SolveParams &P, int64_t p, const float *q, float 
 // has a single call site.
 template <int C, int L, int KIND, bool RESUMABLE, bool TEXIT = false>
 PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict__ qr,
-                         const SolveParams &P, const LaneLds &S, int64_t i)
+                         const SolveParams &P, const LaneLds &S, int64_t i,
+                         LaneFinal<Star<C, L, KIND>::N> *fin = nullptr)
 {
     using St = Star<C, L, KIND>;
     const int64_t p = P.active ? (int64_t)P.active[i] : i;
@@ -655,6 +665,12 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
     float q[St::N], qt[St::N];
     if (!load_problem<C, L, KIND>(P, S, resume ? P.joints : P.seeds, p, q)) {
         write_nonfinite<C, L, KIND>(P, p, q, resumable);
+        if (fin) {
+#pragma unroll
+            for (int j = 0; j < St::N; ++j) fin->q[j] = q[j];
+            fin->cost = fin->pcost = NAN;
+            fin->conv = false;
+        }
         return;
     }
     int iters = 0, accepts = 0, itt = -1, flags = 0;
@@ -770,6 +786,13 @@ PK_DEV void lane_problem(const RobotC *__restrict__ rb, const float *__restrict_
     const bool finished = done || iters >= P.max_iters;
     write_result<C, L, KIND>(P, p, q, cost, pcost, perr, rerr, iters, accepts, itt, flags, stalled, finished,
                              tsolved);
+    if (fin) {
+#pragma unroll
+        for (int j = 0; j < St::N; ++j) fin->q[j] = q[j];
+        fin->cost = cost;
+        fin->pcost = pcost;
+        fin->conv = meets_tol<C, L, KIND>(P, perr, rerr);
+    }
     if (resumable) {
         P.st_lambda[p] = lam;
         P.st_state[p] = flags | (stalled ? PK_ST_STALLED : 0) | (finished ? PK_ST_DONE : 0);

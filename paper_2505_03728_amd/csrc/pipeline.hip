@@ -232,6 +232,9 @@ extern "C" int pk_ik_solve_seeded(pk_ctx *ctx, int32_t robot_id, int64_t T, cons
         so.use_graph = 1;
         rc = sched_run(ctx, 1, &g, &o->refine, so, s);
         if (rc) return rc;
+    } else if (va == PK_VARIANT_LANE && 64 % K == 0) {
+        const BestOut B{best_a, nullptr, succ_a};   // best-of-K in the same launch
+        PK_HIP(ctx, launch_lm(*rb, PA, va, s, 0, &B));
     } else {
         PK_HIP(ctx, launch_lm(*rb, PA, va, s));
         PK_HIP(ctx, launch_best_of_k(PA, n, best_a, nullptr, succ_a, s));

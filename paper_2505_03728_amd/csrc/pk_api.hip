@@ -166,9 +166,10 @@ int pk::prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *
 }
 
 hipError_t pk::launch_lm(const RobotEntry &rb, const SolveParams &P, int variant, hipStream_t s,
-                         int persist_blocks)
+                         int persist_blocks, const BestOut *best)
 {
-    if (variant == PK_VARIANT_LANE) return launch_lm_lane(rb.dev, rb.host, P, s, persist_blocks);
+    if (variant == PK_VARIANT_LANE) return launch_lm_lane(rb.dev, rb.host, P, s, persist_blocks, best);
+    if (best) return hipErrorInvalidValue;
     if (variant == PK_VARIANT_WAVE && path_variant_available(rb.host))
         return launch_lm_path(rb.dev, rb.host, P, s, persist_blocks);
     return launch_lm_wave(rb.dev, rb.host, P, s, persist_blocks);
@@ -567,10 +568,14 @@ static int ik_solve_impl(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const
 
     PK_HIP(ctx, hipSetDevice(ctx->device));
     const bool want_best = out->best_index || out->best_joints || out->target_success;
-    // Workspace: pose-only cost, total cost and status when best-of-K needs
-    // them and the caller did not ask for them.
+    // The per-lane kernel takes best-of-K itself when a target's K problems
+    // share a wavefront (K divides 64): one launch instead of two, and the
+    // costs and statuses need not go through memory.
+    const bool fuse = want_best && variant == PK_VARIANT_LANE && 64 % pr->K == 0;
+    // Workspace: pose-only cost, total cost and status when a separate
+    // best-of-K pass needs them and the caller did not ask for them.
     float *ws_f = nullptr;
-    if (want_best && !(out->pose_cost && out->cost && out->status)) {
+    if (want_best && !fuse && !(out->pose_cost && out->cost && out->status)) {
         if (noalloc) {
             int rc = scratch_ptr(ctx, ctx->device, &ws_f);
             if (rc) return rc;
@@ -584,13 +589,18 @@ static int ik_solve_impl(pk_ctx *ctx, int32_t id, const pk_ik_problem *pr, const
     P.K = pr->K; P.N = N; P.T = pr->n_targets;
     P.targets = pr->targets; P.seeds = pr->seeds;
     P.joints = out->joints; P.pos_err = out->pos_err; P.rot_err = out->rot_err;
-    P.pose_cost = out->pose_cost ? out->pose_cost : (want_best ? ws_f : nullptr);
-    P.cost = out->cost ? out->cost : (want_best ? ws_f + N : nullptr);
-    P.status = out->status ? out->status : (want_best ? (int32_t *)(ws_f + 2 * N) : nullptr);
+    P.pose_cost = out->pose_cost ? out->pose_cost : (ws_f ? ws_f : nullptr);
+    P.cost = out->cost ? out->cost : (ws_f ? ws_f + N : nullptr);
+    P.status = out->status ? out->status : (ws_f ? (int32_t *)(ws_f + 2 * N) : nullptr);
     P.iters = out->iters; P.accepts = out->accepts; P.iters_to_tol = out->iters_to_tol;
     P.trace_iters = out->trace_iters; P.trace_q = out->trace_q; P.trace_acc = out->trace_accept;
 
     hipStream_t s = (hipStream_t)stream;
+    if (fuse) {
+        const BestOut B{out->best_index, out->best_joints, out->target_success};
+        PK_HIP(ctx, launch_lm(*rb, P, variant, s, 0, &B));
+        return PK_OK;
+    }
     PK_HIP(ctx, launch_lm(*rb, P, variant, s));
     if (want_best)
         PK_HIP(ctx, launch_best_of_k(P, H.nv, out->best_index, out->best_joints, out->target_success, s));

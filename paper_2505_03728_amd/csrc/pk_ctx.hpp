@@ -41,8 +41,9 @@ RobotEntry *robot_of(pk_ctx *ctx, int32_t id);
 // resolves the kernel variant.  Returns PK_OK or an error (message set).
 int prepare_solve(pk_ctx *ctx, const RobotEntry &rb, const pk_cost_weights *w,
                   const pk_lm_options *o, SolveParams &P, int &variant);
+// best: best-of-K in the LM launch itself (per-lane kernel only; see launch_lm_lane).
 hipError_t launch_lm(const RobotEntry &rb, const SolveParams &P, int variant, hipStream_t s,
-                     int persist_blocks = 0);
+                     int persist_blocks = 0, const BestOut *best = nullptr);
 void sched_free(pk_ctx *ctx);
 // Reads the autotune table named by PK_AUTOTUNE_TABLE, if any, into ctx.
 void sched_load_env(pk_ctx *ctx);

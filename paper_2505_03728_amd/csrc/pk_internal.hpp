@@ -134,12 +134,23 @@ struct SolveParams {
 #define PK_ST_DONE 0x10000
 #define PK_ST_STALLED 0x20000
 
+// Best-of-K outputs written by the per-lane kernel itself (its K problems of
+// a target share a wavefront when K divides 64); NULL pointers are skipped.
+struct BestOut {
+    int32_t *index;
+    float *joints;     // [n][T]
+    int32_t *success;
+};
+
 // Launchers (defined next to their kernels).  Return hipSuccess or the
 // launch error.
 bool lane_variant_available(int chains, int chain_len, int kind);
 // persist_blocks: grid size when P.queue_head is set (0 = one block per item).
+// best (non-persistent launches without an active list, K dividing 64 only):
+// best-of-K in the same launch.
 hipError_t launch_lm_lane(const RobotC *dev_robot, const RobotC &host_robot,
-                          const SolveParams &P, hipStream_t s, int persist_blocks = 0);
+                          const SolveParams &P, hipStream_t s, int persist_blocks = 0,
+                          const BestOut *best = nullptr);
 bool wave_variant_available(int n);
 hipError_t launch_lm_wave(const RobotC *dev_robot, const RobotC &host_robot,
                           const SolveParams &P, hipStream_t s, int persist_blocks = 0);
