@@ -40,7 +40,7 @@ BF16_MFMA_PEAK = 2500.0     # TFLOP/s, MI355X dense BF16 matrix cores (datasheet
 LANE_KERNEL_SOURCES = ["paper_2505_03728_amd/csrc/lm_lane.hip", "paper_2505_03728_amd/csrc/lm_lane.hpp",
                        "paper_2505_03728_amd/csrc/lm_lane_kernels.hpp", "paper_2505_03728_amd/csrc/pk_device.hpp",
                        "paper_2505_03728_amd/csrc/pk_internal.hpp", "include/pkmi.h"]
-ARM_TRAFFIC = {"sha256": "30cd4e805e425843", "fetch_kib": 2828.0, "write_kib": 7680.0, "fetch_scale": 2.0,
+ARM_TRAFFIC = {"sha256": "e230fbc486226fec", "fetch_kib": 2842.0, "write_kib": 7680.0, "fetch_scale": 2.0,
                "write_scale": 1.0,
                "workload": {"targets": 16384, "K": 8, "max_iters": 30, "early_exit": True},
                "profile": "profiles/lm_lane_arm131k_hbm_counters.md"}
