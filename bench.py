@@ -80,7 +80,7 @@ def parse():
                     help="early exit off (every problem runs all its iterations)")
     ap.add_argument("--workload", default="arm131k",
                     choices=["arm131k", "tree4k", "mixed84k", "seeder", "beam", "mobile", "traj"])
-    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=None)   # None: the seeder workload's
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()

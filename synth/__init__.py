@@ -453,7 +453,7 @@ def workload(name: str, scale: float = 1.0, targets: int | None = None) -> dict:
                 "plain_seeds": uniform_configs(r, T * K, 17),
                 "weights": _weights(w_rest=0.01), "options": _options(30),
                 "mlp": {"hidden": 512, "depth": 3, "batch": 8192, "lr": 1e-3,
-                        "epochs": 20, "init_seed": 18, "shuffle_seed": 19}}
+                        "epochs": 40, "init_seed": 18, "shuffle_seed": 19}}
     raise KeyError(name)
 
 
